@@ -1,0 +1,761 @@
+/*
+ * FP64 CPU oracle for the long-range (tree) part of the P3T force split of
+ * PeTar (Wang, Iwasawa, Nitadori & Makino 2020).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library may include,
+ * link or call this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it. It shares no code, header, table or
+ * helper with the GPU library.
+ *
+ * Everything is plain, slow and written to be checked against the paper by
+ * eye: FP64 throughout, no blocking, no fusion, OpenMP only over the
+ * independent target particles. Build with -ffp-contract=off so the
+ * neighbour distance test rounds exactly as written.
+ *
+ * Contents
+ *   1. Changeover functions f, W, K  (Sec. "Mass-dependent changeover
+ *      function": definitions of f, W and the force weight, eq. Wij).
+ *   2. Changeover radii (eq. rcut) and neighbour search radius (eq. rnb).
+ *   3. Direct sums: long-range (H_L of eq. cf), short-range (H_S), Newton.
+ *   4. Neighbour candidates (Sec. "Orbit-dependent neighbour criterion",
+ *      stage 1: spherical search), pair radius max(r_s,i, r_s,j).
+ *   5. Multipole of a particle set: monopole + traceless quadrupole
+ *      (eq. quad, eq. quadtr) and its field.
+ *   6. Barnes-Hut tree force (Sec. "Particle-tree with individual time
+ *      steps" and the P3T figure caption: cells inside the opening angle are
+ *      replaced by centre-of-mass + quadrupole super-particles), group-wise
+ *      walk with the search-radius opening rule.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------
+ * 1. Changeover functions (literal forms of the paper).
+ *    x = (r - r_in,ij)/(r_out,ij - r_in,ij),
+ *    Lambda = (r_out,ij - r_in,ij)/(r_out,ij + r_in,ij).
+ * ---------------------------------------------------------------------- */
+
+/* f(x) = 1 + Lambda x^5 (14 - 28x + 20x^2 - 5x^3) */
+OR_EXPORT double oracle_f(double x, double lam)
+{
+    double x2 = x * x;
+    double x5 = x2 * x2 * x;
+    return 1.0 + lam * x5 * (14.0 - 28.0 * x + 20.0 * x2 - 5.0 * x2 * x);
+}
+
+/* Potential weight W(x): Lambda(1-2x) for x <= 0, Lambda(1-2x) - 1 + f(x)
+ * inside, 0 for x >= 1. */
+OR_EXPORT double oracle_W(double x, double lam)
+{
+    if (x <= 0.0) return lam * (1.0 - 2.0 * x);
+    if (x >= 1.0) return 0.0;
+    return lam * (1.0 - 2.0 * x) - 1.0 + oracle_f(x, lam);
+}
+
+/* Force weight K(x) (eq. Wij): 1 for x <= 0,
+ * (x-1)^4 (1 + 4x + 10x^2 + 20x^3 + 35 Lambda x^4) inside, 0 for x >= 1. */
+OR_EXPORT double oracle_K(double x, double lam)
+{
+    if (x <= 0.0) return 1.0;
+    if (x >= 1.0) return 0.0;
+    double xm = x - 1.0;
+    double xm4 = xm * xm * xm * xm;
+    double x2 = x * x;
+    return xm4 * (1.0 + 4.0 * x + 10.0 * x2 + 20.0 * x2 * x + 35.0 * lam * x2 * x2);
+}
+
+/* Pair changeover radii: r_in,ij = max(r_in,i, r_in,j), same for r_out. */
+static void pair_radii(double rin_i, double rout_i, double rin_j, double rout_j,
+                       double *rin, double *rout)
+{
+    *rin = rin_i > rin_j ? rin_i : rin_j;
+    *rout = rout_i > rout_j ? rout_i : rout_j;
+}
+
+/* Long-range weights of one pair at distance r (> 0 or == 0):
+ *   fw = 1 - K(x)            (force:  a += G m fw (r_j - r_i)/r^3)
+ *   pw = (1 - W(x)) / r      (potential: phi -= G m pw)
+ * At r == 0 the x <= 0 branch holds and (1 - W)/r is its limit
+ * 2/(r_in + r_out) (the literal form is 0/0 there). */
+static void long_weights(double r, double rin, double rout, double *fw, double *pw)
+{
+    double lam = (rout - rin) / (rout + rin);
+    double x = (r - rin) / (rout - rin);
+    *fw = 1.0 - oracle_K(x, lam);
+    if (r > 0.0)
+        *pw = (1.0 - oracle_W(x, lam)) / r;
+    else
+        *pw = 2.0 / (rin + rout);
+}
+
+/* ------------------------------------------------------------------------
+ * 2. Radii. eq. rcut: r_in,i = max(1, m_i/<m>)^(1/3) r_in,ref, same for
+ *    r_out; <m> = (sum m)/N. Search radius: search_factor * r_out,i, or
+ *    eq. rnb r_out,i + C_r |v_i| dt_L when velocities are given
+ *    (cr_dt = C_r * dt_L). Returns 0, or -1 on invalid arguments.
+ * ---------------------------------------------------------------------- */
+OR_EXPORT int oracle_radii(const double *mass, const double *vel, int64_t n,
+                           double rin_ref, double rout_ref, double search_factor,
+                           double cr_dt, double *r_in, double *r_out, double *r_search)
+{
+    if (n < 1 || !(rin_ref >= 0.0) || !(rout_ref > rin_ref)) return -1;
+    double msum = 0.0;
+    for (int64_t i = 0; i < n; i++) msum += mass[i];
+    double mave = msum / (double)n;
+    for (int64_t i = 0; i < n; i++) {
+        double ratio = mave > 0.0 ? mass[i] / mave : 1.0;
+        double s = cbrt(ratio > 1.0 ? ratio : 1.0);
+        r_in[i] = s * rin_ref;
+        r_out[i] = s * rout_ref;
+        if (vel) {
+            double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+            r_search[i] = r_out[i] + cr_dt * sqrt(vx * vx + vy * vy + vz * vz);
+        } else {
+            r_search[i] = search_factor * r_out[i];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * 3. Direct sums over all j != i, for the target indices idx[0..n_idx).
+ *    pos is SoA [3][n]; acc is SoA [3][n_idx]; pot is [n_idx].
+ * ---------------------------------------------------------------------- */
+OR_EXPORT void oracle_force_long(const double *pos, const double *mass, const double *r_in,
+                                 const double *r_out, int64_t n, double G, const int64_t *idx,
+                                 int64_t n_idx, double *acc, double *pot)
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_idx; k++) {
+        int64_t i = idx ? idx[k] : k;
+        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double rin, rout, fw, pw;
+            pair_radii(r_in[i], r_out[i], r_in[j], r_out[j], &rin, &rout);
+            long_weights(r, rin, rout, &fw, &pw);
+            if (fw != 0.0) {
+                double s = G * mass[j] * fw / (r * r * r);
+                ax += s * dx;
+                ay += s * dy;
+                az += s * dz;
+            }
+            ph -= G * mass[j] * pw;
+        }
+        acc[k] = ax;
+        acc[n_idx + k] = ay;
+        acc[2 * n_idx + k] = az;
+        pot[k] = ph;
+    }
+}
+
+/* Short-range companion (H_S of eq. cf): weights K(x) for the force and
+ * W(x)/r for the potential. Singular at r == 0 (callers avoid it). */
+OR_EXPORT void oracle_force_short(const double *pos, const double *mass, const double *r_in,
+                                  const double *r_out, int64_t n, double G, const int64_t *idx,
+                                  int64_t n_idx, double *acc, double *pot)
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_idx; k++) {
+        int64_t i = idx ? idx[k] : k;
+        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double rin, rout;
+            pair_radii(r_in[i], r_out[i], r_in[j], r_out[j], &rin, &rout);
+            double lam = (rout - rin) / (rout + rin);
+            double x = (r - rin) / (rout - rin);
+            double s = G * mass[j] * oracle_K(x, lam) / (r * r * r);
+            ax += s * dx;
+            ay += s * dy;
+            az += s * dz;
+            ph -= G * mass[j] * oracle_W(x, lam) / r;
+        }
+        acc[k] = ax;
+        acc[n_idx + k] = ay;
+        acc[2 * n_idx + k] = az;
+        pot[k] = ph;
+    }
+}
+
+/* Plain Newtonian direct sum (no changeover). */
+OR_EXPORT void oracle_force_newton(const double *pos, const double *mass, int64_t n, double G,
+                                   const int64_t *idx, int64_t n_idx, double *acc, double *pot)
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_idx; k++) {
+        int64_t i = idx ? idx[k] : k;
+        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double s = G * mass[j] / (r * r * r);
+            ax += s * dx;
+            ay += s * dy;
+            az += s * dz;
+            ph -= G * mass[j] / r;
+        }
+        acc[k] = ax;
+        acc[n_idx + k] = ay;
+        acc[2 * n_idx + k] = az;
+        pot[k] = ph;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * 4. Neighbour candidates: j != i with d^2 < R^2, R = max(r_s,i, r_s,j),
+ *    d^2 = ((dx*dx) + (dy*dy)) + (dz*dz), dx = x_j - x_i, each operation
+ *    rounded (no contraction). Lists come out in ascending j.
+ *    counts[k] receives the count of target k. If out != NULL, the lists
+ *    are written back to back (capacity entries at most). Returns the total.
+ * ---------------------------------------------------------------------- */
+static int is_neighbour(const double *X, const double *Y, const double *Z, const double *rs,
+                        int64_t i, int64_t j)
+{
+    double dx = X[j] - X[i];
+    double dy = Y[j] - Y[i];
+    double dz = Z[j] - Z[i];
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    double d2 = xx + yy;
+    d2 = d2 + zz;
+    double R = rs[i] > rs[j] ? rs[i] : rs[j];
+    double R2 = R * R;
+    return d2 < R2;
+}
+
+OR_EXPORT int64_t oracle_neighbours(const double *pos, const double *r_search, int64_t n,
+                                    const int64_t *idx, int64_t n_idx, int64_t *counts,
+                                    int32_t *out, int64_t capacity)
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_idx; k++) {
+        int64_t i = idx ? idx[k] : k;
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; j++)
+            if (j != i && is_neighbour(X, Y, Z, r_search, i, j)) c++;
+        counts[k] = c;
+    }
+    int64_t total = 0;
+    for (int64_t k = 0; k < n_idx; k++) total += counts[k];
+    if (out && total <= capacity) {
+        int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_idx + 1));
+        start[0] = 0;
+        for (int64_t k = 0; k < n_idx; k++) start[k + 1] = start[k] + counts[k];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t k = 0; k < n_idx; k++) {
+            int64_t i = idx ? idx[k] : k;
+            int64_t w = start[k];
+            for (int64_t j = 0; j < n; j++)
+                if (j != i && is_neighbour(X, Y, Z, r_search, i, j)) out[w++] = (int32_t)j;
+        }
+        free(start);
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------------
+ * 5. Multipole of a particle set about its centre of mass c:
+ *    M = sum m, A' = (3/2) sum m q q^T - (1/2) (sum m |q|^2) I, q = x - c
+ *    (eq. quad, eq. quadtr; the trace term multiplies the identity).
+ *    quad6 = (A'xx, A'yy, A'zz, A'xy, A'xz, A'yz).
+ *    Field at R = p - c (attracting):
+ *      phi = -G (M/|R| + R.A'R/|R|^5)
+ *      a   = G (-M R/|R|^3 + 2 A'R/|R|^5 - 5 (R.A'R) R/|R|^7)   (a = -grad phi)
+ * ---------------------------------------------------------------------- */
+static void moments(const double *X, const double *Y, const double *Z, const double *mass,
+                    const int64_t *members, int64_t cnt, double *M, double com[3], double A[6])
+{
+    double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = 0; k < cnt; k++) {
+        int64_t j = members[k];
+        m += mass[j];
+        sx += mass[j] * X[j];
+        sy += mass[j] * Y[j];
+        sz += mass[j] * Z[j];
+        double p[3] = {X[j], Y[j], Z[j]};
+        for (int d = 0; d < 3; d++) {
+            if (p[d] < lo[d]) lo[d] = p[d];
+            if (p[d] > hi[d]) hi[d] = p[d];
+        }
+    }
+    *M = m;
+    if (m > 0.0) {
+        com[0] = sx / m;
+        com[1] = sy / m;
+        com[2] = sz / m;
+    } else { /* massless set: use the centre of its bounding box */
+        for (int d = 0; d < 3; d++) com[d] = 0.5 * (lo[d] + hi[d]);
+    }
+    double axx = 0, ayy = 0, azz = 0, axy = 0, axz = 0, ayz = 0, q2 = 0;
+    for (int64_t k = 0; k < cnt; k++) {
+        int64_t j = members[k];
+        double qx = X[j] - com[0], qy = Y[j] - com[1], qz = Z[j] - com[2];
+        axx += mass[j] * qx * qx;
+        ayy += mass[j] * qy * qy;
+        azz += mass[j] * qz * qz;
+        axy += mass[j] * qx * qy;
+        axz += mass[j] * qx * qz;
+        ayz += mass[j] * qy * qz;
+        q2 += mass[j] * (qx * qx + qy * qy + qz * qz);
+    }
+    A[0] = 1.5 * axx - 0.5 * q2;
+    A[1] = 1.5 * ayy - 0.5 * q2;
+    A[2] = 1.5 * azz - 0.5 * q2;
+    A[3] = 1.5 * axy;
+    A[4] = 1.5 * axz;
+    A[5] = 1.5 * ayz;
+}
+
+static void multipole_field(double M, const double c[3], const double A[6], double G,
+                            double px, double py, double pz, double *a, double *phi)
+{
+    double Rx = px - c[0], Ry = py - c[1], Rz = pz - c[2];
+    double r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    double r = sqrt(r2);
+    double ARx = A[0] * Rx + A[3] * Ry + A[4] * Rz;
+    double ARy = A[3] * Rx + A[1] * Ry + A[5] * Rz;
+    double ARz = A[4] * Rx + A[5] * Ry + A[2] * Rz;
+    double RAR = Rx * ARx + Ry * ARy + Rz * ARz;
+    double r3 = r2 * r, r5 = r3 * r2, r7 = r5 * r2;
+    a[0] += G * (-M * Rx / r3 + 2.0 * ARx / r5 - 5.0 * RAR * Rx / r7);
+    a[1] += G * (-M * Ry / r3 + 2.0 * ARy / r5 - 5.0 * RAR * Ry / r7);
+    a[2] += G * (-M * Rz / r3 + 2.0 * ARz / r5 - 5.0 * RAR * Rz / r7);
+    *phi -= G * (M / r + RAR / r5);
+}
+
+OR_EXPORT void oracle_multipole(const double *pos, const double *mass, int64_t n, double *M,
+                                double *com, double *quad6)
+{
+    int64_t *all = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t k = 0; k < n; k++) all[k] = k;
+    moments(pos, pos + n, pos + 2 * n, mass, all, n, M, com, quad6);
+    free(all);
+}
+
+/* Field of (M, com, quad6) at npts points (SoA [3][npts]). */
+OR_EXPORT void oracle_multipole_eval(double M, const double *com, const double *quad6, double G,
+                                     const double *pts, int64_t npts, double *acc, double *pot)
+{
+    for (int64_t k = 0; k < npts; k++) {
+        double a[3] = {0, 0, 0}, ph = 0.0;
+        multipole_field(M, com, quad6, G, pts[k], pts[npts + k], pts[2 * npts + k], a, &ph);
+        acc[k] = a[0];
+        acc[npts + k] = a[1];
+        acc[2 * npts + k] = a[2];
+        pot[k] = ph;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * 6. Barnes-Hut tree force with group-wise walk.
+ *
+ *  Root cube: lo_d = min x_d, ext = max_d (max x_d - min x_d) (1 if 0).
+ *  Integer coordinate per axis: q = floor((x - lo) * (2^21/ext)), clamped
+ *  to 2^21 - 1. A cell at level l holds the particles sharing the top l bits
+ *  of all three q; its side is ext / 2^l. A cell with <= leaf_size particles,
+ *  or at level 21, is a leaf; otherwise its non-empty octants are children.
+ *  Cell data: mass, centre of mass, A' (section 5), particle bounding box,
+ *  max r_search of its members.
+ *  i-groups: the first cells on each root-to-leaf path that hold
+ *  <= group_size particles or are leaves.
+ *  Walk of group g (members' bounding box B_g, max r_search S_g), per cell:
+ *    D2   = squared distance between B_g and the cell's bounding box
+ *    dmin2= squared distance from B_g to the cell's centre of mass
+ *    R    = max(S_g, cell max r_search)
+ *    multipole  iff side^2 < theta^2 * dmin2  and not (D2 < R^2)
+ *    otherwise a leaf is "near" (pairs with changeover weights) if
+ *    D2 < R^2, "far" (plain Newtonian pairs) if not; an internal cell opens.
+ *  Since r_search >= r_out, every pair reached through a multipole or a far
+ *  leaf has x >= 1, where K = W = 0: the long-range force there is plain
+ *  Newtonian and the expansion is exact in form.
+ * ---------------------------------------------------------------------- */
+
+#define OR_MAXLEVEL 21
+
+typedef struct {
+    int64_t begin, count; /* range in the member permutation */
+    int level;
+    int leaf;
+    int64_t child[8];
+    int nchild;
+    double M, com[3], A[6], lo[3], hi[3], rsmax;
+} ocell;
+
+typedef struct {
+    ocell *c;
+    int64_t n, cap;
+} ocells;
+
+static int64_t push_cell(ocells *cs)
+{
+    if (cs->n == cs->cap) {
+        cs->cap = cs->cap ? 2 * cs->cap : 1024;
+        cs->c = (ocell *)realloc(cs->c, sizeof(ocell) * (size_t)cs->cap);
+    }
+    memset(&cs->c[cs->n], 0, sizeof(ocell));
+    return cs->n++;
+}
+
+typedef struct {
+    const double *X, *Y, *Z, *mass, *rs;
+    const uint32_t *q; /* [3][n] integer coordinates */
+    int64_t n;
+    int leaf_size;
+    int64_t *perm, *tmp;
+    ocells cells;
+} obuild;
+
+static int octant(const obuild *b, int64_t j, int level)
+{
+    int shift = OR_MAXLEVEL - 1 - level; /* bit of the child level */
+    int bx = (b->q[j] >> shift) & 1;
+    int by = (b->q[b->n + j] >> shift) & 1;
+    int bz = (b->q[2 * b->n + j] >> shift) & 1;
+    return (bx << 2) | (by << 1) | bz;
+}
+
+static int64_t build_cell(obuild *b, int64_t begin, int64_t count, int level)
+{
+    int64_t id = push_cell(&b->cells);
+    ocell *c = &b->cells.c[id];
+    c->begin = begin;
+    c->count = count;
+    c->level = level;
+    c->leaf = (count <= b->leaf_size || level == OR_MAXLEVEL);
+    if (c->leaf) return id;
+    /* stable partition of the range by child octant */
+    int64_t cnt[8] = {0}, off[8];
+    for (int64_t k = begin; k < begin + count; k++) cnt[octant(b, b->perm[k], level)]++;
+    off[0] = begin;
+    for (int o = 1; o < 8; o++) off[o] = off[o - 1] + cnt[o - 1];
+    int64_t w[8];
+    memcpy(w, off, sizeof(w));
+    for (int64_t k = begin; k < begin + count; k++) {
+        int64_t j = b->perm[k];
+        b->tmp[w[octant(b, j, level)]++] = j;
+    }
+    memcpy(b->perm + begin, b->tmp + begin, sizeof(int64_t) * (size_t)count);
+    int64_t kids[8];
+    int nk = 0;
+    for (int o = 0; o < 8; o++)
+        if (cnt[o]) kids[nk++] = build_cell(b, off[o], cnt[o], level + 1);
+    c = &b->cells.c[id]; /* the array may have moved */
+    c->nchild = nk;
+    for (int o = 0; o < nk; o++) c->child[o] = kids[o];
+    return id;
+}
+
+static double box_dist2(const double alo[3], const double ahi[3], const double blo[3],
+                        const double bhi[3])
+{
+    double g[3];
+    for (int d = 0; d < 3; d++) {
+        double t1 = blo[d] - ahi[d];
+        double t2 = alo[d] - bhi[d];
+        double t = t1 > t2 ? t1 : t2;
+        g[d] = t > 0.0 ? t : 0.0;
+    }
+    double gx = g[0] * g[0];
+    double gy = g[1] * g[1];
+    double gz = g[2] * g[2];
+    double s = gx + gy;
+    return s + gz;
+}
+
+static double point_box_dist2(const double alo[3], const double ahi[3], const double p[3])
+{
+    double g[3];
+    for (int d = 0; d < 3; d++) {
+        double t1 = p[d] - ahi[d];
+        double t2 = alo[d] - p[d];
+        double t = t1 > t2 ? t1 : t2;
+        g[d] = t > 0.0 ? t : 0.0;
+    }
+    double gx = g[0] * g[0];
+    double gy = g[1] * g[1];
+    double gz = g[2] * g[2];
+    double s = gx + gy;
+    return s + gz;
+}
+
+typedef struct {
+    int64_t *pc, *far, *near; /* cell ids */
+    int64_t npc, nfar, nnear, cap;
+} olists;
+
+/* Each cell enters a group's lists at most once, so lists sized to the
+ * number of cells never overflow. */
+static void lists_push(int64_t **a, int64_t *na, int64_t v) { (*a)[(*na)++] = v; }
+
+static void walk(const ocells *cs, int64_t cid, const ocell *g, double th2, double ext, olists *L)
+{
+    const ocell *c = &cs->c[cid];
+    double D2 = box_dist2(g->lo, g->hi, c->lo, c->hi);
+    double dmin2 = point_box_dist2(g->lo, g->hi, c->com);
+    double R = g->rsmax > c->rsmax ? g->rsmax : c->rsmax;
+    double R2 = R * R;
+    double side = ldexp(ext, -c->level);
+    double side2 = side * side;
+    double rhs = th2 * dmin2;
+    if (side2 < rhs && !(D2 < R2)) {
+        lists_push(&L->pc, &L->npc, cid);
+        return;
+    }
+    if (c->leaf) {
+        if (D2 < R2)
+            lists_push(&L->near, &L->nnear, cid);
+        else
+            lists_push(&L->far, &L->nfar, cid);
+        return;
+    }
+    for (int k = 0; k < c->nchild; k++) walk(cs, c->child[k], g, th2, ext, L);
+}
+
+static void find_groups(const ocells *cs, int64_t cid, int group_size, int64_t *groups,
+                        int64_t *ng)
+{
+    const ocell *c = &cs->c[cid];
+    if (c->count <= group_size || c->leaf) {
+        groups[(*ng)++] = cid;
+        return;
+    }
+    for (int k = 0; k < c->nchild; k++) find_groups(cs, c->child[k], group_size, groups, ng);
+}
+
+/* Tree structure summary: info[0..5] = n_cells, n_leaves, n_groups,
+ * max_level, max leaf count, sum over leaves of count (== n). */
+static int build_tree(const double *pos, const double *mass, const double *r_search, int64_t n,
+                      int leaf_size, obuild *b, double *ext_out)
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+    double lo[3] = {X[0], Y[0], Z[0]}, hi[3] = {X[0], Y[0], Z[0]};
+    for (int64_t i = 1; i < n; i++) {
+        double p[3] = {X[i], Y[i], Z[i]};
+        for (int d = 0; d < 3; d++) {
+            if (p[d] < lo[d]) lo[d] = p[d];
+            if (p[d] > hi[d]) hi[d] = p[d];
+        }
+    }
+    double ext = 0.0;
+    for (int d = 0; d < 3; d++) {
+        double e = hi[d] - lo[d];
+        if (e > ext) ext = e;
+    }
+    if (!(ext > 0.0)) ext = 1.0;
+    double scale = 2097152.0 / ext;
+    uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
+    const double *P[3] = {X, Y, Z};
+    for (int d = 0; d < 3; d++)
+        for (int64_t i = 0; i < n; i++) {
+            double t = (P[d][i] - lo[d]) * scale;
+            uint64_t v = (uint64_t)t;
+            if (v > 2097151u) v = 2097151u;
+            q[(size_t)d * n + i] = (uint32_t)v;
+        }
+    memset(b, 0, sizeof(*b));
+    b->X = X;
+    b->Y = Y;
+    b->Z = Z;
+    b->mass = mass;
+    b->rs = r_search;
+    b->q = q;
+    b->n = n;
+    b->leaf_size = leaf_size;
+    b->perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    b->tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) b->perm[i] = i;
+    build_cell(b, 0, n, 0);
+    /* cell data straight from each cell's members */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < b->cells.n; k++) {
+        ocell *c = &b->cells.c[k];
+        const int64_t *mem = b->perm + c->begin;
+        moments(X, Y, Z, mass, mem, c->count, &c->M, c->com, c->A);
+        for (int d = 0; d < 3; d++) {
+            c->lo[d] = INFINITY;
+            c->hi[d] = -INFINITY;
+        }
+        c->rsmax = 0.0;
+        for (int64_t t = 0; t < c->count; t++) {
+            int64_t j = mem[t];
+            double p[3] = {X[j], Y[j], Z[j]};
+            for (int d = 0; d < 3; d++) {
+                if (p[d] < c->lo[d]) c->lo[d] = p[d];
+                if (p[d] > c->hi[d]) c->hi[d] = p[d];
+            }
+            if (r_search && r_search[j] > c->rsmax) c->rsmax = r_search[j];
+        }
+    }
+    free(q);
+    b->q = NULL;
+    *ext_out = ext;
+    return 0;
+}
+
+static void free_tree(obuild *b)
+{
+    free(b->perm);
+    free(b->tmp);
+    free(b->cells.c);
+}
+
+OR_EXPORT int oracle_tree_info(const double *pos, const double *mass, int64_t n, int leaf_size,
+                               int group_size, int64_t *info)
+{
+    if (n < 1 || leaf_size < 1 || group_size < 1) return -1;
+    obuild b;
+    double ext;
+    build_tree(pos, mass, NULL, n, leaf_size, &b, &ext);
+    int64_t nleaf = 0, maxlev = 0, maxleaf = 0, sumleaf = 0;
+    for (int64_t k = 0; k < b.cells.n; k++) {
+        ocell *c = &b.cells.c[k];
+        if (c->level > maxlev) maxlev = c->level;
+        if (c->leaf) {
+            nleaf++;
+            sumleaf += c->count;
+            if (c->count > maxleaf) maxleaf = c->count;
+        }
+    }
+    int64_t *groups = (int64_t *)malloc(sizeof(int64_t) * (size_t)b.cells.n);
+    int64_t ng = 0;
+    find_groups(&b.cells, 0, group_size, groups, &ng);
+    info[0] = b.cells.n;
+    info[1] = nleaf;
+    info[2] = ng;
+    info[3] = maxlev;
+    info[4] = maxleaf;
+    info[5] = sumleaf;
+    free(groups);
+    free_tree(&b);
+    return 0;
+}
+
+/* Tree force for the targets idx[0..n_idx) (all particles if idx == NULL).
+ * acc SoA [3][n_idx], pot [n_idx]. counts (optional) SoA [4][n_idx]:
+ * number of multipole cells, far-leaf particles and near-leaf particles in
+ * the target's group lists, and the size of its group. Returns 0 or -1. */
+OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const double *r_in,
+                                const double *r_out, const double *r_search, int64_t n,
+                                double theta, int leaf_size, int group_size, double G,
+                                const int64_t *idx, int64_t n_idx, double *acc, double *pot,
+                                int64_t *counts)
+{
+    if (n < 1 || leaf_size < 1 || group_size < 1 || !(theta >= 0.0)) return -1;
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+    obuild b;
+    double ext;
+    build_tree(pos, mass, r_search, n, leaf_size, &b, &ext);
+    int64_t *groups = (int64_t *)malloc(sizeof(int64_t) * (size_t)b.cells.n);
+    int64_t ng = 0;
+    find_groups(&b.cells, 0, group_size, groups, &ng);
+    /* particle -> group, and target -> slot */
+    int64_t *gof = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t g = 0; g < ng; g++) {
+        ocell *c = &b.cells.c[groups[g]];
+        for (int64_t t = 0; t < c->count; t++) gof[b.perm[c->begin + t]] = g;
+    }
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) slot[i] = -1;
+    char *gwant = (char *)calloc((size_t)ng, 1);
+    for (int64_t k = 0; k < n_idx; k++) {
+        int64_t i = idx ? idx[k] : k;
+        slot[i] = k;
+        gwant[gof[i]] = 1;
+    }
+    double th2 = theta * theta;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < ng; g++) {
+        if (!gwant[g]) continue;
+        const ocell *gc = &b.cells.c[groups[g]];
+        olists L;
+        L.cap = b.cells.n;
+        L.pc = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.cap);
+        L.far = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.cap);
+        L.near = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.cap);
+        L.npc = L.nfar = L.nnear = 0;
+        walk(&b.cells, 0, gc, th2, ext, &L);
+        int64_t nfarp = 0, nnearp = 0;
+        for (int64_t t = 0; t < L.nfar; t++) nfarp += b.cells.c[L.far[t]].count;
+        for (int64_t t = 0; t < L.nnear; t++) nnearp += b.cells.c[L.near[t]].count;
+        for (int64_t m = 0; m < gc->count; m++) {
+            int64_t i = b.perm[gc->begin + m];
+            int64_t k = slot[i];
+            if (k < 0) continue;
+            double a[3] = {0, 0, 0}, ph = 0.0;
+            /* multipole cells */
+            for (int64_t t = 0; t < L.npc; t++) {
+                const ocell *c = &b.cells.c[L.pc[t]];
+                multipole_field(c->M, c->com, c->A, G, X[i], Y[i], Z[i], a, &ph);
+            }
+            /* far leaves: Newtonian pairs */
+            for (int64_t t = 0; t < L.nfar; t++) {
+                const ocell *c = &b.cells.c[L.far[t]];
+                for (int64_t u = 0; u < c->count; u++) {
+                    int64_t j = b.perm[c->begin + u];
+                    double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+                    double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    double s = G * mass[j] / (r * r * r);
+                    a[0] += s * dx;
+                    a[1] += s * dy;
+                    a[2] += s * dz;
+                    ph -= G * mass[j] / r;
+                }
+            }
+            /* near leaves: pairs with changeover weights */
+            for (int64_t t = 0; t < L.nnear; t++) {
+                const ocell *c = &b.cells.c[L.near[t]];
+                for (int64_t u = 0; u < c->count; u++) {
+                    int64_t j = b.perm[c->begin + u];
+                    if (j == i) continue;
+                    double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+                    double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    double rin, rout, fw, pw;
+                    pair_radii(r_in[i], r_out[i], r_in[j], r_out[j], &rin, &rout);
+                    long_weights(r, rin, rout, &fw, &pw);
+                    if (fw != 0.0) {
+                        double s = G * mass[j] * fw / (r * r * r);
+                        a[0] += s * dx;
+                        a[1] += s * dy;
+                        a[2] += s * dz;
+                    }
+                    ph -= G * mass[j] * pw;
+                }
+            }
+            acc[k] = a[0];
+            acc[n_idx + k] = a[1];
+            acc[2 * n_idx + k] = a[2];
+            pot[k] = ph;
+            if (counts) {
+                counts[k] = L.npc;
+                counts[n_idx + k] = nfarp;
+                counts[2 * n_idx + k] = nnearp;
+                counts[3 * n_idx + k] = gc->count;
+            }
+        }
+        free(L.pc);
+        free(L.far);
+        free(L.near);
+    }
+    free(gwant);
+    free(slot);
+    free(gof);
+    free(groups);
+    free_tree(&b);
+    return 0;
+}

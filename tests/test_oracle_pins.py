@@ -1,0 +1,384 @@
+"""Pins of the FP64 oracle against what the PeTar paper and the mathematics fix.
+
+None of these tests re-types the oracle's formulas: each checks a property
+the paper states (boundary values eq. cof, the relations between f, W and K,
+symmetric pair radii), a physical identity (force = -grad potential,
+H_L + H_S = Newton, momentum conservation, superposition), a closed form
+(two-body branches, quadrupole of two point masses, the (l/d)^3 law of a
+quadrupole expansion) or brute force on tiny inputs.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _lam(rin, rout):
+    return (rout - rin) / (rout + rin)
+
+
+# ------------------------------------------------------------- changeover
+
+def test_lambda_ratio10_golden():
+    g = {k: float(v) for k, v in _read_golden("changeover_ratio10.txt")}
+    assert _lam(g["r_in"], g["r_out"]) == pytest.approx(g["lambda_num"] / g["lambda_den"], rel=1e-15)
+
+
+def _deriv(fn, x, order, h):
+    """Central finite difference of the given order (one-sided where needed)."""
+    if order == 0:
+        return fn(x)
+    if order == 1:
+        return (fn(x + h) - fn(x - h)) / (2 * h)
+    if order == 2:
+        return (fn(x + h) - 2 * fn(x) + fn(x - h)) / h ** 2
+    if order == 3:
+        return (fn(x + 2 * h) - 2 * fn(x + h) + 2 * fn(x - h) - fn(x - 2 * h)) / (2 * h ** 3)
+    raise ValueError(order)
+
+
+@pytest.mark.parametrize("lam", [9 / 11, 0.5, 0.1])
+def test_changeover_boundary_values_eq_cof(orc, lam):
+    """eq. cof: W(1)=0, K(0)=1, K(1)=0 and K', K'', K''' vanish at 0 and 1.
+
+    Derivatives are taken by finite differences across the boundary, so a
+    kink or jump in any of the first three derivatives fails."""
+    fns = {"W": lambda x: orc.W(x, lam), "K": lambda x: orc.K(x, lam)}
+    for fname, order, x, value in _read_golden("changeover_boundary.txt"):
+        order, x, value = int(order), float(x), float(value)
+        h = 1e-3
+        got = _deriv(fns[fname], x, order, h)
+        # K has a 4th-order contact (coefficient <= 35(1+Lambda) < 71), so a
+        # difference quotient of order n is off by about 71 (2h)^4 / h^n;
+        # a missing or wrong term leaves an O(1..100) derivative instead.
+        tol = {0: 1e-15, 1: 1e-6, 2: 1e-3, 3: 0.6}[order]
+        assert abs(got - value) <= tol, (fname, order, x, got)
+
+
+@pytest.mark.parametrize("lam", [9 / 11, 0.3])
+def test_changeover_fourth_order_contact(orc, lam):
+    """K meets its constant branches with a 4th-order contact (eq. cof):
+    (1-K(h))/h^4 and K(1-h)/h^4 converge as h -> 0 (no lower-order term)."""
+    for f0 in (lambda h: (1 - orc.K(h, lam)) / h ** 4, lambda h: orc.K(1 - h, lam) / h ** 4):
+        vals = [f0(h) for h in (4e-3, 2e-3, 1e-3)]
+        d1, d2 = vals[0] - vals[1], vals[1] - vals[2]
+        assert np.isfinite(vals).all()
+        assert abs(d2) < 0.6 * abs(d1) + 1e-6  # linear convergence in h
+
+
+@pytest.mark.parametrize("rin,rout", [(1.0, 10.0), (0.002, 0.02), (0.3, 0.5)])
+def test_K_from_f_relation(orc, rin, rout):
+    """K(x) = f(x) - (x + r_in/(r_out - r_in)) f'(x) for 0 < x < 1 (paper's
+    relation between the force weight and f); f' by central differences."""
+    lam = _lam(rin, rout)
+    c = rin / (rout - rin)
+    for x in np.linspace(0.01, 0.99, 99):
+        h = 1e-5
+        fp = (orc.f(x + h, lam) - orc.f(x - h, lam)) / (2 * h)
+        expect = orc.f(x, lam) - (x + c) * fp
+        assert orc.K(x, lam) == pytest.approx(expect, abs=1e-9)
+
+
+@pytest.mark.parametrize("rin,rout", [(1.0, 10.0), (0.002, 0.02)])
+def test_W_from_f_relation(orc, rin, rout):
+    """W(x) = f(x) - f(1) r/r_out for 0 < x < 1 (offset that makes W(1)=0)."""
+    lam = _lam(rin, rout)
+    for x in np.linspace(0.0, 1.0, 101)[1:-1]:
+        r = rin + x * (rout - rin)
+        assert orc.W(x, lam) == pytest.approx(orc.f(x, lam) - orc.f(1.0, lam) * r / rout,
+                                               abs=1e-13)
+
+
+def test_W_K_continuity(orc):
+    lam = 9 / 11
+    for fn in (orc.W, orc.K):
+        for x0 in (0.0, 1.0):
+            assert fn(x0 - 1e-12, lam) == pytest.approx(fn(x0 + 1e-12, lam), abs=1e-10)
+
+
+# ------------------------------------------------------------ two-body pair
+
+def _two_body(orc, r, rin=0.01, rout=0.1, m=0.7, axis=0):
+    pos = np.zeros((3, 2))
+    pos[axis, 0] = r
+    mass = np.array([1.3, m])
+    ri = np.array([rin, rin * 0.5])   # pair radii take the max over i, j
+    ro = np.array([rout * 0.6, rout])
+    return orc.force_long(pos, mass, ri, ro, idx=[0])
+
+
+def test_two_body_branches(orc):
+    """Closed forms per branch of the changeover (x <= 0, x >= 1) and the
+    coincident pair (r = 0): no force, finite potential -2Gm/(r_in + r_out)."""
+    rin, rout, m = 0.01, 0.1, 0.7
+    for r in (0.0, 0.001, 0.005, 0.01):
+        a, p = _two_body(orc, r, rin, rout, m)
+        assert np.all(a == 0.0)
+        assert p[0] == pytest.approx(-2 * m / (rin + rout), rel=1e-14)
+    for r in (0.1, 0.2, 3.0):
+        a, p = _two_body(orc, r, rin, rout, m)
+        assert a[0, 0] == pytest.approx(-m / r ** 2, rel=1e-14)
+        assert p[0] == pytest.approx(-m / r, rel=1e-14)
+
+
+def test_pair_force_is_minus_gradient_of_potential(orc):
+    """The long-range pair force is -d(phi_L)/dr throughout the changeover:
+    this ties K (force weight) to W (potential weight)."""
+    for r in np.linspace(0.0125, 0.0975, 18):
+        h = 1e-5  # fourth-order central difference
+        ph = [_two_body(orc, r + k * h)[1][0] for k in (-2, -1, 1, 2)]
+        a, _ = _two_body(orc, r)
+        dphi = (ph[0] - 8 * ph[1] + 8 * ph[2] - ph[3]) / (12 * h)
+        assert a[0, 0] == pytest.approx(-dphi, rel=1e-6, abs=1e-9)
+
+
+def test_pair_radii_symmetric(orc):
+    """r_in,ij and r_out,ij take the max over i and j, so the pair force is
+    antisymmetric even with unequal radii."""
+    pos = np.array([[0.0, 0.03], [0.0, 0.01], [0.0, -0.02]])
+    mass = np.array([0.3, 0.9])
+    ri = np.array([0.005, 0.02])
+    ro = np.array([0.15, 0.05])
+    a, _ = orc.force_long(pos, mass, ri, ro)
+    np.testing.assert_allclose(mass[0] * a[:, 0], -mass[1] * a[:, 1], rtol=1e-14)
+
+
+# ----------------------------------------------------------- many-body sums
+
+def _clustered(n, seed):
+    c = workloads.make_cluster(n, seed, imf=True, binary_fraction=0.5, a_min=1e-3, a_max=3e-2)
+    return c
+
+
+def test_long_plus_short_is_newton(orc):
+    """H = H_L + H_S (eq. cf): a_L + a_S = a_Newton and phi_L + phi_S = phi_N,
+    from three independent loops."""
+    c = _clustered(300, 3)
+    rin, rout, rs = orc.radii(c.mass, 0.01, 0.1)
+    aL, pL = orc.force_long(c.pos, c.mass, rin, rout)
+    aS, pS = orc.force_short(c.pos, c.mass, rin, rout)
+    aN, pN = orc.force_newton(c.pos, c.mass)
+    scale = np.linalg.norm(aN, axis=0)
+    err = np.linalg.norm(aL + aS - aN, axis=0) / scale
+    assert err.max() < 1e-12
+    np.testing.assert_allclose(pL + pS, pN, rtol=1e-12)
+    # the split is non-trivial for this input
+    assert np.linalg.norm(aS, axis=0).max() > 1e-3 * scale.max()
+
+
+def test_momentum_conservation(orc):
+    """Pair forces are antisymmetric, so sum_i m_i a_L,i = 0."""
+    c = _clustered(400, 4)
+    rin, rout, _ = orc.radii(c.mass, 0.005, 0.05)
+    a, _ = orc.force_long(c.pos, c.mass, rin, rout)
+    tot = (c.mass[None, :] * a).sum(axis=1)
+    assert np.abs(tot).max() < 1e-13 * np.abs(c.mass[None, :] * a).sum()
+
+
+def test_potential_superposition(orc):
+    """1/2 sum_i m_i phi_i equals the sum over pairs i<j of the two-body
+    potential energy (self pairs excluded)."""
+    c = _clustered(24, 5)
+    rin, rout, _ = orc.radii(c.mass, 0.02, 0.2)
+    _, phi = orc.force_long(c.pos, c.mass, rin, rout)
+    e_pairs = 0.0
+    n = c.mass.size
+    for i in range(n):
+        for j in range(i + 1, n):
+            sel = [i, j]
+            _, p2 = orc.force_long(c.pos[:, sel], c.mass[sel], rin[sel], rout[sel], idx=[0])
+            e_pairs += c.mass[i] * p2[0]
+    assert 0.5 * np.dot(c.mass, phi) == pytest.approx(e_pairs, rel=1e-13)
+
+
+def test_coincident_particles(orc):
+    """r = 0 pairs: a_L = 0 from that pair and phi stays finite."""
+    pos = np.array([[0.1, 0.1, 0.5], [0.2, 0.2, 0.0], [0.3, 0.3, 0.0]])
+    mass = np.array([0.2, 0.3, 0.5])
+    rin, rout = np.full(3, 0.01), np.full(3, 0.1)
+    a, p = orc.force_long(pos, mass, rin, rout)
+    assert np.isfinite(a).all() and np.isfinite(p).all()
+    # particle 0 only feels particle 2 (Newtonian: distance 0.5 > r_out)
+    d = pos[:, 2] - pos[:, 0]
+    np.testing.assert_allclose(a[:, 0], mass[2] * d / np.linalg.norm(d) ** 3, rtol=1e-14)
+    assert p[0] == pytest.approx(-mass[1] * 2 / 0.11 - mass[2] / np.linalg.norm(d), rel=1e-14)
+
+
+# --------------------------------------------------------------------- radii
+
+def test_radii_eq_rcut(orc):
+    """eq. rcut: factor max(1, m/<m>)^(1/3); eq. rnb for the search radius."""
+    mass = np.array([1.0, 1.0, 8.0, 27.0, 0.5, 0.5, 0.5, 0.5])
+    mave = mass.mean()
+    rin, rout, rs = orc.radii(mass, 0.01, 0.1, search_factor=1.2)
+    s = np.array([max(1.0, m / mave) ** (1 / 3) for m in mass])
+    np.testing.assert_allclose(rin, 0.01 * s, rtol=1e-15)
+    np.testing.assert_allclose(rout, 0.1 * s, rtol=1e-15)
+    np.testing.assert_allclose(rs, 0.12 * s, rtol=1e-15)
+    # equal masses: factor exactly 1
+    rin, rout, rs = orc.radii(np.full(16, 1 / 16), 0.01, 0.1, 1.2)
+    assert np.all(rin == 0.01) and np.all(rout == 0.1)
+    # eq. rnb: r_nb = r_out + C_r |v| dt
+    vel = np.zeros((3, 8))
+    vel[0] = np.arange(8)
+    rin, rout, rs = orc.radii(mass, 0.01, 0.1, vel=vel, cr_dt=3.0 / 1024)
+    np.testing.assert_allclose(rs, rout + 3.0 / 1024 * np.arange(8), rtol=1e-15)
+
+
+# ---------------------------------------------------------------- neighbours
+
+def _brute_nb(pos, rs):
+    n = rs.size
+    out = []
+    for i in range(n):
+        lst = []
+        for j in range(n):
+            if j == i:
+                continue
+            d = [pos[k, j] - pos[k, i] for k in range(3)]
+            d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+            R = max(rs[i], rs[j])
+            if d2 < R * R:
+                lst.append(j)
+        out.append(lst)
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_neighbours_brute_force(orc, seed):
+    rng = np.random.default_rng(seed)
+    n = 48
+    pos = rng.uniform(-0.2, 0.2, (3, n))
+    rs = rng.uniform(0.02, 0.15, n)
+    # adversarial: pairs at exactly R on an axis, and a duplicate position
+    pos[:, 1] = pos[:, 0]
+    pos[:, 3] = pos[:, 2]
+    pos[0, 3] += max(rs[2], rs[3])
+    offs, idx = orc.neighbours(pos, rs)
+    ref = _brute_nb(pos, rs)
+    for i in range(n):
+        assert list(idx[offs[i]:offs[i + 1]]) == ref[i]
+    assert 1 in list(idx[offs[0]:offs[1]])          # duplicate is a neighbour
+    # permutation invariance of the neighbour relation
+    perm = rng.permutation(n)
+    offs2, idx2 = orc.neighbours(pos[:, perm], rs[perm])
+    inv = np.argsort(perm)
+    for i in range(n):
+        got = sorted(perm[idx2[offs2[inv[i]]:offs2[inv[i] + 1]]])
+        assert got == ref[i]
+
+
+def test_neighbours_symmetric(orc):
+    c = _clustered(500, 9)
+    _, _, rs = orc.radii(c.mass, 0.01, 0.1)
+    offs, idx = orc.neighbours(c.pos, rs)
+    pairs = set()
+    for i in range(500):
+        for j in idx[offs[i]:offs[i + 1]]:
+            pairs.add((i, int(j)))
+    assert all((j, i) in pairs for (i, j) in pairs)
+    assert len(pairs) > 0
+
+
+# ---------------------------------------------------------------- multipoles
+
+def test_quadrupole_two_point_masses(orc):
+    """Two masses m at +-d z: A' = diag(-m d^2, -m d^2, 2 m d^2) (eq. quadtr)."""
+    m, d = 0.25, 0.3
+    pos = np.array([[0.0, 0.0], [0.0, 0.0], [d, -d]])
+    M, com, q = orc.multipole(pos, np.array([m, m]))
+    assert M == 0.5 and np.allclose(com, 0)
+    np.testing.assert_allclose(q, [-m * d * d, -m * d * d, 2 * m * d * d, 0, 0, 0], atol=1e-16)
+
+
+def test_quadrupole_error_law(orc):
+    """With the centre of mass as expansion point and the quadrupole kept,
+    the field error of a compact cluster falls as (l/d)^3 relative; a missing
+    or wrong quadrupole leaves an (l/d)^2 error."""
+    rng = np.random.default_rng(11)
+    n = 64
+    pos = rng.uniform(-0.5, 0.5, (3, n)) * np.array([[1.0], [0.6], [0.3]])
+    mass = rng.uniform(0.5, 1.5, n)
+    M, com, q = orc.multipole(pos, mass)
+    dirs = workloads._isotropic(rng, 20).T
+    errs = []
+    for dist in (8.0, 16.0, 32.0):
+        pts = com[:, None] + dist * dirs
+        a_ex = np.empty((3, 20))
+        for k in range(20):
+            allp = np.concatenate([pts[:, k:k + 1], pos], axis=1)
+            allm = np.concatenate([[0.0], mass])
+            a, _ = orc.force_newton(allp, allm, idx=[0])
+            a_ex[:, k] = a[:, 0]
+        a_mp, _ = orc.multipole_eval(M, com, q, pts)
+        errs.append(np.median(np.linalg.norm(a_mp - a_ex, axis=0) / np.linalg.norm(a_ex, axis=0)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 6.0 < r1 < 10.5 and 6.0 < r2 < 10.5, errs
+
+
+# ---------------------------------------------------------------------- tree
+
+def test_tree_theta0_is_direct_sum(orc):
+    """theta = 0 opens every cell, so the tree reaches exactly the direct
+    sum's pair set."""
+    c = workloads.make_cluster(3000, 21, imf=True, binary_fraction=0.5)
+    rin, rout, rs = orc.radii(c.mass, 0.005, 0.05)
+    a0, p0 = orc.force_long(c.pos, c.mass, rin, rout)
+    for leaf, grp in ((8, 64), (1, 1), (16, 200)):
+        at, pt, cnt = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.0, leaf, grp)
+        err = np.linalg.norm(at - a0, axis=0) / np.linalg.norm(a0, axis=0)
+        assert err.max() < 1e-11
+        np.testing.assert_allclose(pt, p0, rtol=1e-12)
+        assert np.all(cnt[0] == 0)
+        assert np.all(cnt[1] + cnt[2] == 3000)
+
+
+def test_tree_error_decreases_with_theta(orc):
+    c = workloads.make_cluster(4096, 0, imf=False)
+    rin, rout, rs = np.full(4096, 0.01), np.full(4096, 0.1), np.full(4096, 0.12)
+    a0, _ = orc.force_long(c.pos, c.mass, rin, rout)
+    med = []
+    for th in (0.2, 0.4, 0.7):
+        at, _, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, th, 8, 64)
+        med.append(np.median(np.linalg.norm(at - a0, axis=0) / np.linalg.norm(a0, axis=0)))
+    assert med[0] < med[1] < med[2] < 3e-3
+
+
+def test_tree_structure_and_max_depth(orc):
+    """Each particle in exactly one leaf; more than leaf_size coincident
+    particles end in one leaf at the deepest level."""
+    c = workloads.make_cluster(1000, 5, imf=True)
+    info = orc.tree_info(c.pos, c.mass, 8, 64)
+    assert info["sum_leaf"] == 1000 and info["max_leaf"] <= 8
+    pos = c.pos.copy()
+    pos[:, :20] = pos[:, :1]
+    info = orc.tree_info(pos, c.mass, 8, 64)
+    assert info["sum_leaf"] == 1000 and info["max_level"] == 21 and info["max_leaf"] == 20
+
+
+def test_tree_near_list_holds_neighbours(orc):
+    """Walk conservativeness: every pair within r_search is a near pair, so
+    with theta = 0.7 the tree force still matches the direct sum on the
+    changeover part (checked through the short-range split)."""
+    c = workloads.make_cluster(2000, 8, imf=True, binary_fraction=1.0, a_min=1e-3, a_max=2e-2)
+    rin, rout, rs = orc.radii(c.mass, 0.005, 0.05)
+    at, pt, cnt = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.7, 8, 32)
+    offs, _ = orc.neighbours(c.pos, rs)
+    # near particles per target (including itself) cover its neighbours
+    assert np.all(cnt[2] >= np.diff(offs) + 1)
