@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the long-range P3T tree force on one MI355X.
+
+One step is the whole hot path on one batch of particles: changeover radii
+(eq. rcut), tree build (root box, Morton keys, radix sort, octree,
+multipoles), then the long-range force with neighbour lists (radii in tree
+order, cell search radii, i-groups, fused walk + interactions, neighbour
+CSR). Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line on stdout. Everything else goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+FLOPS_PER_INTERACTION = 23    # counting convention for the headline figure
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plummer1m_b100")
+    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--leaf", type=int, default=None)
+    ap.add_argument("--group", type=int, default=None)
+    ap.add_argument("--ipl", type=int, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sample", type=int, default=4096, help="targets in the error / CPU sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2006_16560_amd as pt
+    import workloads
+
+    wl = workloads.WORKLOADS[args.workload]
+    theta = wl.theta if args.theta is None else args.theta
+    leaf = wl.leaf_size if args.leaf is None else args.leaf
+    group = 64 if args.group is None else args.group
+    ipl = 1 if args.ipl is None else args.ipl
+    n = wl.n
+
+    t0 = time.time()
+    c = workloads.make_cluster(n, args.seed, imf=wl.imf, binary_fraction=wl.binary_fraction)
+    log("workload %s: N=%d generated in %.1fs" % (wl.name, n, time.time() - t0))
+
+    dev = "cuda:0"
+    pos = torch.from_numpy(c.pos).to(dev)
+    mass = torch.from_numpy(c.mass).to(dev)
+    r_in = torch.empty(n, dtype=torch.float64, device=dev)
+    r_out = torch.empty_like(r_in)
+    r_s = torch.empty_like(r_in)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx = pt.petar_create(0)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=ipl)
+    nb_cap = 64 * n
+
+    def radii():
+        if wl.uniform_radii:
+            r_in.fill_(wl.r_in_ref)
+            r_out.fill_(wl.r_out_ref)
+            r_s.fill_(wl.search_factor * wl.r_out_ref)
+        else:
+            pt.petar_changeover_radii(ctx, mass, wl.r_in_ref, wl.r_out_ref, wl.search_factor,
+                                      out=(r_in, r_out, r_s))
+
+    def step():
+        radii()
+        pt.petar_tree_build(ctx, pos, mass, theta, leaf)
+        return pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot,
+                                   nb_capacity=nb_cap)
+
+    for k in range(args.warmup):
+        step()
+        log("warmup step %d done" % k)
+    torch.cuda.synchronize()
+    inter = []
+    k_ms = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        st = pt.petar_get_stats(ctx)
+        inter.append(st["inter_pc"] + st["inter_far"] + st["inter_near"])
+        k_ms.append(st["ms_force_kernel"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st = pt.petar_get_stats(ctx)
+    ms_step = 1e3 * elapsed / args.steps
+    inter_step = float(np.mean(inter))
+    value = inter_step / (ms_step * 1e-3)
+    kernel_ms = float(np.mean(k_ms))
+    achieved = inter_step * FLOPS_PER_INTERACTION / (kernel_ms * 1e-3) / 1e12
+    log("timed %d steps: %.3f ms/step; force kernel %.3f ms; build %.3f ms; nb %.3f ms"
+        % (args.steps, ms_step, kernel_ms, st["ms_build"], st["ms_nb"]))
+    log("interactions/step: pc %d far %d near %d" % (st["inter_pc"], st["inter_far"],
+                                                    st["inter_near"]))
+
+    # ---- accuracy on a seeded sample (outside the timed region)
+    sample = workloads.sample_indices(n, args.sample, args.seed)
+    acc_mixed = acc.cpu().numpy()[:, sample].copy()
+    pot_mixed = pot.cpu().numpy()[sample].copy()
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64)
+    pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot)
+    torch.cuda.synchronize()
+    acc64 = acc.cpu().numpy()[:, sample]
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    e_arith = np.linalg.norm(acc_mixed - acc64, axis=0) / np.linalg.norm(acc64, axis=0)
+    err = {"sample": int(sample.size),
+           "p50_arith_vs_fp64gpu": float(np.median(e_arith)),
+           "p99_arith_vs_fp64gpu": float(np.percentile(e_arith, 99))}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rin_h, rout_h = r_in.cpu().numpy(), r_out.cpu().numpy()
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t1 = time.perf_counter()
+        a_ref, p_ref = oracle.force_long(c.pos, c.mass, rin_h, rout_h, idx=sample)
+        dt = time.perf_counter() - t1
+        pairs = float(sample.size) * (n - 1)
+        cpu = {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+               "sample": "FP64 direct sum (changeover-weighted long-range force + potential) "
+                         "for %d seeded targets x all %d sources, %.1f s" % (sample.size, n, dt)}
+        e_tot = np.linalg.norm(acc_mixed - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)
+        e64 = np.linalg.norm(acc64 - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)
+        err.update({"p50_vs_oracle": float(np.median(e_tot)),
+                    "p99_vs_oracle": float(np.percentile(e_tot, 99)),
+                    "p99_fp64gpu_vs_oracle": float(np.percentile(e64, 99)),
+                    "p99_pot_vs_oracle": float(np.percentile(np.abs(pot_mixed / p_ref - 1), 99))})
+        log("oracle sample: %.1f s on %d threads" % (dt, threads))
+
+    line = {
+        "metric": "tree-force interactions/s and % FP32 peak at N=1M; p99 force rel. err vs FP64",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": n, "imf": "kroupa 0.08-150", "binary_fraction":
+                   wl.binary_fraction, "theta": theta, "leaf_size": leaf, "group_size": group,
+                   "i_per_lane": ipl, "r_in_ref": wl.r_in_ref, "r_out_ref": wl.r_out_ref,
+                   "search_factor": wl.search_factor, "precision": "mixed fp32 pair / fp64 tree",
+                   "parallelism": "1 gpu"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_force<float,%d>" % ipl,
+                     "kernel_ms": kernel_ms,
+                     "flops_per_interaction": FLOPS_PER_INTERACTION,
+                     "interactions_per_launch": inter_step},
+        "cpu_baseline": cpu,
+        "particles_per_s": n / (ms_step * 1e-3),
+        "interactions": {"pc": st["inter_pc"], "far": st["inter_far"], "near": st["inter_near"]},
+        "stages_ms": {"build": st["ms_build"], "force_total": st["ms_force"],
+                      "force_kernel": kernel_ms, "neighbours": st["ms_nb"]},
+        "neighbour_entries": st["nb_total"],
+        "errors": err,
+        "workspace_bytes": st["workspace_bytes"],
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,169 @@
+/*
+ * petar.h -- C ABI of the MI355X (gfx950) long-range P3T tree-force library.
+ *
+ * The library computes the long-range half of the particle-particle
+ * particle-tree (P3T) Hamiltonian split used by PeTar (Wang, Iwasawa,
+ * Nitadori & Makino 2020, Sec. "Hybrid methods with Hamiltonian splitting"
+ * and eq. cf): for every particle i
+ *
+ *   a_L,i   = sum_j G m_j (1 - K(x_ij)) (r_j - r_i) / |r_j - r_i|^3
+ *   phi_L,i = -sum_j G m_j (1 - W(x_ij)) / |r_j - r_i|
+ *
+ * with the changeover weights W (potential) and K (force, eq. Wij) of the
+ * section "Mass-dependent changeover function", pair radii
+ * r_in,ij = max(r_in,i, r_in,j), r_out,ij = max(r_out,i, r_out,j),
+ * x = (r - r_in,ij)/(r_out,ij - r_in,ij). Distant particles are grouped in
+ * a Barnes-Hut octree whose cells, when they lie inside the opening angle
+ * theta as seen from a group of target particles, act through their centre
+ * of mass and traceless quadrupole (eq. quad, eq. quadtr; Sec. "Particle-
+ * tree with individual time steps"). Alongside the force it returns the
+ * neighbour candidates of the first stage of the neighbour search (Sec.
+ * "Orbit-dependent neighbour criterion"): all j != i with
+ * |r_j - r_i| < max(r_search,i, r_search,j).
+ *
+ * Conventions shared by every call
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors) on the context's device; everything else is host memory.
+ *  - Arrays of vectors are structure-of-arrays: pos[3][N] means x[0..N),
+ *    then y, then z, contiguous FP64.
+ *  - The caller owns every input and output buffer. The library owns the
+ *    tree and all scratch memory held by the context (freed by
+ *    petar_destroy).
+ *  - All work is enqueued on the context's HIP stream. A call returns after
+ *    it has read back the small status words it needs (the inputs may be
+ *    reused as soon as it returns; outputs are complete when the stream is).
+ *  - Every call validates its arguments before any launch and returns a
+ *    petar_status; petar_last_error() gives a message for the last failure.
+ *  - One context per host thread / stream; contexts are independent.
+ */
+#ifndef PETAR_H
+#define PETAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define PETAR_API __attribute__((visibility("default")))
+#else
+#define PETAR_API
+#endif
+
+typedef struct petar_ctx petar_ctx;
+
+typedef enum {
+    PETAR_OK = 0,
+    PETAR_E_INVALID = -1,     /* bad argument (pointer, size, value range, non-finite input) */
+    PETAR_E_NOMEM = -2,       /* device allocation failed or exceeds the workspace cap       */
+    PETAR_E_HIP = -3,         /* a HIP runtime call failed                                   */
+    PETAR_E_NB_OVERFLOW = -4, /* neighbour capacity too small; nb->required holds the need   */
+    PETAR_E_STATE = -5,       /* call order violated (e.g. force before tree build)          */
+    PETAR_E_NODEVICE = -6,    /* context created without a device (validation only)          */
+    PETAR_E_INTERNAL = -7     /* a kernel reported an internal limit (message says which)    */
+} petar_status;
+
+typedef enum {
+    PETAR_MIXED = 0, /* FP32 pair arithmetic on group-relative coordinates, compensated sums */
+    PETAR_FP64 = 1   /* the same walk and kernels with FP64 pair arithmetic                  */
+} petar_precision;
+
+/* Pass as `device` to petar_create for a context that validates arguments
+ * but owns no GPU (every call that would launch returns PETAR_E_NODEVICE). */
+#define PETAR_NO_DEVICE (-1)
+
+typedef struct {
+    double G;              /* gravitational constant (default 1, Henon units)            */
+    int precision;         /* petar_precision (default PETAR_MIXED)                      */
+    int i_per_lane;        /* target particles per lane in the force kernel: 1, 2 or 4   */
+    int record_counts;     /* 1: keep per-particle interaction counts (petar_copy_counts) */
+    int64_t workspace_cap; /* max bytes of library-owned device memory (0: no cap)        */
+} petar_params;
+
+/* Neighbour lists in CSR form, input order. offsets_dev[N+1] (int64) and
+ * idx_dev[capacity] (int32) are caller-owned device buffers. On return
+ * `required` is the total number of entries. Each list is sorted by
+ * ascending original index and excludes i itself. */
+typedef struct {
+    int64_t *offsets_dev;
+    int32_t *idx_dev;
+    int64_t capacity;
+    int64_t required;
+} petar_nblist;
+
+/* Counters of the last petar_force_long / petar_tree_build. */
+typedef struct {
+    int64_t n;                 /* particles                                     */
+    int64_t n_nodes;           /* octree cells                                  */
+    int64_t n_leaves;
+    int64_t n_groups;          /* i-groups of the last force call               */
+    int64_t max_level;
+    int64_t inter_pc;          /* particle-cell (multipole) interactions        */
+    int64_t inter_far;         /* particle-particle, Newtonian (far leaves)     */
+    int64_t inter_near;        /* particle-particle, changeover (near leaves)   */
+    int64_t nb_total;          /* neighbour-list entries                        */
+    double ms_build;           /* device time of the last tree build            */
+    double ms_force;           /* device time of the last force call (total)   */
+    double ms_force_kernel;    /* device time of the walk + interaction kernel  */
+    double ms_nb;              /* device time of the neighbour-list stage       */
+    int64_t workspace_bytes;   /* library-owned device memory                   */
+} petar_stats;
+
+/* Create a context on `device` (HIP ordinal, or PETAR_NO_DEVICE) whose work
+ * goes to `hip_stream` (a hipStream_t; NULL for the default stream). */
+PETAR_API petar_status petar_create(petar_ctx **out, int device, void *hip_stream);
+PETAR_API petar_status petar_destroy(petar_ctx *ctx);
+
+/* Defaults: G = 1, PETAR_MIXED, i_per_lane = 1, no counts, no cap. */
+PETAR_API petar_status petar_set_params(petar_ctx *ctx, const petar_params *params);
+PETAR_API petar_status petar_get_params(petar_ctx *ctx, petar_params *params);
+
+/* Per-particle changeover radii, eq. rcut: with s_i = max(1, m_i/<m>)^(1/3)
+ * and <m> = sum(m)/N, r_in,i = s_i r_in_ref and r_out,i = s_i r_out_ref.
+ * The search radius is search_factor * r_out,i when vel_dev is NULL, else
+ * eq. rnb: r_out,i + cr_dt |v_i| with cr_dt = C_r * dt_L.
+ * Requires 0 <= r_in_ref < r_out_ref, search_factor >= 1, cr_dt >= 0.
+ * mass_dev[N], vel_dev[3][N] (or NULL); outputs [N] each. */
+PETAR_API petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass_dev, const double *vel_dev,
+                                    int64_t N, double r_in_ref, double r_out_ref,
+                                    double search_factor, double cr_dt, double *r_in_dev,
+                                    double *r_out_dev, double *r_search_dev);
+
+/* Build the octree of N particles: pos_dev[3][N], mass_dev[N] (m >= 0,
+ * finite). theta >= 0 is the opening angle used by the following force
+ * calls; leaf_size >= 1 bounds the particles of a leaf cell (cells at the
+ * deepest level, 21, may hold more). 1 <= N < 2^31.
+ * The positions are copied into the context (sorted); the caller may change
+ * its buffers afterwards. */
+PETAR_API petar_status petar_tree_build(petar_ctx *ctx, const double *pos_dev, const double *mass_dev,
+                              int64_t N, double theta, int leaf_size);
+
+/* Long-range acceleration and potential on every particle of the last
+ * tree build (input order): acc_dev[3][N], pot_dev[N]. group_size >= 1 is
+ * the i-group size of the walk. r_in_dev, r_out_dev, r_search_dev [N] are
+ * the changeover and search radii; 0 <= r_in < r_out <= r_search and finite
+ * for every particle. nb may be NULL (no neighbour lists). On
+ * PETAR_E_NB_OVERFLOW acc and pot are complete and nb->required is set: the
+ * caller retries with a larger buffer. */
+PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in_dev,
+                              const double *r_out_dev, const double *r_search_dev,
+                              double *acc_dev, double *pot_dev, petar_nblist *nb);
+
+/* Per-particle interaction counts of the last force call (input order),
+ * counts_dev[4][N] int32: multipole cells, far-leaf particles, near-leaf
+ * particles (including the particle itself) and the size of its i-group.
+ * Requires params.record_counts = 1 before the force call. */
+PETAR_API petar_status petar_copy_counts(petar_ctx *ctx, int32_t *counts_dev);
+
+PETAR_API petar_status petar_get_stats(petar_ctx *ctx, petar_stats *stats);
+
+/* Message of the last failure on ctx (thread-local message if ctx is NULL). */
+PETAR_API const char *petar_last_error(petar_ctx *ctx);
+PETAR_API const char *petar_status_string(petar_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PETAR_H */

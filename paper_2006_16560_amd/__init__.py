@@ -1,0 +1,203 @@
+"""MI355X (gfx950) long-range P3T tree force of PeTar, as a C-ABI library.
+
+The functions below carry the names of the C entry points of
+``include/petar.h`` and only marshal arguments: every step of the tree
+build, walk and force runs in the HIP kernels of ``libpetar.so``. PyTorch
+provides device memory and the stream. Importing this package fails loudly
+when the HIP library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _capi
+from ._capi import (PETAR_E_INTERNAL, PETAR_E_INVALID, PETAR_E_NB_OVERFLOW, PETAR_E_NODEVICE,
+                    PETAR_E_NOMEM, PETAR_E_STATE, PETAR_FP64, PETAR_MIXED, PETAR_NO_DEVICE,
+                    PETAR_OK)
+
+_lib = _capi.load()
+
+__all__ = [
+    "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
+    "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_force_long",
+    "petar_copy_counts", "petar_get_stats", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
+    "PETAR_NO_DEVICE", "lib_path",
+]
+
+
+def lib_path() -> str:
+    return _capi.LIB_PATH
+
+
+class PetarError(RuntimeError):
+    def __init__(self, status: int, message: str, required: Optional[int] = None):
+        self.status = status
+        self.required = required
+        super().__init__("%s: %s" % (_capi.STATUS_NAMES.get(status, str(status)), message))
+
+
+class Context:
+    """Owns a petar_ctx handle (destroyed with the object)."""
+
+    def __init__(self, handle: ctypes.c_void_p, device: int, stream):
+        self.handle = handle
+        self.device = device
+        self.stream = stream
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.petar_destroy(self.handle)
+            self.handle = None
+
+
+def petar_last_error(ctx: Optional[Context] = None) -> str:
+    msg = _lib.petar_last_error(ctx.handle if ctx else None)
+    return msg.decode() if msg else ""
+
+
+def _check(status: int, ctx: Optional[Context], required: Optional[int] = None) -> None:
+    if status != PETAR_OK:
+        raise PetarError(status, petar_last_error(ctx), required)
+
+
+def _dptr(t: Optional[torch.Tensor], dtype: torch.dtype, shape, name: str, device: int):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError("%s must live on cuda:%d" % (name, device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def petar_create(device: int = 0, stream: Optional[torch.cuda.Stream] = None) -> Context:
+    """Context on `device` whose work goes to `stream` (torch's current by default).
+    device = PETAR_NO_DEVICE gives a validation-only context."""
+    h = ctypes.c_void_p()
+    sp = None
+    if device != PETAR_NO_DEVICE:
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        sp = ctypes.c_void_p(stream.cuda_stream)
+    _check(_lib.petar_create(ctypes.byref(h), device, sp), None)
+    return Context(h, device, stream)
+
+
+def petar_destroy(ctx: Context) -> None:
+    if ctx.handle is not None and ctx.handle.value:
+        _check(_lib.petar_destroy(ctx.handle), None)
+        ctx.handle = None
+
+
+def petar_set_params(ctx: Context, **kw) -> None:
+    p = _capi.petar_params()
+    _check(_lib.petar_get_params(ctx.handle, ctypes.byref(p)), ctx)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    _check(_lib.petar_set_params(ctx.handle, ctypes.byref(p)), ctx)
+
+
+def petar_get_params(ctx: Context) -> dict:
+    p = _capi.petar_params()
+    _check(_lib.petar_get_params(ctx.handle, ctypes.byref(p)), ctx)
+    return {name: getattr(p, name) for name, _ in p._fields_}
+
+
+def petar_changeover_radii(ctx: Context, mass: torch.Tensor, r_in_ref: float, r_out_ref: float,
+                           search_factor: float = 1.2, vel: Optional[torch.Tensor] = None,
+                           cr_dt: float = 0.0, out=None):
+    """(r_in, r_out, r_search) per particle (eq. rcut; eq. rnb if vel is given)."""
+    n = mass.shape[0]
+    dev = ctx.device
+    if out is None:
+        out = tuple(torch.empty(n, dtype=torch.float64, device="cuda:%d" % dev) for _ in range(3))
+    args = [_dptr(mass, torch.float64, (n,), "mass", dev),
+            _dptr(vel, torch.float64, (3, n), "vel", dev)]
+    outs = [_dptr(o, torch.float64, (n,), nm, dev) for o, nm in zip(out, ("r_in", "r_out", "r_search"))]
+    _check(_lib.petar_changeover_radii(ctx.handle, args[0], args[1], n, float(r_in_ref),
+                                       float(r_out_ref), float(search_factor), float(cr_dt), *outs),
+           ctx)
+    return out
+
+
+def petar_tree_build(ctx: Context, pos: torch.Tensor, mass: torch.Tensor, theta: float,
+                     leaf_size: int) -> None:
+    """Octree of the particles pos (3, N), mass (N,)."""
+    n = mass.shape[0] if mass.dim() == 1 else -1
+    _check(_lib.petar_tree_build(ctx.handle, _dptr(pos, torch.float64, (3, n), "pos", ctx.device),
+                                 _dptr(mass, torch.float64, (n,), "mass", ctx.device), n,
+                                 float(theta), int(leaf_size)), ctx)
+
+
+def petar_force_long(ctx: Context, group_size: int, r_in: torch.Tensor, r_out: torch.Tensor,
+                     r_search: torch.Tensor, acc: Optional[torch.Tensor] = None,
+                     pot: Optional[torch.Tensor] = None, nb_capacity: Optional[int] = None):
+    """Long-range acceleration (3, N) and potential (N,) in input order.
+
+    With nb_capacity (int), also returns the neighbour lists as
+    (offsets int64 [N+1], idx int32 [total]). If the capacity is too small a
+    PetarError with status PETAR_E_NB_OVERFLOW and `.required` is raised;
+    acc and pot are complete in that case.
+    """
+    n = r_in.shape[0]
+    dev = ctx.device
+    d = "cuda:%d" % dev
+    if acc is None:
+        acc = torch.empty((3, n), dtype=torch.float64, device=d)
+    if pot is None:
+        pot = torch.empty(n, dtype=torch.float64, device=d)
+    nb = None
+    offsets = idx = None
+    if nb_capacity is not None:
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=d)
+        idx = torch.empty(max(int(nb_capacity), 1), dtype=torch.int32, device=d)
+        nb = _capi.petar_nblist(offsets.data_ptr(), idx.data_ptr(), int(nb_capacity), 0)
+    st = _lib.petar_force_long(ctx.handle, int(group_size),
+                               _dptr(r_in, torch.float64, (n,), "r_in", dev),
+                               _dptr(r_out, torch.float64, (n,), "r_out", dev),
+                               _dptr(r_search, torch.float64, (n,), "r_search", dev),
+                               _dptr(acc, torch.float64, (3, n), "acc", dev),
+                               _dptr(pot, torch.float64, (n,), "pot", dev),
+                               ctypes.byref(nb) if nb is not None else None)
+    _check(st, ctx, nb.required if nb is not None else None)
+    if nb is None:
+        return acc, pot
+    return acc, pot, (offsets, idx[: nb.required])
+
+
+def petar_copy_counts(ctx: Context) -> torch.Tensor:
+    """Per-particle interaction counts (4, N) int32 of the last force call."""
+    n = petar_get_stats(ctx)["n"]
+    out = torch.empty((4, n), dtype=torch.int32, device="cuda:%d" % ctx.device)
+    _check(_lib.petar_copy_counts(ctx.handle, ctypes.c_void_p(out.data_ptr())), ctx)
+    return out
+
+
+def petar_get_stats(ctx: Context) -> dict:
+    s = _capi.petar_stats()
+    _check(_lib.petar_get_stats(ctx.handle, ctypes.byref(s)), ctx)
+    return s.as_dict()
+
+
+def force_long_with_retry(ctx: Context, group_size: int, r_in, r_out, r_search,
+                          nb_capacity: int = 0):
+    """petar_force_long with neighbour lists, retrying once with the required
+    capacity if the first guess was too small."""
+    try:
+        return petar_force_long(ctx, group_size, r_in, r_out, r_search, nb_capacity=nb_capacity)
+    except PetarError as e:
+        if e.status != PETAR_E_NB_OVERFLOW:
+            raise
+        return petar_force_long(ctx, group_size, r_in, r_out, r_search, nb_capacity=e.required)

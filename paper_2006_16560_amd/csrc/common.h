@@ -1,0 +1,159 @@
+// Internal definitions shared by the HIP translation units of libpetar.
+// Device data layout (all in HBM, library-owned unless noted):
+//   particles in Morton order:  ps[k]   = (x, y, z, m)      double4
+//                               rr[k]   = (r_in, r_out)     double2
+//                               rsk[k]  = r_search          double
+//                               orig[k] = input index       uint32
+//   octree cells in depth-first pre-order (children follow their parent,
+//   a cell's subtree is the index range [c, skip[c])):
+//                               nd_lo[c]  = (lo.x, lo.y, lo.z, max r_search)
+//                               nd_hi[c]  = (hi.x, hi.y, hi.z, side)
+//                               nd_com[c] = (com.x, com.y, com.z, M)
+//                               nd_S[c*6 + 0..5] = second moment about com
+//                                        (xx, yy, zz, xy, xz, yz)
+//                               nd_info[c] = (first particle, count, flags, skip)
+//                               nd_child[c*8 + octant] (kNone if empty)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace petar {
+
+constexpr int kMaxLevel = 21;           // 21 bits per axis, 63-bit keys
+constexpr uint32_t kNone = 0xffffffffu;
+constexpr int kWave = 64;
+constexpr uint32_t kLeafFlag = 1u;      // nd_info.z bit 0; level in bits 1..5
+
+// Root cube of the particle set (device-resident, written by the bbox pass).
+struct RootBox {
+    double lo[3];
+    double ext;      // side of the root cube
+    double scale;    // 2^21 / ext
+    int32_t bad;     // count of non-finite coordinates / masses or negative masses
+    int32_t pad;
+};
+
+// Status words read back once per call.
+struct Status {
+    int32_t invalid_radii;   // non-finite or out-of-order radii
+    int32_t stack_overflow;  // walk stack exceeded its capacity
+    int32_t nb_overflow;     // neighbour capacity too small
+    int32_t pad;
+    unsigned long long inter[3];  // pc, far, near interactions
+    int64_t n_groups;
+    int64_t nb_total;
+    int64_t n_nodes;
+    int64_t n_leaves;
+    int64_t max_level;
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+    return __popcll(mask & ((1ull << lane_id()) - 1ull));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T u = __shfl_up(v, d, kWave);
+        if (lane_id() >= d) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmin(v, __shfl_xor(v, d, kWave));
+    return v;
+}
+
+// Orders LDS (and global) accesses of one wave: the data written by some
+// lanes is visible to the others after this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---- Morton keys: digit of level l (1..21) is bits 3(21-l)..3(21-l)+2,
+// ordered (x, y, z) from most to least significant.
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ __forceinline__ uint64_t key_prefix(uint64_t key, int level) {
+    // level 0 -> 0 for every key (bit 63 is always clear)
+    return key >> (3 * (kMaxLevel - level));
+}
+
+// Number of leading octal digits two keys share (0..21).
+__device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
+    uint64_t x = a ^ b;
+    if (x == 0) return kMaxLevel;
+    return (__clzll((long long)x) - 1) / 3;
+}
+
+// ---- FP64 geometry of the walk, rounded exactly as written (no contraction).
+__device__ __forceinline__ double gap_box(double alo, double ahi, double blo, double bhi) {
+#pragma clang fp contract(off)
+    double t1 = blo - ahi;
+    double t2 = alo - bhi;
+    double t = t1 > t2 ? t1 : t2;
+    return t > 0.0 ? t : 0.0;
+}
+
+__device__ __forceinline__ double gap_point(double alo, double ahi, double p) {
+#pragma clang fp contract(off)
+    double t1 = p - ahi;
+    double t2 = alo - p;
+    double t = t1 > t2 ? t1 : t2;
+    return t > 0.0 ? t : 0.0;
+}
+
+__device__ __forceinline__ double sum_sq3(double gx, double gy, double gz) {
+#pragma clang fp contract(off)
+    double xx = gx * gx;
+    double yy = gy * gy;
+    double zz = gz * gz;
+    double s = xx + yy;
+    return s + zz;
+}
+
+// Neighbour relation of the first search stage: d^2 < max(rs_i, rs_j)^2.
+__device__ __forceinline__ bool nb_pair(double xi, double yi, double zi, double rsi, double xj,
+                                        double yj, double zj, double rsj) {
+#pragma clang fp contract(off)
+    double dx = xj - xi;
+    double dy = yj - yi;
+    double dz = zj - zi;
+    double d2 = sum_sq3(dx, dy, dz);
+    double R = rsi > rsj ? rsi : rsj;
+    double R2 = R * R;
+    return d2 < R2;
+}
+
+}  // namespace petar

@@ -1,0 +1,104 @@
+// Host-side launchers of the HIP kernels (one definition per .hip file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace petar {
+
+// ---------------------------------------------------------------- scan.hip
+// Exclusive prefix sum of n counts into out[0..n] (out[n] = total).
+// ws must hold scan_ws_elems(n) int64 values.
+int64_t scan_ws_elems(int64_t n);
+void scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *ws, hipStream_t s);
+void scan_u32_to_u32(const uint32_t *in, uint32_t *out, int64_t n, int64_t *ws, hipStream_t s);
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- tree.hip
+struct TreeDev {
+    // particles (Morton order)
+    double4 *ps;
+    double2 *rr;
+    double *rsk;
+    uint32_t *orig;
+    // cells
+    double4 *nd_lo, *nd_hi, *nd_com;
+    double *nd_S;
+    uint4 *nd_info;
+    uint32_t *nd_child;
+    uint32_t *nd_parent;
+    int64_t n;
+    int64_t n_nodes;
+};
+
+int bbox_partial_blocks(int64_t n);
+void launch_bbox(const double *pos, const double *mass, int64_t n, double *part, RootBox *rb,
+                 hipStream_t s);
+void launch_keys(const double *pos, int64_t n, const RootBox *rb, uint64_t *key, uint32_t *idx,
+                 hipStream_t s);
+
+// LSD radix sort of (key, value) pairs, stable. Buffers are swapped in place:
+// the sorted result ends in (*key, *val).
+int64_t sort_ws_bytes(int64_t n);
+void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **val_alt, int64_t n,
+                void *ws, int64_t *scan_ws, hipStream_t s);
+
+void launch_gather_particles(const double *pos, const double *mass, const uint32_t *idx,
+                             int64_t n, double4 *ps, uint32_t *orig, hipStream_t s);
+void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, uint32_t *emit,
+                         hipStream_t s);
+void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, const int64_t *base,
+                         const RootBox *rb, TreeDev t, uint32_t *level_count, hipStream_t s);
+void launch_level_buckets(const TreeDev &t, const uint32_t *level_count, uint32_t *level_off,
+                          uint32_t *level_fill, uint32_t *level_nodes, hipStream_t s);
+void launch_moments_level(const TreeDev &t, int level, const uint32_t *level_off,
+                          const uint32_t *level_nodes, hipStream_t s);
+void launch_tree_summary(const TreeDev &t, const uint32_t *level_count, Status *st, hipStream_t s);
+
+// force_long preparation
+void launch_gather_radii(const double *r_in, const double *r_out, const double *r_search,
+                         TreeDev t, Status *st, hipStream_t s);
+void launch_rsmax_level(const TreeDev &t, int level, const uint32_t *level_off,
+                        const uint32_t *level_nodes, hipStream_t s);
+void launch_group_flags(const TreeDev &t, int group_size, uint32_t *flag, hipStream_t s);
+void launch_group_compact(const TreeDev &t, const uint32_t *flag, const uint32_t *pos,
+                          uint32_t *groups, Status *st, hipStream_t s);
+
+// changeover radii (eq. rcut / eq. rnb)
+void launch_changeover_radii(const double *mass, const double *vel, int64_t n, double rin_ref,
+                             double rout_ref, double search_factor, double cr_dt, double *r_in,
+                             double *r_out, double *r_search, double *ws, hipStream_t s);
+
+// --------------------------------------------------------------- force.hip
+struct ForceLaunch {
+    TreeDev t;
+    const uint32_t *groups;
+    const Status *st_in;       // n_groups and validity flags
+    Status *st;                // counters out
+    double th2;                // theta^2
+    double G;
+    double *acc, *pot;         // caller's outputs, input order
+    uint32_t *spill;           // walk stack spill, per resident wave
+    uint32_t *queue;           // 8 work-queue heads
+    int32_t *counts;           // optional per-particle counts [4][n]
+    int precision;             // 0 mixed, 1 fp64
+    int ipl;                   // 1, 2, 4
+};
+int force_resident_waves(int precision, int ipl, int device);
+int64_t force_spill_elems_per_wave();
+void launch_force(const ForceLaunch &f, int resident_waves, hipStream_t s);
+
+// -------------------------------------------------------------- nblist.hip
+void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cnt_orig,
+                     uint32_t *spill, uint32_t *queue, int resident_waves, hipStream_t s);
+void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
+                     const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
+                     uint32_t *queue, int resident_waves, hipStream_t s);
+void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
+                    const Status *st, hipStream_t s);
+int nb_resident_waves(int device);
+
+}  // namespace petar

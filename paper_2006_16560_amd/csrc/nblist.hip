@@ -1,0 +1,255 @@
+// Neighbour candidates (first stage of the neighbour search: all j != i
+// with |r_j - r_i| < max(r_search,i, r_search,j)), as CSR lists in input
+// order, each sorted by original index.
+//
+// Per i-group a wavefront walks only the near region: a cell is opened iff
+// its box is closer to the group's box than max(rs_group, rs_cell); the
+// leaves reached are tested pair by pair with the FP64 relation of common.h.
+// The box test is conservative for the pair test (same rounding, monotone),
+// so every candidate is found. Two passes (count, write) around one prefix
+// sum, then a per-list sort.
+#include "launch.h"
+#include "walk.h"
+
+namespace petar {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWavesPerBlock = kThreads / kWave;
+
+struct NbLds {
+    uint32_t stack[kStackLds];
+    uint32_t leaf_start[kWave], leaf_cnt[kWave], leaf_pre[kWave];
+    double4 jp[kWave];
+    double jr[kWave];
+    uint32_t jk[kWave];
+};
+
+__device__ __forceinline__ int find_leaf(const uint32_t *pre, int nleaf, uint32_t s) {
+    int lo = 0, hi = nleaf;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= s)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// kWrite == false: count per target; true: write orig indices at wpos.
+template <bool kWrite>
+__device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &pi, double rsi,
+                         uint32_t ki, bool valid, uint32_t &count, int32_t *out, int64_t wpos) {
+    wave_sync();
+    const int lane = lane_id();
+    uint32_t c = lane < nleaf ? L.leaf_cnt[lane] : 0u;
+    uint32_t incl = wave_incl_scan(c);
+    uint32_t total = __shfl(incl, kWave - 1, kWave);
+    if (lane < nleaf) L.leaf_pre[lane] = incl - c;
+    wave_sync();
+    for (uint32_t base = 0; base < total; base += kWave) {
+        uint32_t s = base + lane;
+        if (s < total) {
+            int l = find_leaf(L.leaf_pre, nleaf, s);
+            uint32_t k = L.leaf_start[l] + (s - L.leaf_pre[l]);
+            L.jp[lane] = t.ps[k];
+            L.jr[lane] = t.rsk[k];
+            L.jk[lane] = k;
+        }
+        wave_sync();
+        int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
+        for (int j = 0; j < m; j++) {
+            double4 pj = L.jp[j];
+            uint32_t kj = L.jk[j];
+            bool hit = valid && kj != ki && nb_pair(pi.x, pi.y, pi.z, rsi, pj.x, pj.y, pj.z, L.jr[j]);
+            if (hit) {
+                if (kWrite) out[wpos + count] = (int32_t)t.orig[kj];
+                count++;
+            }
+        }
+        wave_sync();
+    }
+}
+
+template <bool kWrite>
+__global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *groups, Status *st,
+                                                 uint32_t *cnt_orig, const int64_t *offsets,
+                                                 int32_t *idx, int64_t capacity, uint32_t *spill,
+                                                 uint32_t *queue) {
+    __shared__ NbLds lds_all[kWavesPerBlock];
+    const int w = threadIdx.x / kWave;
+    NbLds &L = lds_all[w];
+    const int lane = lane_id();
+    if (st->invalid_radii || st->stack_overflow) return;
+    if (kWrite && offsets[t.n] > capacity) return;
+    const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t n_groups = st->n_groups;
+    WaveStack stk;
+    stk.lds = L.stack;
+    stk.spill = spill + gwave * kSpillCap;
+    while (true) {
+        uint32_t v = 0;
+        if (lane == 0) v = atomicAdd(queue, 1u);
+        int64_t g = (int64_t)(uint32_t)uniform((int)v);
+        if (g >= n_groups) break;
+        const uint32_t gnode = groups[g];
+        const uint4 ginfo = t.nd_info[gnode];
+        const GroupGeom G = load_group(t.nd_lo, t.nd_hi, gnode);
+        for (uint32_t chunk = 0; chunk < ginfo.y; chunk += kWave) {
+            uint32_t off = chunk + lane;
+            bool valid = off < ginfo.y;
+            uint32_t ki = ginfo.x + (valid ? off : 0u);
+            double4 pi = t.ps[ki];
+            double rsi = t.rsk[ki];
+            uint32_t count = 0;
+            int64_t wpos = 0;
+            if (kWrite && valid) wpos = offsets[t.orig[ki]];
+            int nleaf = 0;
+            stk.init(0u);
+            bool ok = true;
+            while (!stk.empty()) {
+                uint32_t node = stk.pop();
+                bool leaf_hit = false, open = false;
+                uint4 info = make_uint4(0, 0, 0, 0);
+                if (node != kNone) {
+                    double4 lo = t.nd_lo[node], hi = t.nd_hi[node];
+                    info = t.nd_info[node];
+                    double D2, R2;
+                    box_terms(G, lo, hi, &D2, &R2);
+                    if (D2 < R2) {
+                        if (info.z & kLeafFlag)
+                            leaf_hit = true;
+                        else
+                            open = true;
+                    }
+                }
+                uint32_t ch[8];
+                int nc = 0;
+                if (open)
+                    nc = load_children(t.nd_child, node, ch);
+                else
+                    no_children(ch);
+                if (!stk.push(ch, nc)) {
+                    ok = false;
+                    break;
+                }
+                unsigned long long m = __ballot(leaf_hit);
+                int cnt = __popcll(m);
+                if (cnt) {
+                    if (nleaf + cnt > kWave) {
+                        nb_flush<kWrite>(L, nleaf, t, pi, rsi, ki, valid, count, idx, wpos);
+                        nleaf = 0;
+                    }
+                    if (leaf_hit) {
+                        int p = nleaf + lanes_below(m);
+                        L.leaf_start[p] = info.x;
+                        L.leaf_cnt[p] = info.y;
+                    }
+                    nleaf += cnt;
+                }
+            }
+            if (!ok) {
+                if (lane == 0) atomicAdd(&st->stack_overflow, 1);
+                break;
+            }
+            if (nleaf) nb_flush<kWrite>(L, nleaf, t, pi, rsi, ki, valid, count, idx, wpos);
+            if (!kWrite && valid) cnt_orig[t.orig[ki]] = count;
+        }
+    }
+}
+
+// Sorts each list ascending: insertion sort for short lists, heap sort
+// otherwise (both in place).
+__global__ __launch_bounds__(kThreads) void k_nb_sort(const int64_t *offsets, int32_t *idx,
+                                                      int64_t n, int64_t capacity,
+                                                      const Status *st) {
+    if (st->invalid_radii || st->stack_overflow || offsets[n] > capacity) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b = offsets[i], e = offsets[i + 1];
+        int64_t len = e - b;
+        int32_t *a = idx + b;
+        if (len <= 32) {
+            for (int64_t p = 1; p < len; p++) {
+                int32_t v = a[p];
+                int64_t q = p - 1;
+                while (q >= 0 && a[q] > v) {
+                    a[q + 1] = a[q];
+                    q--;
+                }
+                a[q + 1] = v;
+            }
+        } else {
+            // heapify
+            for (int64_t s = len / 2 - 1; s >= 0; s--) {
+                int64_t r = s;
+                while (true) {
+                    int64_t c = 2 * r + 1;
+                    if (c >= len) break;
+                    if (c + 1 < len && a[c + 1] > a[c]) c++;
+                    if (a[r] >= a[c]) break;
+                    int32_t tmp = a[r];
+                    a[r] = a[c];
+                    a[c] = tmp;
+                    r = c;
+                }
+            }
+            for (int64_t end = len - 1; end > 0; end--) {
+                int32_t tmp = a[0];
+                a[0] = a[end];
+                a[end] = tmp;
+                int64_t r = 0;
+                while (true) {
+                    int64_t c = 2 * r + 1;
+                    if (c >= end) break;
+                    if (c + 1 < end && a[c + 1] > a[c]) c++;
+                    if (a[r] >= a[c]) break;
+                    int32_t t2 = a[r];
+                    a[r] = a[c];
+                    a[c] = t2;
+                    r = c;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int nb_resident_waves(int device) {
+    int a = 0, b = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_nb<false>, kThreads, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_nb<true>, kThreads, 0);
+    int per_cu = a < b ? a : b;
+    if (per_cu < 1) per_cu = 1;
+    hipDeviceProp_t p;
+    hipGetDeviceProperties(&p, device);
+    return per_cu * p.multiProcessorCount * kWavesPerBlock;
+}
+
+void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cnt_orig,
+                     uint32_t *spill, uint32_t *queue, int resident_waves, hipStream_t s) {
+    hipLaunchKernelGGL(k_nb<false>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
+                       groups, st, cnt_orig, (const int64_t *)nullptr, (int32_t *)nullptr,
+                       (int64_t)0, spill, queue);
+}
+
+void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
+                     const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
+                     uint32_t *queue, int resident_waves, hipStream_t s) {
+    hipLaunchKernelGGL(k_nb<true>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
+                       groups, st, (uint32_t *)nullptr, offsets, idx, capacity, spill, queue);
+}
+
+void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
+                    const Status *st, hipStream_t s) {
+    int64_t blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_nb_sort, dim3((unsigned)blocks), dim3(kThreads), 0, s, offsets, idx, n,
+                       capacity, st);
+}
+
+}  // namespace petar

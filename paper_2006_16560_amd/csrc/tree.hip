@@ -1,0 +1,709 @@
+// Octree construction: root cube, Morton keys, radix sort, cells from the
+// sorted keys, bottom-up multipoles; and the per-call preparation of the
+// force (radii in Morton order, per-cell max search radius, i-groups).
+//
+// Tree definition (Barnes-Hut octree of the P3T long-range part, Sec.
+// "Particle-tree with individual time steps" and the P3T figure caption):
+// root cube [lo, lo + ext) with ext the largest extent of the particles;
+// integer coordinates q = floor((x - lo) 2^21 / ext) (clamped to 2^21 - 1);
+// a cell of level l holds the particles sharing the top l bits of q on
+// every axis. A cell with <= leaf_size particles, or at level 21, is a
+// leaf; otherwise its non-empty octants are its children. Cells carry mass,
+// centre of mass, second moment about it (giving the traceless quadrupole of
+// eq. quadtr), particle bounding box and max search radius.
+#include "launch.h"
+
+namespace petar {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n, int threads = kThreads, int64_t cap = 65535) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+// ------------------------------------------------------------------ bbox
+constexpr int kBBoxBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_bbox_partial(const double *pos, const double *mass,
+                                                           int64_t n, double *part, RootBox *rb) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int d = 0; d < 3; d++) {
+            double x = pos[(int64_t)d * n + i];
+            if (!isfinite(x)) bad = 1;
+            lo[d] = fmin(lo[d], x);
+            hi[d] = fmax(hi[d], x);
+        }
+        double m = mass[i];
+        if (!isfinite(m) || m < 0.0) bad = 1;
+    }
+    __shared__ double sh[kThreads / kWave][6];
+    int w = threadIdx.x / kWave;
+    for (int d = 0; d < 3; d++) {
+        double a = wave_min(lo[d]), b = wave_max(hi[d]);
+        if (lane_id() == 0) {
+            sh[w][d] = a;
+            sh[w][3 + d] = b;
+        }
+    }
+    if (__ballot(bad)) {
+        if (lane_id() == 0) atomicAdd(&rb->bad, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = sh[0][threadIdx.x];
+        for (int k = 1; k < kThreads / kWave; k++)
+            v = threadIdx.x < 3 ? fmin(v, sh[k][threadIdx.x]) : fmax(v, sh[k][threadIdx.x]);
+        part[blockIdx.x * 6 + threadIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double *part, int nblk, RootBox *rb) {
+#pragma clang fp contract(off)
+    __shared__ double sh[kThreads / kWave][6];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int d = 0; d < 3; d++) {
+            lo[d] = fmin(lo[d], part[b * 6 + d]);
+            hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+        }
+    int w = threadIdx.x / kWave;
+    for (int d = 0; d < 3; d++) {
+        double a = wave_min(lo[d]), b = wave_max(hi[d]);
+        if (lane_id() == 0) {
+            sh[w][d] = a;
+            sh[w][3 + d] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double l[3], h[3];
+        for (int d = 0; d < 3; d++) {
+            l[d] = sh[0][d];
+            h[d] = sh[0][3 + d];
+            for (int k = 1; k < kThreads / kWave; k++) {
+                l[d] = fmin(l[d], sh[k][d]);
+                h[d] = fmax(h[d], sh[k][3 + d]);
+            }
+        }
+        double ext = 0.0;
+        for (int d = 0; d < 3; d++) {
+            double e = h[d] - l[d];
+            if (e > ext) ext = e;
+        }
+        if (!(ext > 0.0)) ext = 1.0;
+        for (int d = 0; d < 3; d++) rb->lo[d] = l[d];
+        rb->ext = ext;
+        rb->scale = 2097152.0 / ext;
+    }
+}
+
+// ------------------------------------------------------------------ keys
+__global__ __launch_bounds__(kThreads) void k_keys(const double *pos, int64_t n, const RootBox *rb,
+                                                   uint64_t *key, uint32_t *idx) {
+#pragma clang fp contract(off)
+    double scale = rb->scale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t q[3];
+        for (int d = 0; d < 3; d++) {
+            double t = (pos[(int64_t)d * n + i] - rb->lo[d]) * scale;
+            uint64_t v = (uint64_t)t;
+            q[d] = v > 2097151ull ? 2097151ull : v;
+        }
+        key[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+        idx[i] = (uint32_t)i;
+    }
+}
+
+// ------------------------------------------------------------- radix sort
+// LSD, 8-bit digits, 8 passes. Per pass: tile histograms, one exclusive scan
+// over (digit, tile), and a stable scatter that ranks equal digits inside a
+// tile with wave ballots and reorders the tile through LDS so that the
+// global writes are contiguous runs per digit.
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kThreads * kSortRounds;  // 2048 keys
+constexpr int kRadix = 256;
+
+__global__ __launch_bounds__(kThreads) void k_sort_hist(const uint64_t *key, int64_t n, int shift,
+                                                        uint32_t *hist, int64_t ntiles) {
+    __shared__ uint32_t cnt[kRadix];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortRounds; r++) {
+        int64_t k = base + r * kThreads + threadIdx.x;
+        if (k < n) atomicAdd(&cnt[(key[k] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_in,
+                                                           const uint32_t *val_in,
+                                                           uint64_t *key_out, uint32_t *val_out,
+                                                           int64_t n, int shift,
+                                                           const uint32_t *hist,
+                                                           const uint32_t *offs, int64_t ntiles) {
+    __shared__ uint64_t sk[kSortTile];
+    __shared__ uint32_t sv[kSortTile];
+    __shared__ uint32_t tile_start[kRadix];
+    __shared__ uint32_t digit_base[kRadix];
+    __shared__ uint32_t wave_cnt[kThreads / kWave][kRadix];
+    __shared__ uint32_t wsum[kThreads / kWave];
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kSortTile;
+    // exclusive scan of this tile's digit counts
+    uint32_t c = hist[(int64_t)t * ntiles + tile];
+    uint32_t incl = wave_incl_scan(c);
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    digit_base[t] = 0;
+    for (int k = 0; k < kThreads / kWave; k++) wave_cnt[k][t] = 0;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; k++) off += wsum[k];
+    tile_start[t] = off + incl - c;
+    __syncthreads();
+    for (int r = 0; r < kSortRounds; r++) {
+        int64_t k = base + r * kThreads + t;
+        bool valid = k < n;
+        uint64_t kk = valid ? key_in[k] : 0;
+        uint32_t vv = valid ? val_in[k] : 0;
+        int d = valid ? (int)((kk >> shift) & 255) : 0;
+        unsigned long long m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            unsigned long long bb = __ballot((d >> b) & 1);
+            m &= ((d >> b) & 1) ? bb : ~bb;
+        }
+        int wrank = lanes_below(m);
+        if (valid && wrank == 0) wave_cnt[w][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t rank = digit_base[d] + (uint32_t)wrank;
+            for (int q = 0; q < w; q++) rank += wave_cnt[q][d];
+            uint32_t p = tile_start[d] + rank;
+            sk[p] = kk;
+            sv[p] = vv;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int q = 0; q < kThreads / kWave; q++) {
+            add += wave_cnt[q][t];
+            wave_cnt[q][t] = 0;
+        }
+        digit_base[t] += add;
+        __syncthreads();
+    }
+    int64_t tile_n = n - base < kSortTile ? n - base : kSortTile;
+    for (int p = t; p < tile_n; p += kThreads) {
+        uint64_t kk = sk[p];
+        int d = (int)((kk >> shift) & 255);
+        uint32_t g = offs[(int64_t)d * ntiles + tile] + ((uint32_t)p - tile_start[d]);
+        key_out[g] = kk;
+        val_out[g] = sv[p];
+    }
+}
+
+// ------------------------------------------------------------ gathers
+__global__ __launch_bounds__(kThreads) void k_gather_particles(const double *pos,
+                                                               const double *mass,
+                                                               const uint32_t *idx, int64_t n,
+                                                               double4 *ps, uint32_t *orig) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t o = idx[k];
+        ps[k] = make_double4(pos[o], pos[n + o], pos[2 * n + o], mass[o]);
+        orig[k] = o;
+    }
+}
+
+// ------------------------------------------------------------ octree
+// First index after k whose level-`level` prefix differs from key[k]'s.
+__device__ int64_t run_end(const uint64_t *key, int64_t n, int64_t k, int level) {
+    uint64_t p = key_prefix(key[k], level);
+    int64_t lo = k, hi = k + 1, step = 1;
+    while (hi < n && key_prefix(key[hi], level) == p) {
+        lo = hi;
+        step <<= 1;
+        hi = k + step;
+    }
+    if (hi > n) hi = n;
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (key_prefix(key[mid], level) == p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
+// First index whose level-`level` prefix equals key[k]'s.
+__device__ int64_t run_start(const uint64_t *key, int64_t k, int level) {
+    uint64_t p = key_prefix(key[k], level);
+    int64_t lo = k, hi = k - 1, step = 1;
+    while (hi >= 0 && key_prefix(key[hi], level) == p) {
+        lo = hi;
+        step <<= 1;
+        hi = k - step;
+    }
+    if (hi < -1) hi = -1;
+    while (lo - hi > 1) {
+        int64_t mid = hi + (lo - hi) / 2;
+        if (key_prefix(key[mid], level) == p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int first_level(const uint64_t *key, int64_t k) {
+    return k == 0 ? 0 : common_digits(key[k - 1], key[k]) + 1;
+}
+
+// Cells are identified by (level, first particle). Particle k starts the
+// cells of levels first_level(k)..21 that contain it; such a cell exists iff
+// its parent holds more than leaf_size particles. Each particle emits the
+// chain of existing cells it starts, from the shallowest; ordering the
+// emitted cells by (first particle, level) is a depth-first pre-order.
+__global__ __launch_bounds__(kThreads) void k_octree_count(const uint64_t *key, int64_t n,
+                                                           int leaf_size, uint32_t *emit) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int l0 = first_level(key, k);
+        uint32_t cnt = 0;
+        if (l0 <= kMaxLevel) {
+            bool exists = true;
+            if (k > 0) {
+                int L = l0 - 1;
+                int64_t s = run_start(key, k, L), e = run_end(key, n, k, L);
+                exists = (e - s) > leaf_size;
+            }
+            if (exists) {
+                for (int l = l0;; l++) {
+                    cnt++;
+                    int64_t e = run_end(key, n, k, l);
+                    if (e - k <= leaf_size || l == kMaxLevel) break;
+                }
+            }
+        }
+        emit[k] = cnt;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_octree_write(const uint64_t *key, int64_t n,
+                                                           int leaf_size, const int64_t *base,
+                                                           const RootBox *rb, TreeDev t,
+                                                           uint32_t *level_count) {
+    const int64_t n_nodes = base[n];
+    const double ext = rb->ext;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b = base[k];
+        int64_t nemit = base[k + 1] - b;
+        if (nemit == 0) continue;
+        int l0 = first_level(key, k);
+        for (int u = 0; u < nemit; u++) {
+            int l = l0 + u;
+            uint32_t idx = (uint32_t)(b + u);
+            int64_t e = run_end(key, n, k, l);
+            uint32_t cnt = (uint32_t)(e - k);
+            bool leaf = (cnt <= (uint32_t)leaf_size) || l == kMaxLevel;
+            uint32_t skip = e < n ? (uint32_t)base[e] : (uint32_t)n_nodes;
+            t.nd_info[idx] = make_uint4((uint32_t)k, cnt, (leaf ? kLeafFlag : 0u) | ((uint32_t)l << 1),
+                                        skip);
+            t.nd_hi[idx].w = ldexp(ext, -l);
+            uint32_t parent;
+            if (u > 0) {
+                parent = idx - 1;
+            } else if (k == 0) {
+                parent = kNone;
+            } else {
+                int L = l - 1;
+                int64_t s = run_start(key, k, L);
+                parent = (uint32_t)(base[s] + (L - first_level(key, s)));
+            }
+            t.nd_parent[idx] = parent;
+            if (parent != kNone) {
+                int digit = (int)((key[k] >> (3 * (kMaxLevel - l))) & 7);
+                t.nd_child[(int64_t)parent * 8 + digit] = idx;
+            }
+            atomicAdd(&level_count[l], 1u);
+        }
+    }
+}
+
+__global__ void k_level_offsets(const uint32_t *level_count, uint32_t *level_off,
+                                uint32_t *level_fill) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t s = 0;
+        for (int l = 0; l <= kMaxLevel; l++) {
+            level_off[l] = s;
+            s += level_count[l];
+            level_fill[l] = 0;
+        }
+        level_off[kMaxLevel + 1] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_level_bucket(TreeDev t, const uint32_t *level_off,
+                                                           uint32_t *level_fill,
+                                                           uint32_t *level_nodes) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int l = (int)(t.nd_info[c].z >> 1);
+        uint32_t p = atomicAdd(&level_fill[l], 1u);
+        level_nodes[level_off[l] + p] = (uint32_t)c;
+    }
+}
+
+// Bottom-up cell data for one level. Leaves sum their particles (two passes:
+// centre of mass, then the second moment about it); other cells combine their
+// children with the parallel-axis shift.
+__global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level,
+                                                            const uint32_t *level_off,
+                                                            const uint32_t *level_nodes) {
+    const uint32_t beg = level_off[level], end = level_off[level + 1];
+    for (int64_t q = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < end;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c = level_nodes[q];
+        uint4 info = t.nd_info[c];
+        double M = 0, sx = 0, sy = 0, sz = 0;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double S[6] = {0, 0, 0, 0, 0, 0};
+        double cx, cy, cz;
+        if (info.z & kLeafFlag) {
+            for (uint32_t k = info.x; k < info.x + info.y; k++) {
+                double4 p = t.ps[k];
+                M += p.w;
+                sx += p.w * p.x;
+                sy += p.w * p.y;
+                sz += p.w * p.z;
+                lo[0] = fmin(lo[0], p.x);
+                lo[1] = fmin(lo[1], p.y);
+                lo[2] = fmin(lo[2], p.z);
+                hi[0] = fmax(hi[0], p.x);
+                hi[1] = fmax(hi[1], p.y);
+                hi[2] = fmax(hi[2], p.z);
+            }
+            if (M > 0.0) {
+                cx = sx / M;
+                cy = sy / M;
+                cz = sz / M;
+            } else {
+                cx = 0.5 * (lo[0] + hi[0]);
+                cy = 0.5 * (lo[1] + hi[1]);
+                cz = 0.5 * (lo[2] + hi[2]);
+            }
+            for (uint32_t k = info.x; k < info.x + info.y; k++) {
+                double4 p = t.ps[k];
+                double qx = p.x - cx, qy = p.y - cy, qz = p.z - cz;
+                S[0] += p.w * qx * qx;
+                S[1] += p.w * qy * qy;
+                S[2] += p.w * qz * qz;
+                S[3] += p.w * qx * qy;
+                S[4] += p.w * qx * qz;
+                S[5] += p.w * qy * qz;
+            }
+        } else {
+            uint32_t ch[8];
+            int nc = 0;
+            for (int o = 0; o < 8; o++) {
+                uint32_t v = t.nd_child[(int64_t)c * 8 + o];
+                if (v != kNone) ch[nc++] = v;
+            }
+            for (int o = 0; o < nc; o++) {
+                double4 cm = t.nd_com[ch[o]];
+                double4 l4 = t.nd_lo[ch[o]], h4 = t.nd_hi[ch[o]];
+                M += cm.w;
+                sx += cm.w * cm.x;
+                sy += cm.w * cm.y;
+                sz += cm.w * cm.z;
+                lo[0] = fmin(lo[0], l4.x);
+                lo[1] = fmin(lo[1], l4.y);
+                lo[2] = fmin(lo[2], l4.z);
+                hi[0] = fmax(hi[0], h4.x);
+                hi[1] = fmax(hi[1], h4.y);
+                hi[2] = fmax(hi[2], h4.z);
+            }
+            if (M > 0.0) {
+                cx = sx / M;
+                cy = sy / M;
+                cz = sz / M;
+            } else {
+                cx = 0.5 * (lo[0] + hi[0]);
+                cy = 0.5 * (lo[1] + hi[1]);
+                cz = 0.5 * (lo[2] + hi[2]);
+            }
+            for (int o = 0; o < nc; o++) {
+                double4 cm = t.nd_com[ch[o]];
+                const double *Sc = t.nd_S + (int64_t)ch[o] * 6;
+                double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
+                S[0] += Sc[0] + cm.w * dx * dx;
+                S[1] += Sc[1] + cm.w * dy * dy;
+                S[2] += Sc[2] + cm.w * dz * dz;
+                S[3] += Sc[3] + cm.w * dx * dy;
+                S[4] += Sc[4] + cm.w * dx * dz;
+                S[5] += Sc[5] + cm.w * dy * dz;
+            }
+        }
+        t.nd_com[c] = make_double4(cx, cy, cz, M);
+        double4 l4 = t.nd_lo[c];
+        l4.x = lo[0];
+        l4.y = lo[1];
+        l4.z = lo[2];
+        t.nd_lo[c] = l4;
+        double side = t.nd_hi[c].w;
+        t.nd_hi[c] = make_double4(hi[0], hi[1], hi[2], side);
+        for (int k = 0; k < 6; k++) t.nd_S[(int64_t)c * 6 + k] = S[k];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_tree_summary(TreeDev t, const uint32_t *level_count,
+                                                           Status *st) {
+    uint32_t leaves = 0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
+         c += (int64_t)gridDim.x * blockDim.x)
+        leaves += t.nd_info[c].z & kLeafFlag;
+    leaves = wave_sum(leaves);
+    if (lane_id() == 0 && leaves) atomicAdd((unsigned long long *)&st->n_leaves, (unsigned long long)leaves);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int ml = 0;
+        for (int l = 0; l <= kMaxLevel; l++)
+            if (level_count[l]) ml = l;
+        st->max_level = ml;
+        st->n_nodes = t.n_nodes;
+    }
+}
+
+// ------------------------------------------------------- force preparation
+__global__ __launch_bounds__(kThreads) void k_gather_radii(const double *r_in, const double *r_out,
+                                                           const double *r_search, TreeDev t,
+                                                           Status *st) {
+    int bad = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < t.n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t o = t.orig[k];
+        double a = r_in[o], b = r_out[o], c = r_search[o];
+        if (!(isfinite(a) && isfinite(b) && isfinite(c) && a >= 0.0 && a < b && b <= c)) bad = 1;
+        t.rr[k] = make_double2(a, b);
+        t.rsk[k] = c;
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicAdd(&st->invalid_radii, 1);
+}
+
+__global__ __launch_bounds__(kThreads) void k_rsmax_level(TreeDev t, int level,
+                                                          const uint32_t *level_off,
+                                                          const uint32_t *level_nodes) {
+    const uint32_t beg = level_off[level], end = level_off[level + 1];
+    for (int64_t q = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < end;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c = level_nodes[q];
+        uint4 info = t.nd_info[c];
+        double r = 0.0;
+        if (info.z & kLeafFlag) {
+            for (uint32_t k = info.x; k < info.x + info.y; k++) r = fmax(r, t.rsk[k]);
+        } else {
+            for (int o = 0; o < 8; o++) {
+                uint32_t v = t.nd_child[(int64_t)c * 8 + o];
+                if (v != kNone) r = fmax(r, t.nd_lo[v].w);
+            }
+        }
+        t.nd_lo[c].w = r;
+    }
+}
+
+// i-groups: the first cells on each root-to-leaf path holding <= group_size
+// particles, or leaves.
+__global__ __launch_bounds__(kThreads) void k_group_flags(TreeDev t, int group_size,
+                                                          uint32_t *flag) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        uint4 info = t.nd_info[c];
+        bool small = info.y <= (uint32_t)group_size || (info.z & kLeafFlag);
+        uint32_t p = t.nd_parent[c];
+        bool parent_big = p == kNone || t.nd_info[p].y > (uint32_t)group_size;
+        flag[c] = (small && parent_big) ? 1u : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_compact(TreeDev t, const uint32_t *flag,
+                                                            const uint32_t *pos, uint32_t *groups,
+                                                            Status *st) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
+         c += (int64_t)gridDim.x * blockDim.x)
+        if (flag[c]) groups[pos[c]] = (uint32_t)c;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_groups = pos[t.n_nodes];
+}
+
+// ------------------------------------------------------- changeover radii
+__global__ __launch_bounds__(kThreads) void k_mass_partial(const double *mass, int64_t n,
+                                                           double *part) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s += mass[i];
+    __shared__ double sh[kThreads / kWave];
+    s = wave_sum(s);
+    if (lane_id() == 0) sh[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int k = 0; k < kThreads / kWave; k++) v += sh[k];
+        part[blockIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_radii(const double *mass, const double *vel,
+                                                    int64_t n, const double *part, int nblk,
+                                                    double rin_ref, double rout_ref,
+                                                    double search_factor, double cr_dt,
+                                                    double *r_in, double *r_out, double *r_s) {
+    double msum = 0.0;
+    for (int b = 0; b < nblk; b++) msum += part[b];
+    double mave = msum / (double)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double ratio = mave > 0.0 ? mass[i] / mave : 1.0;
+        double s = cbrt(ratio > 1.0 ? ratio : 1.0);
+        double ro = s * rout_ref;
+        r_in[i] = s * rin_ref;
+        r_out[i] = ro;
+        if (vel) {
+            double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+            r_s[i] = ro + cr_dt * sqrt(vx * vx + vy * vy + vz * vz);
+        } else {
+            r_s[i] = search_factor * ro;
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+int bbox_partial_blocks(int64_t n) { return (int)grid_for(n, kThreads, kBBoxBlocks); }
+
+void launch_bbox(const double *pos, const double *mass, int64_t n, double *part, RootBox *rb,
+                 hipStream_t s) {
+    int nb = bbox_partial_blocks(n);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kThreads), 0, s, pos, mass, n, part, rb);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, s, (const double *)part, nb, rb);
+}
+
+void launch_keys(const double *pos, int64_t n, const RootBox *rb, uint64_t *key, uint32_t *idx,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, pos, n, rb,
+                       key, idx);
+}
+
+int64_t sort_ws_bytes(int64_t n) {
+    int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    if (ntiles < 1) ntiles = 1;
+    return (int64_t)sizeof(uint32_t) * (2 * kRadix * ntiles + 4);
+}
+
+void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **val_alt, int64_t n,
+                void *ws, int64_t *scan_ws, hipStream_t s) {
+    int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    if (ntiles < 1) ntiles = 1;
+    uint32_t *hist = (uint32_t *)ws;
+    uint32_t *offs = hist + kRadix * ntiles;
+    for (int pass = 0; pass < 8; pass++) {
+        int shift = 8 * pass;
+        hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
+                           (const uint64_t *)*key, n, shift, hist, ntiles);
+        scan_u32_to_u32(hist, offs, kRadix * ntiles, scan_ws, s);
+        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
+                           (const uint64_t *)*key, (const uint32_t *)*val, *key_alt, *val_alt, n,
+                           shift, (const uint32_t *)hist, (const uint32_t *)offs, ntiles);
+        uint64_t *tk = *key;
+        *key = *key_alt;
+        *key_alt = tk;
+        uint32_t *tv = *val;
+        *val = *val_alt;
+        *val_alt = tv;
+    }
+}
+
+void launch_gather_particles(const double *pos, const double *mass, const uint32_t *idx,
+                             int64_t n, double4 *ps, uint32_t *orig, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_particles, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s,
+                       pos, mass, idx, n, ps, orig);
+}
+
+void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, uint32_t *emit,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_octree_count, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
+                       emit);
+}
+
+void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, const int64_t *base,
+                         const RootBox *rb, TreeDev t, uint32_t *level_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_octree_write, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
+                       base, rb, t, level_count);
+}
+
+void launch_level_buckets(const TreeDev &t, const uint32_t *level_count, uint32_t *level_off,
+                          uint32_t *level_fill, uint32_t *level_nodes, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, level_count, level_off,
+                       level_fill);
+    hipLaunchKernelGGL(k_level_bucket, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, t,
+                       (const uint32_t *)level_off, level_fill, level_nodes);
+}
+
+void launch_moments_level(const TreeDev &t, int level, const uint32_t *level_off,
+                          const uint32_t *level_nodes, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments_level, dim3(grid_for(t.n_nodes, kThreads, 2048)), dim3(kThreads),
+                       0, s, t, level, level_off, level_nodes);
+}
+
+void launch_tree_summary(const TreeDev &t, const uint32_t *level_count, Status *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_summary, dim3(grid_for(t.n_nodes, kThreads, 1024)), dim3(kThreads), 0,
+                       s, t, level_count, st);
+}
+
+void launch_gather_radii(const double *r_in, const double *r_out, const double *r_search,
+                         TreeDev t, Status *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_radii, dim3(grid_for(t.n, kThreads, 8192)), dim3(kThreads), 0, s,
+                       r_in, r_out, r_search, t, st);
+}
+
+void launch_rsmax_level(const TreeDev &t, int level, const uint32_t *level_off,
+                        const uint32_t *level_nodes, hipStream_t s) {
+    hipLaunchKernelGGL(k_rsmax_level, dim3(grid_for(t.n_nodes, kThreads, 2048)), dim3(kThreads), 0,
+                       s, t, level, level_off, level_nodes);
+}
+
+void launch_group_flags(const TreeDev &t, int group_size, uint32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, t,
+                       group_size, flag);
+}
+
+void launch_group_compact(const TreeDev &t, const uint32_t *flag, const uint32_t *pos,
+                          uint32_t *groups, Status *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_compact, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, t, flag,
+                       pos, groups, st);
+}
+
+void launch_changeover_radii(const double *mass, const double *vel, int64_t n, double rin_ref,
+                             double rout_ref, double search_factor, double cr_dt, double *r_in,
+                             double *r_out, double *r_search, double *ws, hipStream_t s) {
+    int nb = (int)grid_for(n, kThreads, 1024);
+    hipLaunchKernelGGL(k_mass_partial, dim3(nb), dim3(kThreads), 0, s, mass, n, ws);
+    hipLaunchKernelGGL(k_radii, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, mass, vel,
+                       n, (const double *)ws, nb, rin_ref, rout_ref, search_factor, cr_dt, r_in,
+                       r_out, r_search);
+}
+
+}  // namespace petar

@@ -1,0 +1,63 @@
+// Host-side argument checks of the C ABI (no device access). Each returns
+// nullptr when the arguments are acceptable, else a message.
+#include "validate.h"
+
+#include <cmath>
+
+namespace petar {
+
+const char *check_params(const petar_params *p) {
+    if (!p) return "params is NULL";
+    if (!std::isfinite(p->G) || !(p->G > 0.0)) return "params.G must be finite and > 0";
+    if (p->precision != PETAR_MIXED && p->precision != PETAR_FP64)
+        return "params.precision must be PETAR_MIXED or PETAR_FP64";
+    if (p->i_per_lane != 1 && p->i_per_lane != 2 && p->i_per_lane != 4)
+        return "params.i_per_lane must be 1, 2 or 4";
+    if (p->record_counts != 0 && p->record_counts != 1) return "params.record_counts must be 0 or 1";
+    if (p->workspace_cap < 0) return "params.workspace_cap must be >= 0";
+    return nullptr;
+}
+
+const char *check_build_args(const double *pos, const double *mass, int64_t n, double theta,
+                             int leaf_size) {
+    if (!pos) return "pos is NULL";
+    if (!mass) return "mass is NULL";
+    if (n < 1) return "N must be >= 1";
+    if (n > kMaxParticles) return "N must be < 2^31";
+    if (!std::isfinite(theta) || theta < 0.0) return "theta must be finite and >= 0";
+    if (leaf_size < 1 || leaf_size > kMaxLeafSize) return "leaf_size must be in [1, 2^20]";
+    return nullptr;
+}
+
+const char *check_force_args(int group_size, const double *r_in, const double *r_out,
+                             const double *r_search, const double *acc, const double *pot,
+                             const petar_nblist *nb) {
+    if (group_size < 1 || group_size > kMaxGroupSize) return "group_size must be in [1, 2^20]";
+    if (!r_in || !r_out || !r_search) return "radius array is NULL";
+    if (!acc) return "acc is NULL";
+    if (!pot) return "pot is NULL";
+    if (nb) {
+        if (!nb->offsets_dev) return "nb->offsets_dev is NULL";
+        if (nb->capacity < 0) return "nb->capacity must be >= 0";
+        if (nb->capacity > 0 && !nb->idx_dev) return "nb->idx_dev is NULL";
+    }
+    return nullptr;
+}
+
+const char *check_radii_args(const double *mass, int64_t n, double r_in_ref, double r_out_ref,
+                             double search_factor, double cr_dt, const double *r_in,
+                             const double *r_out, const double *r_search) {
+    if (!mass) return "mass is NULL";
+    if (!r_in || !r_out || !r_search) return "output radius array is NULL";
+    if (n < 1) return "N must be >= 1";
+    if (n > kMaxParticles) return "N must be < 2^31";
+    if (!std::isfinite(r_in_ref) || !std::isfinite(r_out_ref) || r_in_ref < 0.0 ||
+        !(r_out_ref > r_in_ref))
+        return "need 0 <= r_in_ref < r_out_ref (finite)";
+    if (!std::isfinite(search_factor) || search_factor < 1.0)
+        return "search_factor must be finite and >= 1";
+    if (!std::isfinite(cr_dt) || cr_dt < 0.0) return "cr_dt must be finite and >= 0";
+    return nullptr;
+}
+
+}  // namespace petar

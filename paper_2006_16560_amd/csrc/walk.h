@@ -1,0 +1,142 @@
+// Wave-wide depth-first traversal of the octree for one i-group.
+//
+// One wavefront walks the tree for its group: each step pops up to 64 cells
+// (one per lane), classifies them in parallel and pushes the children of the
+// opened cells. The stack lives in LDS (kStackLds entries per wave) and
+// spills to a per-wave global area when a push would not fit; pops refill
+// from the spill when the LDS part is empty. Cells are classified with the
+// FP64 geometry of common.h, rounded as written, so the decisions are
+// reproducible bit for bit by any implementation of the same formulas.
+#pragma once
+
+#include "common.h"
+
+namespace petar {
+
+constexpr int kStackLds = 512;       // >= 64 lanes x 8 children
+constexpr int kSpillCap = 16384;     // per resident wave
+
+struct GroupGeom {
+    double lo[3], hi[3];
+    double rs;       // max r_search of the group's particles
+    double c[3];     // centre of the bounding box (origin of FP32 coordinates)
+};
+
+__device__ __forceinline__ GroupGeom load_group(const double4 *nd_lo, const double4 *nd_hi,
+                                                uint32_t g) {
+    GroupGeom G;
+    double4 lo = nd_lo[g], hi = nd_hi[g];
+    G.lo[0] = lo.x;
+    G.lo[1] = lo.y;
+    G.lo[2] = lo.z;
+    G.hi[0] = hi.x;
+    G.hi[1] = hi.y;
+    G.hi[2] = hi.z;
+    G.rs = lo.w;
+    for (int d = 0; d < 3; d++) G.c[d] = 0.5 * (G.lo[d] + G.hi[d]);
+    return G;
+}
+
+// Squared distance between the group's box and a cell's box, and the
+// squared pair-search radius max(rs_group, rs_cell)^2.
+__device__ __forceinline__ void box_terms(const GroupGeom &G, const double4 &lo,
+                                          const double4 &hi, double *D2, double *R2) {
+#pragma clang fp contract(off)
+    *D2 = sum_sq3(gap_box(G.lo[0], G.hi[0], lo.x, hi.x), gap_box(G.lo[1], G.hi[1], lo.y, hi.y),
+                  gap_box(G.lo[2], G.hi[2], lo.z, hi.z));
+    double R = G.rs > lo.w ? G.rs : lo.w;
+    *R2 = R * R;
+}
+
+// Multipole acceptance: side^2 < theta^2 * dmin^2 with dmin the distance
+// from the group's box to the cell's centre of mass.
+__device__ __forceinline__ bool mac_accept(const GroupGeom &G, const double4 &com, double side,
+                                           double th2) {
+#pragma clang fp contract(off)
+    double dm2 = sum_sq3(gap_point(G.lo[0], G.hi[0], com.x), gap_point(G.lo[1], G.hi[1], com.y),
+                         gap_point(G.lo[2], G.hi[2], com.z));
+    double side2 = side * side;
+    double rhs = th2 * dm2;
+    return side2 < rhs;
+}
+
+struct WaveStack {
+    uint32_t *lds;     // kStackLds entries
+    uint32_t *spill;   // kSpillCap entries
+    int sp_l;          // entries in LDS (wave-uniform)
+    int sp_g;          // entries in the spill (wave-uniform)
+
+    __device__ void init(uint32_t root) {
+        if (lane_id() == 0) lds[0] = root;
+        sp_l = 1;
+        sp_g = 0;
+        wave_sync();
+    }
+    __device__ bool empty() const { return sp_l == 0 && sp_g == 0; }
+
+    // Pops up to 64 cells; lane l gets one or kNone.
+    __device__ uint32_t pop() {
+        if (sp_l == 0) {
+            int m = sp_g < kStackLds / 2 ? sp_g : kStackLds / 2;
+            wave_sync();
+            for (int t = lane_id(); t < m; t += kWave) lds[t] = spill[sp_g - m + t];
+            sp_g -= m;
+            sp_l = m;
+            wave_sync();
+        }
+        int take = sp_l < kWave ? sp_l : kWave;
+        uint32_t v = lane_id() < take ? lds[sp_l - take + lane_id()] : kNone;
+        sp_l -= take;
+        wave_sync();
+        return v;
+    }
+
+    // Pushes the non-empty entries of each lane's child slots (kNone marks
+    // an empty octant). Returns false on spill overflow.
+    __device__ bool push(const uint32_t (&ch)[8], int nc) {
+        int incl = wave_incl_scan(nc);
+        int tot = __shfl(incl, kWave - 1, kWave);
+        if (tot == 0) return true;
+        if (sp_l + tot > kStackLds) {
+            if (sp_g + sp_l > kSpillCap) return false;
+            for (int t = lane_id(); t < sp_l; t += kWave) spill[sp_g + t] = lds[t];
+            sp_g += sp_l;
+            sp_l = 0;
+            wave_sync();
+        }
+        int p = sp_l + incl - nc;
+#pragma unroll
+        for (int o = 0; o < 8; o++) {
+            if (ch[o] != kNone) lds[p++] = ch[o];
+        }
+        sp_l += tot;
+        wave_sync();
+        return true;
+    }
+};
+
+// Reads the eight child slots of a cell (kNone for empty octants) and
+// returns the number of children.
+__device__ __forceinline__ int load_children(const uint32_t *nd_child, uint32_t c, uint32_t (&ch)[8]) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(nd_child + (int64_t)c * 8);
+    uint4 a = p[0], b = p[1];
+    ch[0] = a.x;
+    ch[1] = a.y;
+    ch[2] = a.z;
+    ch[3] = a.w;
+    ch[4] = b.x;
+    ch[5] = b.y;
+    ch[6] = b.z;
+    ch[7] = b.w;
+    int nc = 0;
+#pragma unroll
+    for (int o = 0; o < 8; o++) nc += ch[o] != kNone;
+    return nc;
+}
+
+__device__ __forceinline__ void no_children(uint32_t (&ch)[8]) {
+#pragma unroll
+    for (int o = 0; o < 8; o++) ch[o] = kNone;
+}
+
+}  // namespace petar

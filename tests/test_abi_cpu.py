@@ -1,0 +1,187 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/petar.h, and rejects bad arguments on the host
+before any launch (validation-only context, PETAR_NO_DEVICE)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "petar.h")
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2006_16560_amd import _capi
+    try:
+        return _capi, _capi.load()
+    except ImportError as e:
+        pytest.skip("libpetar.so not built: %s" % e)
+
+
+def header_entry_points():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"PETAR_API\s+[\w\s\*]+?\b(petar_\w+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(capi):
+    _capi, lib = capi
+    names = header_entry_points()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    declared = {s[0] for s in _capi.SIGNATURES}
+    assert set(names) == declared
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2006_16560_amd import _capi
+    saved = _capi._lib
+    _capi._lib = None
+    try:
+        with pytest.raises(ImportError):
+            _capi.load(str(tmp_path / "nope.so"))
+    finally:
+        _capi._lib = saved
+
+
+@pytest.fixture()
+def ctx(capi):
+    _capi, lib = capi
+    h = ctypes.c_void_p()
+    assert lib.petar_create(ctypes.byref(h), _capi.PETAR_NO_DEVICE, None) == _capi.PETAR_OK
+    yield h
+    assert lib.petar_destroy(h) == _capi.PETAR_OK
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation-only context
+
+
+def test_null_ctx(capi):
+    _capi, lib = capi
+    assert lib.petar_tree_build(None, FAKE, FAKE, 10, 0.5, 8) == _capi.PETAR_E_INVALID
+    assert b"ctx" in lib.petar_last_error(None)
+    assert lib.petar_create(None, 0, None) == _capi.PETAR_E_INVALID
+    assert lib.petar_destroy(None) == _capi.PETAR_E_INVALID
+
+
+@pytest.mark.parametrize("args,ok", [
+    ((FAKE, FAKE, 100, 0.5, 8), True),
+    ((None, FAKE, 100, 0.5, 8), False),
+    ((FAKE, None, 100, 0.5, 8), False),
+    ((FAKE, FAKE, 0, 0.5, 8), False),
+    ((FAKE, FAKE, -5, 0.5, 8), False),
+    ((FAKE, FAKE, 2 ** 31, 0.5, 8), False),
+    ((FAKE, FAKE, 100, -0.1, 8), False),
+    ((FAKE, FAKE, 100, float("nan"), 8), False),
+    ((FAKE, FAKE, 100, float("inf"), 8), False),
+    ((FAKE, FAKE, 100, 0.0, 8), True),
+    ((FAKE, FAKE, 100, 0.5, 0), False),
+    ((FAKE, FAKE, 100, 0.5, 1), True),
+])
+def test_tree_build_validation(capi, ctx, args, ok):
+    _capi, lib = capi
+    st = lib.petar_tree_build(ctx, *args)
+    assert st == (_capi.PETAR_E_NODEVICE if ok else _capi.PETAR_E_INVALID)
+    if not ok:
+        assert lib.petar_last_error(ctx)
+
+
+def _nb(capi, offsets=FAKE, idx=FAKE, cap=10):
+    _capi, _ = capi
+    return _capi.petar_nblist(offsets.value if offsets else None, idx.value if idx else None, cap, 0)
+
+
+@pytest.mark.parametrize("case", ["ok", "ok_nonb", "group0", "rin", "acc", "pot", "nb_off",
+                                  "nb_cap", "nb_idx", "nb_cap0"])
+def test_force_validation(capi, ctx, case):
+    _capi, lib = capi
+    args = dict(gs=64, rin=FAKE, rout=FAKE, rs=FAKE, acc=FAKE, pot=FAKE, nb=_nb(capi))
+    expect = _capi.PETAR_E_INVALID
+    if case == "ok":
+        expect = _capi.PETAR_E_NODEVICE
+    elif case == "ok_nonb":
+        args["nb"] = None
+        expect = _capi.PETAR_E_NODEVICE
+    elif case == "group0":
+        args["gs"] = 0
+    elif case == "rin":
+        args["rin"] = None
+    elif case == "acc":
+        args["acc"] = None
+    elif case == "pot":
+        args["pot"] = None
+    elif case == "nb_off":
+        args["nb"] = _nb(capi, offsets=None)
+    elif case == "nb_cap":
+        args["nb"] = _nb(capi, cap=-1)
+    elif case == "nb_idx":
+        args["nb"] = _nb(capi, idx=None, cap=5)
+    elif case == "nb_cap0":
+        args["nb"] = _nb(capi, idx=None, cap=0)
+        expect = _capi.PETAR_E_NODEVICE
+    nbp = ctypes.byref(args["nb"]) if args["nb"] is not None else None
+    st = lib.petar_force_long(ctx, args["gs"], args["rin"], args["rout"], args["rs"], args["acc"],
+                              args["pot"], nbp)
+    assert st == expect, (case, st, lib.petar_last_error(ctx))
+
+
+@pytest.mark.parametrize("kw,ok", [
+    ({}, True),
+    ({"G": 0.0}, False),
+    ({"G": float("nan")}, False),
+    ({"precision": 2}, False),
+    ({"precision": 1}, True),
+    ({"i_per_lane": 3}, False),
+    ({"i_per_lane": 4}, True),
+    ({"record_counts": 2}, False),
+    ({"workspace_cap": -1}, False),
+])
+def test_params_validation(capi, ctx, kw, ok):
+    _capi, lib = capi
+    p = _capi.petar_params()
+    assert lib.petar_get_params(ctx, ctypes.byref(p)) == 0
+    assert (p.G, p.precision, p.i_per_lane, p.record_counts, p.workspace_cap) == (1.0, 0, 1, 0, 0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    st = lib.petar_set_params(ctx, ctypes.byref(p))
+    assert st == (_capi.PETAR_OK if ok else _capi.PETAR_E_INVALID)
+
+
+@pytest.mark.parametrize("args,ok", [
+    ((FAKE, None, 10, 0.01, 0.1, 1.2, 0.0, FAKE, FAKE, FAKE), True),
+    ((FAKE, FAKE, 10, 0.01, 0.1, 1.0, 0.01, FAKE, FAKE, FAKE), True),
+    ((None, None, 10, 0.01, 0.1, 1.2, 0.0, FAKE, FAKE, FAKE), False),
+    ((FAKE, None, 10, 0.1, 0.1, 1.2, 0.0, FAKE, FAKE, FAKE), False),
+    ((FAKE, None, 10, -0.1, 0.1, 1.2, 0.0, FAKE, FAKE, FAKE), False),
+    ((FAKE, None, 10, 0.01, 0.1, 0.9, 0.0, FAKE, FAKE, FAKE), False),
+    ((FAKE, None, 10, 0.01, 0.1, 1.2, -1.0, FAKE, FAKE, FAKE), False),
+    ((FAKE, None, 0, 0.01, 0.1, 1.2, 0.0, FAKE, FAKE, FAKE), False),
+    ((FAKE, None, 10, 0.01, 0.1, 1.2, 0.0, None, FAKE, FAKE), False),
+])
+def test_radii_validation(capi, ctx, args, ok):
+    _capi, lib = capi
+    st = lib.petar_changeover_radii(ctx, *args)
+    assert st == (_capi.PETAR_E_NODEVICE if ok else _capi.PETAR_E_INVALID)
+
+
+def test_status_strings(capi):
+    _capi, lib = capi
+    for code in _capi.STATUS_NAMES:
+        assert lib.petar_status_string(code)
+
+
+def test_product_never_touches_oracle():
+    """The HIP path and the oracle share no code: no file of the package or
+    of the C sources names the oracle."""
+    pkg = os.path.join(ROOT, "paper_2006_16560_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "oracle." not in txt, f
+                assert "workloads" not in txt, f
+    inc = open(HEADER).read()
+    assert "oracle" not in inc

@@ -1,0 +1,280 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Bars (see the module docstrings of oracle/ and the design notes):
+  * FP64 GPU mode vs the oracle tree force (same tree definition, same MAC):
+    relative force / potential error <= 1e-12 per particle, interaction
+    counts equal;
+  * theta = 0 (every cell opened) vs the oracle direct sum: <= 1e-12;
+  * mixed precision vs the oracle: p99 relative force error <= 1e-5 on top
+    of the tree truncation (identical interaction lists);
+  * neighbour lists: bit-exact CSR against brute force.
+"""
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2006_16560_amd as pt
+    return pt
+
+
+@pytest.fixture(scope="module")
+def ctx(pt):
+    c = pt.petar_create(0)
+    yield c
+    pt.petar_destroy(c)
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def rel_err(a, ref):
+    return np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+
+def run(pt, ctx, pos, mass, rin, rout, rs, theta, leaf, group, prec, nb_cap=None, ipl=1,
+        counts=False):
+    pt.petar_set_params(ctx, precision=prec, i_per_lane=ipl, record_counts=int(counts))
+    pt.petar_tree_build(ctx, T(pos), T(mass), theta, leaf)
+    out = pt.petar_force_long(ctx, group, T(rin), T(rout), T(rs), nb_capacity=nb_cap)
+    torch.cuda.synchronize()
+    res = [out[0].cpu().numpy(), out[1].cpu().numpy()]
+    if nb_cap is not None:
+        res.append((out[2][0].cpu().numpy(), out[2][1].cpu().numpy()))
+    if counts:
+        res.append(pt.petar_copy_counts(ctx).cpu().numpy())
+    return res
+
+
+def cluster_with_radii(orc, n, seed, imf=True, bf=0.0, rin_ref=0.002, rout_ref=0.02, **kw):
+    c = workloads.make_cluster(n, seed, imf=imf, binary_fraction=bf, **kw)
+    rin, rout, rs = orc.radii(c.mass, rin_ref, rout_ref, 1.2)
+    return c, rin, rout, rs
+
+
+# ---------------------------------------------------------------- FP64 mode
+
+@pytest.mark.parametrize("n,bf,leaf,group", [(4096, 0.0, 8, 64), (3000, 0.5, 8, 32),
+                                             (2500, 1.0, 1, 1), (5000, 0.2, 16, 300)])
+def test_theta0_fp64_equals_direct_sum(pt, ctx, orc, n, bf, leaf, group):
+    c, rin, rout, rs = cluster_with_radii(orc, n, 11, bf=bf, rin_ref=0.005, rout_ref=0.05)
+    acc, pot = run(pt, ctx, c.pos, c.mass, rin, rout, rs, 0.0, leaf, group, pt.PETAR_FP64)
+    a0, p0 = orc.force_long(c.pos, c.mass, rin, rout)
+    assert rel_err(acc, a0).max() < 1e-12
+    np.testing.assert_allclose(pot, p0, rtol=1e-12)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
+@pytest.mark.parametrize("group", [16, 64, 256])
+def test_fp64_matches_oracle_tree(pt, ctx, orc, theta, group):
+    c, rin, rout, rs = cluster_with_radii(orc, 6000, 3, bf=0.5)
+    acc, pot, cnt = run(pt, ctx, c.pos, c.mass, rin, rout, rs, theta, 8, group, pt.PETAR_FP64,
+                        counts=True)
+    a_ref, p_ref, cnt_ref = orc.tree_force(c.pos, c.mass, rin, rout, rs, theta, 8, group)
+    same = np.all(cnt == cnt_ref, axis=0)
+    # identical interaction lists (a rare opening decision may differ when the
+    # centre of mass rounds differently at the exact threshold)
+    assert same.mean() > 0.999
+    assert rel_err(acc, a_ref)[same].max() < 1e-12
+    np.testing.assert_allclose(pot[same], p_ref[same], rtol=1e-12)
+
+
+def test_fp64_plummer4k_config(pt, ctx, orc):
+    wl = workloads.WORKLOADS["plummer4k"]
+    c = workloads.make_cluster(wl.n, 0, imf=False)
+    n = wl.n
+    rin, rout, rs = (np.full(n, wl.r_in_ref), np.full(n, wl.r_out_ref),
+                     np.full(n, wl.search_factor * wl.r_out_ref))
+    acc, pot, (offs, idx) = run(pt, ctx, c.pos, c.mass, rin, rout, rs, wl.theta, wl.leaf_size, 64,
+                                pt.PETAR_FP64, nb_cap=64 * n)
+    a_ref, p_ref, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, wl.theta, wl.leaf_size, 64)
+    assert rel_err(acc, a_ref).max() < 1e-12
+    o_ref, i_ref = orc.neighbours(c.pos, rs)
+    assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
+
+
+# --------------------------------------------------------------- mixed mode
+
+@pytest.mark.parametrize("ipl", [1, 2, 4])
+def test_mixed_vs_oracle_tree(pt, ctx, orc, ipl):
+    c, rin, rout, rs = cluster_with_radii(orc, 20000, 5, bf=0.5)
+    acc, pot = run(pt, ctx, c.pos, c.mass, rin, rout, rs, 0.5, 8, 64, pt.PETAR_MIXED, ipl=ipl)
+    a_ref, p_ref, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.5, 8, 64)
+    e = rel_err(acc, a_ref)
+    assert np.percentile(e, 99) < 1e-5, np.percentile(e, [50, 99, 100])
+    assert np.percentile(np.abs(pot / p_ref - 1), 99) < 1e-6
+
+
+def test_ipl_bitwise_identical(pt, ctx, orc):
+    """Each target's sum order is the same for 1, 2 or 4 targets per lane."""
+    c, rin, rout, rs = cluster_with_radii(orc, 8000, 6, bf=0.3)
+    outs = [run(pt, ctx, c.pos, c.mass, rin, rout, rs, 0.5, 8, 128, pt.PETAR_MIXED, ipl=k)
+            for k in (1, 2, 4)]
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_plummer64k_b50_config(pt, ctx, orc):
+    """Kroupa IMF, 50% binaries, N = 65536: mixed vs the FP64 GPU mode on
+    identical lists (arithmetic error) and vs the oracle tree; neighbour
+    lists bit-exact against brute force."""
+    wl = workloads.WORKLOADS["plummer64k_b50"]
+    c = workloads.make_cluster(wl.n, 0, imf=True, binary_fraction=wl.binary_fraction)
+    rin, rout, rs = orc.radii(c.mass, wl.r_in_ref, wl.r_out_ref, wl.search_factor)
+    a64, p64 = run(pt, ctx, c.pos, c.mass, rin, rout, rs, wl.theta, wl.leaf_size, 64,
+                   pt.PETAR_FP64)
+    am, pm, (offs, idx) = run(pt, ctx, c.pos, c.mass, rin, rout, rs, wl.theta, wl.leaf_size, 64,
+                              pt.PETAR_MIXED, nb_cap=40 * wl.n)
+    e_arith = rel_err(am, a64)
+    assert np.percentile(e_arith, 99) < 1e-5, np.percentile(e_arith, [50, 99])
+    sample = workloads.sample_indices(wl.n, 2048, 0)
+    a_ref, p_ref, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, wl.theta, wl.leaf_size, 64,
+                                     idx=sample)
+    assert rel_err(a64[:, sample], a_ref).max() < 1e-11
+    o_ref, i_ref = orc.neighbours(c.pos, rs)
+    assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_single_particle(pt, ctx, orc):
+    pos = np.array([[0.3], [0.1], [-0.2]])
+    acc, pot, (offs, idx) = run(pt, ctx, pos, np.array([1.0]), np.array([0.01]), np.array([0.1]),
+                                np.array([0.12]), 0.5, 8, 64, pt.PETAR_MIXED, nb_cap=4)
+    assert np.all(acc == 0) and np.all(pot == 0)
+    assert list(offs) == [0, 0] and idx.size == 0
+
+
+def test_coincident_particles_max_depth(pt, ctx, orc):
+    """More than leaf_size identical positions: a leaf at the deepest level."""
+    c, rin, rout, rs = cluster_with_radii(orc, 3000, 8)
+    pos = c.pos.copy()
+    pos[:, 100:140] = pos[:, 100:101]
+    for prec, tol in ((pt.PETAR_FP64, 1e-12), (pt.PETAR_MIXED, 1e-4)):
+        acc, pot, (offs, idx) = run(pt, ctx, pos, c.mass, rin, rout, rs, 0.0, 8, 16, prec,
+                                    nb_cap=200000)
+        a0, p0 = orc.force_long(pos, c.mass, rin, rout)
+        assert np.percentile(rel_err(acc, a0), 99) < tol
+        assert np.isfinite(acc).all() and np.isfinite(pot).all()
+    o_ref, i_ref = orc.neighbours(pos, rs)
+    assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
+    st = pt.petar_get_stats(ctx)
+    assert st["max_level"] == 21
+
+
+@pytest.mark.parametrize("n", [2, 7, 63, 64, 65, 4097])
+def test_ragged_sizes(pt, ctx, orc, n):
+    c, rin, rout, rs = cluster_with_radii(orc, n, n, rin_ref=0.02, rout_ref=0.2)
+    acc, pot, (offs, idx) = run(pt, ctx, c.pos, c.mass, rin, rout, rs, 0.0, 4, 32, pt.PETAR_FP64,
+                                nb_cap=n * n)
+    a0, p0 = orc.force_long(c.pos, c.mass, rin, rout)
+    assert rel_err(acc, a0).max() < 1e-12
+    o_ref, i_ref = orc.neighbours(c.pos, rs)
+    assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
+
+
+def test_zero_mass_particles(pt, ctx, orc):
+    """Zero-mass test particles feel the field and exert none."""
+    c, rin, rout, rs = cluster_with_radii(orc, 4000, 9)
+    mass = c.mass.copy()
+    mass[::3] = 0.0
+    acc, pot = run(pt, ctx, c.pos, mass, rin, rout, rs, 0.5, 8, 64, pt.PETAR_FP64)
+    a_ref, p_ref, _ = orc.tree_force(c.pos, mass, rin, rout, rs, 0.5, 8, 64)
+    assert np.percentile(rel_err(acc, a_ref), 99.9) < 1e-12
+
+
+def test_large_theta_and_group(pt, ctx, orc):
+    c, rin, rout, rs = cluster_with_radii(orc, 5000, 10, bf=0.2)
+    for theta, group in ((2.0, 5000), (1.0, 10000), (0.5, 1)):
+        acc, pot = run(pt, ctx, c.pos, c.mass, rin, rout, rs, theta, 8, group, pt.PETAR_FP64)
+        a_ref, p_ref, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, theta, 8, group)
+        assert np.percentile(rel_err(acc, a_ref), 99.9) < 1e-12, (theta, group)
+
+
+def test_determinism(pt, ctx, orc):
+    c, rin, rout, rs = cluster_with_radii(orc, 30000, 12, bf=0.5)
+    r1 = run(pt, ctx, c.pos, c.mass, rin, rout, rs, 0.5, 8, 64, pt.PETAR_MIXED, nb_cap=10 ** 6)
+    r2 = run(pt, ctx, c.pos, c.mass, rin, rout, rs, 0.5, 8, 64, pt.PETAR_MIXED, nb_cap=10 ** 6)
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+    assert np.array_equal(r1[2][0], r2[2][0]) and np.array_equal(r1[2][1], r2[2][1])
+
+
+# ------------------------------------------------------------- error paths
+
+def test_nb_overflow_and_retry(pt, ctx, orc):
+    c, rin, rout, rs = cluster_with_radii(orc, 5000, 13, bf=0.5)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 8)
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=3)
+    assert ei.value.status == pt.PETAR_E_NB_OVERFLOW
+    o_ref, i_ref = orc.neighbours(c.pos, rs)
+    assert ei.value.required == o_ref[-1]
+    acc, pot, (offs, idx) = pt.force_long_with_retry(ctx, 64, T(rin), T(rout), T(rs), 3)
+    assert np.array_equal(offs.cpu().numpy(), o_ref) and np.array_equal(idx.cpu().numpy(), i_ref)
+
+
+def test_invalid_radii_rejected(pt, ctx, orc):
+    c, rin, rout, rs = cluster_with_radii(orc, 1000, 14)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 8)
+    for bad in ("order", "nan", "search"):
+        ri, ro, rr = rin.copy(), rout.copy(), rs.copy()
+        if bad == "order":
+            ri[5] = ro[5]
+        elif bad == "nan":
+            ro[7] = np.nan
+        else:
+            rr[9] = 0.5 * ro[9]
+        with pytest.raises(pt.PetarError) as ei:
+            pt.petar_force_long(ctx, 64, T(ri), T(ro), T(rr))
+        assert ei.value.status == pt.PETAR_E_INVALID
+
+
+def test_invalid_positions_rejected(pt, ctx, orc):
+    c, rin, rout, rs = cluster_with_radii(orc, 1000, 15)
+    pos = c.pos.copy()
+    pos[1, 17] = np.inf
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_tree_build(ctx, T(pos), T(c.mass), 0.5, 8)
+    assert ei.value.status == pt.PETAR_E_INVALID
+    mass = c.mass.copy()
+    mass[3] = -1.0
+    with pytest.raises(pt.PetarError):
+        pt.petar_tree_build(ctx, T(c.pos), T(mass), 0.5, 8)
+    # the failed build leaves no tree behind
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs))
+    assert ei.value.status == pt.PETAR_E_STATE
+
+
+def test_workspace_cap(pt, orc):
+    c, rin, rout, rs = cluster_with_radii(orc, 2000, 16)
+    ctx = pt.petar_create(0)
+    pt.petar_set_params(ctx, workspace_cap=100000)
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 8)
+    assert ei.value.status == pt.PETAR_E_NOMEM
+    pt.petar_destroy(ctx)
+
+
+# ------------------------------------------------------------------- radii
+
+def test_changeover_radii_kernel(pt, ctx, orc):
+    c = workloads.make_cluster(50000, 17, imf=True, binary_fraction=0.5)
+    for vel, crdt in ((None, 0.0), (c.vel, 3.0 / 1024)):
+        ri, ro, rs = pt.petar_changeover_radii(ctx, T(c.mass), 0.002, 0.02, 1.2,
+                                               vel=None if vel is None else T(vel), cr_dt=crdt)
+        e_ri, e_ro, e_rs = orc.radii(c.mass, 0.002, 0.02, 1.2, vel=vel, cr_dt=crdt)
+        for got, ref in ((ri, e_ri), (ro, e_ro), (rs, e_rs)):
+            np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=4e-16 * 8, atol=0)
