@@ -38,7 +38,7 @@ struct petar_ctx {
     DevBuf key0, key1, val0, val1, sort_ws, scan_ws, bbox_part, rootbox, status, emit, base;
     DevBuf ps, orig, rr, rsk;
     DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_info, nd_child, nd_parent;
-    DevBuf level_count, level_off, level_fill, level_nodes;
+    DevBuf level_count, level_off, level_ws, level_nodes;
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws;
 
@@ -163,7 +163,7 @@ void free_all(petar_ctx *c) {
                       &c->scan_ws,  &c->bbox_part,   &c->rootbox,    &c->status,     &c->emit,
                       &c->base,     &c->ps,          &c->orig,       &c->rr,         &c->rsk,
                       &c->nd_lo,    &c->nd_hi,       &c->nd_com,     &c->nd_S,       &c->nd_info,
-                      &c->nd_child, &c->nd_parent,   &c->level_count, &c->level_off, &c->level_fill,
+                      &c->nd_child, &c->nd_parent,   &c->level_count, &c->level_off, &c->level_ws,
                       &c->level_nodes, &c->gflag,    &c->gpos,       &c->groups,     &c->spill,
                       &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws};
     for (DevBuf *b : bufs) {
@@ -267,7 +267,7 @@ petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass, const do
         return fail(ctx, PETAR_E_INVALID, "%s", m);
     if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    TRY(ensure(ctx, ctx->radii_ws, 1024 * sizeof(double)));
+    TRY(ensure(ctx, ctx->radii_ws, 1025 * sizeof(double)));
     launch_changeover_radii(mass, vel, n, r_in_ref, r_out_ref, search_factor, cr_dt, r_in, r_out,
                             r_search, ptr<double>(ctx->radii_ws), ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
@@ -304,7 +304,6 @@ petar_status petar_tree_build(petar_ctx *ctx, const double *pos, const double *m
     TRY(ensure(ctx, ctx->orig, N * 4));
     TRY(ensure(ctx, ctx->level_count, 32 * 4));
     TRY(ensure(ctx, ctx->level_off, 32 * 4));
-    TRY(ensure(ctx, ctx->level_fill, 32 * 4));
 
     HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
     zero_status(ctx);
@@ -340,16 +339,15 @@ petar_status petar_tree_build(petar_ctx *ctx, const double *pos, const double *m
     TRY(ensure(ctx, ctx->nd_child, M * 8 * 4));
     TRY(ensure(ctx, ctx->nd_parent, M * 4));
     TRY(ensure(ctx, ctx->level_nodes, M * 4));
+    TRY(ensure(ctx, ctx->level_ws, (size_t)level_ws_elems(n_nodes) * 4));
     ctx->n = n;
     ctx->n_nodes = n_nodes;
     ctx->sorted_key = k;
     TreeDev t = tree_view(ctx);
     fill_u32(t.nd_child, kNone, n_nodes * 8, s);
-    fill_u32(ptr<uint32_t>(ctx->level_count), 0, 32, s);
-    launch_octree_write(k, n, leaf_size, ptr<int64_t>(ctx->base), rb, t,
-                        ptr<uint32_t>(ctx->level_count), s);
+    launch_octree_write(k, n, leaf_size, ptr<int64_t>(ctx->base), rb, t, s);
     launch_level_buckets(t, ptr<uint32_t>(ctx->level_count), ptr<uint32_t>(ctx->level_off),
-                         ptr<uint32_t>(ctx->level_fill), ptr<uint32_t>(ctx->level_nodes), s);
+                         ptr<uint32_t>(ctx->level_ws), ptr<uint32_t>(ctx->level_nodes), s);
     for (int L = kMaxLevel; L >= 0; L--)
         launch_moments_level(t, L, ptr<uint32_t>(ctx->level_off), ptr<uint32_t>(ctx->level_nodes),
                              s);
@@ -439,7 +437,8 @@ petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in
                         s);
         launch_nb_write(t, f.groups, st, nb->offsets_dev, nb->idx_dev, nb->capacity, f.spill,
                         queue + 9, ctx->nb_waves, s);
-        launch_nb_sort(nb->offsets_dev, nb->idx_dev, n, nb->capacity, st, s);
+        launch_nb_sort(nb->offsets_dev, nb->idx_dev, n, nb->capacity, st,
+                       ptr<uint32_t>(ctx->nbcnt), queue + 10, s);
         HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, nb->offsets_dev + n, 8,
                                     hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipEventRecord(ctx->ev[7], s));

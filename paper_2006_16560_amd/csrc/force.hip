@@ -87,6 +87,26 @@ struct Acc<double> {
     __device__ double get(int k) const { return s[k]; }
 };
 
+// Folds the partial sums of the lanes lane ^ d (d = W, 2W, .., 32) that
+// handled other j subsets of the same target.
+__device__ __forceinline__ void combine_split(Acc<float> &a, int W) {
+    for (int d = W; d < kWave; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            float s2 = __shfl_xor(a.s[k], d, kWave);
+            float c2 = __shfl_xor(a.c[k], d, kWave);
+            a.add(k, s2);
+            a.c[k] += c2;
+        }
+    }
+}
+__device__ __forceinline__ void combine_split(Acc<double> &a, int W) {
+    for (int d = W; d < kWave; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) a.s[k] += __shfl_xor(a.s[k], d, kWave);
+    }
+}
+
 template <typename R, int IPL>
 struct Targets {
     R x[IPL], y[IPL], z[IPL], rin[IPL], rout[IPL];
@@ -110,7 +130,7 @@ __device__ __forceinline__ void fold(Targets<R, IPL> &T, const R (&ax)[IPL], con
 // ---- multipole tile
 template <typename R, int IPL>
 __device__ void flush_pc(WaveLds<R> &L, int npc, const ForceLaunch &f, const GroupGeom &G,
-                         Targets<R, IPL> &T) {
+                         Targets<R, IPL> &T, int S, int sl) {
     wave_sync();
     const int lane = lane_id();
     if (lane < npc) {
@@ -136,7 +156,7 @@ __device__ void flush_pc(WaveLds<R> &L, int npc, const ForceLaunch &f, const Gro
     R ax[IPL], ay[IPL], az[IPL], ph[IPL];
 #pragma unroll
     for (int u = 0; u < IPL; u++) ax[u] = ay[u] = az[u] = ph[u] = (R)0;
-    for (int j = 0; j < npc; j++) {
+    for (int j = sl; j < npc; j += S) {
         const PcRec<R> c = L.tile.pc[j];
 #pragma unroll
         for (int u = 0; u < IPL; u++) {
@@ -179,7 +199,7 @@ __device__ __forceinline__ int find_leaf(const uint32_t *pre, int nleaf, uint32_
 // ---- far leaves: Newtonian pairs
 template <typename R, int IPL>
 __device__ uint32_t flush_far(WaveLds<R> &L, int nleaf, const ForceLaunch &f, const GroupGeom &G,
-                              Targets<R, IPL> &T) {
+                              Targets<R, IPL> &T, int S, int sl) {
     wave_sync();
     const int lane = lane_id();
     uint32_t c = lane < nleaf ? L.far_cnt[lane] : 0u;
@@ -205,7 +225,7 @@ __device__ uint32_t flush_far(WaveLds<R> &L, int nleaf, const ForceLaunch &f, co
         R ax[IPL], ay[IPL], az[IPL], ph[IPL];
 #pragma unroll
         for (int u = 0; u < IPL; u++) ax[u] = ay[u] = az[u] = ph[u] = (R)0;
-        for (int j = 0; j < m; j++) {
+        for (int j = sl; j < m; j += S) {
             const JRec<R> p = L.tile.j[j];
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
@@ -229,7 +249,7 @@ __device__ uint32_t flush_far(WaveLds<R> &L, int nleaf, const ForceLaunch &f, co
 // ---- near leaves: changeover-weighted pairs
 template <typename R, int IPL>
 __device__ uint32_t flush_near(WaveLds<R> &L, int nleaf, const ForceLaunch &f, const GroupGeom &G,
-                               Targets<R, IPL> &T) {
+                               Targets<R, IPL> &T, int S, int sl) {
     wave_sync();
     const int lane = lane_id();
     uint32_t c = lane < nleaf ? L.near_cnt[lane] : 0u;
@@ -260,7 +280,7 @@ __device__ uint32_t flush_near(WaveLds<R> &L, int nleaf, const ForceLaunch &f, c
         R ax[IPL], ay[IPL], az[IPL], ph[IPL];
 #pragma unroll
         for (int u = 0; u < IPL; u++) ax[u] = ay[u] = az[u] = ph[u] = (R)0;
-        for (int j = 0; j < m; j++) {
+        for (int j = sl; j < m; j += S) {
             const NRec<R> p = L.tile.nr[j];
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
@@ -335,10 +355,17 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
         const GroupGeom G = load_group(f.t.nd_lo, f.t.nd_hi, gnode);
         const uint32_t gstart = ginfo.x, gn = ginfo.y;
         for (uint32_t chunk = 0; chunk < gn; chunk += CH) {
+            const uint32_t active = gn - chunk < (uint32_t)CH ? gn - chunk : (uint32_t)CH;
+            // Small groups with one target per lane: S lanes share a target and
+            // split the j loop (lane = sl * W + il).
+            int S = 1;
+            if (IPL == 1) S = active <= 8 ? 8 : (active <= 16 ? 4 : (active <= 32 ? 2 : 1));
+            const int W = kWave / S;
+            const int il = lane & (W - 1), sl = lane / W;
             Targets<R, IPL> T;
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
-                uint32_t off = chunk + u * kWave + lane;
+                uint32_t off = chunk + u * kWave + il;
                 T.valid[u] = off < gn;
                 uint32_t k = gstart + (T.valid[u] ? off : 0u);
                 double4 p = f.t.ps[k];
@@ -351,7 +378,6 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 T.k[u] = T.valid[u] ? k : kNone;
                 T.acc[u].zero();
             }
-            const uint32_t active = gn - chunk < (uint32_t)CH ? gn - chunk : (uint32_t)CH;
             uint64_t n_pc = 0, n_far = 0, n_near = 0;
             int npc = 0, nfar = 0, nnear = 0;
             stk.init(0u);
@@ -389,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 cnt = __popcll(m);
                 if (cnt) {
                     if (npc + cnt > kWave) {
-                        flush_pc(L, npc, f, G, T);
+                        flush_pc(L, npc, f, G, T, S, sl);
                         n_pc += npc;
                         npc = 0;
                     }
@@ -400,7 +426,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 cnt = __popcll(m);
                 if (cnt) {
                     if (nfar + cnt > kWave) {
-                        n_far += flush_far(L, nfar, f, G, T);
+                        n_far += flush_far(L, nfar, f, G, T, S, sl);
                         nfar = 0;
                     }
                     if (kind == kKindFar) {
@@ -414,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 cnt = __popcll(m);
                 if (cnt) {
                     if (nnear + cnt > kWave) {
-                        n_near += flush_near(L, nnear, f, G, T);
+                        n_near += flush_near(L, nnear, f, G, T, S, sl);
                         nnear = 0;
                     }
                     if (kind == kKindNear) {
@@ -430,17 +456,18 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 break;
             }
             if (npc) {
-                flush_pc(L, npc, f, G, T);
+                flush_pc(L, npc, f, G, T, S, sl);
                 n_pc += npc;
             }
-            if (nfar) n_far += flush_far(L, nfar, f, G, T);
-            if (nnear) n_near += flush_near(L, nnear, f, G, T);
+            if (nfar) n_far += flush_far(L, nfar, f, G, T, S, sl);
+            if (nnear) n_near += flush_near(L, nnear, f, G, T, S, sl);
             cnt_pc += n_pc * active;
             cnt_far += n_far * active;
             cnt_near += n_near * active - active;  // minus the self pairs
+            if (S > 1) combine_split(T.acc[0], W);
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
-                if (!T.valid[u]) continue;
+                if (!T.valid[u] || sl != 0) continue;
                 uint32_t o = f.t.orig[T.k[u]];
                 f.acc[o] = f.G * T.acc[u].get(0);
                 f.acc[n + o] = f.G * T.acc[u].get(1);

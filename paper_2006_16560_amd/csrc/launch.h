@@ -51,9 +51,12 @@ void launch_gather_particles(const double *pos, const double *mass, const uint32
 void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, uint32_t *emit,
                          hipStream_t s);
 void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, const int64_t *base,
-                         const RootBox *rb, TreeDev t, uint32_t *level_count, hipStream_t s);
-void launch_level_buckets(const TreeDev &t, const uint32_t *level_count, uint32_t *level_off,
-                          uint32_t *level_fill, uint32_t *level_nodes, hipStream_t s);
+                         const RootBox *rb, TreeDev t, hipStream_t s);
+// Cells bucketed by level: level_count[22], level_off[23], level_nodes[n_nodes];
+// level_ws holds level_ws_elems(n_nodes) u32.
+int64_t level_ws_elems(int64_t n_nodes);
+void launch_level_buckets(const TreeDev &t, uint32_t *level_count, uint32_t *level_off,
+                          uint32_t *level_ws, uint32_t *level_nodes, hipStream_t s);
 void launch_moments_level(const TreeDev &t, int level, const uint32_t *level_off,
                           const uint32_t *level_nodes, hipStream_t s);
 void launch_tree_summary(const TreeDev &t, const uint32_t *level_count, Status *st, hipStream_t s);
@@ -97,8 +100,9 @@ void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint3
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
                      const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
                      uint32_t *queue, int resident_waves, hipStream_t s);
+// long_list holds n u32, long_count one u32 zeroed by the caller.
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
-                    const Status *st, hipStream_t s);
+                    const Status *st, uint32_t *long_list, uint32_t *long_count, hipStream_t s);
 int nb_resident_waves(int device);
 
 }  // namespace petar

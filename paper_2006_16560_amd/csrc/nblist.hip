@@ -160,59 +160,111 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
     }
 }
 
-// Sorts each list ascending: insertion sort for short lists, heap sort
-// otherwise (both in place).
-__global__ __launch_bounds__(kThreads) void k_nb_sort(const int64_t *offsets, int32_t *idx,
-                                                      int64_t n, int64_t capacity,
-                                                      const Status *st) {
+// Sorts each list ascending. Short lists (<= 32 entries, almost all) are
+// insertion-sorted by one thread; longer ones are queued and sorted by a
+// whole block with a bitonic network in LDS (heap sort by one thread above
+// kLongMax entries).
+constexpr int kShortMax = 32;
+constexpr int kLongMax = 4096;
+
+__global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offsets, int32_t *idx,
+                                                            int64_t n, int64_t capacity,
+                                                            const Status *st, uint32_t *long_list,
+                                                            uint32_t *long_count) {
     if (st->invalid_radii || st->stack_overflow || offsets[n] > capacity) return;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t b = offsets[i], e = offsets[i + 1];
         int64_t len = e - b;
+        if (len > kShortMax) {
+            long_list[atomicAdd(long_count, 1u)] = (uint32_t)i;
+            continue;
+        }
         int32_t *a = idx + b;
-        if (len <= 32) {
-            for (int64_t p = 1; p < len; p++) {
-                int32_t v = a[p];
-                int64_t q = p - 1;
-                while (q >= 0 && a[q] > v) {
-                    a[q + 1] = a[q];
-                    q--;
-                }
-                a[q + 1] = v;
+        for (int64_t p = 1; p < len; p++) {
+            int32_t v = a[p];
+            int64_t q = p - 1;
+            while (q >= 0 && a[q] > v) {
+                a[q + 1] = a[q];
+                q--;
             }
-        } else {
-            // heapify
-            for (int64_t s = len / 2 - 1; s >= 0; s--) {
-                int64_t r = s;
-                while (true) {
-                    int64_t c = 2 * r + 1;
-                    if (c >= len) break;
-                    if (c + 1 < len && a[c + 1] > a[c]) c++;
-                    if (a[r] >= a[c]) break;
-                    int32_t tmp = a[r];
-                    a[r] = a[c];
-                    a[c] = tmp;
-                    r = c;
+            a[q + 1] = v;
+        }
+    }
+}
+
+__device__ void heap_sort(int32_t *a, int64_t len) {
+    for (int64_t s = len / 2 - 1; s >= 0; s--) {
+        int64_t r = s;
+        while (true) {
+            int64_t c = 2 * r + 1;
+            if (c >= len) break;
+            if (c + 1 < len && a[c + 1] > a[c]) c++;
+            if (a[r] >= a[c]) break;
+            int32_t tmp = a[r];
+            a[r] = a[c];
+            a[c] = tmp;
+            r = c;
+        }
+    }
+    for (int64_t end = len - 1; end > 0; end--) {
+        int32_t tmp = a[0];
+        a[0] = a[end];
+        a[end] = tmp;
+        int64_t r = 0;
+        while (true) {
+            int64_t c = 2 * r + 1;
+            if (c >= end) break;
+            if (c + 1 < end && a[c + 1] > a[c]) c++;
+            if (a[r] >= a[c]) break;
+            int32_t t2 = a[r];
+            a[r] = a[c];
+            a[c] = t2;
+            r = c;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_nb_sort_long(const int64_t *offsets, int32_t *idx,
+                                                           int64_t n, int64_t capacity,
+                                                           const Status *st,
+                                                           const uint32_t *long_list,
+                                                           const uint32_t *long_count) {
+    __shared__ int32_t sh[kLongMax];
+    if (st->invalid_radii || st->stack_overflow || offsets[n] > capacity) return;
+    const uint32_t nl = *long_count;
+    for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
+        const uint32_t i = long_list[q];
+        const int64_t b = offsets[i];
+        const int64_t len = offsets[i + 1] - b;
+        int32_t *a = idx + b;
+        if (len > kLongMax) {
+            if (threadIdx.x == 0) heap_sort(a, len);
+            __syncthreads();
+            continue;
+        }
+        int P = 1;
+        while (P < len) P <<= 1;
+        for (int t = threadIdx.x; t < P; t += blockDim.x) sh[t] = t < len ? a[t] : 0x7fffffff;
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = threadIdx.x; t < P; t += blockDim.x) {
+                    int u = t ^ j;
+                    if (u > t) {
+                        int32_t x = sh[t], y = sh[u];
+                        bool up = (t & k) == 0;
+                        if ((x > y) == up) {
+                            sh[t] = y;
+                            sh[u] = x;
+                        }
+                    }
                 }
-            }
-            for (int64_t end = len - 1; end > 0; end--) {
-                int32_t tmp = a[0];
-                a[0] = a[end];
-                a[end] = tmp;
-                int64_t r = 0;
-                while (true) {
-                    int64_t c = 2 * r + 1;
-                    if (c >= end) break;
-                    if (c + 1 < end && a[c + 1] > a[c]) c++;
-                    if (a[r] >= a[c]) break;
-                    int32_t t2 = a[r];
-                    a[r] = a[c];
-                    a[c] = t2;
-                    r = c;
-                }
+                __syncthreads();
             }
         }
+        for (int t = threadIdx.x; t < len; t += blockDim.x) a[t] = sh[t];
+        __syncthreads();
     }
 }
 
@@ -244,12 +296,14 @@ void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
 }
 
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
-                    const Status *st, hipStream_t s) {
+                    const Status *st, uint32_t *long_list, uint32_t *long_count, hipStream_t s) {
     int64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_nb_sort, dim3((unsigned)blocks), dim3(kThreads), 0, s, offsets, idx, n,
-                       capacity, st);
+    hipLaunchKernelGGL(k_nb_sort_short, dim3((unsigned)blocks), dim3(kThreads), 0, s, offsets, idx,
+                       n, capacity, st, long_list, long_count);
+    hipLaunchKernelGGL(k_nb_sort_long, dim3(1024), dim3(kThreads), 0, s, offsets, idx, n, capacity,
+                       st, (const uint32_t *)long_list, (const uint32_t *)long_count);
 }
 
 }  // namespace petar

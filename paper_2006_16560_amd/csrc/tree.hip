@@ -304,8 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_octree_count(const uint64_t *key, 
 
 __global__ __launch_bounds__(kThreads) void k_octree_write(const uint64_t *key, int64_t n,
                                                            int leaf_size, const int64_t *base,
-                                                           const RootBox *rb, TreeDev t,
-                                                           uint32_t *level_count) {
+                                                           const RootBox *rb, TreeDev t) {
     const int64_t n_nodes = base[n];
     const double ext = rb->ext;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
@@ -339,32 +338,63 @@ __global__ __launch_bounds__(kThreads) void k_octree_write(const uint64_t *key, 
                 int digit = (int)((key[k] >> (3 * (kMaxLevel - l))) & 7);
                 t.nd_child[(int64_t)parent * 8 + digit] = idx;
             }
-            atomicAdd(&level_count[l], 1u);
         }
     }
 }
 
-__global__ void k_level_offsets(const uint32_t *level_count, uint32_t *level_off,
-                                uint32_t *level_fill) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+// Cells grouped by level (for the bottom-up passes) with a counting sort:
+// per-block level histograms, one scan, and a scatter through LDS counters.
+// The order inside a level is irrelevant (each cell is computed on its own).
+constexpr int kLevels = kMaxLevel + 1;
+constexpr int kLevelChunk = 4096;  // cells per histogram block
+
+__global__ __launch_bounds__(kThreads) void k_level_hist(TreeDev t, uint32_t *block_hist) {
+    __shared__ uint32_t h[kLevels];
+    if (threadIdx.x < kLevels) h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t beg = (int64_t)blockIdx.x * kLevelChunk;
+    int64_t end = beg + kLevelChunk < t.n_nodes ? beg + kLevelChunk : t.n_nodes;
+    for (int64_t c = beg + threadIdx.x; c < end; c += blockDim.x)
+        atomicAdd(&h[t.nd_info[c].z >> 1], 1u);
+    __syncthreads();
+    if (threadIdx.x < kLevels) block_hist[(int64_t)blockIdx.x * kLevels + threadIdx.x] = h[threadIdx.x];
+}
+
+// One thread per level: totals, level offsets, then per-block offsets.
+__global__ void k_level_scan(uint32_t *block_hist, int64_t nblk, uint32_t *level_count,
+                             uint32_t *level_off) {
+    __shared__ uint32_t tot[kLevels];
+    int l = threadIdx.x;
+    if (l < kLevels) {
         uint32_t s = 0;
-        for (int l = 0; l <= kMaxLevel; l++) {
-            level_off[l] = s;
-            s += level_count[l];
-            level_fill[l] = 0;
+        for (int64_t b = 0; b < nblk; b++) s += block_hist[b * kLevels + l];
+        tot[l] = s;
+        level_count[l] = s;
+    }
+    __syncthreads();
+    if (l < kLevels) {
+        uint32_t off = 0;
+        for (int k = 0; k < l; k++) off += tot[k];
+        level_off[l] = off;
+        if (l == kLevels - 1) level_off[kLevels] = off + tot[l];
+        for (int64_t b = 0; b < nblk; b++) {
+            uint32_t c = block_hist[b * kLevels + l];
+            block_hist[b * kLevels + l] = off;
+            off += c;
         }
-        level_off[kMaxLevel + 1] = s;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_level_bucket(TreeDev t, const uint32_t *level_off,
-                                                           uint32_t *level_fill,
-                                                           uint32_t *level_nodes) {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        int l = (int)(t.nd_info[c].z >> 1);
-        uint32_t p = atomicAdd(&level_fill[l], 1u);
-        level_nodes[level_off[l] + p] = (uint32_t)c;
+__global__ __launch_bounds__(kThreads) void k_level_scatter(TreeDev t, const uint32_t *block_off,
+                                                            uint32_t *level_nodes) {
+    __shared__ uint32_t cur[kLevels];
+    if (threadIdx.x < kLevels) cur[threadIdx.x] = block_off[(int64_t)blockIdx.x * kLevels + threadIdx.x];
+    __syncthreads();
+    int64_t beg = (int64_t)blockIdx.x * kLevelChunk;
+    int64_t end = beg + kLevelChunk < t.n_nodes ? beg + kLevelChunk : t.n_nodes;
+    for (int64_t c = beg + threadIdx.x; c < end; c += blockDim.x) {
+        uint32_t p = atomicAdd(&cur[t.nd_info[c].z >> 1], 1u);
+        level_nodes[p] = (uint32_t)c;
     }
 }
 
@@ -565,14 +595,21 @@ __global__ __launch_bounds__(kThreads) void k_mass_partial(const double *mass, i
     }
 }
 
+// Mean mass <m> = (sum m)/N, summed in a fixed order (deterministic).
+__global__ void k_mass_final(double *part, int nblk, int64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double msum = 0.0;
+        for (int b = 0; b < nblk; b++) msum += part[b];
+        part[nblk] = msum / (double)n;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_radii(const double *mass, const double *vel,
-                                                    int64_t n, const double *part, int nblk,
+                                                    int64_t n, const double *mave_p,
                                                     double rin_ref, double rout_ref,
                                                     double search_factor, double cr_dt,
                                                     double *r_in, double *r_out, double *r_s) {
-    double msum = 0.0;
-    for (int b = 0; b < nblk; b++) msum += part[b];
-    double mave = msum / (double)n;
+    const double mave = *mave_p;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double ratio = mave > 0.0 ? mass[i] / mave : 1.0;
@@ -649,17 +686,23 @@ void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, uint32_t
 }
 
 void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, const int64_t *base,
-                         const RootBox *rb, TreeDev t, uint32_t *level_count, hipStream_t s) {
+                         const RootBox *rb, TreeDev t, hipStream_t s) {
     hipLaunchKernelGGL(k_octree_write, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
-                       base, rb, t, level_count);
+                       base, rb, t);
 }
 
-void launch_level_buckets(const TreeDev &t, const uint32_t *level_count, uint32_t *level_off,
-                          uint32_t *level_fill, uint32_t *level_nodes, hipStream_t s) {
-    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, level_count, level_off,
-                       level_fill);
-    hipLaunchKernelGGL(k_level_bucket, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, t,
-                       (const uint32_t *)level_off, level_fill, level_nodes);
+int64_t level_ws_elems(int64_t n_nodes) {
+    return ((n_nodes + kLevelChunk - 1) / kLevelChunk + 1) * kLevels;
+}
+
+void launch_level_buckets(const TreeDev &t, uint32_t *level_count, uint32_t *level_off,
+                          uint32_t *level_ws, uint32_t *level_nodes, hipStream_t s) {
+    int64_t nblk = (t.n_nodes + kLevelChunk - 1) / kLevelChunk;
+    hipLaunchKernelGGL(k_level_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, t, level_ws);
+    hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(64), 0, s, level_ws, nblk, level_count,
+                       level_off);
+    hipLaunchKernelGGL(k_level_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, t,
+                       (const uint32_t *)level_ws, level_nodes);
 }
 
 void launch_moments_level(const TreeDev &t, int level, const uint32_t *level_off,
@@ -701,8 +744,9 @@ void launch_changeover_radii(const double *mass, const double *vel, int64_t n, d
                              double *r_out, double *r_search, double *ws, hipStream_t s) {
     int nb = (int)grid_for(n, kThreads, 1024);
     hipLaunchKernelGGL(k_mass_partial, dim3(nb), dim3(kThreads), 0, s, mass, n, ws);
+    hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(64), 0, s, ws, nb, n);
     hipLaunchKernelGGL(k_radii, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, mass, vel,
-                       n, (const double *)ws, nb, rin_ref, rout_ref, search_factor, cr_dt, r_in,
+                       n, (const double *)(ws + nb), rin_ref, rout_ref, search_factor, cr_dt, r_in,
                        r_out, r_search);
 }
 
