@@ -55,6 +55,8 @@ def main() -> int:
     import paper_2006_16560_amd as pt
     import workloads
 
+    if args.workload == "batched128":
+        return bench_batched(args)
     wl = workloads.WORKLOADS[args.workload]
     theta = wl.theta if args.theta is None else args.theta
     leaf = wl.leaf_size if args.leaf is None else args.leaf
@@ -184,6 +186,88 @@ def main() -> int:
         "neighbour_entries": st["nb_total"],
         "errors": err,
         "workspace_bytes": st["workspace_bytes"],
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_batched(args) -> int:
+    """128 independent clusters (N log-uniform in [1024, 131072], 20% binaries):
+    one batched build + force (one persistent launch over all groups) against
+    128 sequential per-cluster build + force calls on the same GPU."""
+    import torch
+    import paper_2006_16560_amd as pt
+    import workloads
+
+    t0 = time.time()
+    offs, pos_h, vel_h, mass_h, sizes = workloads.make_batched(args.seed)
+    n = int(offs[-1])
+    log("batched workload: %d systems, N=%d generated in %.1fs" % (sizes.size, n, time.time() - t0))
+    dev = "cuda:0"
+    pos = torch.from_numpy(pos_h).to(dev)
+    mass = torch.from_numpy(mass_h).to(dev)
+    r_in = torch.empty(n, dtype=torch.float64, device=dev)
+    r_out, r_s = torch.empty_like(r_in), torch.empty_like(r_in)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    theta = 0.5 if args.theta is None else args.theta
+    leaf = 8 if args.leaf is None else args.leaf
+    group = 64 if args.group is None else args.group
+    ctx = pt.petar_create(0)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1 if args.ipl is None else args.ipl)
+    for k in range(sizes.size):  # per-cluster radii (own <m> and r_out,ref ~ N^-1/3)
+        a, b = int(offs[k]), int(offs[k + 1])
+        ro = workloads.r_out_ref_for(int(sizes[k]))
+        pt.petar_changeover_radii(ctx, mass[a:b], 0.1 * ro, ro, 1.2,
+                                  out=(r_in[a:b], r_out[a:b], r_s[a:b]))
+    nb_cap = 64 * n
+
+    def batched():
+        pt.petar_batch_build(ctx, offs, pos, mass, theta, leaf)
+        return pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot,
+                                   nb_capacity=nb_cap)
+
+    def sequential():
+        tot = 0
+        for k in range(sizes.size):
+            a, b = int(offs[k]), int(offs[k + 1])
+            pt.petar_batch_build(ctx, [0, b - a], pos[:, a:b].contiguous(), mass[a:b], theta, leaf)
+            pt.petar_force_long(ctx, group, r_in[a:b], r_out[a:b], r_s[a:b], acc=None, pot=None,
+                                nb_capacity=64 * (b - a))
+            st = pt.petar_get_stats(ctx)
+            tot += st["inter_pc"] + st["inter_far"] + st["inter_near"]
+        return tot
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    ms_b = 1e3 * (time.perf_counter() - t1) / args.steps
+    st = pt.petar_get_stats(ctx)
+    inter = st["inter_pc"] + st["inter_far"] + st["inter_near"]
+    sequential()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    inter_seq = sequential()
+    torch.cuda.synchronize()
+    ms_s = 1e3 * (time.perf_counter() - t2)
+    log("batched %.3f ms/step, sequential %.3f ms/step" % (ms_b, ms_s))
+    line = {
+        "metric": "tree-force interactions/s (batched clusters)",
+        "value": inter / (ms_b * 1e-3), "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched128", "n_systems": int(sizes.size), "n": n,
+                   "theta": theta, "leaf_size": leaf, "group_size": group,
+                   "binary_fraction": 0.2},
+        "sequential_ms_per_step": ms_s, "speedup_vs_sequential": ms_s / ms_b,
+        "interactions": inter, "interactions_sequential": inter_seq,
+        "stages_ms": {"build": st["ms_build"], "force_total": st["ms_force"],
+                      "force_kernel": st["ms_force_kernel"], "neighbours": st["ms_nb"]},
     }
     print(json.dumps(line), flush=True)
     return 0

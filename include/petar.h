@@ -107,6 +107,7 @@ typedef struct {
     double ms_force;           /* device time of the last force call (total)   */
     double ms_force_kernel;    /* device time of the walk + interaction kernel  */
     double ms_nb;              /* device time of the neighbour-list stage       */
+    double ms_graph;           /* device time of the last replayed step graph   */
     int64_t workspace_bytes;   /* library-owned device memory                   */
 } petar_stats;
 
@@ -139,6 +140,17 @@ PETAR_API petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass
 PETAR_API petar_status petar_tree_build(petar_ctx *ctx, const double *pos_dev, const double *mass_dev,
                               int64_t N, double theta, int leaf_size);
 
+/* Batched mode: n_sys independent particle systems (star clusters) stored
+ * back to back; system s holds particles sys_offsets[s] .. sys_offsets[s+1]-1
+ * (sys_offsets is a host array of n_sys + 1 entries, sys_offsets[0] = 0,
+ * strictly increasing; 1 <= n_sys <= 512). Builds one octree per system (own
+ * root cube, 18 levels) in a single pass; the next petar_force_long computes
+ * every system's long-range force and neighbour lists in one launch, with
+ * no interaction between systems. Output indices are global (input order). */
+PETAR_API petar_status petar_batch_build(petar_ctx *ctx, int n_sys, const int64_t *sys_offsets,
+                                         const double *pos_dev, const double *mass_dev,
+                                         double theta, int leaf_size);
+
 /* Long-range acceleration and potential on every particle of the last
  * tree build (input order): acc_dev[3][N], pot_dev[N]. group_size >= 1 is
  * the i-group size of the walk. r_in_dev, r_out_dev, r_search_dev [N] are
@@ -150,6 +162,23 @@ PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const do
                               const double *r_out_dev, const double *r_search_dev,
                               double *acc_dev, double *pot_dev, petar_nblist *nb);
 
+/* One step -- tree build (petar_tree_build when n_sys == 0, else
+ * petar_batch_build with sys_offsets[n_sys + 1] and N = sys_offsets[n_sys])
+ * followed by petar_force_long -- executed as a captured hipGraph. The
+ * first call (and any call whose pointers, sizes, offsets or parameters
+ * differ from the captured ones) runs eagerly and captures the launches on a
+ * private stream; later calls replay the graph on the context's stream with
+ * one status read at the end. Buffer contents may change between calls. The
+ * graph holds cells for twice the tree of the capturing call; a tree that
+ * outgrows it is redone eagerly and recaptured on the next call. Results and
+ * errors are those of the two eager calls. */
+PETAR_API petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offsets,
+                                        const double *pos_dev, const double *mass_dev, int64_t N,
+                                        double theta, int leaf_size, int group_size,
+                                        const double *r_in_dev, const double *r_out_dev,
+                                        const double *r_search_dev, double *acc_dev,
+                                        double *pot_dev, petar_nblist *nb);
+
 /* Per-particle interaction counts of the last force call (input order),
  * counts_dev[4][N] int32: multipole cells, far-leaf particles, near-leaf
  * particles (including the particle itself) and the size of its i-group.
@@ -157,6 +186,30 @@ PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const do
 PETAR_API petar_status petar_copy_counts(petar_ctx *ctx, int32_t *counts_dev);
 
 PETAR_API petar_status petar_get_stats(petar_ctx *ctx, petar_stats *stats);
+
+/* Tree/walk parameters picked by petar_autotune. */
+typedef struct {
+    int leaf_size;   /* for petar_tree_build                     */
+    int group_size;  /* for petar_force_long                     */
+    int i_per_lane;  /* also stored into the context's params    */
+    double ms;       /* measured build + force time (device ms)  */
+} petar_tuned;
+
+/* Times tree build + long-range force on the given particles (same argument
+ * rules as petar_tree_build / petar_force_long) for leaf sizes {4, 8, 16, 32},
+ * group sizes {32, 64, 128, 256} and 1, 2 or 4 targets per lane, keeps the
+ * fastest, sets params.i_per_lane to it and returns it in *out. With
+ * cache_path (host string, may be NULL) results are read from / appended to
+ * a JSON-lines file keyed by (floor(log2 N), theta, precision); a cache hit
+ * returns without launching anything. The practice follows the paper's
+ * wall-clock scans of its integrator parameters (Sec. "Performance on
+ * GPU-based Desktop"). Leaves the context holding a tree of some candidate:
+ * rebuild with the returned leaf size. */
+PETAR_API petar_status petar_autotune(petar_ctx *ctx, const double *pos_dev,
+                                      const double *mass_dev, int64_t N, double theta,
+                                      const double *r_in_dev, const double *r_out_dev,
+                                      const double *r_search_dev, const char *cache_path,
+                                      petar_tuned *out);
 
 /* Message of the last failure on ctx (thread-local message if ctx is NULL). */
 PETAR_API const char *petar_last_error(petar_ctx *ctx);

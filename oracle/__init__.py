@@ -73,10 +73,12 @@ def lib():
         L.oracle_multipole.restype = None
         L.oracle_multipole_eval.argtypes = [d, p_d, p_d, d, p_d, i64, p_d, p_d]
         L.oracle_multipole_eval.restype = None
-        L.oracle_tree_info.argtypes = [p_d, p_d, i64, ctypes.c_int, ctypes.c_int, p_i64]
+        L.oracle_tree_info.argtypes = [p_d, p_d, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       p_i64]
         L.oracle_tree_info.restype = ctypes.c_int
         L.oracle_tree_force.argtypes = [p_d, p_d, p_d, p_d, p_d, i64, d, ctypes.c_int,
-                                        ctypes.c_int, d, p_i64, i64, p_d, p_d, p_i64]
+                                        ctypes.c_int, ctypes.c_int, d, p_i64, i64, p_d, p_d,
+                                        p_i64]
         L.oracle_tree_force.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -198,10 +200,10 @@ def multipole_eval(M, com, quad6, pts, G: float = 1.0):
 
 
 # ---------------------------------------------------------------------- tree
-def tree_info(pos, mass, leaf_size: int, group_size: int) -> dict:
+def tree_info(pos, mass, leaf_size: int, group_size: int, max_level: int = 21) -> dict:
     pos, mass = _f64(pos), _f64(mass)
     info = np.zeros(6, dtype=np.int64)
-    rc = lib().oracle_tree_info(_p(pos), _p(mass), mass.size, leaf_size, group_size,
+    rc = lib().oracle_tree_info(_p(pos), _p(mass), mass.size, leaf_size, group_size, max_level,
                                 _p(info, _c_i64_p))
     if rc != 0:
         raise ValueError("invalid tree arguments")
@@ -210,8 +212,9 @@ def tree_info(pos, mass, leaf_size: int, group_size: int) -> dict:
 
 
 def tree_force(pos, mass, r_in, r_out, r_search, theta: float, leaf_size: int,
-               group_size: int, G: float = 1.0, idx=None):
-    """Barnes-Hut long-range force with the group-wise walk.
+               group_size: int, G: float = 1.0, idx=None, max_level: int = 21):
+    """Barnes-Hut long-range force with the group-wise walk (tree depth
+    max_level: 21 for a single system, 18 per system in batched mode).
 
     Returns (acc (3,k), pot (k,), counts (4,k)) where counts rows are:
     multipole cells, far-leaf particles, near-leaf particles, group size.
@@ -223,7 +226,8 @@ def tree_force(pos, mass, r_in, r_out, r_search, theta: float, leaf_size: int,
     acc, pot = np.empty((3, k)), np.empty(k)
     counts = np.empty((4, k), dtype=np.int64)
     rc = lib().oracle_tree_force(_p(pos), _p(mass), _p(r_in), _p(r_out), _p(r_search), n,
-                                 float(theta), int(leaf_size), int(group_size), G,
+                                 float(theta), int(leaf_size), int(group_size),
+                                 int(max_level), G,
                                  _p(ix, _c_i64_p), k, _p(acc), _p(pot), _p(counts, _c_i64_p))
     if rc != 0:
         raise ValueError("invalid tree arguments")

@@ -366,10 +366,11 @@ OR_EXPORT void oracle_multipole_eval(double M, const double *com, const double *
  * 6. Barnes-Hut tree force with group-wise walk.
  *
  *  Root cube: lo_d = min x_d, ext = max_d (max x_d - min x_d) (1 if 0).
- *  Integer coordinate per axis: q = floor((x - lo) * (2^21/ext)), clamped
- *  to 2^21 - 1. A cell at level l holds the particles sharing the top l bits
- *  of all three q; its side is ext / 2^l. A cell with <= leaf_size particles,
- *  or at level 21, is a leaf; otherwise its non-empty octants are children.
+ *  Integer coordinate per axis: q = floor((x - lo) * (2^L/ext)), clamped
+ *  to 2^L - 1, with L = max_level (21 by default). A cell at level l holds
+ *  the particles sharing the top l bits of all three q; its side is
+ *  ext / 2^l. A cell with <= leaf_size particles, or at level L, is a leaf;
+ *  otherwise its non-empty octants are children.
  *  Cell data: mass, centre of mass, A' (section 5), particle bounding box,
  *  max r_search of its members.
  *  i-groups: the first cells on each root-to-leaf path that hold
@@ -386,7 +387,7 @@ OR_EXPORT void oracle_multipole_eval(double M, const double *com, const double *
  *  Newtonian and the expansion is exact in form.
  * ---------------------------------------------------------------------- */
 
-#define OR_MAXLEVEL 21
+#define OR_MAXLEVEL 21 /* default depth: 21 bits per axis */
 
 typedef struct {
     int64_t begin, count; /* range in the member permutation */
@@ -417,13 +418,14 @@ typedef struct {
     const uint32_t *q; /* [3][n] integer coordinates */
     int64_t n;
     int leaf_size;
+    int max_level; /* levels below the root (bits per axis) */
     int64_t *perm, *tmp;
     ocells cells;
 } obuild;
 
 static int octant(const obuild *b, int64_t j, int level)
 {
-    int shift = OR_MAXLEVEL - 1 - level; /* bit of the child level */
+    int shift = b->max_level - 1 - level; /* bit of the child level */
     int bx = (b->q[j] >> shift) & 1;
     int by = (b->q[b->n + j] >> shift) & 1;
     int bz = (b->q[2 * b->n + j] >> shift) & 1;
@@ -437,7 +439,7 @@ static int64_t build_cell(obuild *b, int64_t begin, int64_t count, int level)
     c->begin = begin;
     c->count = count;
     c->level = level;
-    c->leaf = (count <= b->leaf_size || level == OR_MAXLEVEL);
+    c->leaf = (count <= b->leaf_size || level == b->max_level);
     if (c->leaf) return id;
     /* stable partition of the range by child octant */
     int64_t cnt[8] = {0}, off[8];
@@ -541,7 +543,7 @@ static void find_groups(const ocells *cs, int64_t cid, int group_size, int64_t *
 /* Tree structure summary: info[0..5] = n_cells, n_leaves, n_groups,
  * max_level, max leaf count, sum over leaves of count (== n). */
 static int build_tree(const double *pos, const double *mass, const double *r_search, int64_t n,
-                      int leaf_size, obuild *b, double *ext_out)
+                      int leaf_size, int max_level, obuild *b, double *ext_out)
 {
     const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
     double lo[3] = {X[0], Y[0], Z[0]}, hi[3] = {X[0], Y[0], Z[0]};
@@ -558,14 +560,16 @@ static int build_tree(const double *pos, const double *mass, const double *r_sea
         if (e > ext) ext = e;
     }
     if (!(ext > 0.0)) ext = 1.0;
-    double scale = 2097152.0 / ext;
+    const double cells_per_axis = ldexp(1.0, max_level); /* 2^max_level */
+    const uint64_t qmax = ((uint64_t)1 << max_level) - 1;
+    double scale = cells_per_axis / ext;
     uint32_t *q = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
     const double *P[3] = {X, Y, Z};
     for (int d = 0; d < 3; d++)
         for (int64_t i = 0; i < n; i++) {
             double t = (P[d][i] - lo[d]) * scale;
             uint64_t v = (uint64_t)t;
-            if (v > 2097151u) v = 2097151u;
+            if (v > qmax) v = qmax;
             q[(size_t)d * n + i] = (uint32_t)v;
         }
     memset(b, 0, sizeof(*b));
@@ -577,6 +581,7 @@ static int build_tree(const double *pos, const double *mass, const double *r_sea
     b->q = q;
     b->n = n;
     b->leaf_size = leaf_size;
+    b->max_level = max_level;
     b->perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     b->tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     for (int64_t i = 0; i < n; i++) b->perm[i] = i;
@@ -616,12 +621,12 @@ static void free_tree(obuild *b)
 }
 
 OR_EXPORT int oracle_tree_info(const double *pos, const double *mass, int64_t n, int leaf_size,
-                               int group_size, int64_t *info)
+                               int group_size, int max_level, int64_t *info)
 {
-    if (n < 1 || leaf_size < 1 || group_size < 1) return -1;
+    if (n < 1 || leaf_size < 1 || group_size < 1 || max_level < 1 || max_level > 21) return -1;
     obuild b;
     double ext;
-    build_tree(pos, mass, NULL, n, leaf_size, &b, &ext);
+    build_tree(pos, mass, NULL, n, leaf_size, max_level, &b, &ext);
     int64_t nleaf = 0, maxlev = 0, maxleaf = 0, sumleaf = 0;
     for (int64_t k = 0; k < b.cells.n; k++) {
         ocell *c = &b.cells.c[k];
@@ -652,15 +657,17 @@ OR_EXPORT int oracle_tree_info(const double *pos, const double *mass, int64_t n,
  * the target's group lists, and the size of its group. Returns 0 or -1. */
 OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const double *r_in,
                                 const double *r_out, const double *r_search, int64_t n,
-                                double theta, int leaf_size, int group_size, double G,
-                                const int64_t *idx, int64_t n_idx, double *acc, double *pot,
-                                int64_t *counts)
+                                double theta, int leaf_size, int group_size, int max_level,
+                                double G, const int64_t *idx, int64_t n_idx, double *acc,
+                                double *pot, int64_t *counts)
 {
-    if (n < 1 || leaf_size < 1 || group_size < 1 || !(theta >= 0.0)) return -1;
+    if (n < 1 || leaf_size < 1 || group_size < 1 || !(theta >= 0.0) || max_level < 1 ||
+        max_level > 21)
+        return -1;
     const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
     obuild b;
     double ext;
-    build_tree(pos, mass, r_search, n, leaf_size, &b, &ext);
+    build_tree(pos, mass, r_search, n, leaf_size, max_level, &b, &ext);
     int64_t *groups = (int64_t *)malloc(sizeof(int64_t) * (size_t)b.cells.n);
     int64_t ng = 0;
     find_groups(&b.cells, 0, group_size, groups, &ng);

@@ -23,8 +23,9 @@ _lib = _capi.load()
 
 __all__ = [
     "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
-    "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_force_long",
-    "petar_copy_counts", "petar_get_stats", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
+    "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_batch_build",
+    "petar_force_long", "petar_step_graph",
+    "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
     "PETAR_NO_DEVICE", "lib_path",
 ]
 
@@ -141,6 +142,19 @@ def petar_tree_build(ctx: Context, pos: torch.Tensor, mass: torch.Tensor, theta:
                                  float(theta), int(leaf_size)), ctx)
 
 
+def petar_batch_build(ctx: Context, sys_offsets, pos: torch.Tensor, mass: torch.Tensor,
+                      theta: float, leaf_size: int) -> None:
+    """One octree per system; system s owns particles sys_offsets[s]:sys_offsets[s+1]."""
+    offs = [int(v) for v in sys_offsets]
+    n_sys = len(offs) - 1
+    n = mass.shape[0] if mass.dim() == 1 else -1
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    _check(_lib.petar_batch_build(ctx.handle, n_sys, arr,
+                                  _dptr(pos, torch.float64, (3, n), "pos", ctx.device),
+                                  _dptr(mass, torch.float64, (n,), "mass", ctx.device),
+                                  float(theta), int(leaf_size)), ctx)
+
+
 def petar_force_long(ctx: Context, group_size: int, r_in: torch.Tensor, r_out: torch.Tensor,
                      r_search: torch.Tensor, acc: Optional[torch.Tensor] = None,
                      pot: Optional[torch.Tensor] = None, nb_capacity: Optional[int] = None):
@@ -177,6 +191,41 @@ def petar_force_long(ctx: Context, group_size: int, r_in: torch.Tensor, r_out: t
     return acc, pot, (offsets, idx[: nb.required])
 
 
+def petar_step_graph(ctx: Context, pos: torch.Tensor, mass: torch.Tensor, theta: float,
+                     leaf_size: int, group_size: int, r_in: torch.Tensor, r_out: torch.Tensor,
+                     r_search: torch.Tensor, acc: torch.Tensor, pot: torch.Tensor,
+                     sys_offsets=None, nb=None):
+    """Tree build + long-range force as a captured, replayed hipGraph.
+
+    The output tensors (and nb = (offsets, idx) if given) must be the same
+    objects on every call for the graph to be replayed. Returns the number of
+    neighbour entries (or None).
+    """
+    n = mass.shape[0]
+    dev = ctx.device
+    n_sys, arr = 0, None
+    if sys_offsets is not None:
+        offs = [int(v) for v in sys_offsets]
+        n_sys = len(offs) - 1
+        arr = (ctypes.c_int64 * len(offs))(*offs)
+    nbs = None
+    if nb is not None:
+        off_t, idx_t = nb
+        nbs = _capi.petar_nblist(off_t.data_ptr(), idx_t.data_ptr(), idx_t.numel(), 0)
+    st = _lib.petar_step_graph(ctx.handle, n_sys, arr,
+                               _dptr(pos, torch.float64, (3, n), "pos", dev),
+                               _dptr(mass, torch.float64, (n,), "mass", dev), n, float(theta),
+                               int(leaf_size), int(group_size),
+                               _dptr(r_in, torch.float64, (n,), "r_in", dev),
+                               _dptr(r_out, torch.float64, (n,), "r_out", dev),
+                               _dptr(r_search, torch.float64, (n,), "r_search", dev),
+                               _dptr(acc, torch.float64, (3, n), "acc", dev),
+                               _dptr(pot, torch.float64, (n,), "pot", dev),
+                               ctypes.byref(nbs) if nbs is not None else None)
+    _check(st, ctx, nbs.required if nbs is not None else None)
+    return nbs.required if nbs is not None else None
+
+
 def petar_copy_counts(ctx: Context) -> torch.Tensor:
     """Per-particle interaction counts (4, N) int32 of the last force call."""
     n = petar_get_stats(ctx)["n"]
@@ -189,6 +238,23 @@ def petar_get_stats(ctx: Context) -> dict:
     s = _capi.petar_stats()
     _check(_lib.petar_get_stats(ctx.handle, ctypes.byref(s)), ctx)
     return s.as_dict()
+
+
+def petar_autotune(ctx: Context, pos: torch.Tensor, mass: torch.Tensor, theta: float,
+                   r_in: torch.Tensor, r_out: torch.Tensor, r_search: torch.Tensor,
+                   cache_path: Optional[str] = None) -> dict:
+    """Fastest (leaf_size, group_size, i_per_lane) for these particles; see petar.h."""
+    n = mass.shape[0]
+    dev = ctx.device
+    out = _capi.petar_tuned()
+    st = _lib.petar_autotune(ctx.handle, _dptr(pos, torch.float64, (3, n), "pos", dev),
+                             _dptr(mass, torch.float64, (n,), "mass", dev), n, float(theta),
+                             _dptr(r_in, torch.float64, (n,), "r_in", dev),
+                             _dptr(r_out, torch.float64, (n,), "r_out", dev),
+                             _dptr(r_search, torch.float64, (n,), "r_search", dev),
+                             cache_path.encode() if cache_path else None, ctypes.byref(out))
+    _check(st, ctx)
+    return {name: getattr(out, name) for name, _ in out._fields_}
 
 
 def force_long_with_retry(ctx: Context, group_size: int, r_in, r_out, r_search,

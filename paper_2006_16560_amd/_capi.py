@@ -46,10 +46,15 @@ class petar_stats(ctypes.Structure):
                 ("inter_near", ctypes.c_int64), ("nb_total", ctypes.c_int64),
                 ("ms_build", ctypes.c_double), ("ms_force", ctypes.c_double),
                 ("ms_force_kernel", ctypes.c_double), ("ms_nb", ctypes.c_double),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("ms_graph", ctypes.c_double), ("workspace_bytes", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class petar_tuned(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int), ("group_size", ctypes.c_int),
+                ("i_per_lane", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 # (name, restype, argtypes) of every exported entry point
@@ -64,9 +69,14 @@ SIGNATURES = [
     ("petar_get_params", _INT, [_P, ctypes.POINTER(petar_params)]),
     ("petar_changeover_radii", _INT, [_P, _P, _P, _I64, _D, _D, _D, _D, _P, _P, _P]),
     ("petar_tree_build", _INT, [_P, _P, _P, _I64, _D, _INT]),
+    ("petar_batch_build", _INT, [_P, _INT, ctypes.POINTER(_I64), _P, _P, _D, _INT]),
     ("petar_force_long", _INT, [_P, _INT, _P, _P, _P, _P, _P, ctypes.POINTER(petar_nblist)]),
+    ("petar_step_graph", _INT, [_P, _INT, ctypes.POINTER(_I64), _P, _P, _I64, _D, _INT, _INT,
+                                _P, _P, _P, _P, _P, ctypes.POINTER(petar_nblist)]),
     ("petar_copy_counts", _INT, [_P, _P]),
     ("petar_get_stats", _INT, [_P, ctypes.POINTER(petar_stats)]),
+    ("petar_autotune", _INT, [_P, _P, _P, _I64, _D, _P, _P, _P, ctypes.c_char_p,
+                              ctypes.POINTER(petar_tuned)]),
     ("petar_last_error", ctypes.c_char_p, [_P]),
     ("petar_status_string", ctypes.c_char_p, [_INT]),
 ]

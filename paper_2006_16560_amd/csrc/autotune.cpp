@@ -1,0 +1,177 @@
+// Autotuner of the tree/walk parameters: leaf size, i-group size and targets
+// per lane. It times tree build + long-range force for each candidate on the
+// caller's particles and keeps the fastest; results are cached as JSON lines
+// keyed by (floor(log2 N), theta, precision).
+//
+// The paper tunes its integrator parameters (dt_L, r_out) by scanning
+// wall-clock time over a range of values (Sec. "Performance on GPU-based
+// Desktop", the dt_L scan); this applies the same practice to the
+// GPU-specific parameters of the long-range force.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/petar.h"
+
+namespace {
+
+struct Entry {
+    int nbucket = -1;
+    double theta = 0.0;
+    int precision = 0;
+    petar_tuned t{};
+};
+
+int n_bucket(int64_t n) {
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n) b++;
+    return b;
+}
+
+bool same_key(const Entry &e, int nb, double theta, int prec) {
+    return e.nbucket == nb && std::fabs(e.theta - theta) < 1e-12 && e.precision == prec;
+}
+
+// Reads "key": number pairs from one line of the cache.
+bool parse_line(const char *line, Entry *e) {
+    auto num = [&](const char *key, double *v) {
+        const char *p = std::strstr(line, key);
+        if (!p) return false;
+        p = std::strchr(p, ':');
+        if (!p) return false;
+        return std::sscanf(p + 1, "%lf", v) == 1;
+    };
+    double nb, th, pr, lf, gs, ipl, ms;
+    if (!num("\"n_bucket\"", &nb) || !num("\"theta\"", &th) || !num("\"precision\"", &pr) ||
+        !num("\"leaf_size\"", &lf) || !num("\"group_size\"", &gs) || !num("\"i_per_lane\"", &ipl) ||
+        !num("\"ms\"", &ms))
+        return false;
+    e->nbucket = (int)nb;
+    e->theta = th;
+    e->precision = (int)pr;
+    e->t.leaf_size = (int)lf;
+    e->t.group_size = (int)gs;
+    e->t.i_per_lane = (int)ipl;
+    e->t.ms = ms;
+    return true;
+}
+
+std::vector<Entry> read_cache(const char *path) {
+    std::vector<Entry> out;
+    FILE *f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return out;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        Entry e;
+        if (parse_line(line, &e)) out.push_back(e);
+    }
+    std::fclose(f);
+    return out;
+}
+
+void write_cache(const char *path, const std::vector<Entry> &entries) {
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const Entry &e : entries)
+        std::fprintf(f,
+                     "{\"n_bucket\": %d, \"theta\": %.17g, \"precision\": %d, \"leaf_size\": %d, "
+                     "\"group_size\": %d, \"i_per_lane\": %d, \"ms\": %.6f}\n",
+                     e.nbucket, e.theta, e.precision, e.t.leaf_size, e.t.group_size,
+                     e.t.i_per_lane, e.t.ms);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" petar_status petar_autotune(petar_ctx *ctx, const double *pos, const double *mass,
+                                       int64_t N, double theta, const double *r_in,
+                                       const double *r_out, const double *r_search,
+                                       const char *cache_path, petar_tuned *out) {
+    if (!ctx || !out) return PETAR_E_INVALID;
+    petar_params p;
+    petar_status st = petar_get_params(ctx, &p);
+    if (st != PETAR_OK) return st;
+    const int nb = n_bucket(N < 1 ? 1 : N);
+    std::vector<Entry> cache = read_cache(cache_path);
+    for (const Entry &e : cache) {
+        if (same_key(e, nb, theta, p.precision)) {
+            *out = e.t;
+            p.i_per_lane = e.t.i_per_lane;
+            return petar_set_params(ctx, &p);
+        }
+    }
+    if (N < 1 || !pos || !mass || !r_in || !r_out || !r_search) {
+        // let the entry points report the exact problem
+        return petar_tree_build(ctx, pos, mass, N, theta, 8);
+    }
+    // scratch outputs for the timing runs
+    double *acc = nullptr, *pot = nullptr;
+    {
+        petar_status chk = petar_tree_build(ctx, pos, mass, N, theta, 8);
+        if (chk != PETAR_OK) return chk;
+    }
+    if (hipMalloc((void **)&acc, (size_t)N * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&pot, (size_t)N * sizeof(double)) != hipSuccess) {
+        if (acc) (void)hipFree(acc);
+        return PETAR_E_NOMEM;
+    }
+    const int leaves[] = {4, 8, 16, 32};
+    const int groups[] = {32, 64, 128, 256};
+    const int ipls[] = {1, 2, 4};
+    petar_tuned best{};
+    best.ms = -1.0;
+    for (int leaf : leaves) {
+        for (int group : groups) {
+            for (int ipl : ipls) {
+                if (ipl > 1 && group <= 64) continue;
+                if (ipl * 64 < group / 2) continue;
+                p.i_per_lane = ipl;
+                if ((st = petar_set_params(ctx, &p)) != PETAR_OK) return st;
+                double ms[3];
+                for (int rep = 0; rep < 3; rep++) {  // first call warms up
+                    st = petar_tree_build(ctx, pos, mass, N, theta, leaf);
+                    if (st == PETAR_OK)
+                        st = petar_force_long(ctx, group, r_in, r_out, r_search, acc, pot, nullptr);
+                    if (st != PETAR_OK) {
+                        (void)hipFree(acc);
+                        (void)hipFree(pot);
+                        return st;
+                    }
+                    petar_stats s;
+                    petar_get_stats(ctx, &s);
+                    ms[rep] = s.ms_build + s.ms_force;
+                }
+                double t = std::min(ms[1], ms[2]);
+                if (best.ms < 0.0 || t < best.ms) {
+                    best.leaf_size = leaf;
+                    best.group_size = group;
+                    best.i_per_lane = ipl;
+                    best.ms = t;
+                }
+            }
+        }
+    }
+    (void)hipFree(acc);
+    (void)hipFree(pot);
+    p.i_per_lane = best.i_per_lane;
+    if ((st = petar_set_params(ctx, &p)) != PETAR_OK) return st;
+    *out = best;
+    if (cache_path) {
+        Entry e;
+        e.nbucket = nb;
+        e.theta = theta;
+        e.precision = p.precision;
+        e.t = best;
+        cache.push_back(e);
+        write_cache(cache_path, cache);
+    }
+    return PETAR_OK;
+}

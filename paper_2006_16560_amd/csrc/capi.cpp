@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/petar.h"
 #include "launch.h"
@@ -37,10 +38,11 @@ struct petar_ctx {
     // tree build
     DevBuf key0, key1, val0, val1, sort_ws, scan_ws, bbox_part, rootbox, status, emit, base;
     DevBuf ps, orig, rr, rsk;
-    DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_info, nd_child, nd_parent;
-    DevBuf level_count, level_off, level_ws, level_nodes;
+    DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_info, level_off;
+    DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
-    DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws;
+    DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbrec, sys_off;
+    uint32_t nbrec_cap = 0;
 
     Status *host_status = nullptr;  // pinned
     int64_t *host_scalar = nullptr; // pinned
@@ -51,10 +53,19 @@ struct petar_ctx {
     double theta = 0.0;
     int leaf_size = 0;
     int64_t n_nodes = 0;
-    uint64_t *sorted_key = nullptr;
+    int levels = kMaxLevel;
+    int n_sys = 1;
 
     int force_waves[2][5] = {{0}};
     int nb_waves = 0;
+
+    // captured step (petar_step_graph)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_stale = true;
+    std::vector<int64_t> graph_key;  // arguments the graph was captured with
+    int64_t node_cap = 0;            // cell capacity of the captured graph
 
     hipEvent_t ev[8] = {};
     petar_stats stats{};
@@ -122,8 +133,18 @@ T *ptr(DevBuf &b) {
     return static_cast<T *>(b.p);
 }
 
+PreOrder pre_view(petar_ctx *c) {
+    PreOrder p;
+    p.info = ptr<uint4>(c->pre_info);
+    p.parent = ptr<uint32_t>(c->pre_parent);
+    p.nchild = ptr<uint32_t>(c->pre_nchild);
+    p.new_of_old = ptr<uint32_t>(c->new_of_old);
+    return p;
+}
+
 TreeDev tree_view(petar_ctx *c) {
     TreeDev t;
+    t.n_nodes_dev = &ptr<Status>(c->status)->n_nodes;  // set by the build (0 on overflow)
     t.ps = ptr<double4>(c->ps);
     t.rr = ptr<double2>(c->rr);
     t.rsk = ptr<double>(c->rsk);
@@ -133,23 +154,33 @@ TreeDev tree_view(petar_ctx *c) {
     t.nd_com = ptr<double4>(c->nd_com);
     t.nd_S = ptr<double>(c->nd_S);
     t.nd_info = ptr<uint4>(c->nd_info);
-    t.nd_child = ptr<uint32_t>(c->nd_child);
-    t.nd_parent = ptr<uint32_t>(c->nd_parent);
+    t.level_off = ptr<uint32_t>(c->level_off);
     t.n = c->n;
     t.n_nodes = c->n_nodes;
     return t;
 }
 
-petar_status zero_status(petar_ctx *c) {
-    fill_i64(ptr<int64_t>(c->status), 0, (int64_t)(sizeof(Status) / sizeof(int64_t)), c->stream);
+void zero_status(petar_ctx *c, hipStream_t s) {
+    fill_i64(ptr<int64_t>(c->status), 0, (int64_t)(sizeof(Status) / sizeof(int64_t)), s);
+}
+
+void zero_force_status(petar_ctx *c, hipStream_t s) {
+    fill_i64(ptr<int64_t>(c->status), 0, kStatusForceWords, s);
+}
+
+petar_status read_status(petar_ctx *c, hipStream_t s) {
+    HIP_TRY(c, hipMemcpyAsync(c->host_status, c->status.p, sizeof(Status), hipMemcpyDeviceToHost,
+                              s));
+    HIP_TRY(c, hipStreamSynchronize(s));
     return PETAR_OK;
 }
 
-petar_status read_status(petar_ctx *c) {
-    HIP_TRY(c, hipMemcpyAsync(c->host_status, c->status.p, sizeof(Status), hipMemcpyDeviceToHost,
-                              c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return PETAR_OK;
+void drop_graph(petar_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_stale = true;
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -163,9 +194,11 @@ void free_all(petar_ctx *c) {
                       &c->scan_ws,  &c->bbox_part,   &c->rootbox,    &c->status,     &c->emit,
                       &c->base,     &c->ps,          &c->orig,       &c->rr,         &c->rsk,
                       &c->nd_lo,    &c->nd_hi,       &c->nd_com,     &c->nd_S,       &c->nd_info,
-                      &c->nd_child, &c->nd_parent,   &c->level_count, &c->level_off, &c->level_ws,
-                      &c->level_nodes, &c->gflag,    &c->gpos,       &c->groups,     &c->spill,
-                      &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws};
+                      &c->level_off, &c->pre_info,   &c->pre_parent, &c->pre_nchild, &c->new_of_old,
+                      &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
+                      &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
+                      &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws,   &c->nbrec,
+                      &c->sys_off};
     for (DevBuf *b : bufs) {
         if (b->p) hipFree(b->p);
         b->p = nullptr;
@@ -233,6 +266,8 @@ petar_status petar_destroy(petar_ctx *ctx) {
     if (ctx->device != PETAR_NO_DEVICE) {
         hipSetDevice(ctx->device);
         if (ctx->stream) hipStreamSynchronize(ctx->stream);
+        drop_graph(ctx);
+        if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
         free_all(ctx);
         if (ctx->host_status) hipHostFree(ctx->host_status);
         if (ctx->host_scalar) hipHostFree(ctx->host_scalar);
@@ -275,91 +310,168 @@ petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass, const do
     return PETAR_OK;
 }
 
-petar_status petar_tree_build(petar_ctx *ctx, const double *pos, const double *mass, int64_t n,
-                              double theta, int leaf_size) {
-    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
-    if (const char *m = check_build_args(pos, mass, n, theta, leaf_size))
-        return fail(ctx, PETAR_E_INVALID, "%s", m);
-    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
-    ctx->have_tree = false;
-    ctx->have_counts = false;
+}  // extern "C"
 
-    const size_t N = (size_t)n;
-    int64_t sort_scan = 256 * ((n + 2047) / 2048);
-    int64_t scan_need = scan_ws_elems(sort_scan > n + 1 ? sort_scan : n + 1);
+namespace {
+
+// ---------------------------------------------------------------- build
+// The tree build runs in two phases around the only host read it needs in
+// eager mode (the cell count, to size the cell arrays):
+//   A: root cube(s), keys, sort, particle gather, cell counting and scan;
+//   B: cells in pre-order, level sort, level-order layout, multipoles.
+// One system (n_sys == 0): one root cube, 21 levels. Batches: one root cube
+// per system, kBatchLevels levels, system id above the Morton digits.
+
+struct BuildArgs {
+    const double *pos;
+    const double *mass;
+    int64_t n;
+    double theta;
+    int leaf_size;
+    int n_sys;                  // 0: one system
+    const int64_t *sys_off;     // host offsets [n_sys + 1] (batched)
+};
+
+petar_status alloc_build_a(petar_ctx *ctx, const BuildArgs &a) {
+    const size_t N = (size_t)a.n;
+    const int n_boxes = a.n_sys > 0 ? a.n_sys : 1;
+    int64_t sort_scan = 256 * ((a.n + 2047) / 2048);
+    int64_t scan_need = scan_ws_elems(sort_scan > a.n + 1 ? sort_scan : a.n + 1);
     TRY(ensure(ctx, ctx->key0, N * 8));
     TRY(ensure(ctx, ctx->key1, N * 8));
     TRY(ensure(ctx, ctx->val0, N * 4));
     TRY(ensure(ctx, ctx->val1, N * 4));
-    TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(n)));
+    TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(a.n)));
     TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_need * 8));
-    TRY(ensure(ctx, ctx->bbox_part, (size_t)bbox_partial_blocks(n) * 6 * 8));
-    TRY(ensure(ctx, ctx->rootbox, sizeof(RootBox)));
+    TRY(ensure(ctx, ctx->bbox_part, (size_t)bbox_partial_blocks(a.n) * 6 * 8));
+    TRY(ensure(ctx, ctx->rootbox, sizeof(RootBox) * (size_t)n_boxes));
     TRY(ensure(ctx, ctx->status, sizeof(Status)));
     TRY(ensure(ctx, ctx->emit, N * 4));
     TRY(ensure(ctx, ctx->base, (N + 1) * 8));
     TRY(ensure(ctx, ctx->ps, N * sizeof(double4)));
     TRY(ensure(ctx, ctx->orig, N * 4));
-    TRY(ensure(ctx, ctx->level_count, 32 * 4));
     TRY(ensure(ctx, ctx->level_off, 32 * 4));
+    if (a.n_sys > 0) TRY(ensure(ctx, ctx->sys_off, (size_t)(a.n_sys + 1) * 8));
+    return PETAR_OK;
+}
 
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
-    zero_status(ctx);
-    fill_i64(ptr<int64_t>(ctx->rootbox), 0, (int64_t)(sizeof(RootBox) / 8), s);
-    RootBox *rb = ptr<RootBox>(ctx->rootbox);
-    launch_bbox(pos, mass, n, ptr<double>(ctx->bbox_part), rb, s);
-    uint64_t *k = ptr<uint64_t>(ctx->key0), *ka = ptr<uint64_t>(ctx->key1);
-    uint32_t *v = ptr<uint32_t>(ctx->val0), *va = ptr<uint32_t>(ctx->val1);
-    launch_keys(pos, n, rb, k, v, s);
-    radix_sort(&k, &v, &ka, &va, n, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s);
-    launch_gather_particles(pos, mass, v, n, ptr<double4>(ctx->ps), ptr<uint32_t>(ctx->orig), s);
-    launch_octree_count(k, n, leaf_size, ptr<uint32_t>(ctx->emit), s);
-    scan_u32_to_i64(ptr<uint32_t>(ctx->emit), ptr<int64_t>(ctx->base), n,
-                    ptr<int64_t>(ctx->scan_ws), s);
-    HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, ptr<int64_t>(ctx->base) + n, 8,
-                                hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, &rb->bad, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    int32_t bad = 0;
-    memcpy(&bad, ctx->host_scalar + 1, 4);
-    if (bad) return fail(ctx, PETAR_E_INVALID, "non-finite position or mass, or negative mass");
-    int64_t n_nodes = ctx->host_scalar[0];
-    if (n_nodes < 1 || n_nodes >= (int64_t)kNone)
-        return fail(ctx, PETAR_E_INTERNAL, "cell count %lld out of range", (long long)n_nodes);
-
-    const size_t M = (size_t)n_nodes;
+petar_status alloc_build_b(petar_ctx *ctx, int64_t node_cap) {
+    const size_t M = (size_t)node_cap;
+    const int64_t n = ctx->n;
     TRY(ensure(ctx, ctx->nd_lo, M * sizeof(double4)));
     TRY(ensure(ctx, ctx->nd_hi, M * sizeof(double4)));
     TRY(ensure(ctx, ctx->nd_com, M * sizeof(double4)));
     TRY(ensure(ctx, ctx->nd_S, M * 6 * 8));
     TRY(ensure(ctx, ctx->nd_info, M * sizeof(uint4)));
-    TRY(ensure(ctx, ctx->nd_child, M * 8 * 4));
-    TRY(ensure(ctx, ctx->nd_parent, M * 4));
-    TRY(ensure(ctx, ctx->level_nodes, M * 4));
-    TRY(ensure(ctx, ctx->level_ws, (size_t)level_ws_elems(n_nodes) * 4));
-    ctx->n = n;
-    ctx->n_nodes = n_nodes;
-    ctx->sorted_key = k;
+    TRY(ensure(ctx, ctx->pre_info, M * sizeof(uint4)));
+    TRY(ensure(ctx, ctx->pre_parent, M * 4));
+    TRY(ensure(ctx, ctx->pre_nchild, M * 4));
+    TRY(ensure(ctx, ctx->new_of_old, M * 4));
+    TRY(ensure(ctx, ctx->lkey0, M * 8));
+    TRY(ensure(ctx, ctx->lkey1, M * 8));
+    TRY(ensure(ctx, ctx->lval0, M * 4));
+    TRY(ensure(ctx, ctx->lval1, M * 4));
+    TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(node_cap > n ? node_cap : n)));
+    int64_t lsort_scan = 256 * ((node_cap + 2047) / 2048);
+    TRY(ensure(ctx, ctx->scan_ws,
+               (size_t)scan_ws_elems(lsort_scan > n + 1 ? lsort_scan : n + 1) * 8));
+    return PETAR_OK;
+}
+
+// Phase A. The sorted keys end in key0 (8 passes).
+void enqueue_build_a(petar_ctx *ctx, const BuildArgs &a, hipStream_t s) {
+    zero_status(ctx, s);
+    const int n_boxes = a.n_sys > 0 ? a.n_sys : 1;
+    const int levels = a.n_sys > 0 ? kBatchLevels : kMaxLevel;
+    RootBox *rb = ptr<RootBox>(ctx->rootbox);
+    fill_i64(ptr<int64_t>(ctx->rootbox), 0, (int64_t)(sizeof(RootBox) / 8) * n_boxes, s);
+    uint64_t *k = ptr<uint64_t>(ctx->key0), *ka = ptr<uint64_t>(ctx->key1);
+    uint32_t *v = ptr<uint32_t>(ctx->val0), *va = ptr<uint32_t>(ctx->val1);
+    if (a.n_sys > 0) {
+        const int64_t *off = ptr<int64_t>(ctx->sys_off);
+        launch_bbox_systems(a.pos, a.mass, a.n, off, a.n_sys, rb, s);
+        launch_keys_systems(a.pos, a.n, off, a.n_sys, rb, k, v, s);
+    } else {
+        launch_bbox(a.pos, a.mass, a.n, ptr<double>(ctx->bbox_part), rb, s);
+        launch_keys(a.pos, a.n, rb, k, v, s);
+    }
+    radix_sort(&k, &v, &ka, &va, a.n, 8, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s);
+    launch_gather_particles(a.pos, a.mass, v, a.n, ptr<double4>(ctx->ps), ptr<uint32_t>(ctx->orig),
+                            s);
+    launch_octree_count(k, a.n, a.leaf_size, levels, ptr<uint32_t>(ctx->emit), s);
+    scan_u32_to_i64(ptr<uint32_t>(ctx->emit), ptr<int64_t>(ctx->base), a.n,
+                    ptr<int64_t>(ctx->scan_ws), s);
+}
+
+// Phase B with cell arrays of node_cap entries (the cell count is read on the
+// device; more cells than node_cap raise Status::cell_overflow).
+void enqueue_build_b(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap, hipStream_t s) {
+    const int levels = a.n_sys > 0 ? kBatchLevels : kMaxLevel;
     TreeDev t = tree_view(ctx);
-    fill_u32(t.nd_child, kNone, n_nodes * 8, s);
-    launch_octree_write(k, n, leaf_size, ptr<int64_t>(ctx->base), rb, t, s);
-    launch_level_buckets(t, ptr<uint32_t>(ctx->level_count), ptr<uint32_t>(ctx->level_off),
-                         ptr<uint32_t>(ctx->level_ws), ptr<uint32_t>(ctx->level_nodes), s);
-    for (int L = kMaxLevel; L >= 0; L--)
-        launch_moments_level(t, L, ptr<uint32_t>(ctx->level_off), ptr<uint32_t>(ctx->level_nodes),
-                             s);
-    launch_tree_summary(t, ptr<uint32_t>(ctx->level_count), ptr<Status>(ctx->status), s);
+    t.n_nodes = node_cap;
+    PreOrder pre = pre_view(ctx);
+    Status *st = ptr<Status>(ctx->status);
+    fill_u32(pre.nchild, 0, node_cap, s);
+    uint64_t *lk = ptr<uint64_t>(ctx->lkey0), *lka = ptr<uint64_t>(ctx->lkey1);
+    uint32_t *lv = ptr<uint32_t>(ctx->lval0), *lva = ptr<uint32_t>(ctx->lval1);
+    const uint64_t *k = ptr<uint64_t>(ctx->key0);
+    launch_octree_write(k, a.n, a.leaf_size, levels, ptr<int64_t>(ctx->base), pre, lk, lv,
+                        node_cap, st, s);
+    radix_sort(&lk, &lv, &lka, &lva, node_cap, 1, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s,
+               t.n_nodes_dev);
+    launch_relayout(lv, pre, ptr<RootBox>(ctx->rootbox), k, levels, t,
+                    ptr<uint32_t>(ctx->level_off), s);
+    for (int L = levels; L >= 0; L--) launch_moments_level(t, L, s);
+    launch_tree_summary(t, st, s);
+}
+
+void set_tree_state(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap) {
+    ctx->n = a.n;
+    ctx->n_nodes = node_cap;
+    ctx->levels = a.n_sys > 0 ? kBatchLevels : kMaxLevel;
+    ctx->theta = a.theta;
+    ctx->leaf_size = a.leaf_size;
+    ctx->n_sys = a.n_sys > 0 ? a.n_sys : 1;
+}
+
+petar_status copy_offsets(petar_ctx *ctx, const BuildArgs &a, hipStream_t s) {
+    if (a.n_sys > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->sys_off.p, a.sys_off, (size_t)(a.n_sys + 1) * 8,
+                                    hipMemcpyHostToDevice, s));
+    return PETAR_OK;
+}
+
+petar_status build_eager(petar_ctx *ctx, const BuildArgs &a) {
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    ctx->have_tree = false;
+    ctx->have_counts = false;
+    ctx->n = a.n;
+    TRY(alloc_build_a(ctx, a));
+    TRY(copy_offsets(ctx, a, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
+    enqueue_build_a(ctx, a, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, ptr<int64_t>(ctx->base) + a.n, 8,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, &ptr<RootBox>(ctx->rootbox)->bad, 4,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    int32_t bad = 0;
+    memcpy(&bad, ctx->host_scalar + 1, 4);
+    if (bad) return fail(ctx, PETAR_E_INVALID, "non-finite position or mass, or negative mass");
+    const int64_t n_nodes = ctx->host_scalar[0];
+    if (n_nodes < 1 || n_nodes >= (int64_t)kNone)
+        return fail(ctx, PETAR_E_INTERNAL, "cell count %lld out of range", (long long)n_nodes);
+    TRY(alloc_build_b(ctx, n_nodes));
+    enqueue_build_b(ctx, a, n_nodes, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
-    TRY(read_status(ctx));
+    TRY(read_status(ctx, s));
+    set_tree_state(ctx, a, n_nodes);
     ctx->have_tree = true;
-    ctx->theta = theta;
-    ctx->leaf_size = leaf_size;
     ctx->stats = petar_stats{};
-    ctx->stats.n = n;
+    ctx->stats.n = a.n;
     ctx->stats.n_nodes = n_nodes;
     ctx->stats.n_leaves = ctx->host_status->n_leaves;
     ctx->stats.max_level = ctx->host_status->max_level;
@@ -368,23 +480,21 @@ petar_status petar_tree_build(petar_ctx *ctx, const double *pos, const double *m
     return PETAR_OK;
 }
 
-petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in,
-                              const double *r_out, const double *r_search, double *acc,
-                              double *pot, petar_nblist *nb) {
-    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
-    if (const char *m = check_force_args(group_size, r_in, r_out, r_search, acc, pot, nb))
-        return fail(ctx, PETAR_E_INVALID, "%s", m);
-    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
-    if (!ctx->have_tree) return fail(ctx, PETAR_E_STATE, "petar_tree_build has not succeeded");
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
+// ---------------------------------------------------------------- force
+struct ForceArgs {
+    int group_size;
+    const double *r_in, *r_out, *r_search;
+    double *acc, *pot;
+    petar_nblist *nb;
+};
+
+petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
     const int64_t n = ctx->n, n_nodes = ctx->n_nodes;
     const int prec = ctx->params.precision, ipl = ctx->params.i_per_lane;
     int &fw = ctx->force_waves[prec][ipl];
     if (fw == 0) fw = force_resident_waves(prec, ipl, ctx->device);
-    if (nb && ctx->nb_waves == 0) ctx->nb_waves = nb_resident_waves(ctx->device);
+    if (a.nb && ctx->nb_waves == 0) ctx->nb_waves = nb_resident_waves(ctx->device);
     int spill_waves = fw > ctx->nb_waves ? fw : ctx->nb_waves;
-
     TRY(ensure(ctx, ctx->rr, (size_t)n * sizeof(double2)));
     TRY(ensure(ctx, ctx->rsk, (size_t)n * 8));
     TRY(ensure(ctx, ctx->gflag, (size_t)(n_nodes + 1) * 4));
@@ -393,22 +503,38 @@ petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in
     TRY(ensure(ctx, ctx->queue, 64 * 4));
     TRY(ensure(ctx, ctx->spill, (size_t)spill_waves * (size_t)kSpillCap * 4));
     if (ctx->params.record_counts) TRY(ensure(ctx, ctx->counts, (size_t)n * 4 * 4));
-    if (nb) TRY(ensure(ctx, ctx->nbcnt, (size_t)(n + 1) * 4));
+    if (a.nb) {
+        TRY(ensure(ctx, ctx->nbcnt, (size_t)(n + 1) * 4));
+        // near-leaf records of the force walk; grown after a call overflowed
+        uint64_t want = (uint64_t)n_nodes * 2 + 4096;
+        if (want < ctx->nbrec_cap) want = ctx->nbrec_cap;
+        if (want > 0xffffffffull) want = 0xffffffffull;
+        TRY(ensure(ctx, ctx->nbrec, (size_t)want * sizeof(uint4)));
+        ctx->nbrec_cap = (uint32_t)want;
+    }
     TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n_nodes + n + 1) * 8));
+    return PETAR_OK;
+}
 
+// Every launch of the force call; no host synchronisation (capturable).
+// `timed` records the stage events (not inside a captured graph).
+void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed) {
+    const int64_t n = ctx->n, n_nodes = ctx->n_nodes;
+    const int prec = ctx->params.precision, ipl = ctx->params.i_per_lane;
+    const int fw = ctx->force_waves[prec][ipl];
     TreeDev t = tree_view(ctx);
+    PreOrder pre = pre_view(ctx);
     Status *st = ptr<Status>(ctx->status);
     uint32_t *queue = ptr<uint32_t>(ctx->queue);
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
-    zero_status(ctx);
+    if (timed) (void)hipEventRecord(ctx->ev[2], s);
+    zero_force_status(ctx, s);
     fill_u32(queue, 0, 64, s);
-    launch_gather_radii(r_in, r_out, r_search, t, st, s);
-    for (int L = kMaxLevel; L >= 0; L--)
-        launch_rsmax_level(t, L, ptr<uint32_t>(ctx->level_off), ptr<uint32_t>(ctx->level_nodes), s);
-    launch_group_flags(t, group_size, ptr<uint32_t>(ctx->gflag), s);
+    launch_gather_radii(a.r_in, a.r_out, a.r_search, t, st, s);
+    for (int L = ctx->levels; L >= 0; L--) launch_rsmax_level(t, L, s);
+    launch_group_flags(pre, t, a.group_size, ptr<uint32_t>(ctx->gflag), s);
     scan_u32_to_u32(ptr<uint32_t>(ctx->gflag), ptr<uint32_t>(ctx->gpos), n_nodes,
                     ptr<int64_t>(ctx->scan_ws), s);
-    launch_group_compact(t, ptr<uint32_t>(ctx->gflag), ptr<uint32_t>(ctx->gpos),
+    launch_group_compact(pre, t, ptr<uint32_t>(ctx->gflag), ptr<uint32_t>(ctx->gpos),
                          ptr<uint32_t>(ctx->groups), st, s);
 
     ForceLaunch f;
@@ -418,34 +544,52 @@ petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in
     f.st = st;
     f.th2 = ctx->theta * ctx->theta;
     f.G = ctx->params.G;
-    f.acc = acc;
-    f.pot = pot;
+    f.acc = a.acc;
+    f.pot = a.pot;
     f.spill = ptr<uint32_t>(ctx->spill);
     f.queue = queue;
     f.counts = ctx->params.record_counts ? ptr<int32_t>(ctx->counts) : nullptr;
+    f.nb_rec = a.nb ? ptr<uint4>(ctx->nbrec) : nullptr;
+    f.nb_rec_count = queue + 16;
+    f.nb_rec_cap = a.nb ? ctx->nbrec_cap : 0;
     f.precision = prec;
     f.ipl = ipl;
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[4], s));
+    if (timed) (void)hipEventRecord(ctx->ev[4], s);
     launch_force(f, fw, s);
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[5], s));
-    if (nb) {
-        HIP_TRY(ctx, hipEventRecord(ctx->ev[6], s));
-        fill_u32(ptr<uint32_t>(ctx->nbcnt), 0, n + 1, s);
-        launch_nb_count(t, f.groups, st, ptr<uint32_t>(ctx->nbcnt), f.spill, queue + 8,
+    if (timed) (void)hipEventRecord(ctx->ev[5], s);
+    if (a.nb) {
+        // Passes over the near leaves handed over by the force walk; the
+        // walk-based passes take over (on the device) if the records overflowed.
+        petar_nblist *nb = a.nb;
+        if (timed) (void)hipEventRecord(ctx->ev[6], s);
+        uint32_t *cnt = ptr<uint32_t>(ctx->nbcnt);
+        fill_u32(cnt, 0, n + 1, s);
+        launch_nb_count_rec(t, f.nb_rec, f.nb_rec_count, f.nb_rec_cap, st, cnt, s);
+        launch_nb_count(t, f.groups, st, cnt, f.spill, queue + 8, f.nb_rec_count, f.nb_rec_cap,
                         ctx->nb_waves, s);
-        scan_u32_to_i64(ptr<uint32_t>(ctx->nbcnt), nb->offsets_dev, n, ptr<int64_t>(ctx->scan_ws),
-                        s);
+        scan_u32_to_i64(cnt, nb->offsets_dev, n, ptr<int64_t>(ctx->scan_ws), s);
+        fill_u32(cnt, 0, n + 1, s);
+        launch_nb_write_rec(t, f.nb_rec, f.nb_rec_count, f.nb_rec_cap, st, nb->offsets_dev, cnt,
+                            nb->idx_dev, nb->capacity, s);
         launch_nb_write(t, f.groups, st, nb->offsets_dev, nb->idx_dev, nb->capacity, f.spill,
-                        queue + 9, ctx->nb_waves, s);
-        launch_nb_sort(nb->offsets_dev, nb->idx_dev, n, nb->capacity, st,
-                       ptr<uint32_t>(ctx->nbcnt), queue + 10, s);
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, nb->offsets_dev + n, 8,
+                        queue + 9, f.nb_rec_count, f.nb_rec_cap, ctx->nb_waves, s);
+        launch_nb_sort(nb->offsets_dev, nb->idx_dev, n, nb->capacity, st, cnt, queue + 10, s);
+        if (timed) (void)hipEventRecord(ctx->ev[7], s);
+    }
+    if (timed) (void)hipEventRecord(ctx->ev[3], s);
+}
+
+// Reads the status words after a force call and fills the statistics.
+petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed) {
+    uint32_t *queue = ptr<uint32_t>(ctx->queue);
+    if (a.nb) {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, a.nb->offsets_dev + ctx->n, 8,
                                     hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipEventRecord(ctx->ev[7], s));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 2, queue + 16, 4, hipMemcpyDeviceToHost,
+                                    s));
     }
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
-    TRY(read_status(ctx));
+    TRY(read_status(ctx, s));
     const Status &h = *ctx->host_status;
     if (h.invalid_radii)
         return fail(ctx, PETAR_E_INVALID,
@@ -457,18 +601,174 @@ petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in
     ctx->stats.inter_pc = (int64_t)h.inter[0];
     ctx->stats.inter_far = (int64_t)h.inter[1];
     ctx->stats.inter_near = (int64_t)h.inter[2];
-    ctx->stats.ms_force = elapsed(ctx->ev[2], ctx->ev[3]);
-    ctx->stats.ms_force_kernel = elapsed(ctx->ev[4], ctx->ev[5]);
-    ctx->stats.ms_nb = nb ? elapsed(ctx->ev[6], ctx->ev[7]) : 0.0;
+    if (timed) {
+        ctx->stats.ms_force = elapsed(ctx->ev[2], ctx->ev[3]);
+        ctx->stats.ms_force_kernel = elapsed(ctx->ev[4], ctx->ev[5]);
+        ctx->stats.ms_nb = a.nb ? elapsed(ctx->ev[6], ctx->ev[7]) : 0.0;
+    }
     ctx->stats.workspace_bytes = ctx->ws_bytes;
-    if (nb) {
-        nb->required = ctx->host_scalar[0];
-        ctx->stats.nb_total = nb->required;
-        if (nb->required > nb->capacity)
+    if (a.nb) {
+        uint32_t nrec = 0;
+        memcpy(&nrec, ctx->host_scalar + 2, 4);
+        if (nrec > ctx->nbrec_cap) {  // grow the records for the next call
+            uint64_t want = (uint64_t)nrec + nrec / 4;
+            ctx->nbrec_cap = (uint32_t)(want > 0xffffffffull ? 0xffffffffull : want);
+            ctx->graph_stale = true;
+        }
+        a.nb->required = ctx->host_scalar[0];
+        ctx->stats.nb_total = a.nb->required;
+        if (a.nb->required > a.nb->capacity)
             return fail(ctx, PETAR_E_NB_OVERFLOW, "neighbour capacity %lld < required %lld",
-                        (long long)nb->capacity, (long long)nb->required);
+                        (long long)a.nb->capacity, (long long)a.nb->required);
     }
     return PETAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+petar_status petar_tree_build(petar_ctx *ctx, const double *pos, const double *mass, int64_t n,
+                              double theta, int leaf_size) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_build_args(pos, mass, n, theta, leaf_size))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    BuildArgs a{pos, mass, n, theta, leaf_size, 0, nullptr};
+    return build_eager(ctx, a);
+}
+
+petar_status petar_batch_build(petar_ctx *ctx, int n_sys, const int64_t *sys_offsets,
+                               const double *pos, const double *mass, double theta,
+                               int leaf_size) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_batch_args(n_sys, sys_offsets))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    const int64_t n = sys_offsets[n_sys];
+    if (const char *m = check_build_args(pos, mass, n, theta, leaf_size))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    BuildArgs a{pos, mass, n, theta, leaf_size, n_sys, sys_offsets};
+    return build_eager(ctx, a);
+}
+
+petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in,
+                              const double *r_out, const double *r_search, double *acc,
+                              double *pot, petar_nblist *nb) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_force_args(group_size, r_in, r_out, r_search, acc, pot, nb))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    if (!ctx->have_tree) return fail(ctx, PETAR_E_STATE, "petar_tree_build has not succeeded");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ForceArgs a{group_size, r_in, r_out, r_search, acc, pot, nb};
+    TRY(alloc_force(ctx, a));
+    enqueue_force(ctx, a, ctx->stream, true);
+    return finish_force(ctx, a, ctx->stream, true);
+}
+
+petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offsets,
+                              const double *pos, const double *mass, int64_t N, double theta,
+                              int leaf_size, int group_size, const double *r_in,
+                              const double *r_out, const double *r_search, double *acc,
+                              double *pot, petar_nblist *nb) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (n_sys < 0) return fail(ctx, PETAR_E_INVALID, "n_sys must be >= 0");
+    if (n_sys > 0) {
+        if (const char *m = check_batch_args(n_sys, sys_offsets))
+            return fail(ctx, PETAR_E_INVALID, "%s", m);
+        N = sys_offsets[n_sys];
+    }
+    if (const char *m = check_build_args(pos, mass, N, theta, leaf_size))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (const char *m = check_force_args(group_size, r_in, r_out, r_search, acc, pot, nb))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    BuildArgs ba{pos, mass, N, theta, leaf_size, n_sys, sys_offsets};
+    ForceArgs fa{group_size, r_in, r_out, r_search, acc, pot, nb};
+
+    // everything the captured launches depend on
+    std::vector<int64_t> key = {(int64_t)(intptr_t)pos, (int64_t)(intptr_t)mass, N, n_sys,
+                                leaf_size, group_size, (int64_t)(intptr_t)r_in,
+                                (int64_t)(intptr_t)r_out, (int64_t)(intptr_t)r_search,
+                                (int64_t)(intptr_t)acc, (int64_t)(intptr_t)pot,
+                                nb ? (int64_t)(intptr_t)nb->offsets_dev : 0,
+                                nb ? (int64_t)(intptr_t)nb->idx_dev : 0, nb ? nb->capacity : -1,
+                                ctx->params.precision, ctx->params.i_per_lane,
+                                ctx->params.record_counts};
+    double th = theta, g = ctx->params.G;
+    int64_t bits;
+    memcpy(&bits, &th, 8);
+    key.push_back(bits);
+    memcpy(&bits, &g, 8);
+    key.push_back(bits);
+    for (int sIdx = 0; sIdx <= n_sys && n_sys > 0; sIdx++) key.push_back(sys_offsets[sIdx]);
+
+    if (ctx->graph_stale || !ctx->gexec || key != ctx->graph_key) {
+        // eager step (its results are this call's), then capture with room for
+        // twice as many cells as this tree has
+        drop_graph(ctx);
+        TRY(build_eager(ctx, ba));
+        TRY(alloc_force(ctx, fa));
+        enqueue_force(ctx, fa, ctx->stream, true);
+        petar_status st = finish_force(ctx, fa, ctx->stream, true);
+        if (st != PETAR_OK && st != PETAR_E_NB_OVERFLOW) return st;
+        const int64_t node_cap = 2 * ctx->n_nodes + 1024;
+        ctx->have_tree = false;  // the arrays may move; the next replay rebuilds them
+        TRY(alloc_build_b(ctx, node_cap));
+        const int64_t n_nodes_now = ctx->n_nodes;
+        ctx->n_nodes = node_cap;
+        TRY(alloc_force(ctx, fa));
+        ctx->n_nodes = n_nodes_now;
+        if (!ctx->cap_stream)
+            HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = ctx->cap_stream;
+        HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        enqueue_build_a(ctx, ba, cs);
+        enqueue_build_b(ctx, ba, node_cap, cs);
+        set_tree_state(ctx, ba, node_cap);
+        enqueue_force(ctx, fa, cs, false);
+        hipError_t e = hipStreamEndCapture(cs, &ctx->graph);
+        if (e == hipSuccess) e = hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(ctx);
+            return fail(ctx, PETAR_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        }
+        ctx->graph_key = key;
+        ctx->node_cap = node_cap;
+        ctx->graph_stale = false;
+        ctx->n_nodes = n_nodes_now;
+        ctx->stats.ms_graph = 0.0;
+        return st;
+    }
+    // replay
+    hipStream_t s = ctx->stream;
+    set_tree_state(ctx, ba, ctx->node_cap);
+    ctx->have_tree = false;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
+    HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
+    petar_status st = finish_force(ctx, fa, s, false);
+    const Status &h = *ctx->host_status;
+    if (h.cell_overflow) {  // tree outgrew the captured capacity: redo eagerly, recapture next
+        ctx->graph_stale = true;
+        TRY(build_eager(ctx, ba));
+        TRY(alloc_force(ctx, fa));
+        enqueue_force(ctx, fa, ctx->stream, true);
+        return finish_force(ctx, fa, ctx->stream, true);
+    }
+    ctx->have_tree = true;
+    ctx->stats.n = N;
+    ctx->stats.n_nodes = h.n_nodes;
+    ctx->stats.n_leaves = h.n_leaves;
+    ctx->stats.max_level = h.max_level;
+    ctx->stats.ms_build = 0.0;
+    ctx->stats.ms_force = 0.0;
+    ctx->stats.ms_force_kernel = 0.0;
+    ctx->stats.ms_nb = 0.0;
+    ctx->stats.ms_graph = elapsed(ctx->ev[0], ctx->ev[1]);
+    return st;
 }
 
 petar_status petar_copy_counts(petar_ctx *ctx, int32_t *counts) {

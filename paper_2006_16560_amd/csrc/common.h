@@ -4,15 +4,14 @@
 //                               rr[k]   = (r_in, r_out)     double2
 //                               rsk[k]  = r_search          double
 //                               orig[k] = input index       uint32
-//   octree cells in depth-first pre-order (children follow their parent,
-//   a cell's subtree is the index range [c, skip[c])):
+//   octree cells in level order (root first; inside a level in Morton
+//   order, so the children of a cell are contiguous):
 //                               nd_lo[c]  = (lo.x, lo.y, lo.z, max r_search)
 //                               nd_hi[c]  = (hi.x, hi.y, hi.z, side)
 //                               nd_com[c] = (com.x, com.y, com.z, M)
 //                               nd_S[c*6 + 0..5] = second moment about com
 //                                        (xx, yy, zz, xy, xz, yz)
-//                               nd_info[c] = (first particle, count, flags, skip)
-//                               nd_child[c*8 + octant] (kNone if empty)
+//                               nd_info[c] = (first particle, count, flags, first child)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,10 +19,15 @@
 
 namespace petar {
 
-constexpr int kMaxLevel = 21;           // 21 bits per axis, 63-bit keys
+constexpr int kMaxLevel = 21;           // 21 bits per axis, 63-bit keys (one system)
+constexpr int kBatchLevels = 18;        // per-system depth in batched mode
+constexpr int kMaxSystems = 512;        // batched mode: system id above 54 key bits
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kWave = 64;
-constexpr uint32_t kLeafFlag = 1u;      // nd_info.z bit 0; level in bits 1..5
+// nd_info.z: bit 0 leaf, bits 1..5 level, bits 8..11 number of children.
+constexpr uint32_t kLeafFlag = 1u;
+__host__ __device__ __forceinline__ int info_level(uint32_t z) { return (int)((z >> 1) & 31u); }
+__host__ __device__ __forceinline__ int info_nchild(uint32_t z) { return (int)((z >> 8) & 15u); }
 
 // Root cube of the particle set (device-resident, written by the bbox pass).
 struct RootBox {
@@ -34,19 +38,23 @@ struct RootBox {
     int32_t pad;
 };
 
-// Status words read back once per call.
+// Status words read back once per call. The force fields come first so a
+// force call can clear them without touching the build fields.
 struct Status {
+    // force
     int32_t invalid_radii;   // non-finite or out-of-order radii
     int32_t stack_overflow;  // walk stack exceeded its capacity
-    int32_t nb_overflow;     // neighbour capacity too small
-    int32_t pad;
     unsigned long long inter[3];  // pc, far, near interactions
     int64_t n_groups;
     int64_t nb_total;
+    // build
+    int32_t cell_overflow;   // more cells than the preallocated capacity (captured graphs)
+    int32_t pad;
     int64_t n_nodes;
     int64_t n_leaves;
     int64_t max_level;
 };
+constexpr int kStatusForceWords = 6;  // int64 words of the force fields
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -93,8 +101,9 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// ---- Morton keys: digit of level l (1..21) is bits 3(21-l)..3(21-l)+2,
-// ordered (x, y, z) from most to least significant.
+// ---- Morton keys. With L levels the octal digit of level l (1..L) is bits
+// 3(L-l)..3(L-l)+2, ordered (x, y, z) from most to least significant; bits
+// from 3L upwards hold the system id (batched mode; 0 for one system).
 __device__ __forceinline__ uint64_t spread3(uint64_t v) {
     v &= 0x1fffffull;
     v = (v | (v << 32)) & 0x1f00000000ffffull;
@@ -105,16 +114,18 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
     return v;
 }
 
-__device__ __forceinline__ uint64_t key_prefix(uint64_t key, int level) {
-    // level 0 -> 0 for every key (bit 63 is always clear)
-    return key >> (3 * (kMaxLevel - level));
+// Prefix identifying the level-`level` cell of a key (level 0: the system).
+__device__ __forceinline__ uint64_t key_prefix(uint64_t key, int level, int levels) {
+    return key >> (3 * (levels - level));
 }
 
-// Number of leading octal digits two keys share (0..21).
-__device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
+// Number of leading octal digits two keys share (0..levels), or -1 when they
+// belong to different systems.
+__device__ __forceinline__ int common_digits(uint64_t a, uint64_t b, int levels) {
     uint64_t x = a ^ b;
-    if (x == 0) return kMaxLevel;
-    return (__clzll((long long)x) - 1) / 3;
+    if (x == 0) return levels;
+    if (x >> (3 * levels)) return -1;
+    return (__clzll((long long)x) - (64 - 3 * levels)) / 3;
 }
 
 // ---- FP64 geometry of the walk, rounded exactly as written (no contraction).

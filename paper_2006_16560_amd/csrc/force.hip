@@ -1,5 +1,5 @@
 // Long-range force kernel: group-wise tree walk fused with the interaction
-// passes, one wavefront per i-group, persistent over a device work queue.
+// passes, one wavefront per i-group, persistent over per-XCD work queues.
 //
 // Per group the walk sorts every cell it reaches into
 //   multipole (PC): the cell is inside the opening angle and no pair can be
@@ -7,10 +7,11 @@
 //   far leaf:       opened leaf out of search range -> Newtonian pairs;
 //   near leaf:      opened leaf within search range -> pairs weighted by
 //                   the changeover functions (1 - K) and (1 - W)/r.
-// Cells are buffered in LDS and, when a buffer holds a tile, staged as
-// FP32 (or FP64) records relative to the group centre and broadcast to all
-// lanes; each lane holds 1, 2 or 4 target particles. In mixed precision the
-// per-tile FP32 partial sums are folded into Neumaier-compensated FP32
+// Cells are buffered in LDS; a full buffer is staged as records relative to
+// the group centre (FP32 in mixed mode, FP64 otherwise) and broadcast from
+// LDS to all lanes. A lane holds up to IPL targets; small groups spread one
+// target over S lanes that split the j loop. In mixed precision the FP32
+// per-tile partial sums are folded into Neumaier-compensated FP32
 // accumulators and converted to FP64 at the end.
 #include "launch.h"
 #include "walk.h"
@@ -21,37 +22,41 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWavesPerBlock = kThreads / kWave;
+constexpr float kFarAway = 1e18f;  // position of padding records (zero mass)
 
 template <typename R>
-struct PcRec {  // centre of mass (group-relative), mass, traceless quadrupole
-    R x, y, z, m;
-    R qxx, qyy, qzz, qxy;
-    R qxz, qyz, pad0, pad1;
+struct Vec;
+template <>
+struct Vec<float> {
+    using v4 = float4;
+    using v2 = float2;
 };
-template <typename R>
-struct JRec {
-    R x, y, z, m;
-};
-template <typename R>
-struct NRec {
-    R x, y, z, m;
-    R rin, rout;
-    uint32_t k, pad;
+template <>
+struct Vec<double> {
+    using v4 = double4;
+    using v2 = double2;
 };
 
+// One tile of up to 64 sources, structure of arrays so that every read is an
+// aligned 16/8/4-byte broadcast:
+//   PC:   a = (x, y, z, M), b = (A'xx, A'yy, A'zz, A'xy), c = (A'xz, A'yz)
+//   far:  a = (x, y, z, m)
+//   near: a = (x, y, z, m), c = (r_in, r_out), k = index in Morton order
 template <typename R>
-union Tile {
-    PcRec<R> pc[kWave];
-    JRec<R> j[kWave];
-    NRec<R> nr[kWave];
+struct Tile {
+    typename Vec<R>::v4 a[kWave];
+    typename Vec<R>::v4 b[kWave];
+    typename Vec<R>::v2 c[kWave];
+    uint32_t k[kWave];
 };
 
 template <typename R>
 struct WaveLds {
     uint32_t stack[kStackLds];
     uint32_t pc_buf[kWave];
-    uint32_t far_start[kWave], far_cnt[kWave], far_pre[kWave];
-    uint32_t near_start[kWave], near_cnt[kWave], near_pre[kWave];
+    uint32_t far_start[kWave], far_pre[kWave];
+    uint32_t near_start[kWave], near_pre[kWave];
+    GroupGeom g;
     Tile<R> tile;
 };
 
@@ -110,76 +115,195 @@ __device__ __forceinline__ void combine_split(Acc<double> &a, int W) {
 template <typename R, int IPL>
 struct Targets {
     R x[IPL], y[IPL], z[IPL], rin[IPL], rout[IPL];
-    uint32_t k[IPL];
-    bool valid[IPL];
+    uint32_t k[IPL];  // index in Morton order, kNone for an empty slot
     Acc<R> acc[IPL];
 };
 
-template <typename R, int IPL>
-__device__ __forceinline__ void fold(Targets<R, IPL> &T, const R (&ax)[IPL], const R (&ay)[IPL],
-                                     const R (&az)[IPL], const R (&ph)[IPL]) {
+// Work layout of the current chunk of targets (wave-uniform except sl).
+struct Layout {
+    int nu;  // target slots in use per lane (1..IPL)
+    int S;   // lanes sharing a target (j loop split), 1 when nu > 1
+    int sl;  // this lane's j subset
+};
+
+// ---------------------------------------------------------------- loops
+// Each loop runs uniformly over a tile padded to a multiple of pad_of(S):
+// S lanes share a target and take every S-th source; F sources per lane
+// are unrolled per iteration.
+
+__host__ __device__ constexpr int pad_of(int S) { return S >= 4 ? S : 4; }
+
+template <typename R, int U>
+struct Partial {
+    R ax[U], ay[U], az[U], ph[U];
+    __device__ void zero() {
 #pragma unroll
-    for (int u = 0; u < IPL; u++) {
-        T.acc[u].add(0, ax[u]);
-        T.acc[u].add(1, ay[u]);
-        T.acc[u].add(2, az[u]);
-        T.acc[u].add(3, ph[u]);
+        for (int u = 0; u < U; u++) ax[u] = ay[u] = az[u] = ph[u] = (R)0;
     }
+};
+
+template <typename R, int IPL, int U>
+__device__ __forceinline__ void pc_one(const typename Vec<R>::v4 &a, const typename Vec<R>::v4 &b,
+                                       const typename Vec<R>::v2 &c, const Targets<R, IPL> &T,
+                                       Partial<R, U> &P) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        R Rx = T.x[u] - a.x, Ry = T.y[u] - a.y, Rz = T.z[u] - a.z;
+        R r2 = Rx * Rx + Ry * Ry + Rz * Rz;
+        R ri = rsq(r2);
+        R ri2 = ri * ri;
+        R qx = b.x * Rx + b.w * Ry + c.x * Rz;
+        R qy = b.w * Rx + b.y * Ry + c.y * Rz;
+        R qz = c.x * Rx + c.y * Ry + b.z * Rz;
+        R rqr = Rx * qx + Ry * qy + Rz * qz;
+        R ri3 = ri * ri2;
+        R ri5 = ri3 * ri2;
+        R mri = a.w * ri;
+        R t = rqr * ri5;                  // R.A'R / r^5
+        R t7 = t * ri2;                   // R.A'R / r^7
+        R coef = (R)5 * t7 + mri * ri2;   // M/r^3 + 5 R.A'R/r^7
+        R two5 = ri5 + ri5;
+        // a += (2/r^5) A'R - coef R ;  phi -= M/r + R.A'R/r^5
+        P.ax[u] += two5 * qx;
+        P.ay[u] += two5 * qy;
+        P.az[u] += two5 * qz;
+        P.ax[u] -= coef * Rx;
+        P.ay[u] -= coef * Ry;
+        P.az[u] -= coef * Rz;
+        P.ph[u] -= mri;
+        P.ph[u] -= t;
+    }
+}
+
+template <typename R, int IPL, int U>
+__device__ __forceinline__ void far_one(const typename Vec<R>::v4 &p, const Targets<R, IPL> &T,
+                                        Partial<R, U> &P) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        R dx = p.x - T.x[u], dy = p.y - T.y[u], dz = p.z - T.z[u];
+        R r2 = dx * dx + dy * dy + dz * dz;
+        R ri = rsq(r2);
+        R mri = p.w * ri;
+        R mri3 = mri * ri * ri;
+        P.ax[u] += mri3 * dx;
+        P.ay[u] += mri3 * dy;
+        P.az[u] += mri3 * dz;
+        P.ph[u] -= mri;
+    }
+}
+
+template <typename R, int IPL, int U>
+__device__ __forceinline__ void near_one(const typename Vec<R>::v4 &p,
+                                         const typename Vec<R>::v2 &rr, uint32_t kj,
+                                         const Targets<R, IPL> &T, Partial<R, U> &P) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        R dx = p.x - T.x[u], dy = p.y - T.y[u], dz = p.z - T.z[u];
+        R r2 = dx * dx + dy * dy + dz * dz;
+        R rin = T.rin[u] > rr.x ? T.rin[u] : rr.x;
+        R rout = T.rout[u] > rr.y ? T.rout[u] : rr.y;
+        R ri = r2 > (R)0 ? rsq(r2) : (R)0;
+        R r = r2 * ri;
+        R dr = rout - rin;
+        R sum = rout + rin;
+        R x = (r - rin) * rcp(dr);
+        R lam = dr * rcp(sum);
+        R xc = x < (R)0 ? (R)0 : (x > (R)1 ? (R)1 : x);
+        R x2 = xc * xc, x4 = x2 * x2;
+        R xm = xc - (R)1, xm2 = xm * xm;
+        // 1 - K(x) = x^4 [(35 - 84x + 70x^2 - 20x^3) - 35 Lambda (x-1)^4]
+        R fw = x4 * (((R)35 + xc * ((R)-84 + xc * ((R)70 - (R)20 * xc))) -
+                     (R)35 * lam * xm2 * xm2);
+        // (1 - W)/r = 2/(r_in + r_out) - Lambda x^5 (14 - 28x + 20x^2 - 5x^3)/r
+        R pw_in = (R)2 * rcp(sum) -
+                  lam * x4 * xc * ((R)14 + xc * ((R)-28 + xc * ((R)20 - (R)5 * xc))) * ri;
+        R pw = x >= (R)1 ? ri : pw_in;
+        bool self = kj == T.k[u];
+        fw = self ? (R)0 : fw;
+        pw = self ? (R)0 : pw;
+        R mf = p.w * fw * ri * ri * ri;
+        P.ax[u] += mf * dx;
+        P.ay[u] += mf * dy;
+        P.az[u] += mf * dz;
+        P.ph[u] -= p.w * pw;
+    }
+}
+
+enum { kTilePc = 0, kTileFar = 1, kTileNear = 2 };
+
+// mpad is a multiple of pad_of(S); F sources per lane per iteration.
+template <int KIND, int U, int S, typename R, int IPL>
+__device__ void loop_kind(const Tile<R> &tile, int mpad, int sl, Targets<R, IPL> &T) {
+    constexpr int F = KIND == kTileFar ? pad_of(S) / S : (KIND == kTilePc && S <= 2 ? 2 : 1);
+    Partial<R, U> P;
+    P.zero();
+    for (int jj = 0; jj < mpad; jj += F * S) {
+#pragma unroll
+        for (int f = 0; f < F; f++) {
+            const int j = jj + f * S + sl;
+            if (KIND == kTilePc) pc_one<R, IPL, U>(tile.a[j], tile.b[j], tile.c[j], T, P);
+            if (KIND == kTileFar) far_one<R, IPL, U>(tile.a[j], T, P);
+            if (KIND == kTileNear) near_one<R, IPL, U>(tile.a[j], tile.c[j], tile.k[j], T, P);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        T.acc[u].add(0, P.ax[u]);
+        T.acc[u].add(1, P.ay[u]);
+        T.acc[u].add(2, P.az[u]);
+        T.acc[u].add(3, P.ph[u]);
+    }
+}
+
+// Runs the loop of a staged tile with the number of target slots in use and
+// the split factor (both wave-uniform).
+template <int KIND, typename R, int IPL>
+__device__ __forceinline__ void run_tile(const Tile<R> &tile, int mpad, const Layout &ly,
+                                         Targets<R, IPL> &T) {
+    constexpr int U2 = IPL >= 2 ? 2 : 1;
+    if (IPL > 2 && ly.nu > 2)
+        loop_kind<KIND, IPL, 1>(tile, mpad, ly.sl, T);
+    else if (IPL >= 2 && ly.nu == 2)
+        loop_kind<KIND, U2, 1>(tile, mpad, ly.sl, T);
+    else if (ly.S == 1)
+        loop_kind<KIND, 1, 1>(tile, mpad, ly.sl, T);
+    else if (ly.S == 2)
+        loop_kind<KIND, 1, 2>(tile, mpad, ly.sl, T);
+    else if (ly.S == 4)
+        loop_kind<KIND, 1, 4>(tile, mpad, ly.sl, T);
+    else
+        loop_kind<KIND, 1, 8>(tile, mpad, ly.sl, T);
+}
+
+__device__ __forceinline__ int pad_to(int m, int S) {
+    const int q = pad_of(S);
+    return (m + q - 1) / q * q;
 }
 
 // ---- multipole tile
 template <typename R, int IPL>
-__device__ void flush_pc(WaveLds<R> &L, int npc, const ForceLaunch &f, const GroupGeom &G,
-                         Targets<R, IPL> &T, int S, int sl) {
+__device__ void flush_pc(WaveLds<R> &L, int npc, const ForceLaunch &f, const Layout &ly,
+                         Targets<R, IPL> &T) {
     wave_sync();
     const int lane = lane_id();
+    const int mpad = pad_to(npc, ly.S);
     if (lane < npc) {
         uint32_t c = L.pc_buf[lane];
         double4 cm = f.t.nd_com[c];
         const double *S = f.t.nd_S + (int64_t)c * 6;
         double tr = S[0] + S[1] + S[2];
-        PcRec<R> r;
-        r.x = (R)(cm.x - G.c[0]);
-        r.y = (R)(cm.y - G.c[1]);
-        r.z = (R)(cm.z - G.c[2]);
-        r.m = (R)cm.w;
-        r.qxx = (R)(1.5 * S[0] - 0.5 * tr);
-        r.qyy = (R)(1.5 * S[1] - 0.5 * tr);
-        r.qzz = (R)(1.5 * S[2] - 0.5 * tr);
-        r.qxy = (R)(1.5 * S[3]);
-        r.qxz = (R)(1.5 * S[4]);
-        r.qyz = (R)(1.5 * S[5]);
-        r.pad0 = r.pad1 = (R)0;
-        L.tile.pc[lane] = r;
+        L.tile.a[lane] = {(R)(cm.x - L.g.c[0]), (R)(cm.y - L.g.c[1]), (R)(cm.z - L.g.c[2]),
+                          (R)cm.w};
+        L.tile.b[lane] = {(R)(1.5 * S[0] - 0.5 * tr), (R)(1.5 * S[1] - 0.5 * tr),
+                          (R)(1.5 * S[2] - 0.5 * tr), (R)(1.5 * S[3])};
+        L.tile.c[lane] = {(R)(1.5 * S[4]), (R)(1.5 * S[5])};
+    } else if (lane < mpad) {
+        L.tile.a[lane] = {(R)kFarAway, (R)kFarAway, (R)kFarAway, (R)0};
+        L.tile.b[lane] = {(R)0, (R)0, (R)0, (R)0};
+        L.tile.c[lane] = {(R)0, (R)0};
     }
     wave_sync();
-    R ax[IPL], ay[IPL], az[IPL], ph[IPL];
-#pragma unroll
-    for (int u = 0; u < IPL; u++) ax[u] = ay[u] = az[u] = ph[u] = (R)0;
-    for (int j = sl; j < npc; j += S) {
-        const PcRec<R> c = L.tile.pc[j];
-#pragma unroll
-        for (int u = 0; u < IPL; u++) {
-            R Rx = T.x[u] - c.x, Ry = T.y[u] - c.y, Rz = T.z[u] - c.z;
-            R r2 = Rx * Rx + Ry * Ry + Rz * Rz;
-            R ri = rsq(r2);
-            R ri2 = ri * ri;
-            R qx = c.qxx * Rx + c.qxy * Ry + c.qxz * Rz;
-            R qy = c.qxy * Rx + c.qyy * Ry + c.qyz * Rz;
-            R qz = c.qxz * Rx + c.qyz * Ry + c.qzz * Rz;
-            R rqr = Rx * qx + Ry * qy + Rz * qz;
-            R ri3 = ri * ri2;
-            R ri5 = ri3 * ri2;
-            R mri = c.m * ri;
-            R coef = -(mri * ri2 + (R)5 * rqr * ri5 * ri2);
-            R two5 = (R)2 * ri5;
-            ax[u] += coef * Rx + two5 * qx;
-            ay[u] += coef * Ry + two5 * qy;
-            az[u] += coef * Rz + two5 * qz;
-            ph[u] -= mri + rqr * ri5;
-        }
-    }
-    fold(T, ax, ay, az, ph);
+    run_tile<kTilePc>(L.tile, mpad, ly, T);
     wave_sync();
 }
 
@@ -196,125 +320,52 @@ __device__ __forceinline__ int find_leaf(const uint32_t *pre, int nleaf, uint32_
     return lo;
 }
 
-// ---- far leaves: Newtonian pairs
-template <typename R, int IPL>
-__device__ uint32_t flush_far(WaveLds<R> &L, int nleaf, const ForceLaunch &f, const GroupGeom &G,
-                              Targets<R, IPL> &T, int S, int sl) {
+// ---- leaves (far: Newtonian pairs; near: changeover pairs). On entry
+// pre[] holds each buffered leaf's particle count; it is turned into an
+// exclusive prefix and the particles are expanded in tiles of 64.
+template <int KIND, typename R, int IPL>
+__device__ uint32_t flush_leaves(WaveLds<R> &L, const uint32_t *start, uint32_t *pre, int nleaf,
+                                 const ForceLaunch &f, const Layout &ly, Targets<R, IPL> &T,
+                                 bool record, uint32_t gstart, uint32_t gn) {
     wave_sync();
     const int lane = lane_id();
-    uint32_t c = lane < nleaf ? L.far_cnt[lane] : 0u;
-    uint32_t incl = wave_incl_scan(c);
-    uint32_t total = __shfl(incl, kWave - 1, kWave);
-    if (lane < nleaf) L.far_pre[lane] = incl - c;
-    wave_sync();
-    for (uint32_t base = 0; base < total; base += kWave) {
-        uint32_t s = base + lane;
-        if (s < total) {
-            int l = find_leaf(L.far_pre, nleaf, s);
-            uint32_t k = L.far_start[l] + (s - L.far_pre[l]);
-            double4 p = f.t.ps[k];
-            JRec<R> r;
-            r.x = (R)(p.x - G.c[0]);
-            r.y = (R)(p.y - G.c[1]);
-            r.z = (R)(p.z - G.c[2]);
-            r.m = (R)p.w;
-            L.tile.j[lane] = r;
-        }
-        wave_sync();
-        int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
-        R ax[IPL], ay[IPL], az[IPL], ph[IPL];
-#pragma unroll
-        for (int u = 0; u < IPL; u++) ax[u] = ay[u] = az[u] = ph[u] = (R)0;
-        for (int j = sl; j < m; j += S) {
-            const JRec<R> p = L.tile.j[j];
-#pragma unroll
-            for (int u = 0; u < IPL; u++) {
-                R dx = p.x - T.x[u], dy = p.y - T.y[u], dz = p.z - T.z[u];
-                R r2 = dx * dx + dy * dy + dz * dz;
-                R ri = rsq(r2);
-                R mri = p.m * ri;
-                R mri3 = mri * ri * ri;
-                ax[u] += mri3 * dx;
-                ay[u] += mri3 * dy;
-                az[u] += mri3 * dz;
-                ph[u] -= mri;
-            }
-        }
-        fold(T, ax, ay, az, ph);
-        wave_sync();
+    uint32_t c = lane < nleaf ? pre[lane] : 0u;
+    if (KIND == kTileNear && record) {
+        // hand the near leaves of this group to the neighbour-list passes
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(f.nb_rec_count, (uint32_t)nleaf);
+        base = (uint32_t)uniform((int)base);
+        if (lane < nleaf && base + (uint32_t)lane < f.nb_rec_cap)
+            f.nb_rec[base + lane] = make_uint4(gstart, gn, start[lane], c);
     }
-    return total;
-}
-
-// ---- near leaves: changeover-weighted pairs
-template <typename R, int IPL>
-__device__ uint32_t flush_near(WaveLds<R> &L, int nleaf, const ForceLaunch &f, const GroupGeom &G,
-                               Targets<R, IPL> &T, int S, int sl) {
-    wave_sync();
-    const int lane = lane_id();
-    uint32_t c = lane < nleaf ? L.near_cnt[lane] : 0u;
     uint32_t incl = wave_incl_scan(c);
-    uint32_t total = __shfl(incl, kWave - 1, kWave);
-    if (lane < nleaf) L.near_pre[lane] = incl - c;
+    uint32_t total = (uint32_t)uniform((int)__shfl(incl, kWave - 1, kWave));
+    if (lane < nleaf) pre[lane] = incl - c;
     wave_sync();
     for (uint32_t base = 0; base < total; base += kWave) {
-        uint32_t s = base + lane;
+        const uint32_t s = base + lane;
+        const int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
+        const int mpad = pad_to(m, ly.S);
         if (s < total) {
-            int l = find_leaf(L.near_pre, nleaf, s);
-            uint32_t k = L.near_start[l] + (s - L.near_pre[l]);
+            int l = find_leaf(pre, nleaf, s);
+            uint32_t k = start[l] + (s - pre[l]);
             double4 p = f.t.ps[k];
-            double2 rr = f.t.rr[k];
-            NRec<R> r;
-            r.x = (R)(p.x - G.c[0]);
-            r.y = (R)(p.y - G.c[1]);
-            r.z = (R)(p.z - G.c[2]);
-            r.m = (R)p.w;
-            r.rin = (R)rr.x;
-            r.rout = (R)rr.y;
-            r.k = k;
-            r.pad = 0;
-            L.tile.nr[lane] = r;
-        }
-        wave_sync();
-        int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
-        R ax[IPL], ay[IPL], az[IPL], ph[IPL];
-#pragma unroll
-        for (int u = 0; u < IPL; u++) ax[u] = ay[u] = az[u] = ph[u] = (R)0;
-        for (int j = sl; j < m; j += S) {
-            const NRec<R> p = L.tile.nr[j];
-#pragma unroll
-            for (int u = 0; u < IPL; u++) {
-                R dx = p.x - T.x[u], dy = p.y - T.y[u], dz = p.z - T.z[u];
-                R r2 = dx * dx + dy * dy + dz * dz;
-                R rin = T.rin[u] > p.rin ? T.rin[u] : p.rin;
-                R rout = T.rout[u] > p.rout ? T.rout[u] : p.rout;
-                R ri = r2 > (R)0 ? rsq(r2) : (R)0;
-                R r = r2 * ri;
-                R dr = rout - rin;
-                R sum = rout + rin;
-                R x = (r - rin) * rcp(dr);
-                R lam = dr * rcp(sum);
-                R xc = x < (R)0 ? (R)0 : (x > (R)1 ? (R)1 : x);
-                R x2 = xc * xc, x4 = x2 * x2;
-                R xm = xc - (R)1, xm2 = xm * xm;
-                // 1 - K(x) = x^4 [(35 - 84x + 70x^2 - 20x^3) - 35 Lambda (x-1)^4]
-                R fw = x4 * (((R)35 + xc * ((R)-84 + xc * ((R)70 - (R)20 * xc))) -
-                             (R)35 * lam * xm2 * xm2);
-                // (1 - W)/r = 2/(r_in + r_out) - Lambda x^5 (14 - 28x + 20x^2 - 5x^3)/r
-                R pw_in = (R)2 * rcp(sum) -
-                          lam * x4 * xc * ((R)14 + xc * ((R)-28 + xc * ((R)20 - (R)5 * xc))) * ri;
-                R pw = x >= (R)1 ? ri : pw_in;
-                bool self = p.k == T.k[u];
-                fw = self ? (R)0 : fw;
-                pw = self ? (R)0 : pw;
-                R mf = p.m * fw * ri * ri * ri;
-                ax[u] += mf * dx;
-                ay[u] += mf * dy;
-                az[u] += mf * dz;
-                ph[u] -= p.m * pw;
+            L.tile.a[lane] = {(R)(p.x - L.g.c[0]), (R)(p.y - L.g.c[1]), (R)(p.z - L.g.c[2]),
+                              (R)p.w};
+            if (KIND == kTileNear) {
+                double2 rr = f.t.rr[k];
+                L.tile.c[lane] = {(R)rr.x, (R)rr.y};
+                L.tile.k[lane] = k;
+            }
+        } else if (lane < mpad) {
+            L.tile.a[lane] = {(R)kFarAway, (R)kFarAway, (R)kFarAway, (R)0};
+            if (KIND == kTileNear) {
+                L.tile.c[lane] = {(R)0, (R)1};
+                L.tile.k[lane] = kNone - 1;
             }
         }
-        fold(T, ax, ay, az, ph);
+        wave_sync();
+        run_tile<KIND>(L.tile, mpad, ly, T);
         wave_sync();
     }
     return total;
@@ -329,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
     WaveLds<R> &L = lds_all[w];
     const int lane = lane_id();
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + w;
-    if (f.st_in->invalid_radii) return;
+    if (f.st_in->invalid_radii || f.st_in->cell_overflow) return;
     const int64_t n_groups = f.st_in->n_groups;
     const int64_t n = f.t.n;
     WaveStack stk;
@@ -350,37 +401,43 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
             q = (q + 1) & 7;
             continue;
         }
-        const uint32_t gnode = f.groups[g];
+        const uint32_t gnode = (uint32_t)uniform((int)f.groups[g]);
         const uint4 ginfo = f.t.nd_info[gnode];
-        const GroupGeom G = load_group(f.t.nd_lo, f.t.nd_hi, gnode);
-        const uint32_t gstart = ginfo.x, gn = ginfo.y;
+        wave_sync();
+        if (lane == 0) L.g = load_group(f.t.nd_lo, f.t.nd_hi, gnode);
+        wave_sync();
+        const uint32_t gstart = (uint32_t)uniform((int)ginfo.x);
+        const uint32_t gn = (uint32_t)uniform((int)ginfo.y);
         for (uint32_t chunk = 0; chunk < gn; chunk += CH) {
             const uint32_t active = gn - chunk < (uint32_t)CH ? gn - chunk : (uint32_t)CH;
-            // Small groups with one target per lane: S lanes share a target and
-            // split the j loop (lane = sl * W + il).
-            int S = 1;
-            if (IPL == 1) S = active <= 8 ? 8 : (active <= 16 ? 4 : (active <= 32 ? 2 : 1));
-            const int W = kWave / S;
-            const int il = lane & (W - 1), sl = lane / W;
+            Layout ly;
+            ly.nu = (int)((active + kWave - 1) / kWave);
+            // One slot in use: S lanes share a target and split the j loop
+            // (lane = sl * W + il).
+            ly.S = ly.nu > 1 ? 1 : (active <= 8 ? 8 : (active <= 16 ? 4 : (active <= 32 ? 2 : 1)));
+            const int W = kWave / ly.S;
+            const int il = lane & (W - 1);
+            ly.sl = lane / W;
             Targets<R, IPL> T;
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
                 uint32_t off = chunk + u * kWave + il;
-                T.valid[u] = off < gn;
-                uint32_t k = gstart + (T.valid[u] ? off : 0u);
+                bool valid = off < gn;
+                uint32_t k = gstart + (valid ? off : 0u);
                 double4 p = f.t.ps[k];
                 double2 rr = f.t.rr[k];
-                T.x[u] = (R)(p.x - G.c[0]);
-                T.y[u] = (R)(p.y - G.c[1]);
-                T.z[u] = (R)(p.z - G.c[2]);
+                T.x[u] = (R)(p.x - L.g.c[0]);
+                T.y[u] = (R)(p.y - L.g.c[1]);
+                T.z[u] = (R)(p.z - L.g.c[2]);
                 T.rin[u] = (R)rr.x;
                 T.rout[u] = (R)rr.y;
-                T.k[u] = T.valid[u] ? k : kNone;
+                T.k[u] = valid ? k : kNone;
                 T.acc[u].zero();
             }
             uint64_t n_pc = 0, n_far = 0, n_near = 0;
             int npc = 0, nfar = 0, nnear = 0;
-            stk.init(0u);
+            const bool record = f.nb_rec != nullptr && chunk == 0;
+            stk.init((uint32_t)uniform((int)root_of(f.t.nd_info, f.t.level_off, gstart)));
             bool ok = true;
             while (!stk.empty()) {
                 uint32_t node = stk.pop();
@@ -390,22 +447,17 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                     double4 lo = f.t.nd_lo[node], hi = f.t.nd_hi[node], cm = f.t.nd_com[node];
                     info = f.t.nd_info[node];
                     double D2, R2;
-                    box_terms(G, lo, hi, &D2, &R2);
+                    box_terms(L.g, lo, hi, &D2, &R2);
                     bool near = D2 < R2;
-                    if (!near && mac_accept(G, cm, hi.w, f.th2))
+                    if (!near && mac_accept(L.g, cm, hi.w, f.th2))
                         kind = kKindPc;
                     else if (info.z & kLeafFlag)
                         kind = near ? kKindNear : kKindFar;
                     else
                         kind = kKindOpen;
                 }
-                uint32_t ch[8];
-                int nc = 0;
-                if (kind == kKindOpen)
-                    nc = load_children(f.t.nd_child, node, ch);
-                else
-                    no_children(ch);
-                if (!stk.push(ch, nc)) {
+                int nc = kind == kKindOpen ? info_nchild(info.z) : 0;
+                if (!stk.push(info.w, nc)) {
                     ok = false;
                     break;
                 }
@@ -415,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 cnt = __popcll(m);
                 if (cnt) {
                     if (npc + cnt > kWave) {
-                        flush_pc(L, npc, f, G, T, S, sl);
+                        flush_pc(L, npc, f, ly, T);
                         n_pc += npc;
                         npc = 0;
                     }
@@ -426,13 +478,14 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 cnt = __popcll(m);
                 if (cnt) {
                     if (nfar + cnt > kWave) {
-                        n_far += flush_far(L, nfar, f, G, T, S, sl);
+                        n_far += flush_leaves<kTileFar>(L, L.far_start, L.far_pre, nfar, f, ly, T,
+                                                        false, gstart, gn);
                         nfar = 0;
                     }
                     if (kind == kKindFar) {
                         int p = nfar + lanes_below(m);
                         L.far_start[p] = info.x;
-                        L.far_cnt[p] = info.y;
+                        L.far_pre[p] = info.y;
                     }
                     nfar += cnt;
                 }
@@ -440,13 +493,14 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 cnt = __popcll(m);
                 if (cnt) {
                     if (nnear + cnt > kWave) {
-                        n_near += flush_near(L, nnear, f, G, T, S, sl);
+                        n_near += flush_leaves<kTileNear>(L, L.near_start, L.near_pre, nnear, f,
+                                                          ly, T, record, gstart, gn);
                         nnear = 0;
                     }
                     if (kind == kKindNear) {
                         int p = nnear + lanes_below(m);
                         L.near_start[p] = info.x;
-                        L.near_cnt[p] = info.y;
+                        L.near_pre[p] = info.y;
                     }
                     nnear += cnt;
                 }
@@ -456,18 +510,21 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 break;
             }
             if (npc) {
-                flush_pc(L, npc, f, G, T, S, sl);
+                flush_pc(L, npc, f, ly, T);
                 n_pc += npc;
             }
-            if (nfar) n_far += flush_far(L, nfar, f, G, T, S, sl);
-            if (nnear) n_near += flush_near(L, nnear, f, G, T, S, sl);
+            if (nfar) n_far += flush_leaves<kTileFar>(L, L.far_start, L.far_pre, nfar, f, ly, T,
+                                                        false, gstart, gn);
+            if (nnear)
+                n_near += flush_leaves<kTileNear>(L, L.near_start, L.near_pre, nnear, f, ly, T,
+                                                  record, gstart, gn);
             cnt_pc += n_pc * active;
             cnt_far += n_far * active;
             cnt_near += n_near * active - active;  // minus the self pairs
-            if (S > 1) combine_split(T.acc[0], W);
+            if (ly.S > 1) combine_split(T.acc[0], W);
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
-                if (!T.valid[u] || sl != 0) continue;
+                if (T.k[u] == kNone || ly.sl != 0) continue;
                 uint32_t o = f.t.orig[T.k[u]];
                 f.acc[o] = f.G * T.acc[u].get(0);
                 f.acc[n + o] = f.G * T.acc[u].get(1);
@@ -492,9 +549,9 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
 template <typename R, int IPL>
 int resident_for(int device) {
     int per_cu = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<R, IPL>, kThreads, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<R, IPL>, kThreads, 0);
     hipDeviceProp_t p;
-    hipGetDeviceProperties(&p, device);
+    (void)hipGetDeviceProperties(&p, device);
     if (per_cu < 1) per_cu = 1;
     return per_cu * p.multiProcessorCount * kWavesPerBlock;
 }

@@ -28,10 +28,19 @@ struct TreeDev {
     double4 *nd_lo, *nd_hi, *nd_com;
     double *nd_S;
     uint4 *nd_info;
-    uint32_t *nd_child;
-    uint32_t *nd_parent;
+    const uint32_t *level_off;  // [23]: cells of level l are [level_off[l], level_off[l+1])
+    const int64_t *n_nodes_dev; // number of cells (device); n_nodes below bounds it
     int64_t n;
-    int64_t n_nodes;
+    int64_t n_nodes;            // capacity of the cell arrays (grid sizes)
+};
+
+// Cells as emitted in depth-first pre-order, kept for the group selection
+// (groups listed in Morton order) and the renumbering into level order.
+struct PreOrder {
+    uint4 *info;        // (first particle, count, leaf | level << 1, -)
+    uint32_t *parent;   // kNone for the root
+    uint32_t *nchild;
+    uint32_t *new_of_old;
 };
 
 int bbox_partial_blocks(int64_t n);
@@ -39,36 +48,45 @@ void launch_bbox(const double *pos, const double *mass, int64_t n, double *part,
                  hipStream_t s);
 void launch_keys(const double *pos, int64_t n, const RootBox *rb, uint64_t *key, uint32_t *idx,
                  hipStream_t s);
+// batched mode: rb[n_sys], off = system offsets on the device [n_sys + 1]
+void launch_bbox_systems(const double *pos, const double *mass, int64_t n, const int64_t *off,
+                         int n_sys, RootBox *rb, hipStream_t s);
+void launch_keys_systems(const double *pos, int64_t n, const int64_t *off, int n_sys,
+                         const RootBox *rb, uint64_t *key, uint32_t *idx, hipStream_t s);
 
-// LSD radix sort of (key, value) pairs, stable. Buffers are swapped in place:
-// the sorted result ends in (*key, *val).
+// LSD radix sort of (key, value) pairs on the low 8*passes key bits, stable.
+// Buffers are swapped in place: the sorted result ends in (*key, *val).
 int64_t sort_ws_bytes(int64_t n);
+// n bounds the element count; with n_dev the actual count is read on the device.
 void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **val_alt, int64_t n,
-                void *ws, int64_t *scan_ws, hipStream_t s);
+                int passes, void *ws, int64_t *scan_ws, hipStream_t s,
+                const int64_t *n_dev = nullptr);
 
 void launch_gather_particles(const double *pos, const double *mass, const uint32_t *idx,
                              int64_t n, double4 *ps, uint32_t *orig, hipStream_t s);
-void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, uint32_t *emit,
-                         hipStream_t s);
-void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, const int64_t *base,
-                         const RootBox *rb, TreeDev t, hipStream_t s);
-// Cells bucketed by level: level_count[22], level_off[23], level_nodes[n_nodes];
-// level_ws holds level_ws_elems(n_nodes) u32.
-int64_t level_ws_elems(int64_t n_nodes);
-void launch_level_buckets(const TreeDev &t, uint32_t *level_count, uint32_t *level_off,
-                          uint32_t *level_ws, uint32_t *level_nodes, hipStream_t s);
-void launch_moments_level(const TreeDev &t, int level, const uint32_t *level_off,
-                          const uint32_t *level_nodes, hipStream_t s);
-void launch_tree_summary(const TreeDev &t, const uint32_t *level_count, Status *st, hipStream_t s);
+void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int levels,
+                         uint32_t *emit, hipStream_t s);
+// Pre-order cells; also the level keys (lkey, lval) sorted next.
+// Cells beyond node_cap are not written; st->cell_overflow is raised instead.
+void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int levels,
+                         const int64_t *base, PreOrder pre, uint64_t *lkey, uint32_t *lval,
+                         int64_t node_cap, Status *st, hipStream_t s);
+// Level-order arrays from the level-sorted permutation perm (new -> old).
+// rb holds one root box per system (one in single-system mode).
+void launch_relayout(const uint32_t *perm, PreOrder pre, const RootBox *rb, const uint64_t *key,
+                     int levels, TreeDev t, uint32_t *level_off, hipStream_t s);
+void launch_moments_level(const TreeDev &t, int level, hipStream_t s);
+void launch_tree_summary(const TreeDev &t, Status *st, hipStream_t s);
 
 // force_long preparation
 void launch_gather_radii(const double *r_in, const double *r_out, const double *r_search,
                          TreeDev t, Status *st, hipStream_t s);
-void launch_rsmax_level(const TreeDev &t, int level, const uint32_t *level_off,
-                        const uint32_t *level_nodes, hipStream_t s);
-void launch_group_flags(const TreeDev &t, int group_size, uint32_t *flag, hipStream_t s);
-void launch_group_compact(const TreeDev &t, const uint32_t *flag, const uint32_t *pos,
-                          uint32_t *groups, Status *st, hipStream_t s);
+void launch_rsmax_level(const TreeDev &t, int level, hipStream_t s);
+// flag[] is written for every slot up to t.n_nodes (the capacity), 0 past the cells.
+void launch_group_flags(const PreOrder &pre, const TreeDev &t, int group_size, uint32_t *flag,
+                        hipStream_t s);
+void launch_group_compact(const PreOrder &pre, const TreeDev &t, const uint32_t *flag,
+                          const uint32_t *pos, uint32_t *groups, Status *st, hipStream_t s);
 
 // changeover radii (eq. rcut / eq. rnb)
 void launch_changeover_radii(const double *mass, const double *vel, int64_t n, double rin_ref,
@@ -87,6 +105,10 @@ struct ForceLaunch {
     uint32_t *spill;           // walk stack spill, per resident wave
     uint32_t *queue;           // 8 work-queue heads
     int32_t *counts;           // optional per-particle counts [4][n]
+    uint4 *nb_rec;             // near-leaf records (group first, group count, leaf first,
+                               // leaf count) for the neighbour lists; nullptr: none
+    uint32_t *nb_rec_count;    // records written (may exceed nb_rec_cap: overflow)
+    uint32_t nb_rec_cap;
     int precision;             // 0 mixed, 1 fp64
     int ipl;                   // 1, 2, 4
 };
@@ -95,14 +117,25 @@ int64_t force_spill_elems_per_wave();
 void launch_force(const ForceLaunch &f, int resident_waves, hipStream_t s);
 
 // -------------------------------------------------------------- nblist.hip
+// Walk-based neighbour passes: run only when the near-leaf records of the
+// force walk overflowed (*rec_count > rec_cap; rec_count may be nullptr).
 void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cnt_orig,
-                     uint32_t *spill, uint32_t *queue, int resident_waves, hipStream_t s);
+                     uint32_t *spill, uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
+                     int resident_waves, hipStream_t s);
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
                      const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
-                     uint32_t *queue, int resident_waves, hipStream_t s);
+                     uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
+                     int resident_waves, hipStream_t s);
 // long_list holds n u32, long_count one u32 zeroed by the caller.
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
                     const Status *st, uint32_t *long_list, uint32_t *long_count, hipStream_t s);
 int nb_resident_waves(int device);
+// Neighbour passes over the near-leaf records of the force walk (no walk);
+// they do nothing when the records overflowed (*rec_count > rec_cap).
+void launch_nb_count_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
+                         uint32_t rec_cap, const Status *st, uint32_t *cnt_orig, hipStream_t s);
+void launch_nb_write_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
+                         uint32_t rec_cap, const Status *st, const int64_t *offsets,
+                         uint32_t *cursor, int32_t *idx, int64_t capacity, hipStream_t s);
 
 }  // namespace petar

@@ -46,7 +46,7 @@ __device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &p
     const int lane = lane_id();
     uint32_t c = lane < nleaf ? L.leaf_cnt[lane] : 0u;
     uint32_t incl = wave_incl_scan(c);
-    uint32_t total = __shfl(incl, kWave - 1, kWave);
+    uint32_t total = (uint32_t)uniform((int)__shfl(incl, kWave - 1, kWave));
     if (lane < nleaf) L.leaf_pre[lane] = incl - c;
     wave_sync();
     for (uint32_t base = 0; base < total; base += kWave) {
@@ -77,12 +77,14 @@ template <bool kWrite>
 __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *groups, Status *st,
                                                  uint32_t *cnt_orig, const int64_t *offsets,
                                                  int32_t *idx, int64_t capacity, uint32_t *spill,
-                                                 uint32_t *queue) {
+                                                 uint32_t *queue, const uint32_t *rec_count,
+                                                 uint32_t rec_cap) {
     __shared__ NbLds lds_all[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
     NbLds &L = lds_all[w];
     const int lane = lane_id();
-    if (st->invalid_radii || st->stack_overflow) return;
+    if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
+    if (rec_count && *rec_count <= rec_cap) return;  // the record passes run instead
     if (kWrite && offsets[t.n] > capacity) return;
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + w;
     const int64_t n_groups = st->n_groups;
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
             int64_t wpos = 0;
             if (kWrite && valid) wpos = offsets[t.orig[ki]];
             int nleaf = 0;
-            stk.init(0u);
+            stk.init((uint32_t)uniform((int)root_of(t.nd_info, t.level_off, ginfo.x)));
             bool ok = true;
             while (!stk.empty()) {
                 uint32_t node = stk.pop();
@@ -125,13 +127,8 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
                             open = true;
                     }
                 }
-                uint32_t ch[8];
-                int nc = 0;
-                if (open)
-                    nc = load_children(t.nd_child, node, ch);
-                else
-                    no_children(ch);
-                if (!stk.push(ch, nc)) {
+                int nc = open ? info_nchild(info.z) : 0;
+                if (!stk.push(info.w, nc)) {
                     ok = false;
                     break;
                 }
@@ -160,6 +157,43 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
     }
 }
 
+// Neighbour passes over the near-leaf records written by the force walk:
+// one wave per record (group particles x leaf particles), FP64 pair test.
+// Counting adds 1 per hit; writing takes a slot per hit from a per-target
+// cursor (the lists are sorted afterwards, so the slot order is irrelevant).
+template <bool kWrite>
+__global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, const uint4 *rec,
+                                                     const uint32_t *rec_count, const Status *st,
+                                                     uint32_t *cnt_orig, const int64_t *offsets,
+                                                     uint32_t *cursor, int32_t *idx,
+                                                     int64_t capacity, uint32_t rec_cap) {
+    if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
+    if (kWrite && offsets[t.n] > capacity) return;
+    const uint32_t nrec = *rec_count;
+    if (nrec > rec_cap) return;  // overflowed: the walk-based passes run instead
+    const int lane = lane_id();
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r = wave0; r < nrec; r += nwaves) {
+        const uint4 q = rec[r];  // group first, group count, leaf first, leaf count
+        const uint32_t pairs = q.y * q.w;
+        for (uint32_t p = lane; p < pairs; p += kWave) {
+            const uint32_t a = p / q.w, b = p - a * q.w;
+            const uint32_t ki = q.x + a, kj = q.z + b;
+            if (ki == kj) continue;
+            const double4 pi = t.ps[ki], pj = t.ps[kj];
+            if (!nb_pair(pi.x, pi.y, pi.z, t.rsk[ki], pj.x, pj.y, pj.z, t.rsk[kj])) continue;
+            const uint32_t oi = t.orig[ki];
+            if (kWrite) {
+                const uint32_t slot = atomicAdd(&cursor[oi], 1u);
+                idx[offsets[oi] + slot] = (int32_t)t.orig[kj];
+            } else {
+                atomicAdd(&cnt_orig[oi], 1u);
+            }
+        }
+    }
+}
+
 // Sorts each list ascending. Short lists (<= 32 entries, almost all) are
 // insertion-sorted by one thread; longer ones are queued and sorted by a
 // whole block with a bitonic network in LDS (heap sort by one thread above
@@ -171,7 +205,8 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offse
                                                             int64_t n, int64_t capacity,
                                                             const Status *st, uint32_t *long_list,
                                                             uint32_t *long_count) {
-    if (st->invalid_radii || st->stack_overflow || offsets[n] > capacity) return;
+    if (st->invalid_radii || st->stack_overflow || st->cell_overflow || offsets[n] > capacity)
+        return;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t b = offsets[i], e = offsets[i + 1];
@@ -231,7 +266,8 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_long(const int64_t *offset
                                                            const uint32_t *long_list,
                                                            const uint32_t *long_count) {
     __shared__ int32_t sh[kLongMax];
-    if (st->invalid_radii || st->stack_overflow || offsets[n] > capacity) return;
+    if (st->invalid_radii || st->stack_overflow || st->cell_overflow || offsets[n] > capacity)
+        return;
     const uint32_t nl = *long_count;
     for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
         const uint32_t i = long_list[q];
@@ -281,18 +317,35 @@ int nb_resident_waves(int device) {
     return per_cu * p.multiProcessorCount * kWavesPerBlock;
 }
 
+void launch_nb_count_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
+                         uint32_t rec_cap, const Status *st, uint32_t *cnt_orig, hipStream_t s) {
+    hipLaunchKernelGGL(k_nb_rec<false>, dim3(4096), dim3(kThreads), 0, s, t, rec, rec_count, st,
+                       cnt_orig, (const int64_t *)nullptr, (uint32_t *)nullptr,
+                       (int32_t *)nullptr, (int64_t)0, rec_cap);
+}
+
+void launch_nb_write_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
+                         uint32_t rec_cap, const Status *st, const int64_t *offsets,
+                         uint32_t *cursor, int32_t *idx, int64_t capacity, hipStream_t s) {
+    hipLaunchKernelGGL(k_nb_rec<true>, dim3(4096), dim3(kThreads), 0, s, t, rec, rec_count, st,
+                       (uint32_t *)nullptr, offsets, cursor, idx, capacity, rec_cap);
+}
+
 void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cnt_orig,
-                     uint32_t *spill, uint32_t *queue, int resident_waves, hipStream_t s) {
+                     uint32_t *spill, uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
+                     int resident_waves, hipStream_t s) {
     hipLaunchKernelGGL(k_nb<false>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
                        groups, st, cnt_orig, (const int64_t *)nullptr, (int32_t *)nullptr,
-                       (int64_t)0, spill, queue);
+                       (int64_t)0, spill, queue, rec_count, rec_cap);
 }
 
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
                      const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
-                     uint32_t *queue, int resident_waves, hipStream_t s) {
+                     uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
+                     int resident_waves, hipStream_t s) {
     hipLaunchKernelGGL(k_nb<true>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
-                       groups, st, (uint32_t *)nullptr, offsets, idx, capacity, spill, queue);
+                       groups, st, (uint32_t *)nullptr, offsets, idx, capacity, spill, queue,
+                       rec_count, rec_cap);
 }
 
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,

@@ -123,6 +123,88 @@ __global__ __launch_bounds__(kThreads) void k_keys(const double *pos, int64_t n,
     }
 }
 
+// Batched mode: each system gets its own root cube (one block per system)
+// and keys with the system id above kBatchLevels octal digits.
+__global__ __launch_bounds__(kThreads) void k_bbox_systems(const double *pos, const double *mass,
+                                                           int64_t n, const int64_t *off,
+                                                           RootBox *rb) {
+#pragma clang fp contract(off)
+    const int s = blockIdx.x;
+    const int64_t beg = off[s], end = off[s + 1];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        for (int d = 0; d < 3; d++) {
+            double x = pos[(int64_t)d * n + i];
+            if (!isfinite(x)) bad = 1;
+            lo[d] = fmin(lo[d], x);
+            hi[d] = fmax(hi[d], x);
+        }
+        double m = mass[i];
+        if (!isfinite(m) || m < 0.0) bad = 1;
+    }
+    __shared__ double sh[kThreads / kWave][6];
+    const int w = threadIdx.x / kWave;
+    for (int d = 0; d < 3; d++) {
+        double a = wave_min(lo[d]), b = wave_max(hi[d]);
+        if (lane_id() == 0) {
+            sh[w][d] = a;
+            sh[w][3 + d] = b;
+        }
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicAdd(&rb[0].bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double l[3], h[3];
+        for (int d = 0; d < 3; d++) {
+            l[d] = sh[0][d];
+            h[d] = sh[0][3 + d];
+            for (int k = 1; k < kThreads / kWave; k++) {
+                l[d] = fmin(l[d], sh[k][d]);
+                h[d] = fmax(h[d], sh[k][3 + d]);
+            }
+        }
+        double ext = 0.0;
+        for (int d = 0; d < 3; d++) {
+            double e = h[d] - l[d];
+            if (e > ext) ext = e;
+        }
+        if (!(ext > 0.0)) ext = 1.0;
+        for (int d = 0; d < 3; d++) rb[s].lo[d] = end > beg ? l[d] : 0.0;
+        rb[s].ext = ext;
+        rb[s].scale = ldexp(1.0, kBatchLevels) / ext;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_keys_systems(const double *pos, int64_t n,
+                                                           const int64_t *off, int n_sys,
+                                                           const RootBox *rb, uint64_t *key,
+                                                           uint32_t *idx) {
+#pragma clang fp contract(off)
+    const uint64_t qmax = (1ull << kBatchLevels) - 1ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_sys;  // system s with off[s] <= i < off[s+1]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (off[mid] <= i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const RootBox &b = rb[lo];
+        uint64_t q[3];
+        for (int d = 0; d < 3; d++) {
+            double t = (pos[(int64_t)d * n + i] - b.lo[d]) * b.scale;
+            uint64_t v = (uint64_t)t;
+            q[d] = v > qmax ? qmax : v;
+        }
+        key[i] = ((uint64_t)lo << (3 * kBatchLevels)) |
+                 (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+        idx[i] = (uint32_t)i;
+    }
+}
+
 // ------------------------------------------------------------- radix sort
 // LSD, 8-bit digits, 8 passes. Per pass: tile histograms, one exclusive scan
 // over (digit, tile), and a stable scatter that ranks equal digits inside a
@@ -133,7 +215,9 @@ constexpr int kSortTile = kThreads * kSortRounds;  // 2048 keys
 constexpr int kRadix = 256;
 
 __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint64_t *key, int64_t n, int shift,
-                                                        uint32_t *hist, int64_t ntiles) {
+                                                        uint32_t *hist, int64_t ntiles,
+                                                        const int64_t *n_dev) {
+    if (n_dev) n = *n_dev;
     __shared__ uint32_t cnt[kRadix];
     cnt[threadIdx.x] = 0;
     __syncthreads();
@@ -151,7 +235,9 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_i
                                                            uint64_t *key_out, uint32_t *val_out,
                                                            int64_t n, int shift,
                                                            const uint32_t *hist,
-                                                           const uint32_t *offs, int64_t ntiles) {
+                                                           const uint32_t *offs, int64_t ntiles,
+                                                           const int64_t *n_dev) {
+    if (n_dev) n = *n_dev;
     __shared__ uint64_t sk[kSortTile];
     __shared__ uint32_t sv[kSortTile];
     __shared__ uint32_t tile_start[kRadix];
@@ -229,10 +315,10 @@ __global__ __launch_bounds__(kThreads) void k_gather_particles(const double *pos
 
 // ------------------------------------------------------------ octree
 // First index after k whose level-`level` prefix differs from key[k]'s.
-__device__ int64_t run_end(const uint64_t *key, int64_t n, int64_t k, int level) {
-    uint64_t p = key_prefix(key[k], level);
+__device__ int64_t run_end(const uint64_t *key, int64_t n, int64_t k, int level, int levels) {
+    uint64_t p = key_prefix(key[k], level, levels);
     int64_t lo = k, hi = k + 1, step = 1;
-    while (hi < n && key_prefix(key[hi], level) == p) {
+    while (hi < n && key_prefix(key[hi], level, levels) == p) {
         lo = hi;
         step <<= 1;
         hi = k + step;
@@ -240,7 +326,7 @@ __device__ int64_t run_end(const uint64_t *key, int64_t n, int64_t k, int level)
     if (hi > n) hi = n;
     while (hi - lo > 1) {
         int64_t mid = lo + (hi - lo) / 2;
-        if (key_prefix(key[mid], level) == p)
+        if (key_prefix(key[mid], level, levels) == p)
             lo = mid;
         else
             hi = mid;
@@ -249,10 +335,10 @@ __device__ int64_t run_end(const uint64_t *key, int64_t n, int64_t k, int level)
 }
 
 // First index whose level-`level` prefix equals key[k]'s.
-__device__ int64_t run_start(const uint64_t *key, int64_t k, int level) {
-    uint64_t p = key_prefix(key[k], level);
+__device__ int64_t run_start(const uint64_t *key, int64_t k, int level, int levels) {
+    uint64_t p = key_prefix(key[k], level, levels);
     int64_t lo = k, hi = k - 1, step = 1;
-    while (hi >= 0 && key_prefix(key[hi], level) == p) {
+    while (hi >= 0 && key_prefix(key[hi], level, levels) == p) {
         lo = hi;
         step <<= 1;
         hi = k - step;
@@ -260,7 +346,7 @@ __device__ int64_t run_start(const uint64_t *key, int64_t k, int level) {
     if (hi < -1) hi = -1;
     while (lo - hi > 1) {
         int64_t mid = hi + (lo - hi) / 2;
-        if (key_prefix(key[mid], level) == p)
+        if (key_prefix(key[mid], level, levels) == p)
             lo = mid;
         else
             hi = mid;
@@ -268,8 +354,9 @@ __device__ int64_t run_start(const uint64_t *key, int64_t k, int level) {
     return lo;
 }
 
-__device__ __forceinline__ int first_level(const uint64_t *key, int64_t k) {
-    return k == 0 ? 0 : common_digits(key[k - 1], key[k]) + 1;
+// Shallowest level at which particle k starts a cell (0 where a system starts).
+__device__ __forceinline__ int first_level(const uint64_t *key, int64_t k, int levels) {
+    return k == 0 ? 0 : common_digits(key[k - 1], key[k], levels) + 1;
 }
 
 // Cells are identified by (level, first particle). Particle k starts the
@@ -278,23 +365,24 @@ __device__ __forceinline__ int first_level(const uint64_t *key, int64_t k) {
 // chain of existing cells it starts, from the shallowest; ordering the
 // emitted cells by (first particle, level) is a depth-first pre-order.
 __global__ __launch_bounds__(kThreads) void k_octree_count(const uint64_t *key, int64_t n,
-                                                           int leaf_size, uint32_t *emit) {
+                                                           int leaf_size, int levels,
+                                                           uint32_t *emit) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
-        int l0 = first_level(key, k);
+        int l0 = first_level(key, k, levels);
         uint32_t cnt = 0;
-        if (l0 <= kMaxLevel) {
+        if (l0 <= levels) {
             bool exists = true;
-            if (k > 0) {
+            if (l0 > 0) {
                 int L = l0 - 1;
-                int64_t s = run_start(key, k, L), e = run_end(key, n, k, L);
+                int64_t s = run_start(key, k, L, levels), e = run_end(key, n, k, L, levels);
                 exists = (e - s) > leaf_size;
             }
             if (exists) {
                 for (int l = l0;; l++) {
                     cnt++;
-                    int64_t e = run_end(key, n, k, l);
-                    if (e - k <= leaf_size || l == kMaxLevel) break;
+                    int64_t e = run_end(key, n, k, l, levels);
+                    if (e - k <= leaf_size || l == levels) break;
                 }
             }
         }
@@ -303,111 +391,107 @@ __global__ __launch_bounds__(kThreads) void k_octree_count(const uint64_t *key, 
 }
 
 __global__ __launch_bounds__(kThreads) void k_octree_write(const uint64_t *key, int64_t n,
-                                                           int leaf_size, const int64_t *base,
-                                                           const RootBox *rb, TreeDev t) {
-    const int64_t n_nodes = base[n];
-    const double ext = rb->ext;
+                                                           int leaf_size, int levels,
+                                                           const int64_t *base, PreOrder pre,
+                                                           uint64_t *lkey, uint32_t *lval,
+                                                           const Status *st) {
+    if (st->cell_overflow) return;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
         int64_t b = base[k];
         int64_t nemit = base[k + 1] - b;
         if (nemit == 0) continue;
-        int l0 = first_level(key, k);
+        int l0 = first_level(key, k, levels);
         for (int u = 0; u < nemit; u++) {
             int l = l0 + u;
             uint32_t idx = (uint32_t)(b + u);
-            int64_t e = run_end(key, n, k, l);
+            int64_t e = run_end(key, n, k, l, levels);
             uint32_t cnt = (uint32_t)(e - k);
-            bool leaf = (cnt <= (uint32_t)leaf_size) || l == kMaxLevel;
-            uint32_t skip = e < n ? (uint32_t)base[e] : (uint32_t)n_nodes;
-            t.nd_info[idx] = make_uint4((uint32_t)k, cnt, (leaf ? kLeafFlag : 0u) | ((uint32_t)l << 1),
-                                        skip);
-            t.nd_hi[idx].w = ldexp(ext, -l);
+            bool leaf = (cnt <= (uint32_t)leaf_size) || l == levels;
+            pre.info[idx] = make_uint4((uint32_t)k, cnt, (leaf ? kLeafFlag : 0u) | ((uint32_t)l << 1),
+                                       0u);
             uint32_t parent;
             if (u > 0) {
                 parent = idx - 1;
-            } else if (k == 0) {
-                parent = kNone;
+            } else if (l == 0) {
+                parent = kNone;  // root of a system
             } else {
                 int L = l - 1;
-                int64_t s = run_start(key, k, L);
-                parent = (uint32_t)(base[s] + (L - first_level(key, s)));
+                int64_t s = run_start(key, k, L, levels);
+                parent = (uint32_t)(base[s] + (L - first_level(key, s, levels)));
             }
-            t.nd_parent[idx] = parent;
-            if (parent != kNone) {
-                int digit = (int)((key[k] >> (3 * (kMaxLevel - l))) & 7);
-                t.nd_child[(int64_t)parent * 8 + digit] = idx;
-            }
+            pre.parent[idx] = parent;
+            if (parent != kNone) atomicAdd(&pre.nchild[parent], 1u);
+            lkey[idx] = (uint64_t)l;
+            lval[idx] = idx;
         }
     }
 }
 
-// Cells grouped by level (for the bottom-up passes) with a counting sort:
-// per-block level histograms, one scan, and a scatter through LDS counters.
-// The order inside a level is irrelevant (each cell is computed on its own).
-constexpr int kLevels = kMaxLevel + 1;
-constexpr int kLevelChunk = 4096;  // cells per histogram block
-
-__global__ __launch_bounds__(kThreads) void k_level_hist(TreeDev t, uint32_t *block_hist) {
-    __shared__ uint32_t h[kLevels];
-    if (threadIdx.x < kLevels) h[threadIdx.x] = 0;
-    __syncthreads();
-    int64_t beg = (int64_t)blockIdx.x * kLevelChunk;
-    int64_t end = beg + kLevelChunk < t.n_nodes ? beg + kLevelChunk : t.n_nodes;
-    for (int64_t c = beg + threadIdx.x; c < end; c += blockDim.x)
-        atomicAdd(&h[t.nd_info[c].z >> 1], 1u);
-    __syncthreads();
-    if (threadIdx.x < kLevels) block_hist[(int64_t)blockIdx.x * kLevels + threadIdx.x] = h[threadIdx.x];
+// Device cell count for the build's second half: the scanned count, or 0
+// (with Status::cell_overflow raised) when it exceeds the arrays' capacity,
+// so that every later kernel does nothing.
+__global__ void k_cell_count(const int64_t *base, int64_t n, int64_t node_cap, Status *st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t c = base[n];
+        if (c > node_cap) {
+            st->cell_overflow = 1;
+            c = 0;
+        }
+        st->n_nodes = c;
+    }
 }
 
-// One thread per level: totals, level offsets, then per-block offsets.
-__global__ void k_level_scan(uint32_t *block_hist, int64_t nblk, uint32_t *level_count,
-                             uint32_t *level_off) {
-    __shared__ uint32_t tot[kLevels];
+// perm[new] = old after the stable sort by level; its inverse.
+__global__ __launch_bounds__(kThreads) void k_invert(const uint32_t *perm, const int64_t *n_dev,
+                                                     uint32_t *new_of_old) {
+    const int64_t n_nodes = *n_dev;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes;
+         i += (int64_t)gridDim.x * blockDim.x)
+        new_of_old[perm[i]] = (uint32_t)i;
+}
+
+// Level-order cell records. Sorting the pre-order cells stably by level keeps
+// each level in Morton order, so siblings are contiguous and the first child
+// of a cell is the cell that follows it in pre-order.
+__global__ __launch_bounds__(kThreads) void k_relayout(const uint32_t *perm, PreOrder pre,
+                                                       const RootBox *rb, const uint64_t *key,
+                                                       int levels, TreeDev t) {
+    const int64_t n_nodes = *t.n_nodes_dev;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t old = perm[i];
+        uint4 in = pre.info[old];
+        uint32_t nc = pre.nchild[old];
+        uint32_t first = nc ? pre.new_of_old[old + 1] : 0u;
+        t.nd_info[i] = make_uint4(in.x, in.y, in.z | (nc << 8), first);
+        const uint64_t sys = key[in.x] >> (3 * levels);
+        t.nd_hi[i].w = ldexp(rb[sys].ext, -info_level(in.z));
+    }
+}
+
+// level_off[l] = first cell of level >= l (cells are sorted by level).
+__global__ void k_level_offsets(TreeDev t, uint32_t *level_off) {
     int l = threadIdx.x;
-    if (l < kLevels) {
-        uint32_t s = 0;
-        for (int64_t b = 0; b < nblk; b++) s += block_hist[b * kLevels + l];
-        tot[l] = s;
-        level_count[l] = s;
+    if (l > kMaxLevel + 1) return;  // levels above the deepest one get n_nodes
+    int64_t lo = 0, hi = *t.n_nodes_dev;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (info_level(t.nd_info[mid].z) < l)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    __syncthreads();
-    if (l < kLevels) {
-        uint32_t off = 0;
-        for (int k = 0; k < l; k++) off += tot[k];
-        level_off[l] = off;
-        if (l == kLevels - 1) level_off[kLevels] = off + tot[l];
-        for (int64_t b = 0; b < nblk; b++) {
-            uint32_t c = block_hist[b * kLevels + l];
-            block_hist[b * kLevels + l] = off;
-            off += c;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_level_scatter(TreeDev t, const uint32_t *block_off,
-                                                            uint32_t *level_nodes) {
-    __shared__ uint32_t cur[kLevels];
-    if (threadIdx.x < kLevels) cur[threadIdx.x] = block_off[(int64_t)blockIdx.x * kLevels + threadIdx.x];
-    __syncthreads();
-    int64_t beg = (int64_t)blockIdx.x * kLevelChunk;
-    int64_t end = beg + kLevelChunk < t.n_nodes ? beg + kLevelChunk : t.n_nodes;
-    for (int64_t c = beg + threadIdx.x; c < end; c += blockDim.x) {
-        uint32_t p = atomicAdd(&cur[t.nd_info[c].z >> 1], 1u);
-        level_nodes[p] = (uint32_t)c;
-    }
+    level_off[l] = (uint32_t)lo;
 }
 
 // Bottom-up cell data for one level. Leaves sum their particles (two passes:
 // centre of mass, then the second moment about it); other cells combine their
 // children with the parallel-axis shift.
-__global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level,
-                                                            const uint32_t *level_off,
-                                                            const uint32_t *level_nodes) {
-    const uint32_t beg = level_off[level], end = level_off[level + 1];
-    for (int64_t q = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < end;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t c = level_nodes[q];
+__global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level) {
+    const uint32_t beg = t.level_off[level], end = t.level_off[level + 1];
+    for (int64_t c = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < end;
+         c += (int64_t)gridDim.x * blockDim.x) {
         uint4 info = t.nd_info[c];
         double M = 0, sx = 0, sy = 0, sz = 0;
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -447,15 +531,10 @@ __global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level
                 S[5] += p.w * qy * qz;
             }
         } else {
-            uint32_t ch[8];
-            int nc = 0;
-            for (int o = 0; o < 8; o++) {
-                uint32_t v = t.nd_child[(int64_t)c * 8 + o];
-                if (v != kNone) ch[nc++] = v;
-            }
-            for (int o = 0; o < nc; o++) {
-                double4 cm = t.nd_com[ch[o]];
-                double4 l4 = t.nd_lo[ch[o]], h4 = t.nd_hi[ch[o]];
+            const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
+            for (uint32_t o = first; o < first + nc; o++) {
+                double4 cm = t.nd_com[o];
+                double4 l4 = t.nd_lo[o], h4 = t.nd_hi[o];
                 M += cm.w;
                 sx += cm.w * cm.x;
                 sy += cm.w * cm.y;
@@ -476,9 +555,9 @@ __global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level
                 cy = 0.5 * (lo[1] + hi[1]);
                 cz = 0.5 * (lo[2] + hi[2]);
             }
-            for (int o = 0; o < nc; o++) {
-                double4 cm = t.nd_com[ch[o]];
-                const double *Sc = t.nd_S + (int64_t)ch[o] * 6;
+            for (uint32_t o = first; o < first + nc; o++) {
+                double4 cm = t.nd_com[o];
+                const double *Sc = t.nd_S + (int64_t)o * 6;
                 double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
                 S[0] += Sc[0] + cm.w * dx * dx;
                 S[1] += Sc[1] + cm.w * dy * dy;
@@ -500,21 +579,17 @@ __global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_tree_summary(TreeDev t, const uint32_t *level_count,
-                                                           Status *st) {
+__global__ __launch_bounds__(kThreads) void k_tree_summary(TreeDev t, Status *st) {
+    const int64_t n_nodes = *t.n_nodes_dev;
     uint32_t leaves = 0;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
          c += (int64_t)gridDim.x * blockDim.x)
         leaves += t.nd_info[c].z & kLeafFlag;
     leaves = wave_sum(leaves);
-    if (lane_id() == 0 && leaves) atomicAdd((unsigned long long *)&st->n_leaves, (unsigned long long)leaves);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        int ml = 0;
-        for (int l = 0; l <= kMaxLevel; l++)
-            if (level_count[l]) ml = l;
-        st->max_level = ml;
-        st->n_nodes = t.n_nodes;
-    }
+    if (lane_id() == 0 && leaves)
+        atomicAdd((unsigned long long *)&st->n_leaves, (unsigned long long)leaves);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_nodes > 0)
+        st->max_level = info_level(t.nd_info[n_nodes - 1].z);
 }
 
 // ------------------------------------------------------- force preparation
@@ -533,22 +608,17 @@ __global__ __launch_bounds__(kThreads) void k_gather_radii(const double *r_in, c
     if (__ballot(bad) && lane_id() == 0) atomicAdd(&st->invalid_radii, 1);
 }
 
-__global__ __launch_bounds__(kThreads) void k_rsmax_level(TreeDev t, int level,
-                                                          const uint32_t *level_off,
-                                                          const uint32_t *level_nodes) {
-    const uint32_t beg = level_off[level], end = level_off[level + 1];
-    for (int64_t q = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < end;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t c = level_nodes[q];
+__global__ __launch_bounds__(kThreads) void k_rsmax_level(TreeDev t, int level) {
+    const uint32_t beg = t.level_off[level], end = t.level_off[level + 1];
+    for (int64_t c = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < end;
+         c += (int64_t)gridDim.x * blockDim.x) {
         uint4 info = t.nd_info[c];
         double r = 0.0;
         if (info.z & kLeafFlag) {
             for (uint32_t k = info.x; k < info.x + info.y; k++) r = fmax(r, t.rsk[k]);
         } else {
-            for (int o = 0; o < 8; o++) {
-                uint32_t v = t.nd_child[(int64_t)c * 8 + o];
-                if (v != kNone) r = fmax(r, t.nd_lo[v].w);
-            }
+            const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
+            for (uint32_t o = first; o < first + nc; o++) r = fmax(r, t.nd_lo[o].w);
         }
         t.nd_lo[c].w = r;
     }
@@ -556,25 +626,34 @@ __global__ __launch_bounds__(kThreads) void k_rsmax_level(TreeDev t, int level,
 
 // i-groups: the first cells on each root-to-leaf path holding <= group_size
 // particles, or leaves.
-__global__ __launch_bounds__(kThreads) void k_group_flags(TreeDev t, int group_size,
-                                                          uint32_t *flag) {
+__global__ __launch_bounds__(kThreads) void k_group_flags(PreOrder pre, TreeDev t,
+                                                          int group_size, uint32_t *flag) {
+    const int64_t n_nodes = *t.n_nodes_dev;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
          c += (int64_t)gridDim.x * blockDim.x) {
-        uint4 info = t.nd_info[c];
+        if (c >= n_nodes) {
+            flag[c] = 0u;
+            continue;
+        }
+        uint4 info = pre.info[c];
         bool small = info.y <= (uint32_t)group_size || (info.z & kLeafFlag);
-        uint32_t p = t.nd_parent[c];
-        bool parent_big = p == kNone || t.nd_info[p].y > (uint32_t)group_size;
+        uint32_t p = pre.parent[c];
+        bool parent_big = p == kNone || pre.info[p].y > (uint32_t)group_size;
         flag[c] = (small && parent_big) ? 1u : 0u;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_group_compact(TreeDev t, const uint32_t *flag,
+// Groups listed in pre-order (= Morton order of their particles), as
+// level-order cell indices.
+__global__ __launch_bounds__(kThreads) void k_group_compact(PreOrder pre, TreeDev t,
+                                                            const uint32_t *flag,
                                                             const uint32_t *pos, uint32_t *groups,
                                                             Status *st) {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < t.n_nodes;
+    const int64_t n_nodes = *t.n_nodes_dev;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
          c += (int64_t)gridDim.x * blockDim.x)
-        if (flag[c]) groups[pos[c]] = (uint32_t)c;
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_groups = pos[t.n_nodes];
+        if (flag[c]) groups[pos[c]] = pre.new_of_old[c];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_groups = pos[n_nodes];
 }
 
 // ------------------------------------------------------- changeover radii
@@ -638,6 +717,17 @@ void launch_bbox(const double *pos, const double *mass, int64_t n, double *part,
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, s, (const double *)part, nb, rb);
 }
 
+void launch_bbox_systems(const double *pos, const double *mass, int64_t n, const int64_t *off,
+                         int n_sys, RootBox *rb, hipStream_t s) {
+    hipLaunchKernelGGL(k_bbox_systems, dim3(n_sys), dim3(kThreads), 0, s, pos, mass, n, off, rb);
+}
+
+void launch_keys_systems(const double *pos, int64_t n, const int64_t *off, int n_sys,
+                         const RootBox *rb, uint64_t *key, uint32_t *idx, hipStream_t s) {
+    hipLaunchKernelGGL(k_keys_systems, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, pos,
+                       n, off, n_sys, rb, key, idx);
+}
+
 void launch_keys(const double *pos, int64_t n, const RootBox *rb, uint64_t *key, uint32_t *idx,
                  hipStream_t s) {
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, pos, n, rb,
@@ -651,19 +741,19 @@ int64_t sort_ws_bytes(int64_t n) {
 }
 
 void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **val_alt, int64_t n,
-                void *ws, int64_t *scan_ws, hipStream_t s) {
+                int passes, void *ws, int64_t *scan_ws, hipStream_t s, const int64_t *n_dev) {
     int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     if (ntiles < 1) ntiles = 1;
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + kRadix * ntiles;
-    for (int pass = 0; pass < 8; pass++) {
+    for (int pass = 0; pass < passes; pass++) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
-                           (const uint64_t *)*key, n, shift, hist, ntiles);
+                           (const uint64_t *)*key, n, shift, hist, ntiles, n_dev);
         scan_u32_to_u32(hist, offs, kRadix * ntiles, scan_ws, s);
         hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
                            (const uint64_t *)*key, (const uint32_t *)*val, *key_alt, *val_alt, n,
-                           shift, (const uint32_t *)hist, (const uint32_t *)offs, ntiles);
+                           shift, (const uint32_t *)hist, (const uint32_t *)offs, ntiles, n_dev);
         uint64_t *tk = *key;
         *key = *key_alt;
         *key_alt = tk;
@@ -679,41 +769,37 @@ void launch_gather_particles(const double *pos, const double *mass, const uint32
                        pos, mass, idx, n, ps, orig);
 }
 
-void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, uint32_t *emit,
-                         hipStream_t s) {
+void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int levels,
+                         uint32_t *emit, hipStream_t s) {
     hipLaunchKernelGGL(k_octree_count, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
-                       emit);
+                       levels, emit);
 }
 
-void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, const int64_t *base,
-                         const RootBox *rb, TreeDev t, hipStream_t s) {
+void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int levels,
+                         const int64_t *base, PreOrder pre, uint64_t *lkey, uint32_t *lval,
+                         int64_t node_cap, Status *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_count, dim3(1), dim3(64), 0, s, base, n, node_cap, st);
     hipLaunchKernelGGL(k_octree_write, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
-                       base, rb, t);
+                       levels, base, pre, lkey, lval, (const Status *)st);
 }
 
-int64_t level_ws_elems(int64_t n_nodes) {
-    return ((n_nodes + kLevelChunk - 1) / kLevelChunk + 1) * kLevels;
+void launch_relayout(const uint32_t *perm, PreOrder pre, const RootBox *rb, const uint64_t *key,
+                     int levels, TreeDev t, uint32_t *level_off, hipStream_t s) {
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, perm,
+                       t.n_nodes_dev, pre.new_of_old);
+    hipLaunchKernelGGL(k_relayout, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, perm, pre, rb,
+                       key, levels, t);
+    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(32), 0, s, t, level_off);
 }
 
-void launch_level_buckets(const TreeDev &t, uint32_t *level_count, uint32_t *level_off,
-                          uint32_t *level_ws, uint32_t *level_nodes, hipStream_t s) {
-    int64_t nblk = (t.n_nodes + kLevelChunk - 1) / kLevelChunk;
-    hipLaunchKernelGGL(k_level_hist, dim3((unsigned)nblk), dim3(kThreads), 0, s, t, level_ws);
-    hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(64), 0, s, level_ws, nblk, level_count,
-                       level_off);
-    hipLaunchKernelGGL(k_level_scatter, dim3((unsigned)nblk), dim3(kThreads), 0, s, t,
-                       (const uint32_t *)level_ws, level_nodes);
-}
-
-void launch_moments_level(const TreeDev &t, int level, const uint32_t *level_off,
-                          const uint32_t *level_nodes, hipStream_t s) {
+void launch_moments_level(const TreeDev &t, int level, hipStream_t s) {
     hipLaunchKernelGGL(k_moments_level, dim3(grid_for(t.n_nodes, kThreads, 2048)), dim3(kThreads),
-                       0, s, t, level, level_off, level_nodes);
+                       0, s, t, level);
 }
 
-void launch_tree_summary(const TreeDev &t, const uint32_t *level_count, Status *st, hipStream_t s) {
+void launch_tree_summary(const TreeDev &t, Status *st, hipStream_t s) {
     hipLaunchKernelGGL(k_tree_summary, dim3(grid_for(t.n_nodes, kThreads, 1024)), dim3(kThreads), 0,
-                       s, t, level_count, st);
+                       s, t, st);
 }
 
 void launch_gather_radii(const double *r_in, const double *r_out, const double *r_search,
@@ -722,21 +808,21 @@ void launch_gather_radii(const double *r_in, const double *r_out, const double *
                        r_in, r_out, r_search, t, st);
 }
 
-void launch_rsmax_level(const TreeDev &t, int level, const uint32_t *level_off,
-                        const uint32_t *level_nodes, hipStream_t s) {
+void launch_rsmax_level(const TreeDev &t, int level, hipStream_t s) {
     hipLaunchKernelGGL(k_rsmax_level, dim3(grid_for(t.n_nodes, kThreads, 2048)), dim3(kThreads), 0,
-                       s, t, level, level_off, level_nodes);
+                       s, t, level);
 }
 
-void launch_group_flags(const TreeDev &t, int group_size, uint32_t *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, t,
+void launch_group_flags(const PreOrder &pre, const TreeDev &t, int group_size, uint32_t *flag,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, pre, t,
                        group_size, flag);
 }
 
-void launch_group_compact(const TreeDev &t, const uint32_t *flag, const uint32_t *pos,
-                          uint32_t *groups, Status *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_group_compact, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, t, flag,
-                       pos, groups, st);
+void launch_group_compact(const PreOrder &pre, const TreeDev &t, const uint32_t *flag,
+                          const uint32_t *pos, uint32_t *groups, Status *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_compact, dim3(grid_for(t.n_nodes)), dim3(kThreads), 0, s, pre, t,
+                       flag, pos, groups, st);
 }
 
 void launch_changeover_radii(const double *mass, const double *vel, int64_t n, double rin_ref,

@@ -29,6 +29,15 @@ const char *check_build_args(const double *pos, const double *mass, int64_t n, d
     return nullptr;
 }
 
+const char *check_batch_args(int n_sys, const int64_t *off) {
+    if (!off) return "sys_offsets is NULL";
+    if (n_sys < 1 || n_sys > kMaxSystemsHost) return "n_sys must be in [1, 512]";
+    if (off[0] != 0) return "sys_offsets[0] must be 0";
+    for (int s = 0; s < n_sys; s++)
+        if (off[s + 1] <= off[s]) return "every system needs at least one particle";
+    return nullptr;
+}
+
 const char *check_force_args(int group_size, const double *r_in, const double *r_out,
                              const double *r_search, const double *acc, const double *pot,
                              const petar_nblist *nb) {

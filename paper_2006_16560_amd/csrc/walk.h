@@ -60,6 +60,21 @@ __device__ __forceinline__ bool mac_accept(const GroupGeom &G, const double4 &co
     return side2 < rhs;
 }
 
+// Root of the tree (system) that holds particle `first`: level 0 lists the
+// roots, one per system, in particle order.
+__device__ __forceinline__ uint32_t root_of(const uint4 *nd_info, const uint32_t *level_off,
+                                            uint32_t first) {
+    uint32_t lo = 0, hi = level_off[1];
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (nd_info[mid].x <= first)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 struct WaveStack {
     uint32_t *lds;     // kStackLds entries
     uint32_t *spill;   // kSpillCap entries
@@ -91,11 +106,12 @@ struct WaveStack {
         return v;
     }
 
-    // Pushes the non-empty entries of each lane's child slots (kNone marks
-    // an empty octant). Returns false on spill overflow.
-    __device__ bool push(const uint32_t (&ch)[8], int nc) {
+    // Pushes each lane's children: the nc cells first .. first + nc - 1
+    // (children are contiguous in level order). Returns false on spill
+    // overflow.
+    __device__ bool push(uint32_t first, int nc) {
         int incl = wave_incl_scan(nc);
-        int tot = __shfl(incl, kWave - 1, kWave);
+        int tot = uniform(__shfl(incl, kWave - 1, kWave));
         if (tot == 0) return true;
         if (sp_l + tot > kStackLds) {
             if (sp_g + sp_l > kSpillCap) return false;
@@ -105,38 +121,11 @@ struct WaveStack {
             wave_sync();
         }
         int p = sp_l + incl - nc;
-#pragma unroll
-        for (int o = 0; o < 8; o++) {
-            if (ch[o] != kNone) lds[p++] = ch[o];
-        }
+        for (int c = 0; c < nc; c++) lds[p + c] = first + (uint32_t)c;
         sp_l += tot;
         wave_sync();
         return true;
     }
 };
-
-// Reads the eight child slots of a cell (kNone for empty octants) and
-// returns the number of children.
-__device__ __forceinline__ int load_children(const uint32_t *nd_child, uint32_t c, uint32_t (&ch)[8]) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(nd_child + (int64_t)c * 8);
-    uint4 a = p[0], b = p[1];
-    ch[0] = a.x;
-    ch[1] = a.y;
-    ch[2] = a.z;
-    ch[3] = a.w;
-    ch[4] = b.x;
-    ch[5] = b.y;
-    ch[6] = b.z;
-    ch[7] = b.w;
-    int nc = 0;
-#pragma unroll
-    for (int o = 0; o < 8; o++) nc += ch[o] != kNone;
-    return nc;
-}
-
-__device__ __forceinline__ void no_children(uint32_t (&ch)[8]) {
-#pragma unroll
-    for (int o = 0; o < 8; o++) ch[o] = kNone;
-}
 
 }  // namespace petar

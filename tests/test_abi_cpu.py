@@ -185,3 +185,67 @@ def test_product_never_touches_oracle():
                 assert "workloads" not in txt, f
     inc = open(HEADER).read()
     assert "oracle" not in inc
+
+
+def test_autotune_cache_hit_without_device(capi, ctx, tmp_path):
+    """A cached entry for (floor(log2 N), theta, precision) is returned without
+    any launch; a miss reaches the tree build (no device here)."""
+    _capi, lib = capi
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"n_bucket": 20, "theta": 0.5, "precision": 0, "leaf_size": 16, '
+                     '"group_size": 128, "i_per_lane": 2, "ms": 3.5}\n'
+                     'garbage line\n')
+    out = _capi.petar_tuned()
+    st = lib.petar_autotune(ctx, FAKE, FAKE, 1 << 20 | 5, 0.5, FAKE, FAKE, FAKE,
+                            str(cache).encode(), ctypes.byref(out))
+    assert st == _capi.PETAR_OK
+    assert (out.leaf_size, out.group_size, out.i_per_lane, out.ms) == (16, 128, 2, 3.5)
+    p = _capi.petar_params()
+    lib.petar_get_params(ctx, ctypes.byref(p))
+    assert p.i_per_lane == 2
+    st = lib.petar_autotune(ctx, FAKE, FAKE, 1 << 10, 0.5, FAKE, FAKE, FAKE,
+                            str(cache).encode(), ctypes.byref(out))
+    assert st == _capi.PETAR_E_NODEVICE
+    st = lib.petar_autotune(ctx, None, FAKE, 1 << 10, 0.5, FAKE, FAKE, FAKE, None,
+                            ctypes.byref(out))
+    assert st == _capi.PETAR_E_INVALID
+
+
+@pytest.mark.parametrize("offs,ok", [
+    ([0, 10, 25], True),
+    ([0, 1], True),
+    ([1, 10], False),
+    ([0, 10, 10], False),
+    ([0, 10, 5], False),
+])
+def test_batch_build_validation(capi, ctx, offs, ok):
+    _capi, lib = capi
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    st = lib.petar_batch_build(ctx, len(offs) - 1, arr, FAKE, FAKE, 0.5, 8)
+    assert st == (_capi.PETAR_E_NODEVICE if ok else _capi.PETAR_E_INVALID)
+
+
+def test_batch_build_limits(capi, ctx):
+    _capi, lib = capi
+    offs = list(range(514))
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    assert lib.petar_batch_build(ctx, 513, arr, FAKE, FAKE, 0.5, 8) == _capi.PETAR_E_INVALID
+    assert lib.petar_batch_build(ctx, 512, arr, FAKE, FAKE, 0.5, 8) == _capi.PETAR_E_NODEVICE
+    assert lib.petar_batch_build(ctx, 0, arr, FAKE, FAKE, 0.5, 8) == _capi.PETAR_E_INVALID
+    assert lib.petar_batch_build(ctx, 2, None, FAKE, FAKE, 0.5, 8) == _capi.PETAR_E_INVALID
+
+
+def test_step_graph_validation(capi, ctx):
+    _capi, lib = capi
+    nb = _nb(capi)
+    args = [FAKE, FAKE, 1000, 0.5, 8, 64, FAKE, FAKE, FAKE, FAKE, FAKE]
+    assert lib.petar_step_graph(ctx, 0, None, *args, ctypes.byref(nb)) == _capi.PETAR_E_NODEVICE
+    assert lib.petar_step_graph(ctx, -1, None, *args, None) == _capi.PETAR_E_INVALID
+    bad = list(args)
+    bad[4] = 0  # leaf size
+    assert lib.petar_step_graph(ctx, 0, None, *bad, None) == _capi.PETAR_E_INVALID
+    bad = list(args)
+    bad[5] = 0  # group size
+    assert lib.petar_step_graph(ctx, 0, None, *bad, None) == _capi.PETAR_E_INVALID
+    offs = (ctypes.c_int64 * 3)(0, 5, 5)
+    assert lib.petar_step_graph(ctx, 2, offs, *args, None) == _capi.PETAR_E_INVALID

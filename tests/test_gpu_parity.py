@@ -280,3 +280,127 @@ def test_changeover_radii_kernel(pt, ctx, orc):
         e_ri, e_ro, e_rs = orc.radii(c.mass, 0.002, 0.02, 1.2, vel=vel, cr_dt=crdt)
         for got, ref in ((ri, e_ri), (ro, e_ro), (rs, e_rs)):
             np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=4e-16 * 8, atol=0)
+
+
+def test_autotune_small(pt, orc, tmp_path):
+    c, rin, rout, rs = cluster_with_radii(orc, 20000, 18, bf=0.5)
+    ctx = pt.petar_create(0)
+    cache = str(tmp_path / "tune.jsonl")
+    best = pt.petar_autotune(ctx, T(c.pos), T(c.mass), 0.5, T(rin), T(rout), T(rs), cache)
+    assert best["leaf_size"] in (4, 8, 16, 32) and best["group_size"] in (32, 64, 128, 256)
+    assert best["ms"] > 0
+    again = pt.petar_autotune(ctx, T(c.pos), T(c.mass), 0.5, T(rin), T(rout), T(rs), cache)
+    assert again == best
+    # the tuned parameters still give the oracle's answer
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, best["leaf_size"])
+    acc, pot = pt.petar_force_long(ctx, best["group_size"], T(rin), T(rout), T(rs))
+    a_ref, _, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.5, best["leaf_size"],
+                                 best["group_size"])
+    assert np.percentile(rel_err(acc.cpu().numpy(), a_ref), 99.9) < 1e-12
+    pt.petar_destroy(ctx)
+
+
+# ------------------------------------------------------------ batched mode
+
+def _batch(orc, sizes, seed, bf=0.2):
+    offs = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    pos = np.empty((3, offs[-1]))
+    mass = np.empty(offs[-1])
+    rin, rout, rs = (np.empty(offs[-1]) for _ in range(3))
+    for k, nk in enumerate(sizes):
+        c = workloads.make_cluster(int(nk), seed * 100 + k, imf=True, binary_fraction=bf)
+        sl = slice(offs[k], offs[k + 1])
+        pos[:, sl], mass[sl] = c.pos, c.mass
+        ro = workloads.r_out_ref_for(int(nk))
+        rin[sl], rout[sl], rs[sl] = orc.radii(c.mass, 0.1 * ro, ro, 1.2)
+    return offs, pos, mass, rin, rout, rs
+
+
+def test_batched_matches_oracle_per_system(pt, ctx, orc):
+    """Forest of per-system trees (18 levels) vs the oracle tree of each
+    system alone; neighbour lists vs brute force per system (global ids)."""
+    sizes = [1500, 700, 3000, 64, 1]
+    offs, pos, mass, rin, rout, rs = _batch(orc, sizes, 1)
+    for prec, tol in ((pt.PETAR_FP64, 1e-12), (pt.PETAR_MIXED, 1e-5)):
+        pt.petar_set_params(ctx, precision=prec, i_per_lane=1, record_counts=0)
+        pt.petar_batch_build(ctx, offs, T(pos), T(mass), 0.5, 8)
+        acc, pot, (no, ni) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs),
+                                                 nb_capacity=10 ** 6)
+        acc, pot, no, ni = (x.cpu().numpy() for x in (acc, pot, no, ni))
+        for k in range(len(sizes)):
+            sl = slice(offs[k], offs[k + 1])
+            if sizes[k] == 1:
+                assert np.all(acc[:, sl] == 0) and np.all(pot[sl] == 0)
+                continue
+            a_ref, p_ref, _ = orc.tree_force(pos[:, sl], mass[sl], rin[sl], rout[sl], rs[sl], 0.5,
+                                             8, 64, max_level=18)
+            e = rel_err(acc[:, sl], a_ref)
+            assert (e.max() if prec == pt.PETAR_FP64 else np.percentile(e, 99)) < tol, (k, prec)
+            o_ref, i_ref = orc.neighbours(pos[:, sl], rs[sl])
+            got_o = no[offs[k]:offs[k + 1] + 1] - no[offs[k]]
+            got_i = ni[no[offs[k]]:no[offs[k + 1]]] - offs[k]
+            assert np.array_equal(got_o, o_ref) and np.array_equal(got_i, i_ref)
+
+
+def test_batched_bitwise_equals_per_system(pt, ctx, orc):
+    sizes = [2000, 5000, 1024, 333]
+    offs, pos, mass, rin, rout, rs = _batch(orc, sizes, 2)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_batch_build(ctx, offs, T(pos), T(mass), 0.5, 8)
+    acc, pot, (no, ni) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=10 ** 6)
+    acc, pot = acc.cpu().numpy(), pot.cpu().numpy()
+    for k in range(len(sizes)):
+        sl = slice(offs[k], offs[k + 1])
+        pt.petar_batch_build(ctx, [0, sizes[k]], T(pos[:, sl]), T(mass[sl]), 0.5, 8)
+        a1, p1 = pt.petar_force_long(ctx, 64, T(rin[sl]), T(rout[sl]), T(rs[sl]))
+        assert np.array_equal(a1.cpu().numpy(), acc[:, sl])
+        assert np.array_equal(p1.cpu().numpy(), pot[sl])
+
+
+# ------------------------------------------------------------- graph replay
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_step_graph_replays_match_eager(pt, orc, batched):
+    """Replays of the captured step give the eager results bit for bit, also
+    after the particle data changed between replays (host work between)."""
+    if batched:
+        offs, pos, mass, rin, rout, rs = _batch(orc, [3000, 1200, 4500], 3)
+    else:
+        offs = None
+        c, rin, rout, rs = cluster_with_radii(orc, 8000, 19, bf=0.5)
+        pos, mass = c.pos, c.mass
+    n = mass.size
+    ctx = pt.petar_create(0)
+    dpos, dmass = T(pos), T(mass)
+    drin, drout, drs = T(rin), T(rout), T(rs)
+    acc = torch.empty((3, n), dtype=torch.float64, device="cuda:0")
+    pot = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    nbo = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+    nbi = torch.empty(40 * n, dtype=torch.int32, device="cuda:0")
+    rng = np.random.default_rng(5)
+    for it in range(4):
+        if it == 2:  # move the particles a little: same buffers, new contents
+            pos = pos + rng.normal(scale=1e-3, size=pos.shape)
+            dpos.copy_(T(pos))
+        tot = pt.petar_step_graph(ctx, dpos, dmass, 0.5, 8, 64, drin, drout, drs, acc, pot,
+                                  sys_offsets=offs, nb=(nbo, nbi))
+        torch.cuda.synchronize()
+        got = (acc.cpu().numpy().copy(), pot.cpu().numpy().copy(), nbo.cpu().numpy().copy(),
+               nbi.cpu().numpy()[:tot].copy())
+        # eager reference on a separate context
+        ref_ctx = pt.petar_create(0)
+        if batched:
+            pt.petar_batch_build(ref_ctx, offs, dpos, dmass, 0.5, 8)
+        else:
+            pt.petar_tree_build(ref_ctx, dpos, dmass, 0.5, 8)
+        a, p, (o, i) = pt.petar_force_long(ref_ctx, 64, drin, drout, drs, nb_capacity=40 * n)
+        assert np.array_equal(got[0], a.cpu().numpy()), it
+        assert np.array_equal(got[1], p.cpu().numpy()), it
+        assert np.array_equal(got[2], o.cpu().numpy()) and np.array_equal(got[3], i.cpu().numpy())
+        pt.petar_destroy(ref_ctx)
+        st = pt.petar_get_stats(ctx)
+        if it > 0:
+            assert st["ms_graph"] > 0  # replayed, not re-captured
+    pt.petar_destroy(ctx)
