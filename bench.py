@@ -44,6 +44,9 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sample", type=int, default=4096, help="targets in the error / CPU sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates the "
+                         "HBM byte counters of a profiler) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -55,6 +58,15 @@ def main() -> int:
     import paper_2006_16560_amd as pt
     import workloads
 
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d bytes 5 times" % nbytes)
+        return 0
     if args.workload == "batched128":
         return bench_batched(args)
     wl = workloads.WORKLOADS[args.workload]
@@ -192,9 +204,13 @@ def main() -> int:
 
 
 def bench_batched(args) -> int:
-    """128 independent clusters (N log-uniform in [1024, 131072], 20% binaries):
-    one batched build + force (one persistent launch over all groups) against
-    128 sequential per-cluster build + force calls on the same GPU."""
+    """128 independent clusters (N log-uniform in [1024, 131072], 20% binaries).
+
+    Three ways to run the same step (tree build + long-range force +
+    neighbour lists): the whole batched step replayed as one hipGraph, the
+    batched step launched eagerly, and 128 sequential per-cluster calls. The
+    batched outputs must equal the sequential ones bit for bit.
+    """
     import torch
     import paper_2006_16560_amd as pt
     import workloads
@@ -208,69 +224,89 @@ def bench_batched(args) -> int:
     mass = torch.from_numpy(mass_h).to(dev)
     r_in = torch.empty(n, dtype=torch.float64, device=dev)
     r_out, r_s = torch.empty_like(r_in), torch.empty_like(r_in)
-    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
-    pot = torch.empty(n, dtype=torch.float64, device=dev)
     theta = 0.5 if args.theta is None else args.theta
     leaf = 8 if args.leaf is None else args.leaf
     group = 64 if args.group is None else args.group
+    ipl = 1 if args.ipl is None else args.ipl
     ctx = pt.petar_create(0)
-    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1 if args.ipl is None else args.ipl)
+    ctx_g = pt.petar_create(0)
+    for c in (ctx, ctx_g):
+        pt.petar_set_params(c, precision=pt.PETAR_MIXED, i_per_lane=ipl)
     for k in range(sizes.size):  # per-cluster radii (own <m> and r_out,ref ~ N^-1/3)
         a, b = int(offs[k]), int(offs[k + 1])
         ro = workloads.r_out_ref_for(int(sizes[k]))
         pt.petar_changeover_radii(ctx, mass[a:b], 0.1 * ro, ro, 1.2,
                                   out=(r_in[a:b], r_out[a:b], r_s[a:b]))
     nb_cap = 64 * n
+    acc_b = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot_b = torch.empty(n, dtype=torch.float64, device=dev)
+    acc_g, pot_g = torch.empty_like(acc_b), torch.empty_like(pot_b)
+    acc_s, pot_s = torch.empty_like(acc_b), torch.empty_like(pot_b)
+    nb_g = (torch.empty(n + 1, dtype=torch.int64, device=dev),
+            torch.empty(nb_cap, dtype=torch.int32, device=dev))
+    offs_l = [int(v) for v in offs]
+
+    def graph():
+        pt.petar_step_graph(ctx_g, pos, mass, theta, leaf, group, r_in, r_out, r_s, acc_g,
+                            pot_g, sys_offsets=offs_l, nb=nb_g)
 
     def batched():
-        pt.petar_batch_build(ctx, offs, pos, mass, theta, leaf)
-        return pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot,
+        pt.petar_batch_build(ctx, offs_l, pos, mass, theta, leaf)
+        return pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc_b, pot=pot_b,
                                    nb_capacity=nb_cap)
 
     def sequential():
         tot = 0
         for k in range(sizes.size):
-            a, b = int(offs[k]), int(offs[k + 1])
+            a, b = offs_l[k], offs_l[k + 1]
             pt.petar_batch_build(ctx, [0, b - a], pos[:, a:b].contiguous(), mass[a:b], theta, leaf)
-            pt.petar_force_long(ctx, group, r_in[a:b], r_out[a:b], r_s[a:b], acc=None, pot=None,
-                                nb_capacity=64 * (b - a))
+            acc_k, pot_k, _ = pt.petar_force_long(ctx, group, r_in[a:b], r_out[a:b], r_s[a:b],
+                                                  nb_capacity=64 * (b - a))
+            acc_s[:, a:b] = acc_k
+            pot_s[a:b] = pot_k
             st = pt.petar_get_stats(ctx)
             tot += st["inter_pc"] + st["inter_far"] + st["inter_near"]
         return tot
 
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / steps
+
     for _ in range(args.warmup):
+        graph()
         batched()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        batched()
-    torch.cuda.synchronize()
-    ms_b = 1e3 * (time.perf_counter() - t1) / args.steps
+    ms_g = timed(graph, args.steps)
+    ms_b = timed(batched, args.steps)
     st = pt.petar_get_stats(ctx)
     inter = st["inter_pc"] + st["inter_far"] + st["inter_near"]
-    sequential()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
     inter_seq = sequential()
-    torch.cuda.synchronize()
-    ms_s = 1e3 * (time.perf_counter() - t2)
-    log("batched %.3f ms/step, sequential %.3f ms/step" % (ms_b, ms_s))
+    ms_s = timed(sequential, 1)
+    same_b = bool(torch.equal(acc_b, acc_s) and torch.equal(pot_b, pot_s))
+    same_g = bool(torch.equal(acc_g, acc_b) and torch.equal(pot_g, pot_b))
+    log("graph %.3f ms/step, batched eager %.3f ms/step, sequential %.3f ms/step; "
+        "bitwise batched==sequential %s, graph==batched %s" % (ms_g, ms_b, ms_s, same_b, same_g))
     line = {
         "metric": "tree-force interactions/s (batched clusters)",
-        "value": inter / (ms_b * 1e-3), "unit": "interactions/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b,
+        "value": inter / (ms_g * 1e-3), "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_g,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched128", "n_systems": int(sizes.size), "n": n,
-                   "theta": theta, "leaf_size": leaf, "group_size": group,
-                   "binary_fraction": 0.2},
-        "sequential_ms_per_step": ms_s, "speedup_vs_sequential": ms_s / ms_b,
+                   "theta": theta, "leaf_size": leaf, "group_size": group, "i_per_lane": ipl,
+                   "binary_fraction": 0.2, "mode": "hipGraph replay of the batched step"},
+        "batched_eager_ms_per_step": ms_b, "sequential_ms_per_step": ms_s,
+        "speedup_vs_sequential": ms_s / ms_g,
+        "bitwise_batched_eq_sequential": same_b, "bitwise_graph_eq_batched": same_g,
         "interactions": inter, "interactions_sequential": inter_seq,
         "stages_ms": {"build": st["ms_build"], "force_total": st["ms_force"],
                       "force_kernel": st["ms_force_kernel"], "neighbours": st["ms_nb"]},
     }
     print(json.dumps(line), flush=True)
-    return 0
+    return 0 if (same_b and same_g) else 1
 
 
 if __name__ == "__main__":

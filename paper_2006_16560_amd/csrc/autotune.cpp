@@ -82,7 +82,7 @@ void write_cache(const char *path, const std::vector<Entry> &entries) {
     for (const Entry &e : entries)
         std::fprintf(f,
                      "{\"n_bucket\": %d, \"theta\": %.17g, \"precision\": %d, \"leaf_size\": %d, "
-                     "\"group_size\": %d, \"i_per_lane\": %d, \"ms\": %.6f}\n",
+                     "\"group_size\": %d, \"i_per_lane\": %d, \"ms\": %.17g}\n",
                      e.nbucket, e.theta, e.precision, e.t.leaf_size, e.t.group_size,
                      e.t.i_per_lane, e.t.ms);
     std::fclose(f);

@@ -37,12 +37,12 @@ struct petar_ctx {
 
     // tree build
     DevBuf key0, key1, val0, val1, sort_ws, scan_ws, bbox_part, rootbox, status, emit, base;
-    DevBuf ps, orig, rr, rsk;
+    DevBuf ps, orig, rank, rr, rsk;
     DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_info, level_off;
     DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
-    DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbrec, sys_off;
-    uint32_t nbrec_cap = 0;
+    DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
+    uint32_t nbhead_cap = 0, nbleaf_cap = 0;
 
     Status *host_status = nullptr;  // pinned
     int64_t *host_scalar = nullptr; // pinned
@@ -149,6 +149,7 @@ TreeDev tree_view(petar_ctx *c) {
     t.rr = ptr<double2>(c->rr);
     t.rsk = ptr<double>(c->rsk);
     t.orig = ptr<uint32_t>(c->orig);
+    t.rank = ptr<uint32_t>(c->rank);
     t.nd_lo = ptr<double4>(c->nd_lo);
     t.nd_hi = ptr<double4>(c->nd_hi);
     t.nd_com = ptr<double4>(c->nd_com);
@@ -192,12 +193,12 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 void free_all(petar_ctx *c) {
     DevBuf *bufs[] = {&c->key0,     &c->key1,        &c->val0,       &c->val1,       &c->sort_ws,
                       &c->scan_ws,  &c->bbox_part,   &c->rootbox,    &c->status,     &c->emit,
-                      &c->base,     &c->ps,          &c->orig,       &c->rr,         &c->rsk,
+                      &c->base,     &c->ps,          &c->orig,       &c->rank,       &c->rr,         &c->rsk,
                       &c->nd_lo,    &c->nd_hi,       &c->nd_com,     &c->nd_S,       &c->nd_info,
                       &c->level_off, &c->pre_info,   &c->pre_parent, &c->pre_nchild, &c->new_of_old,
                       &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
                       &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
-                      &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws,   &c->nbrec,
+                      &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws,   &c->nbhead, &c->nbleaf,
                       &c->sys_off};
     for (DevBuf *b : bufs) {
         if (b->p) hipFree(b->p);
@@ -350,6 +351,7 @@ petar_status alloc_build_a(petar_ctx *ctx, const BuildArgs &a) {
     TRY(ensure(ctx, ctx->base, (N + 1) * 8));
     TRY(ensure(ctx, ctx->ps, N * sizeof(double4)));
     TRY(ensure(ctx, ctx->orig, N * 4));
+    TRY(ensure(ctx, ctx->rank, N * 4));
     TRY(ensure(ctx, ctx->level_off, 32 * 4));
     if (a.n_sys > 0) TRY(ensure(ctx, ctx->sys_off, (size_t)(a.n_sys + 1) * 8));
     return PETAR_OK;
@@ -397,7 +399,7 @@ void enqueue_build_a(petar_ctx *ctx, const BuildArgs &a, hipStream_t s) {
     }
     radix_sort(&k, &v, &ka, &va, a.n, 8, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s);
     launch_gather_particles(a.pos, a.mass, v, a.n, ptr<double4>(ctx->ps), ptr<uint32_t>(ctx->orig),
-                            s);
+                            ptr<uint32_t>(ctx->rank), s);
     launch_octree_count(k, a.n, a.leaf_size, levels, ptr<uint32_t>(ctx->emit), s);
     scan_u32_to_i64(ptr<uint32_t>(ctx->emit), ptr<int64_t>(ctx->base), a.n,
                     ptr<int64_t>(ctx->scan_ws), s);
@@ -421,7 +423,7 @@ void enqueue_build_b(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap, hipSt
                t.n_nodes_dev);
     launch_relayout(lv, pre, ptr<RootBox>(ctx->rootbox), k, levels, t,
                     ptr<uint32_t>(ctx->level_off), s);
-    for (int L = levels; L >= 0; L--) launch_moments_level(t, L, s);
+    launch_moments(t, levels, s);
     launch_tree_summary(t, st, s);
 }
 
@@ -505,12 +507,15 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
     if (ctx->params.record_counts) TRY(ensure(ctx, ctx->counts, (size_t)n * 4 * 4));
     if (a.nb) {
         TRY(ensure(ctx, ctx->nbcnt, (size_t)(n + 1) * 4));
-        // near-leaf records of the force walk; grown after a call overflowed
-        uint64_t want = (uint64_t)n_nodes * 2 + 4096;
-        if (want < ctx->nbrec_cap) want = ctx->nbrec_cap;
-        if (want > 0xffffffffull) want = 0xffffffffull;
-        TRY(ensure(ctx, ctx->nbrec, (size_t)want * sizeof(uint4)));
-        ctx->nbrec_cap = (uint32_t)want;
+        // near-leaf hand-over of the force walk; grown after a call overflowed
+        auto cap = [](uint64_t want, uint32_t have) {
+            if (want < have) want = have;
+            return (uint32_t)(want > 0xffffffffull ? 0xffffffffull : want);
+        };
+        ctx->nbhead_cap = cap((uint64_t)n_nodes + 4096, ctx->nbhead_cap);
+        ctx->nbleaf_cap = cap((uint64_t)n * 2 + 4096, ctx->nbleaf_cap);
+        TRY(ensure(ctx, ctx->nbhead, (size_t)ctx->nbhead_cap * sizeof(uint4)));
+        TRY(ensure(ctx, ctx->nbleaf, (size_t)ctx->nbleaf_cap * sizeof(uint2)));
     }
     TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n_nodes + n + 1) * 8));
     return PETAR_OK;
@@ -530,7 +535,7 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     zero_force_status(ctx, s);
     fill_u32(queue, 0, 64, s);
     launch_gather_radii(a.r_in, a.r_out, a.r_search, t, st, s);
-    for (int L = ctx->levels; L >= 0; L--) launch_rsmax_level(t, L, s);
+    launch_rsmax(t, ctx->levels, s);
     launch_group_flags(pre, t, a.group_size, ptr<uint32_t>(ctx->gflag), s);
     scan_u32_to_u32(ptr<uint32_t>(ctx->gflag), ptr<uint32_t>(ctx->gpos), n_nodes,
                     ptr<int64_t>(ctx->scan_ws), s);
@@ -549,9 +554,11 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     f.spill = ptr<uint32_t>(ctx->spill);
     f.queue = queue;
     f.counts = ctx->params.record_counts ? ptr<int32_t>(ctx->counts) : nullptr;
-    f.nb_rec = a.nb ? ptr<uint4>(ctx->nbrec) : nullptr;
-    f.nb_rec_count = queue + 16;
-    f.nb_rec_cap = a.nb ? ctx->nbrec_cap : 0;
+    f.nb.head = a.nb ? ptr<uint4>(ctx->nbhead) : nullptr;
+    f.nb.leaf = a.nb ? ptr<uint2>(ctx->nbleaf) : nullptr;
+    f.nb.count = queue + 16;  // [16] headers, [17] leaf entries (zeroed with the queue)
+    f.nb.head_cap = a.nb ? ctx->nbhead_cap : 0;
+    f.nb.leaf_cap = a.nb ? ctx->nbleaf_cap : 0;
     f.precision = prec;
     f.ipl = ipl;
     if (timed) (void)hipEventRecord(ctx->ev[4], s);
@@ -564,15 +571,13 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
         if (timed) (void)hipEventRecord(ctx->ev[6], s);
         uint32_t *cnt = ptr<uint32_t>(ctx->nbcnt);
         fill_u32(cnt, 0, n + 1, s);
-        launch_nb_count_rec(t, f.nb_rec, f.nb_rec_count, f.nb_rec_cap, st, cnt, s);
-        launch_nb_count(t, f.groups, st, cnt, f.spill, queue + 8, f.nb_rec_count, f.nb_rec_cap,
-                        ctx->nb_waves, s);
+        launch_nb_count_rec(t, f.nb, st, cnt, s);
+        launch_nb_count(t, f.groups, st, cnt, f.spill, queue + 8, f.nb, ctx->nb_waves, s);
         scan_u32_to_i64(cnt, nb->offsets_dev, n, ptr<int64_t>(ctx->scan_ws), s);
         fill_u32(cnt, 0, n + 1, s);
-        launch_nb_write_rec(t, f.nb_rec, f.nb_rec_count, f.nb_rec_cap, st, nb->offsets_dev, cnt,
-                            nb->idx_dev, nb->capacity, s);
+        launch_nb_write_rec(t, f.nb, st, nb->offsets_dev, cnt, nb->idx_dev, nb->capacity, s);
         launch_nb_write(t, f.groups, st, nb->offsets_dev, nb->idx_dev, nb->capacity, f.spill,
-                        queue + 9, f.nb_rec_count, f.nb_rec_cap, ctx->nb_waves, s);
+                        queue + 9, f.nb, ctx->nb_waves, s);
         launch_nb_sort(nb->offsets_dev, nb->idx_dev, n, nb->capacity, st, cnt, queue + 10, s);
         if (timed) (void)hipEventRecord(ctx->ev[7], s);
     }
@@ -585,7 +590,7 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
     if (a.nb) {
         HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, a.nb->offsets_dev + ctx->n, 8,
                                     hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 2, queue + 16, 4, hipMemcpyDeviceToHost,
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 2, queue + 16, 8, hipMemcpyDeviceToHost,
                                     s));
     }
     HIP_TRY(ctx, hipGetLastError());
@@ -608,11 +613,15 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
     }
     ctx->stats.workspace_bytes = ctx->ws_bytes;
     if (a.nb) {
-        uint32_t nrec = 0;
-        memcpy(&nrec, ctx->host_scalar + 2, 4);
-        if (nrec > ctx->nbrec_cap) {  // grow the records for the next call
-            uint64_t want = (uint64_t)nrec + nrec / 4;
-            ctx->nbrec_cap = (uint32_t)(want > 0xffffffffull ? 0xffffffffull : want);
+        uint32_t used[2] = {0, 0};  // hand-over headers and leaf entries claimed
+        memcpy(used, ctx->host_scalar + 2, 8);
+        auto grow = [](uint32_t need) {
+            uint64_t want = (uint64_t)need + need / 4;
+            return (uint32_t)(want > 0xffffffffull ? 0xffffffffull : want);
+        };
+        if (used[0] > ctx->nbhead_cap || used[1] > ctx->nbleaf_cap) {  // grow for the next call
+            if (used[0] > ctx->nbhead_cap) ctx->nbhead_cap = grow(used[0]);
+            if (used[1] > ctx->nbleaf_cap) ctx->nbleaf_cap = grow(used[1]);
             ctx->graph_stale = true;
         }
         a.nb->required = ctx->host_scalar[0];

@@ -331,12 +331,19 @@ __device__ uint32_t flush_leaves(WaveLds<R> &L, const uint32_t *start, uint32_t 
     const int lane = lane_id();
     uint32_t c = lane < nleaf ? pre[lane] : 0u;
     if (KIND == kTileNear && record) {
-        // hand the near leaves of this group to the neighbour-list passes
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(f.nb_rec_count, (uint32_t)nleaf);
-        base = (uint32_t)uniform((int)base);
-        if (lane < nleaf && base + (uint32_t)lane < f.nb_rec_cap)
-            f.nb_rec[base + lane] = make_uint4(gstart, gn, start[lane], c);
+        // hand the near leaves of this group to the neighbour-list passes:
+        // one header per flush and the flushed leaves
+        uint32_t hb = 0, lb = 0;
+        if (lane == 0) {
+            hb = atomicAdd(&f.nb.count[0], 1u);
+            lb = atomicAdd(&f.nb.count[1], (uint32_t)nleaf);
+        }
+        hb = (uint32_t)uniform((int)hb);
+        lb = (uint32_t)uniform((int)lb);
+        if (hb < f.nb.head_cap && (uint64_t)lb + (uint64_t)nleaf <= f.nb.leaf_cap) {
+            if (lane < nleaf) f.nb.leaf[lb + lane] = make_uint2(start[lane], c);
+            if (lane == 0) f.nb.head[hb] = make_uint4(gstart, gn, lb, (uint32_t)nleaf);
+        }
     }
     uint32_t incl = wave_incl_scan(c);
     uint32_t total = (uint32_t)uniform((int)__shfl(incl, kWave - 1, kWave));
@@ -436,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
             }
             uint64_t n_pc = 0, n_far = 0, n_near = 0;
             int npc = 0, nfar = 0, nnear = 0;
-            const bool record = f.nb_rec != nullptr && chunk == 0;
+            const bool record = f.nb.head != nullptr && chunk == 0;
             stk.init((uint32_t)uniform((int)root_of(f.t.nd_info, f.t.level_off, gstart)));
             bool ok = true;
             while (!stk.empty()) {

@@ -23,7 +23,8 @@ struct TreeDev {
     double4 *ps;
     double2 *rr;
     double *rsk;
-    uint32_t *orig;
+    uint32_t *orig;             // input index of each particle
+    uint32_t *rank;             // Morton position of each input index
     // cells
     double4 *nd_lo, *nd_hi, *nd_com;
     double *nd_S;
@@ -63,7 +64,8 @@ void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **v
                 const int64_t *n_dev = nullptr);
 
 void launch_gather_particles(const double *pos, const double *mass, const uint32_t *idx,
-                             int64_t n, double4 *ps, uint32_t *orig, hipStream_t s);
+                             int64_t n, double4 *ps, uint32_t *orig, uint32_t *rank,
+                             hipStream_t s);
 void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int levels,
                          uint32_t *emit, hipStream_t s);
 // Pre-order cells; also the level keys (lkey, lval) sorted next.
@@ -75,13 +77,13 @@ void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int leve
 // rb holds one root box per system (one in single-system mode).
 void launch_relayout(const uint32_t *perm, PreOrder pre, const RootBox *rb, const uint64_t *key,
                      int levels, TreeDev t, uint32_t *level_off, hipStream_t s);
-void launch_moments_level(const TreeDev &t, int level, hipStream_t s);
+void launch_moments(const TreeDev &t, int levels, hipStream_t s);
 void launch_tree_summary(const TreeDev &t, Status *st, hipStream_t s);
 
 // force_long preparation
 void launch_gather_radii(const double *r_in, const double *r_out, const double *r_search,
                          TreeDev t, Status *st, hipStream_t s);
-void launch_rsmax_level(const TreeDev &t, int level, hipStream_t s);
+void launch_rsmax(const TreeDev &t, int levels, hipStream_t s);
 // flag[] is written for every slot up to t.n_nodes (the capacity), 0 past the cells.
 void launch_group_flags(const PreOrder &pre, const TreeDev &t, int group_size, uint32_t *flag,
                         hipStream_t s);
@@ -94,6 +96,19 @@ void launch_changeover_radii(const double *mass, const double *vel, int64_t n, d
                              double *r_out, double *r_search, double *ws, hipStream_t s);
 
 // --------------------------------------------------------------- force.hip
+// Near leaves handed from the force walk to the neighbour passes: one header
+// per near flush of a group (group's first particle, group size, first leaf
+// entry, number of leaf entries) and the flushed leaves (first particle,
+// particle count), all in Morton order. count[0] and count[1] are the
+// headers and leaf entries claimed; either above its capacity means the
+// lists are incomplete and the walk-based passes run instead.
+struct NbRecords {
+    uint4 *head;
+    uint2 *leaf;
+    uint32_t *count;
+    uint32_t head_cap, leaf_cap;
+};
+
 struct ForceLaunch {
     TreeDev t;
     const uint32_t *groups;
@@ -105,10 +120,7 @@ struct ForceLaunch {
     uint32_t *spill;           // walk stack spill, per resident wave
     uint32_t *queue;           // 8 work-queue heads
     int32_t *counts;           // optional per-particle counts [4][n]
-    uint4 *nb_rec;             // near-leaf records (group first, group count, leaf first,
-                               // leaf count) for the neighbour lists; nullptr: none
-    uint32_t *nb_rec_count;    // records written (may exceed nb_rec_cap: overflow)
-    uint32_t nb_rec_cap;
+    NbRecords nb;              // near-leaf lists for the neighbour passes (head null: none)
     int precision;             // 0 mixed, 1 fp64
     int ipl;                   // 1, 2, 4
 };
@@ -118,24 +130,22 @@ void launch_force(const ForceLaunch &f, int resident_waves, hipStream_t s);
 
 // -------------------------------------------------------------- nblist.hip
 // Walk-based neighbour passes: run only when the near-leaf records of the
-// force walk overflowed (*rec_count > rec_cap; rec_count may be nullptr).
+// force walk overflowed (or were not written: rec.count == nullptr).
 void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cnt_orig,
-                     uint32_t *spill, uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
-                     int resident_waves, hipStream_t s);
+                     uint32_t *spill, uint32_t *queue, const NbRecords &rec, int resident_waves,
+                     hipStream_t s);
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
                      const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
-                     uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
-                     int resident_waves, hipStream_t s);
-// long_list holds n u32, long_count one u32 zeroed by the caller.
+                     uint32_t *queue, const NbRecords &rec, int resident_waves, hipStream_t s);
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
                     const Status *st, uint32_t *long_list, uint32_t *long_count, hipStream_t s);
 int nb_resident_waves(int device);
 // Neighbour passes over the near-leaf records of the force walk (no walk);
 // they do nothing when the records overflowed (*rec_count > rec_cap).
-void launch_nb_count_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
-                         uint32_t rec_cap, const Status *st, uint32_t *cnt_orig, hipStream_t s);
-void launch_nb_write_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
-                         uint32_t rec_cap, const Status *st, const int64_t *offsets,
-                         uint32_t *cursor, int32_t *idx, int64_t capacity, hipStream_t s);
+void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
+                         uint32_t *cnt_orig, hipStream_t s);
+void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
+                         const int64_t *offsets, uint32_t *cursor, int32_t *idx, int64_t capacity,
+                         hipStream_t s);
 
 }  // namespace petar

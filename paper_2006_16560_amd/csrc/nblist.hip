@@ -2,12 +2,13 @@
 // with |r_j - r_i| < max(r_search,i, r_search,j)), as CSR lists in input
 // order, each sorted by original index.
 //
-// Per i-group a wavefront walks only the near region: a cell is opened iff
-// its box is closer to the group's box than max(rs_group, rs_cell); the
-// leaves reached are tested pair by pair with the FP64 relation of common.h.
-// The box test is conservative for the pair test (same rounding, monotone),
-// so every candidate is found. Two passes (count, write) around one prefix
-// sum, then a per-list sort.
+// The force walk hands over, per i-group, every leaf whose box is closer to
+// the group's box than max(rs_group, rs_leaf); the pairs of the group with
+// those leaves are tested with the FP64 relation of common.h. The box test
+// is conservative for the pair test (same rounding, monotone), so every
+// candidate is found. Two passes (count, write) around one prefix sum, then
+// a per-list sort. If the hand-over buffers overflowed, a walk of the near
+// region per group (same opening rule) replaces the hand-over.
 #include "launch.h"
 #include "walk.h"
 
@@ -77,14 +78,14 @@ template <bool kWrite>
 __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *groups, Status *st,
                                                  uint32_t *cnt_orig, const int64_t *offsets,
                                                  int32_t *idx, int64_t capacity, uint32_t *spill,
-                                                 uint32_t *queue, const uint32_t *rec_count,
-                                                 uint32_t rec_cap) {
+                                                 uint32_t *queue, NbRecords rec) {
     __shared__ NbLds lds_all[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
     NbLds &L = lds_all[w];
     const int lane = lane_id();
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
-    if (rec_count && *rec_count <= rec_cap) return;  // the record passes run instead
+    if (rec.count && rec.count[0] <= rec.head_cap && rec.count[1] <= rec.leaf_cap)
+        return;  // the record passes run instead
     if (kWrite && offsets[t.n] > capacity) return;
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + w;
     const int64_t n_groups = st->n_groups;
@@ -157,73 +158,147 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
     }
 }
 
-// Neighbour passes over the near-leaf records written by the force walk:
-// one wave per record (group particles x leaf particles), FP64 pair test.
-// Counting adds 1 per hit; writing takes a slot per hit from a per-target
-// cursor (the lists are sorted afterwards, so the slot order is irrelevant).
+// Neighbour passes over the near leaves handed over by the force walk. A
+// wave takes one header at a time: the group's targets sit in the lanes
+// (FP64 position and search radius in registers; a group of g < 64 targets
+// puts each target on 64/g lanes that split the source loop), the leaves'
+// particles are staged in LDS 64 at a time with one load per lane, and every
+// lane tests its target against its share of the staged particles (LDS
+// broadcasts). Counting adds a lane's hits once per header; writing takes a
+// slot per hit from a per-target cursor (the lists are sorted afterwards, so
+// the slot order is irrelevant).
+struct NbRecLds {
+    uint32_t start[kWave], pre[kWave];
+    double4 jp[kWave];  // x, y, z, r_search
+    uint32_t jk[kWave];
+};
+
 template <bool kWrite>
-__global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, const uint4 *rec,
-                                                     const uint32_t *rec_count, const Status *st,
+__global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, const Status *st,
                                                      uint32_t *cnt_orig, const int64_t *offsets,
                                                      uint32_t *cursor, int32_t *idx,
-                                                     int64_t capacity, uint32_t rec_cap) {
+                                                     int64_t capacity) {
+    __shared__ NbRecLds lds_all[kWavesPerBlock];
+    NbRecLds &L = lds_all[threadIdx.x / kWave];
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
     if (kWrite && offsets[t.n] > capacity) return;
-    const uint32_t nrec = *rec_count;
-    if (nrec > rec_cap) return;  // overflowed: the walk-based passes run instead
+    const uint32_t nrec = rec.count[0];
+    if (nrec > rec.head_cap || rec.count[1] > rec.leaf_cap) return;  // walk-based passes run
     const int lane = lane_id();
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     for (int64_t r = wave0; r < nrec; r += nwaves) {
-        const uint4 q = rec[r];  // group first, group count, leaf first, leaf count
-        const uint32_t pairs = q.y * q.w;
-        for (uint32_t p = lane; p < pairs; p += kWave) {
-            const uint32_t a = p / q.w, b = p - a * q.w;
-            const uint32_t ki = q.x + a, kj = q.z + b;
-            if (ki == kj) continue;
-            const double4 pi = t.ps[ki], pj = t.ps[kj];
-            if (!nb_pair(pi.x, pi.y, pi.z, t.rsk[ki], pj.x, pj.y, pj.z, t.rsk[kj])) continue;
+        const uint4 q = rec.head[r];
+        const uint32_t gfirst = (uint32_t)uniform((int)q.x), gn = (uint32_t)uniform((int)q.y);
+        const uint32_t loff = (uint32_t)uniform((int)q.z);
+        const int nleaf = uniform((int)q.w);
+        uint2 lf = make_uint2(0u, 0u);
+        if (lane < nleaf) lf = rec.leaf[loff + lane];
+        const uint32_t incl = wave_incl_scan(lf.y);
+        const uint32_t total = (uint32_t)uniform((int)__shfl(incl, kWave - 1, kWave));
+        wave_sync();
+        if (lane < nleaf) {
+            L.start[lane] = lf.x;
+            L.pre[lane] = incl - lf.y;
+        }
+        wave_sync();
+        for (uint32_t a0 = 0; a0 < gn; a0 += kWave) {
+            const int g = (int)(gn - a0 < (uint32_t)kWave ? gn - a0 : (uint32_t)kWave);
+            const int S = kWave / g;  // lanes per target
+            const int a = lane % g, sl = lane / g;
+            const bool act = sl < S;
+            const uint32_t ki = gfirst + a0 + (uint32_t)a;
+            const double4 pi = t.ps[ki];
+            const double rsi = t.rsk[ki];
             const uint32_t oi = t.orig[ki];
-            if (kWrite) {
-                const uint32_t slot = atomicAdd(&cursor[oi], 1u);
-                idx[offsets[oi] + slot] = (int32_t)t.orig[kj];
-            } else {
-                atomicAdd(&cnt_orig[oi], 1u);
+            uint32_t c = 0;
+            for (uint32_t base = 0; base < total; base += kWave) {
+                const uint32_t sidx = base + lane;
+                if (sidx < total) {
+                    const int l = find_leaf(L.pre, nleaf, sidx);
+                    const uint32_t k = L.start[l] + (sidx - L.pre[l]);
+                    const double4 p = t.ps[k];
+                    L.jp[lane] = make_double4(p.x, p.y, p.z, t.rsk[k]);
+                    L.jk[lane] = k;
+                }
+                wave_sync();
+                const int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
+                if (act) {
+                    for (int j = sl; j < m; j += S) {
+                        const double4 pj = L.jp[j];
+                        if (nb_pair(pi.x, pi.y, pi.z, rsi, pj.x, pj.y, pj.z, pj.w)) {
+                            const uint32_t kj = L.jk[j];
+                            if (kj == ki) continue;
+                            if (kWrite) {
+                                const uint32_t slot = atomicAdd(&cursor[oi], 1u);
+                                idx[offsets[oi] + slot] = (int32_t)t.orig[kj];
+                            } else {
+                                c++;
+                            }
+                        }
+                    }
+                }
+                wave_sync();
             }
+            if (!kWrite && c) atomicAdd(&cnt_orig[oi], c);
         }
     }
 }
 
-// Sorts each list ascending. Short lists (<= 32 entries, almost all) are
-// insertion-sorted by one thread; longer ones are queued and sorted by a
-// whole block with a bitonic network in LDS (heap sort by one thread above
-// kLongMax entries).
+// Sorts each list ascending. A block takes 256 consecutive targets; their
+// lists are contiguous, so the block stages them in LDS with coalesced reads
+// (when they fit), each thread insertion-sorts its own short list there
+// (<= 32 entries, almost all), and the block writes them back. Longer lists
+// are queued for a whole block each: bitonic network in LDS, or heap sort
+// by one thread above kLongMax entries.
 constexpr int kShortMax = 32;
 constexpr int kLongMax = 4096;
+constexpr int kStage = 4096;
+
+__device__ __forceinline__ void insertion_sort(int32_t *a, int64_t len) {
+    for (int64_t p = 1; p < len; p++) {
+        int32_t v = a[p];
+        int64_t q = p - 1;
+        while (q >= 0 && a[q] > v) {
+            a[q + 1] = a[q];
+            q--;
+        }
+        a[q + 1] = v;
+    }
+}
 
 __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offsets, int32_t *idx,
                                                             int64_t n, int64_t capacity,
                                                             const Status *st, uint32_t *long_list,
                                                             uint32_t *long_count) {
+    __shared__ int32_t sh[kStage];
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow || offsets[n] > capacity)
         return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t b = offsets[i], e = offsets[i + 1];
-        int64_t len = e - b;
-        if (len > kShortMax) {
-            long_list[atomicAdd(long_count, 1u)] = (uint32_t)i;
-            continue;
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < n;
+         base += (int64_t)gridDim.x * kThreads) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t iend = base + kThreads < n ? base + kThreads : n;
+        const int64_t r0 = offsets[base], r1 = offsets[iend];
+        const bool staged = r1 - r0 <= kStage;  // same for the whole block
+        int64_t b = 0, len = 0;
+        if (i < n) {
+            b = offsets[i];
+            len = offsets[i + 1] - b;
         }
-        int32_t *a = idx + b;
-        for (int64_t p = 1; p < len; p++) {
-            int32_t v = a[p];
-            int64_t q = p - 1;
-            while (q >= 0 && a[q] > v) {
-                a[q + 1] = a[q];
-                q--;
-            }
-            a[q + 1] = v;
+        if (staged) {
+            for (int64_t p = threadIdx.x; p < r1 - r0; p += kThreads) sh[p] = idx[r0 + p];
+            __syncthreads();
+        }
+        if (i < n) {
+            if (len > kShortMax)
+                long_list[atomicAdd(long_count, 1u)] = (uint32_t)i;
+            else if (len > 1)
+                insertion_sort(staged ? sh + (b - r0) : idx + b, len);
+        }
+        if (staged) {
+            __syncthreads();
+            for (int64_t p = threadIdx.x; p < r1 - r0; p += kThreads) idx[r0 + p] = sh[p];
+            __syncthreads();
         }
     }
 }
@@ -317,35 +392,33 @@ int nb_resident_waves(int device) {
     return per_cu * p.multiProcessorCount * kWavesPerBlock;
 }
 
-void launch_nb_count_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
-                         uint32_t rec_cap, const Status *st, uint32_t *cnt_orig, hipStream_t s) {
-    hipLaunchKernelGGL(k_nb_rec<false>, dim3(4096), dim3(kThreads), 0, s, t, rec, rec_count, st,
-                       cnt_orig, (const int64_t *)nullptr, (uint32_t *)nullptr,
-                       (int32_t *)nullptr, (int64_t)0, rec_cap);
+void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
+                         uint32_t *cnt_orig, hipStream_t s) {
+    hipLaunchKernelGGL(k_nb_rec<false>, dim3(2048), dim3(kThreads), 0, s, t, rec, st, cnt_orig,
+                       (const int64_t *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr,
+                       (int64_t)0);
 }
 
-void launch_nb_write_rec(const TreeDev &t, const uint4 *rec, const uint32_t *rec_count,
-                         uint32_t rec_cap, const Status *st, const int64_t *offsets,
-                         uint32_t *cursor, int32_t *idx, int64_t capacity, hipStream_t s) {
-    hipLaunchKernelGGL(k_nb_rec<true>, dim3(4096), dim3(kThreads), 0, s, t, rec, rec_count, st,
-                       (uint32_t *)nullptr, offsets, cursor, idx, capacity, rec_cap);
+void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
+                         const int64_t *offsets, uint32_t *cursor, int32_t *idx, int64_t capacity,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_nb_rec<true>, dim3(2048), dim3(kThreads), 0, s, t, rec, st,
+                       (uint32_t *)nullptr, offsets, cursor, idx, capacity);
 }
 
 void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cnt_orig,
-                     uint32_t *spill, uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
-                     int resident_waves, hipStream_t s) {
+                     uint32_t *spill, uint32_t *queue, const NbRecords &rec, int resident_waves,
+                     hipStream_t s) {
     hipLaunchKernelGGL(k_nb<false>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
                        groups, st, cnt_orig, (const int64_t *)nullptr, (int32_t *)nullptr,
-                       (int64_t)0, spill, queue, rec_count, rec_cap);
+                       (int64_t)0, spill, queue, rec);
 }
 
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
                      const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
-                     uint32_t *queue, const uint32_t *rec_count, uint32_t rec_cap,
-                     int resident_waves, hipStream_t s) {
+                     uint32_t *queue, const NbRecords &rec, int resident_waves, hipStream_t s) {
     hipLaunchKernelGGL(k_nb<true>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
-                       groups, st, (uint32_t *)nullptr, offsets, idx, capacity, spill, queue,
-                       rec_count, rec_cap);
+                       groups, st, (uint32_t *)nullptr, offsets, idx, capacity, spill, queue, rec);
 }
 
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,

@@ -301,16 +301,27 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_i
 }
 
 // ------------------------------------------------------------ gathers
-__global__ __launch_bounds__(kThreads) void k_gather_particles(const double *pos,
-                                                               const double *mass,
-                                                               const uint32_t *idx, int64_t n,
-                                                               double4 *ps, uint32_t *orig) {
+// orig[k] = input index of the k-th particle in Morton order; rank is its
+// inverse. The particle data are then moved with coalesced reads in input
+// order and scattered writes (which the caches merge), rather than with
+// scattered reads of four separate arrays.
+__global__ __launch_bounds__(kThreads) void k_rank(const uint32_t *idx, int64_t n, uint32_t *orig,
+                                                   uint32_t *rank) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t o = idx[k];
-        ps[k] = make_double4(pos[o], pos[n + o], pos[2 * n + o], mass[o]);
+        const uint32_t o = idx[k];
         orig[k] = o;
+        rank[o] = (uint32_t)k;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter_particles(const double *pos,
+                                                                const double *mass,
+                                                                const uint32_t *rank, int64_t n,
+                                                                double4 *ps) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        ps[rank[i]] = make_double4(pos[i], pos[n + i], pos[2 * n + i], mass[i]);
 }
 
 // ------------------------------------------------------------ octree
@@ -364,28 +375,42 @@ __device__ __forceinline__ int first_level(const uint64_t *key, int64_t k, int l
 // its parent holds more than leaf_size particles. Each particle emits the
 // chain of existing cells it starts, from the shallowest; ordering the
 // emitted cells by (first particle, level) is a depth-first pre-order.
+//
+// Both tests only compare a cell size with leaf_size, so they need no search
+// over the sorted keys:
+//  * the level-L cell holding k-1 and k has more than leaf_size particles iff
+//    some window [j, j + leaf_size] with k - leaf_size <= j < k lies in one
+//    level-L cell;
+//  * the level-l cell starting at k holds at most leaf_size particles iff
+//    key[k + leaf_size] (if any) is outside it, i.e. the chain ends at
+//    level max(first_level, common_digits(k, k + leaf_size) + 1), capped
+//    at the deepest level.
+__device__ __forceinline__ bool parent_big(const uint64_t *key, int64_t n, int64_t k, int L,
+                                           int leaf_size, int levels) {
+    const int64_t j0 = k - leaf_size > 0 ? k - leaf_size : 0;
+    for (int64_t j = j0; j < k; j++) {
+        if (j + leaf_size >= n) break;
+        if (common_digits(key[j], key[j + leaf_size], levels) >= L) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ int chain_last(const uint64_t *key, int64_t n, int64_t k, int l0,
+                                          int leaf_size, int levels) {
+    const int cd = k + leaf_size < n ? common_digits(key[k], key[k + leaf_size], levels) : -1;
+    int last = cd + 1 > l0 ? cd + 1 : l0;
+    return last < levels ? last : levels;
+}
+
 __global__ __launch_bounds__(kThreads) void k_octree_count(const uint64_t *key, int64_t n,
                                                            int leaf_size, int levels,
                                                            uint32_t *emit) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
-        int l0 = first_level(key, k, levels);
+        const int l0 = first_level(key, k, levels);
         uint32_t cnt = 0;
-        if (l0 <= levels) {
-            bool exists = true;
-            if (l0 > 0) {
-                int L = l0 - 1;
-                int64_t s = run_start(key, k, L, levels), e = run_end(key, n, k, L, levels);
-                exists = (e - s) > leaf_size;
-            }
-            if (exists) {
-                for (int l = l0;; l++) {
-                    cnt++;
-                    int64_t e = run_end(key, n, k, l, levels);
-                    if (e - k <= leaf_size || l == levels) break;
-                }
-            }
-        }
+        if (l0 <= levels && (l0 == 0 || parent_big(key, n, k, l0 - 1, leaf_size, levels)))
+            cnt = (uint32_t)(chain_last(key, n, k, l0, leaf_size, levels) - l0 + 1);
         emit[k] = cnt;
     }
 }
@@ -405,8 +430,18 @@ __global__ __launch_bounds__(kThreads) void k_octree_write(const uint64_t *key, 
         for (int u = 0; u < nemit; u++) {
             int l = l0 + u;
             uint32_t idx = (uint32_t)(b + u);
-            int64_t e = run_end(key, n, k, l, levels);
-            uint32_t cnt = (uint32_t)(e - k);
+            // the last cell of the chain holds <= leaf_size particles unless it
+            // sits at the deepest level; the others hold more
+            const bool small = u == nemit - 1 && (k + leaf_size >= n ||
+                               common_digits(key[k], key[k + leaf_size], levels) < l);
+            uint32_t cnt = 1;
+            if (small) {
+                while (cnt < (uint32_t)leaf_size && k + cnt < n &&
+                       common_digits(key[k], key[k + cnt], levels) >= l)
+                    cnt++;
+            } else {
+                cnt = (uint32_t)(run_end(key, n, k, l, levels) - k);
+            }
             bool leaf = (cnt <= (uint32_t)leaf_size) || l == levels;
             pre.info[idx] = make_uint4((uint32_t)k, cnt, (leaf ? kLeafFlag : 0u) | ((uint32_t)l << 1),
                                        0u);
@@ -485,122 +520,142 @@ __global__ void k_level_offsets(TreeDev t, uint32_t *level_off) {
     level_off[l] = (uint32_t)lo;
 }
 
-// Bottom-up cell data for one level. Leaves sum their particles (two passes:
-// centre of mass, then the second moment about it); other cells combine their
-// children with the parallel-axis shift.
+// Cell data of cell c. Leaves sum their particles (two passes: centre of
+// mass, then the second moment about it); other cells combine their children
+// with the parallel-axis shift.
+__device__ void cell_moments(const TreeDev &t, uint32_t c) {
+    uint4 info = t.nd_info[c];
+    double M = 0, sx = 0, sy = 0, sz = 0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double S[6] = {0, 0, 0, 0, 0, 0};
+    double cx, cy, cz;
+    if (info.z & kLeafFlag) {
+        for (uint32_t k = info.x; k < info.x + info.y; k++) {
+            double4 p = t.ps[k];
+            M += p.w;
+            sx += p.w * p.x;
+            sy += p.w * p.y;
+            sz += p.w * p.z;
+            lo[0] = fmin(lo[0], p.x);
+            lo[1] = fmin(lo[1], p.y);
+            lo[2] = fmin(lo[2], p.z);
+            hi[0] = fmax(hi[0], p.x);
+            hi[1] = fmax(hi[1], p.y);
+            hi[2] = fmax(hi[2], p.z);
+        }
+        if (M > 0.0) {
+            cx = sx / M;
+            cy = sy / M;
+            cz = sz / M;
+        } else {
+            cx = 0.5 * (lo[0] + hi[0]);
+            cy = 0.5 * (lo[1] + hi[1]);
+            cz = 0.5 * (lo[2] + hi[2]);
+        }
+        for (uint32_t k = info.x; k < info.x + info.y; k++) {
+            double4 p = t.ps[k];
+            double qx = p.x - cx, qy = p.y - cy, qz = p.z - cz;
+            S[0] += p.w * qx * qx;
+            S[1] += p.w * qy * qy;
+            S[2] += p.w * qz * qz;
+            S[3] += p.w * qx * qy;
+            S[4] += p.w * qx * qz;
+            S[5] += p.w * qy * qz;
+        }
+    } else {
+        const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
+        for (uint32_t o = first; o < first + nc; o++) {
+            double4 cm = t.nd_com[o];
+            double4 l4 = t.nd_lo[o], h4 = t.nd_hi[o];
+            M += cm.w;
+            sx += cm.w * cm.x;
+            sy += cm.w * cm.y;
+            sz += cm.w * cm.z;
+            lo[0] = fmin(lo[0], l4.x);
+            lo[1] = fmin(lo[1], l4.y);
+            lo[2] = fmin(lo[2], l4.z);
+            hi[0] = fmax(hi[0], h4.x);
+            hi[1] = fmax(hi[1], h4.y);
+            hi[2] = fmax(hi[2], h4.z);
+        }
+        if (M > 0.0) {
+            cx = sx / M;
+            cy = sy / M;
+            cz = sz / M;
+        } else {
+            cx = 0.5 * (lo[0] + hi[0]);
+            cy = 0.5 * (lo[1] + hi[1]);
+            cz = 0.5 * (lo[2] + hi[2]);
+        }
+        for (uint32_t o = first; o < first + nc; o++) {
+            double4 cm = t.nd_com[o];
+            const double *Sc = t.nd_S + (int64_t)o * 6;
+            double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
+            S[0] += Sc[0] + cm.w * dx * dx;
+            S[1] += Sc[1] + cm.w * dy * dy;
+            S[2] += Sc[2] + cm.w * dz * dz;
+            S[3] += Sc[3] + cm.w * dx * dy;
+            S[4] += Sc[4] + cm.w * dx * dz;
+            S[5] += Sc[5] + cm.w * dy * dz;
+        }
+    }
+    t.nd_com[c] = make_double4(cx, cy, cz, M);
+    double4 l4 = t.nd_lo[c];
+    l4.x = lo[0];
+    l4.y = lo[1];
+    l4.z = lo[2];
+    t.nd_lo[c] = l4;
+    double side = t.nd_hi[c].w;
+    t.nd_hi[c] = make_double4(hi[0], hi[1], hi[2], side);
+    for (int k = 0; k < 6; k++) t.nd_S[(int64_t)c * 6 + k] = S[k];
+}
+
+// Bottom-up cell data: every leaf in one launch (leaves of all levels are
+// independent), then one launch per level, deepest first, for the other
+// cells (each combines its children, which are complete by then).
+__global__ __launch_bounds__(kThreads) void k_moments_leaves(TreeDev t) {
+    const int64_t n_nodes = *t.n_nodes_dev;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
+         c += (int64_t)gridDim.x * blockDim.x)
+        if (t.nd_info[c].z & kLeafFlag) cell_moments(t, (uint32_t)c);
+}
+
 __global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level) {
     const uint32_t beg = t.level_off[level], end = t.level_off[level + 1];
     for (int64_t c = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < end;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        uint4 info = t.nd_info[c];
-        double M = 0, sx = 0, sy = 0, sz = 0;
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        double S[6] = {0, 0, 0, 0, 0, 0};
-        double cx, cy, cz;
-        if (info.z & kLeafFlag) {
-            for (uint32_t k = info.x; k < info.x + info.y; k++) {
-                double4 p = t.ps[k];
-                M += p.w;
-                sx += p.w * p.x;
-                sy += p.w * p.y;
-                sz += p.w * p.z;
-                lo[0] = fmin(lo[0], p.x);
-                lo[1] = fmin(lo[1], p.y);
-                lo[2] = fmin(lo[2], p.z);
-                hi[0] = fmax(hi[0], p.x);
-                hi[1] = fmax(hi[1], p.y);
-                hi[2] = fmax(hi[2], p.z);
-            }
-            if (M > 0.0) {
-                cx = sx / M;
-                cy = sy / M;
-                cz = sz / M;
-            } else {
-                cx = 0.5 * (lo[0] + hi[0]);
-                cy = 0.5 * (lo[1] + hi[1]);
-                cz = 0.5 * (lo[2] + hi[2]);
-            }
-            for (uint32_t k = info.x; k < info.x + info.y; k++) {
-                double4 p = t.ps[k];
-                double qx = p.x - cx, qy = p.y - cy, qz = p.z - cz;
-                S[0] += p.w * qx * qx;
-                S[1] += p.w * qy * qy;
-                S[2] += p.w * qz * qz;
-                S[3] += p.w * qx * qy;
-                S[4] += p.w * qx * qz;
-                S[5] += p.w * qy * qz;
-            }
-        } else {
-            const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
-            for (uint32_t o = first; o < first + nc; o++) {
-                double4 cm = t.nd_com[o];
-                double4 l4 = t.nd_lo[o], h4 = t.nd_hi[o];
-                M += cm.w;
-                sx += cm.w * cm.x;
-                sy += cm.w * cm.y;
-                sz += cm.w * cm.z;
-                lo[0] = fmin(lo[0], l4.x);
-                lo[1] = fmin(lo[1], l4.y);
-                lo[2] = fmin(lo[2], l4.z);
-                hi[0] = fmax(hi[0], h4.x);
-                hi[1] = fmax(hi[1], h4.y);
-                hi[2] = fmax(hi[2], h4.z);
-            }
-            if (M > 0.0) {
-                cx = sx / M;
-                cy = sy / M;
-                cz = sz / M;
-            } else {
-                cx = 0.5 * (lo[0] + hi[0]);
-                cy = 0.5 * (lo[1] + hi[1]);
-                cz = 0.5 * (lo[2] + hi[2]);
-            }
-            for (uint32_t o = first; o < first + nc; o++) {
-                double4 cm = t.nd_com[o];
-                const double *Sc = t.nd_S + (int64_t)o * 6;
-                double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
-                S[0] += Sc[0] + cm.w * dx * dx;
-                S[1] += Sc[1] + cm.w * dy * dy;
-                S[2] += Sc[2] + cm.w * dz * dz;
-                S[3] += Sc[3] + cm.w * dx * dy;
-                S[4] += Sc[4] + cm.w * dx * dz;
-                S[5] += Sc[5] + cm.w * dy * dz;
-            }
-        }
-        t.nd_com[c] = make_double4(cx, cy, cz, M);
-        double4 l4 = t.nd_lo[c];
-        l4.x = lo[0];
-        l4.y = lo[1];
-        l4.z = lo[2];
-        t.nd_lo[c] = l4;
-        double side = t.nd_hi[c].w;
-        t.nd_hi[c] = make_double4(hi[0], hi[1], hi[2], side);
-        for (int k = 0; k < 6; k++) t.nd_S[(int64_t)c * 6 + k] = S[k];
-    }
+         c += (int64_t)gridDim.x * blockDim.x)
+        if (!(t.nd_info[c].z & kLeafFlag)) cell_moments(t, (uint32_t)c);
 }
 
 __global__ __launch_bounds__(kThreads) void k_tree_summary(TreeDev t, Status *st) {
+    __shared__ uint32_t sh[kThreads / kWave];
     const int64_t n_nodes = *t.n_nodes_dev;
     uint32_t leaves = 0;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
          c += (int64_t)gridDim.x * blockDim.x)
         leaves += t.nd_info[c].z & kLeafFlag;
     leaves = wave_sum(leaves);
-    if (lane_id() == 0 && leaves)
-        atomicAdd((unsigned long long *)&st->n_leaves, (unsigned long long)leaves);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n_nodes > 0)
-        st->max_level = info_level(t.nd_info[n_nodes - 1].z);
+    if (lane_id() == 0) sh[threadIdx.x / kWave] = leaves;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int w = 0; w < kThreads / kWave; w++) b += sh[w];
+        if (b) atomicAdd((unsigned long long *)&st->n_leaves, (unsigned long long)b);
+        if (blockIdx.x == 0 && n_nodes > 0) st->max_level = info_level(t.nd_info[n_nodes - 1].z);
+    }
 }
 
 // ------------------------------------------------------- force preparation
+// Radii into Morton order (coalesced reads, scattered writes), with the
+// validity check 0 <= r_in < r_out <= r_search (all finite).
 __global__ __launch_bounds__(kThreads) void k_gather_radii(const double *r_in, const double *r_out,
                                                            const double *r_search, TreeDev t,
                                                            Status *st) {
     int bad = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < t.n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t o = t.orig[k];
-        double a = r_in[o], b = r_out[o], c = r_search[o];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < t.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = t.rank[i];
+        double a = r_in[i], b = r_out[i], c = r_search[i];
         if (!(isfinite(a) && isfinite(b) && isfinite(c) && a >= 0.0 && a < b && b <= c)) bad = 1;
         t.rr[k] = make_double2(a, b);
         t.rsk[k] = c;
@@ -608,20 +663,32 @@ __global__ __launch_bounds__(kThreads) void k_gather_radii(const double *r_in, c
     if (__ballot(bad) && lane_id() == 0) atomicAdd(&st->invalid_radii, 1);
 }
 
+// Largest search radius per cell, bottom-up (leaves, then one launch per
+// level for the other cells).
+__device__ __forceinline__ void cell_rsmax(const TreeDev &t, uint32_t c) {
+    const uint4 info = t.nd_info[c];
+    double r = 0.0;
+    if (info.z & kLeafFlag) {
+        for (uint32_t k = info.x; k < info.x + info.y; k++) r = fmax(r, t.rsk[k]);
+    } else {
+        const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
+        for (uint32_t o = first; o < first + nc; o++) r = fmax(r, t.nd_lo[o].w);
+    }
+    t.nd_lo[c].w = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_rsmax_leaves(TreeDev t) {
+    const int64_t n_nodes = *t.n_nodes_dev;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
+         c += (int64_t)gridDim.x * blockDim.x)
+        if (t.nd_info[c].z & kLeafFlag) cell_rsmax(t, (uint32_t)c);
+}
+
 __global__ __launch_bounds__(kThreads) void k_rsmax_level(TreeDev t, int level) {
     const uint32_t beg = t.level_off[level], end = t.level_off[level + 1];
     for (int64_t c = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < end;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        uint4 info = t.nd_info[c];
-        double r = 0.0;
-        if (info.z & kLeafFlag) {
-            for (uint32_t k = info.x; k < info.x + info.y; k++) r = fmax(r, t.rsk[k]);
-        } else {
-            const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
-            for (uint32_t o = first; o < first + nc; o++) r = fmax(r, t.nd_lo[o].w);
-        }
-        t.nd_lo[c].w = r;
-    }
+         c += (int64_t)gridDim.x * blockDim.x)
+        if (!(t.nd_info[c].z & kLeafFlag)) cell_rsmax(t, (uint32_t)c);
 }
 
 // i-groups: the first cells on each root-to-leaf path holding <= group_size
@@ -675,12 +742,13 @@ __global__ __launch_bounds__(kThreads) void k_mass_partial(const double *mass, i
 }
 
 // Mean mass <m> = (sum m)/N, summed in a fixed order (deterministic).
+// Mean mass from the block partials: one wave, strided partial sums, then a
+// butterfly (a fixed order, so the result is reproducible).
 __global__ void k_mass_final(double *part, int nblk, int64_t n) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double msum = 0.0;
-        for (int b = 0; b < nblk; b++) msum += part[b];
-        part[nblk] = msum / (double)n;
-    }
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kWave) v += part[b];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) part[nblk] = v / (double)n;
 }
 
 __global__ __launch_bounds__(kThreads) void k_radii(const double *mass, const double *vel,
@@ -764,9 +832,12 @@ void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **v
 }
 
 void launch_gather_particles(const double *pos, const double *mass, const uint32_t *idx,
-                             int64_t n, double4 *ps, uint32_t *orig, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_particles, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s,
-                       pos, mass, idx, n, ps, orig);
+                             int64_t n, double4 *ps, uint32_t *orig, uint32_t *rank,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, idx, n,
+                       orig, rank);
+    hipLaunchKernelGGL(k_scatter_particles, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0,
+                       s, pos, mass, (const uint32_t *)rank, n, ps);
 }
 
 void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int levels,
@@ -792,13 +863,16 @@ void launch_relayout(const uint32_t *perm, PreOrder pre, const RootBox *rb, cons
     hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(32), 0, s, t, level_off);
 }
 
-void launch_moments_level(const TreeDev &t, int level, hipStream_t s) {
-    hipLaunchKernelGGL(k_moments_level, dim3(grid_for(t.n_nodes, kThreads, 2048)), dim3(kThreads),
-                       0, s, t, level);
+void launch_moments(const TreeDev &t, int levels, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments_leaves, dim3(grid_for(t.n_nodes, kThreads, 8192)), dim3(kThreads),
+                       0, s, t);
+    for (int l = levels - 1; l >= 0; l--)
+        hipLaunchKernelGGL(k_moments_level, dim3(grid_for(t.n_nodes, kThreads, 1024)),
+                           dim3(kThreads), 0, s, t, l);
 }
 
 void launch_tree_summary(const TreeDev &t, Status *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_tree_summary, dim3(grid_for(t.n_nodes, kThreads, 1024)), dim3(kThreads), 0,
+    hipLaunchKernelGGL(k_tree_summary, dim3(grid_for(t.n_nodes, kThreads, 256)), dim3(kThreads), 0,
                        s, t, st);
 }
 
@@ -808,9 +882,12 @@ void launch_gather_radii(const double *r_in, const double *r_out, const double *
                        r_in, r_out, r_search, t, st);
 }
 
-void launch_rsmax_level(const TreeDev &t, int level, hipStream_t s) {
-    hipLaunchKernelGGL(k_rsmax_level, dim3(grid_for(t.n_nodes, kThreads, 2048)), dim3(kThreads), 0,
-                       s, t, level);
+void launch_rsmax(const TreeDev &t, int levels, hipStream_t s) {
+    hipLaunchKernelGGL(k_rsmax_leaves, dim3(grid_for(t.n_nodes, kThreads, 8192)), dim3(kThreads), 0,
+                       s, t);
+    for (int l = levels - 1; l >= 0; l--)
+        hipLaunchKernelGGL(k_rsmax_level, dim3(grid_for(t.n_nodes, kThreads, 1024)), dim3(kThreads),
+                           0, s, t, l);
 }
 
 void launch_group_flags(const PreOrder &pre, const TreeDev &t, int group_size, uint32_t *flag,

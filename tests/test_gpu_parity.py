@@ -148,6 +148,107 @@ def test_plummer64k_b50_config(pt, ctx, orc):
     assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
 
 
+@pytest.mark.parametrize("leaf", [1, 2, 8, 16, 33])
+@pytest.mark.parametrize("n,bf", [(1000, 0.0), (30000, 0.5)])
+def test_tree_shape_matches_oracle(pt, ctx, orc, n, bf, leaf):
+    """Cell, leaf and group counts and the depth equal the oracle's tree."""
+    c, rin, rout, rs = cluster_with_radii(orc, n, 21, bf=bf)
+    run(pt, ctx, c.pos, c.mass, rin, rout, rs, 0.5, leaf, 48, pt.PETAR_MIXED)
+    st = pt.petar_get_stats(ctx)
+    ref = orc.tree_info(c.pos, c.mass, leaf, 48)
+    assert (st["n_nodes"], st["n_leaves"], st["n_groups"], st["max_level"]) == \
+        (ref["n_cells"], ref["n_leaves"], ref["n_groups"], ref["max_level"])
+
+
+# ------------------------------------------------- full-size configurations
+
+def _csr_valid(offs, idx, n):
+    """Rows strictly ascending, no self, the relation symmetric."""
+    assert offs[0] == 0 and offs[-1] == idx.size and np.all(np.diff(offs) >= 0)
+    row = np.repeat(np.arange(n, dtype=np.int64), np.diff(offs))
+    assert np.all((idx >= 0) & (idx < n)) and not np.any(idx == row)
+    same_row = row[1:] == row[:-1]
+    assert np.all(idx[1:][same_row] > idx[:-1][same_row])
+    fwd = np.sort(row * n + idx)
+    bwd = np.sort(idx.astype(np.int64) * n + row)
+    assert np.array_equal(fwd, bwd)
+
+
+def _full_size(pt, ctx, orc, c, wl, theta, n_sample, seed=0):
+    """The launch configuration of the benchmark (mixed precision, leaf and
+    group as below, one target per lane, neighbour lists on) at the full N:
+    arithmetic error on every particle against the FP64 GPU mode; on a seeded
+    sample, the FP64 mode against the oracle tree (same lists), the mixed
+    result against the oracle direct sum, and the neighbour rows against brute
+    force; CSR invariants on every row."""
+    n = wl.n
+    leaf, group = wl.leaf_size, 64
+    rin, rout, rs = orc.radii(c.mass, wl.r_in_ref, wl.r_out_ref, wl.search_factor)
+    pos_d, mass_d = T(c.pos), T(c.mass)
+    rin_d, rout_d, rs_d = T(rin), T(rout), T(rs)
+    # the radii kernel gives the same radii up to the rounding of <m>
+    gi, go, gs = pt.petar_changeover_radii(ctx, mass_d, wl.r_in_ref, wl.r_out_ref,
+                                           wl.search_factor)
+    np.testing.assert_allclose(go.cpu().numpy(), rout, rtol=1e-14, atol=0)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, pos_d, mass_d, theta, leaf)
+    am, pm, (offs, idx) = pt.petar_force_long(ctx, group, rin_d, rout_d, rs_d,
+                                              nb_capacity=64 * n)
+    am, pm = am.cpu().numpy(), pm.cpu().numpy()
+    offs, idx = offs.cpu().numpy(), idx.cpu().numpy()
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64, record_counts=1)
+    a64, p64 = pt.petar_force_long(ctx, group, rin_d, rout_d, rs_d)
+    a64, p64 = a64.cpu().numpy(), p64.cpu().numpy()
+    cnt = pt.petar_copy_counts(ctx).cpu().numpy()
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, record_counts=0)
+
+    e_arith = rel_err(am, a64)
+    assert np.percentile(e_arith, 99) < 1e-5, np.percentile(e_arith, [50, 99, 100])
+    assert np.percentile(np.abs(pm / p64 - 1), 99) < 1e-6
+
+    s = workloads.sample_indices(n, n_sample, seed)
+    a_ref, p_ref, cnt_ref = orc.tree_force(c.pos, c.mass, rin, rout, rs, theta, leaf, group,
+                                           idx=s)
+    same = np.all(cnt[:, s] == cnt_ref, axis=0)
+    assert same.mean() > 0.995, same.mean()
+    assert rel_err(a64[:, s], a_ref)[same].max() < 1e-11
+    np.testing.assert_allclose(p64[s][same], p_ref[same], rtol=1e-11)
+
+    a_dir, _ = orc.force_long(c.pos, c.mass, rin, rout, idx=s)
+    e_tot = rel_err(am[:, s], a_dir)
+    e64 = rel_err(a64[:, s], a_dir)
+    assert np.mean(e_tot <= e64 + 1e-5) >= 0.99
+
+    o_ref, i_ref = orc.neighbours(c.pos, rs, idx=s)
+    for k, i in enumerate(s):
+        assert np.array_equal(idx[offs[i]:offs[i + 1]], i_ref[o_ref[k]:o_ref[k + 1]]), i
+    _csr_valid(offs, idx, n)
+
+
+@pytest.fixture(scope="module")
+def cluster1m():
+    wl = workloads.WORKLOADS["plummer1m_b100"]
+    return wl, workloads.make_cluster(wl.n, 0, imf=wl.imf, binary_fraction=wl.binary_fraction)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
+def test_plummer1m_b100_config_sampled(pt, ctx, orc, cluster1m, theta):
+    wl, c = cluster1m
+    _full_size(pt, ctx, orc, c, wl, theta, 1024)
+
+
+@pytest.mark.slow
+def test_plummer10m_b10_config_sampled(pt, orc):
+    wl = workloads.WORKLOADS["plummer10m_b10"]
+    c = workloads.make_cluster(wl.n, 0, imf=wl.imf, binary_fraction=wl.binary_fraction)
+    ctx = pt.petar_create(0)
+    try:
+        _full_size(pt, ctx, orc, c, wl, wl.theta, 256)
+    finally:
+        pt.petar_destroy(ctx)
+        torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_single_particle(pt, ctx, orc):
@@ -225,6 +326,30 @@ def test_nb_overflow_and_retry(pt, ctx, orc):
     assert ei.value.required == o_ref[-1]
     acc, pot, (offs, idx) = pt.force_long_with_retry(ctx, 64, T(rin), T(rout), T(rs), 3)
     assert np.array_equal(offs.cpu().numpy(), o_ref) and np.array_equal(idx.cpu().numpy(), i_ref)
+
+
+def test_nb_handover_overflow_falls_back(pt, orc):
+    """Search radii so large that the near leaves handed from the force walk
+    to the neighbour passes overflow their buffers on the first call: the
+    walk-based passes take over (same lists); the buffers then grow and the
+    second call uses the hand-over."""
+    c = workloads.make_cluster(4000, 23, imf=True, binary_fraction=0.5)
+    n = c.mass.size
+    rin, rout, rs = orc.radii(c.mass, 0.05, 0.2, 3.0)
+    o_ref, i_ref = orc.neighbours(c.pos, rs)
+    a_ref, p_ref, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.5, 8, 64)
+    ctx = pt.petar_create(0)
+    try:
+        pt.petar_set_params(ctx, precision=pt.PETAR_FP64)
+        for _ in range(2):
+            pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 8)
+            acc, pot, (offs, idx) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs),
+                                                        nb_capacity=int(o_ref[-1]))
+            assert np.array_equal(offs.cpu().numpy(), o_ref)
+            assert np.array_equal(idx.cpu().numpy(), i_ref)
+            assert rel_err(acc.cpu().numpy(), a_ref).max() < 1e-12
+    finally:
+        pt.petar_destroy(ctx)
 
 
 def test_invalid_radii_rejected(pt, ctx, orc):
