@@ -62,7 +62,7 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask) {
     return __popcll(mask & ((1ull << lane_id()) - 1ull));
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
+// Inclusive prefix sum across the 64 lanes of a wave (all lanes active).
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
 #pragma unroll
@@ -72,6 +72,34 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     }
     return v;
 }
+
+// 32-bit version on DPP lane moves (no LDS round trips): shifts by 1, 2, 4
+// and 8 lanes within each row of 16 give the row prefixes; the last lane of
+// row 0 (and of row 2) is then broadcast into row 1 (row 3), and the last
+// lane of row 1 into rows 2 and 3. Lanes without a source add 0.
+__device__ __forceinline__ int wave_incl_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+template <>
+__device__ __forceinline__ int wave_incl_scan<int>(int v) {
+    return wave_incl_scan_dpp(v);
+}
+template <>
+__device__ __forceinline__ uint32_t wave_incl_scan<uint32_t>(uint32_t v) {
+    return (uint32_t)wave_incl_scan_dpp((int)v);
+}
+
+// Value of the last lane (e.g. the total of an inclusive scan), wave-uniform.
+__device__ __forceinline__ uint32_t last_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
+}
+__device__ __forceinline__ int last_lane(int v) { return __builtin_amdgcn_readlane(v, kWave - 1); }
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -129,20 +157,20 @@ __device__ __forceinline__ int common_digits(uint64_t a, uint64_t b, int levels)
 }
 
 // ---- FP64 geometry of the walk, rounded exactly as written (no contraction).
+// The maxima are fmax: on finite inputs they can differ from a comparison-
+// based maximum only in the sign of a zero, which squaring removes.
 __device__ __forceinline__ double gap_box(double alo, double ahi, double blo, double bhi) {
 #pragma clang fp contract(off)
     double t1 = blo - ahi;
     double t2 = alo - bhi;
-    double t = t1 > t2 ? t1 : t2;
-    return t > 0.0 ? t : 0.0;
+    return fmax(fmax(t1, t2), 0.0);
 }
 
 __device__ __forceinline__ double gap_point(double alo, double ahi, double p) {
 #pragma clang fp contract(off)
     double t1 = p - ahi;
     double t2 = alo - p;
-    double t = t1 > t2 ? t1 : t2;
-    return t > 0.0 ? t : 0.0;
+    return fmax(fmax(t1, t2), 0.0);
 }
 
 __device__ __forceinline__ double sum_sq3(double gx, double gy, double gz) {
@@ -162,7 +190,7 @@ __device__ __forceinline__ bool nb_pair(double xi, double yi, double zi, double 
     double dy = yj - yi;
     double dz = zj - zi;
     double d2 = sum_sq3(dx, dy, dz);
-    double R = rsi > rsj ? rsi : rsj;
+    double R = fmax(rsi, rsj);
     double R2 = R * R;
     return d2 < R2;
 }

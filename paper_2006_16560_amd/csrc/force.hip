@@ -37,27 +37,45 @@ struct Vec<double> {
     using v2 = double2;
 };
 
-// One tile of up to 64 sources, structure of arrays so that every read is an
-// aligned 16/8/4-byte broadcast:
-//   PC:   a = (x, y, z, M), b = (A'xx, A'yy, A'zz, A'xy), c = (A'xz, A'yz)
-//   far:  a = (x, y, z, m)
-//   near: a = (x, y, z, m), c = (r_in, r_out), k = index in Morton order
+// Tiles of up to 64 sources (plus padding); every read is an aligned
+// 16/8/4-byte broadcast:
+//   multipoles: a = (x, y, z, M), b = 2 (A'xx, A'yy, A'zz, A'xy), c = 2 (A'xz, A'yz)
+//   particles:  a = (x, y, z, m), c = (r_in, r_out), k = index in Morton order
+//               (far leaves use a only)
+// Multipole entries are written by the walk as soon as a cell is accepted
+// (its data are already in registers); particle entries are expanded from
+// the buffered leaves when those are flushed.
+constexpr int kTileCap = 72;  // 64 entries + padding up to a multiple of the loop step
+
 template <typename R>
-struct Tile {
-    typename Vec<R>::v4 a[kWave];
-    typename Vec<R>::v4 b[kWave];
-    typename Vec<R>::v2 c[kWave];
-    uint32_t k[kWave];
+struct PcEntry {
+    typename Vec<R>::v4 a, b;
+    typename Vec<R>::v2 c, pad;
+};
+template <typename R>
+struct PartEntry {
+    typename Vec<R>::v4 a;
+    typename Vec<R>::v2 c;
+    uint32_t k, pad[sizeof(R) == 4 ? 1 : 3];
+};
+// Array of entries: one LDS base per tile, immediate offsets per field.
+template <typename R>
+struct PcTile {
+    PcEntry<R> e[kTileCap];
+};
+template <typename R>
+struct PartTile {
+    PartEntry<R> e[kTileCap];
 };
 
 template <typename R>
 struct WaveLds {
     uint32_t stack[kStackLds];
-    uint32_t pc_buf[kWave];
     uint32_t far_start[kWave], far_pre[kWave];
     uint32_t near_start[kWave], near_pre[kWave];
     GroupGeom g;
-    Tile<R> tile;
+    PcTile<R> pc;
+    PartTile<R> part;
 };
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -92,26 +110,6 @@ struct Acc<double> {
     __device__ double get(int k) const { return s[k]; }
 };
 
-// Folds the partial sums of the lanes lane ^ d (d = W, 2W, .., 32) that
-// handled other j subsets of the same target.
-__device__ __forceinline__ void combine_split(Acc<float> &a, int W) {
-    for (int d = W; d < kWave; d <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            float s2 = __shfl_xor(a.s[k], d, kWave);
-            float c2 = __shfl_xor(a.c[k], d, kWave);
-            a.add(k, s2);
-            a.c[k] += c2;
-        }
-    }
-}
-__device__ __forceinline__ void combine_split(Acc<double> &a, int W) {
-    for (int d = W; d < kWave; d <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) a.s[k] += __shfl_xor(a.s[k], d, kWave);
-    }
-}
-
 template <typename R, int IPL>
 struct Targets {
     R x[IPL], y[IPL], z[IPL], rin[IPL], rout[IPL];
@@ -119,19 +117,67 @@ struct Targets {
     Acc<R> acc[IPL];
 };
 
-// Work layout of the current chunk of targets (wave-uniform except sl).
+// Work layout of a chunk of targets. nu target slots per lane are in use;
+// W lanes hold one slot each of distinct targets, and S = 64 / W such lane
+// sets split the source loop (lane = sl * W + il). Lanes past S * W idle:
+// they mirror split 0 and their sums are dropped. Everything but sl, il and
+// act is wave-uniform.
 struct Layout {
-    int nu;  // target slots in use per lane (1..IPL)
-    int S;   // lanes sharing a target (j loop split), 1 when nu > 1
-    int sl;  // this lane's j subset
+    int nu, W, S;
+    int sl, il;
+    bool act;
 };
 
-// ---------------------------------------------------------------- loops
-// Each loop runs uniformly over a tile padded to a multiple of pad_of(S):
-// S lanes share a target and take every S-th source; F sources per lane
-// are unrolled per iteration.
+// Chooses (nu, S) to keep as many lanes busy as possible: nu = 1 with
+// S = 64 / active lanes per target (at most 8), or, when the kernel holds
+// two targets per lane and it is better, nu = 2 with S = 64 / ceil(active/2)
+// (at most 3); chunks above 64 targets use nu = ceil(active / 64), S = 1.
+template <int IPL>
+__device__ __forceinline__ Layout choose_layout(uint32_t active) {
+    Layout ly;
+    if (active > (uint32_t)kWave) {
+        ly.nu = (int)((active + kWave - 1) / kWave);
+        ly.W = kWave;
+        ly.S = 1;
+    } else {
+        const int a = (int)active;
+        int S1 = kWave / a;
+        S1 = S1 > 8 ? 8 : S1;
+        ly.nu = 1;
+        ly.W = a;
+        ly.S = S1;
+        if (IPL >= 2 && a >= 2) {
+            const int W2 = (a + 1) / 2;
+            int S2 = kWave / W2;
+            S2 = S2 > 3 ? 3 : S2;
+            if (S2 > 2 * S1) {  // utilisation a * S / (64 * nu) is higher
+                ly.nu = 2;
+                ly.W = W2;
+                ly.S = S2;
+            }
+        }
+    }
+    const int lane = lane_id();
+    ly.sl = lane / ly.W;
+    ly.il = lane - ly.sl * ly.W;
+    ly.act = ly.sl < ly.S;
+    if (!ly.act) ly.sl = 0;
+    return ly;
+}
 
-__host__ __device__ constexpr int pad_of(int S) { return S >= 4 ? S : 4; }
+// ---------------------------------------------------------------- loops
+// Each loop runs uniformly over a tile padded to a multiple of its step
+// F * S: S lanes share a target and take every S-th source, F sources per
+// lane are unrolled per iteration.
+enum { kTilePc = 0, kTileFar = 1, kTileNear = 2 };
+
+__host__ __device__ constexpr int unroll_of(int kind, int S) {
+    return kind == kTileFar ? (S >= 4 ? 1 : 4 / S) : (kind == kTilePc && S <= 4 ? 2 : 1);
+}
+__device__ __forceinline__ int pad_to(int m, int kind, int S) {
+    const int q = unroll_of(kind, S) * S;
+    return (m + q - 1) / q * q;
+}
 
 template <typename R, int U>
 struct Partial {
@@ -142,6 +188,10 @@ struct Partial {
     }
 };
 
+// Multipole term of one cell: with R the target minus the centre of mass,
+// q = A'R and the tile holding 2A' (so q2 = 2q):
+//   a   += (2/r^5) A'R - (M/r^3 + 5 R.A'R/r^7) R
+//   phi -= M/r + R.A'R/r^5
 template <typename R, int IPL, int U>
 __device__ __forceinline__ void pc_one(const typename Vec<R>::v4 &a, const typename Vec<R>::v4 &b,
                                        const typename Vec<R>::v2 &c, const Targets<R, IPL> &T,
@@ -152,26 +202,22 @@ __device__ __forceinline__ void pc_one(const typename Vec<R>::v4 &a, const typen
         R r2 = Rx * Rx + Ry * Ry + Rz * Rz;
         R ri = rsq(r2);
         R ri2 = ri * ri;
-        R qx = b.x * Rx + b.w * Ry + c.x * Rz;
+        R qx = b.x * Rx + b.w * Ry + c.x * Rz;  // 2 A'R
         R qy = b.w * Rx + b.y * Ry + c.y * Rz;
         R qz = c.x * Rx + c.y * Ry + b.z * Rz;
-        R rqr = Rx * qx + Ry * qy + Rz * qz;
-        R ri3 = ri * ri2;
-        R ri5 = ri3 * ri2;
-        R mri = a.w * ri;
-        R t = rqr * ri5;                  // R.A'R / r^5
-        R t7 = t * ri2;                   // R.A'R / r^7
-        R coef = (R)5 * t7 + mri * ri2;   // M/r^3 + 5 R.A'R/r^7
-        R two5 = ri5 + ri5;
-        // a += (2/r^5) A'R - coef R ;  phi -= M/r + R.A'R/r^5
-        P.ax[u] += two5 * qx;
-        P.ay[u] += two5 * qy;
-        P.az[u] += two5 * qz;
+        R rqr = Rx * qx + Ry * qy + Rz * qz;    // 2 R.A'R
+        R ri5 = ri * (ri2 * ri2);
+        R mri = a.w * ri;                       // M/r
+        R t2 = rqr * ri5;                       // 2 R.A'R / r^5
+        R coef = ((R)2.5 * t2 + mri) * ri2;     // M/r^3 + 5 R.A'R/r^7
+        P.ax[u] += ri5 * qx;
+        P.ay[u] += ri5 * qy;
+        P.az[u] += ri5 * qz;
         P.ax[u] -= coef * Rx;
         P.ay[u] -= coef * Ry;
         P.az[u] -= coef * Rz;
         P.ph[u] -= mri;
-        P.ph[u] -= t;
+        P.ph[u] -= (R)0.5 * t2;
     }
 }
 
@@ -229,21 +275,22 @@ __device__ __forceinline__ void near_one(const typename Vec<R>::v4 &p,
     }
 }
 
-enum { kTilePc = 0, kTileFar = 1, kTileNear = 2 };
-
-// mpad is a multiple of pad_of(S); F sources per lane per iteration.
-template <int KIND, int U, int S, typename R, int IPL>
-__device__ void loop_kind(const Tile<R> &tile, int mpad, int sl, Targets<R, IPL> &T) {
-    constexpr int F = KIND == kTileFar ? pad_of(S) / S : (KIND == kTilePc && S <= 2 ? 2 : 1);
+// mpad is a multiple of the step F * S.
+template <int KIND, int U, int S, typename R, int IPL, typename TileT>
+__device__ void loop_kind(const TileT &tile, int mpad, int sl, Targets<R, IPL> &T) {
+    constexpr int F = unroll_of(KIND, S);
     Partial<R, U> P;
     P.zero();
     for (int jj = 0; jj < mpad; jj += F * S) {
 #pragma unroll
         for (int f = 0; f < F; f++) {
             const int j = jj + f * S + sl;
-            if (KIND == kTilePc) pc_one<R, IPL, U>(tile.a[j], tile.b[j], tile.c[j], T, P);
-            if (KIND == kTileFar) far_one<R, IPL, U>(tile.a[j], T, P);
-            if (KIND == kTileNear) near_one<R, IPL, U>(tile.a[j], tile.c[j], tile.k[j], T, P);
+            if constexpr (KIND == kTilePc)
+                pc_one<R, IPL, U>(tile.e[j].a, tile.e[j].b, tile.e[j].c, T, P);
+            else if constexpr (KIND == kTileFar)
+                far_one<R, IPL, U>(tile.e[j].a, T, P);
+            else
+                near_one<R, IPL, U>(tile.e[j].a, tile.e[j].c, tile.e[j].k, T, P);
         }
     }
 #pragma unroll
@@ -255,56 +302,67 @@ __device__ void loop_kind(const Tile<R> &tile, int mpad, int sl, Targets<R, IPL>
     }
 }
 
-// Runs the loop of a staged tile with the number of target slots in use and
-// the split factor (both wave-uniform).
-template <int KIND, typename R, int IPL>
-__device__ __forceinline__ void run_tile(const Tile<R> &tile, int mpad, const Layout &ly,
+// Runs the loop of a staged tile for the chunk's layout (nu, S).
+template <int KIND, typename R, int IPL, typename TileT>
+__device__ __forceinline__ void run_tile(const TileT &tile, int mpad, const Layout &ly,
                                          Targets<R, IPL> &T) {
-    constexpr int U2 = IPL >= 2 ? 2 : 1;
-    if (IPL > 2 && ly.nu > 2)
-        loop_kind<KIND, IPL, 1>(tile, mpad, ly.sl, T);
-    else if (IPL >= 2 && ly.nu == 2)
-        loop_kind<KIND, U2, 1>(tile, mpad, ly.sl, T);
-    else if (ly.S == 1)
-        loop_kind<KIND, 1, 1>(tile, mpad, ly.sl, T);
-    else if (ly.S == 2)
-        loop_kind<KIND, 1, 2>(tile, mpad, ly.sl, T);
-    else if (ly.S == 4)
-        loop_kind<KIND, 1, 4>(tile, mpad, ly.sl, T);
-    else
-        loop_kind<KIND, 1, 8>(tile, mpad, ly.sl, T);
+    if constexpr (IPL > 2) {
+        if (ly.nu > 2) {
+            loop_kind<KIND, IPL, 1>(tile, mpad, ly.sl, T);
+            return;
+        }
+    }
+    if constexpr (IPL >= 2) {
+        if (ly.nu == 2) {
+            if (ly.S == 1)
+                loop_kind<KIND, 2, 1>(tile, mpad, ly.sl, T);
+            else if (ly.S == 2)
+                loop_kind<KIND, 2, 2>(tile, mpad, ly.sl, T);
+            else
+                loop_kind<KIND, 2, 3>(tile, mpad, ly.sl, T);
+            return;
+        }
+    }
+    switch (ly.S) {
+        case 1: loop_kind<KIND, 1, 1>(tile, mpad, ly.sl, T); break;
+        case 2: loop_kind<KIND, 1, 2>(tile, mpad, ly.sl, T); break;
+        case 3: loop_kind<KIND, 1, 3>(tile, mpad, ly.sl, T); break;
+        case 4: loop_kind<KIND, 1, 4>(tile, mpad, ly.sl, T); break;
+        case 5: loop_kind<KIND, 1, 5>(tile, mpad, ly.sl, T); break;
+        case 6: loop_kind<KIND, 1, 6>(tile, mpad, ly.sl, T); break;
+        case 7: loop_kind<KIND, 1, 7>(tile, mpad, ly.sl, T); break;
+        default: loop_kind<KIND, 1, 8>(tile, mpad, ly.sl, T); break;
+    }
 }
 
-__device__ __forceinline__ int pad_to(int m, int S) {
-    const int q = pad_of(S);
-    return (m + q - 1) / q * q;
-}
-
-// ---- multipole tile
+// ---- multipole tile: entries [0, npc) were written by the walk; pads the
+// tile to the loop's multiple and runs it.
 template <typename R, int IPL>
-__device__ void flush_pc(WaveLds<R> &L, int npc, const ForceLaunch &f, const Layout &ly,
-                         Targets<R, IPL> &T) {
-    wave_sync();
-    const int lane = lane_id();
-    const int mpad = pad_to(npc, ly.S);
-    if (lane < npc) {
-        uint32_t c = L.pc_buf[lane];
-        double4 cm = f.t.nd_com[c];
-        const double *S = f.t.nd_S + (int64_t)c * 6;
-        double tr = S[0] + S[1] + S[2];
-        L.tile.a[lane] = {(R)(cm.x - L.g.c[0]), (R)(cm.y - L.g.c[1]), (R)(cm.z - L.g.c[2]),
-                          (R)cm.w};
-        L.tile.b[lane] = {(R)(1.5 * S[0] - 0.5 * tr), (R)(1.5 * S[1] - 0.5 * tr),
-                          (R)(1.5 * S[2] - 0.5 * tr), (R)(1.5 * S[3])};
-        L.tile.c[lane] = {(R)(1.5 * S[4]), (R)(1.5 * S[5])};
-    } else if (lane < mpad) {
-        L.tile.a[lane] = {(R)kFarAway, (R)kFarAway, (R)kFarAway, (R)0};
-        L.tile.b[lane] = {(R)0, (R)0, (R)0, (R)0};
-        L.tile.c[lane] = {(R)0, (R)0};
+__device__ void flush_pc(WaveLds<R> &L, int npc, const Layout &ly, Targets<R, IPL> &T) {
+    const int mpad = pad_to(npc, kTilePc, ly.S);
+    for (int t = npc + lane_id(); t < mpad; t += kWave) {
+        L.pc.e[t].a = {(R)kFarAway, (R)kFarAway, (R)kFarAway, (R)0};
+        L.pc.e[t].b = {(R)0, (R)0, (R)0, (R)0};
+        L.pc.e[t].c = {(R)0, (R)0};
     }
     wave_sync();
-    run_tile<kTilePc>(L.tile, mpad, ly, T);
+    run_tile<kTilePc>(L.pc, mpad, ly, T);
     wave_sync();
+}
+
+// Multipole entry of cell data held in registers (relative to the group
+// centre; traceless quadrupole A' = 3/2 S - 1/2 tr(S) I of the second
+// moment S about the centre of mass).
+template <typename R>
+__device__ __forceinline__ void stage_pc(WaveLds<R> &L, int p, const double4 &cm,
+                                         const double2 &s01, const double2 &s23,
+                                         const double2 &s45) {
+    const double tr = s01.x + s01.y + s23.x;
+    L.pc.e[p].a = {(R)(cm.x - L.g.c[0]), (R)(cm.y - L.g.c[1]), (R)(cm.z - L.g.c[2]), (R)cm.w};
+    // 2 A' (the doubling is exact after rounding)
+    L.pc.e[p].b = {(R)2 * (R)(1.5 * s01.x - 0.5 * tr), (R)2 * (R)(1.5 * s01.y - 0.5 * tr),
+                 (R)2 * (R)(1.5 * s23.x - 0.5 * tr), (R)2 * (R)(1.5 * s23.y)};
+    L.pc.e[p].c = {(R)2 * (R)(1.5 * s45.x), (R)2 * (R)(1.5 * s45.y)};
 }
 
 // Binary search of the buffered leaf that holds expanded slot s.
@@ -346,36 +404,79 @@ __device__ uint32_t flush_leaves(WaveLds<R> &L, const uint32_t *start, uint32_t 
         }
     }
     uint32_t incl = wave_incl_scan(c);
-    uint32_t total = (uint32_t)uniform((int)__shfl(incl, kWave - 1, kWave));
+    uint32_t total = last_lane(incl);
     if (lane < nleaf) pre[lane] = incl - c;
     wave_sync();
     for (uint32_t base = 0; base < total; base += kWave) {
         const uint32_t s = base + lane;
         const int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
-        const int mpad = pad_to(m, ly.S);
+        const int mpad = pad_to(m, KIND, ly.S);
         if (s < total) {
             int l = find_leaf(pre, nleaf, s);
             uint32_t k = start[l] + (s - pre[l]);
             double4 p = f.t.ps[k];
-            L.tile.a[lane] = {(R)(p.x - L.g.c[0]), (R)(p.y - L.g.c[1]), (R)(p.z - L.g.c[2]),
+            L.part.e[lane].a = {(R)(p.x - L.g.c[0]), (R)(p.y - L.g.c[1]), (R)(p.z - L.g.c[2]),
                               (R)p.w};
             if (KIND == kTileNear) {
                 double2 rr = f.t.rr[k];
-                L.tile.c[lane] = {(R)rr.x, (R)rr.y};
-                L.tile.k[lane] = k;
+                L.part.e[lane].c = {(R)rr.x, (R)rr.y};
+                L.part.e[lane].k = k;
             }
-        } else if (lane < mpad) {
-            L.tile.a[lane] = {(R)kFarAway, (R)kFarAway, (R)kFarAway, (R)0};
+        }
+        for (int t = m + lane; t < mpad; t += kWave) {
+            L.part.e[t].a = {(R)kFarAway, (R)kFarAway, (R)kFarAway, (R)0};
             if (KIND == kTileNear) {
-                L.tile.c[lane] = {(R)0, (R)1};
-                L.tile.k[lane] = kNone - 1;
+                L.part.e[t].c = {(R)0, (R)1};
+                L.part.e[t].k = kNone - 1;
             }
         }
         wave_sync();
-        run_tile<KIND>(L.tile, mpad, ly, T);
+        run_tile<KIND>(L.part, mpad, ly, T);
         wave_sync();
     }
     return total;
+}
+
+// Folds the partial sums of the S lanes that split one target's sources
+// into the lane of split 0, in the fixed order of the splits (staged in the
+// multipole tile, which is free once the walk of the chunk is done).
+__device__ __forceinline__ void fold_in(Acc<float> &a, const float *src, int k, int lane2) {
+    a.add(k, src[k * kWave + lane2]);
+    a.c[k] += src[(4 + k) * kWave + lane2];
+}
+__device__ __forceinline__ void fold_in(Acc<double> &a, const double *src, int k, int lane2) {
+    a.add(k, src[k * kWave + lane2]);
+}
+__device__ __forceinline__ void park(const Acc<float> &a, float *dst, int lane) {
+    for (int k = 0; k < 4; k++) {
+        dst[k * kWave + lane] = a.s[k];
+        dst[(4 + k) * kWave + lane] = a.c[k];
+    }
+}
+__device__ __forceinline__ void park(const Acc<double> &a, double *dst, int lane) {
+    for (int k = 0; k < 4; k++) dst[k * kWave + lane] = a.s[k];
+}
+
+template <typename R, int IPL>
+__device__ void combine_split(WaveLds<R> &L, Targets<R, IPL> &T, const Layout &ly) {
+    static_assert(sizeof(PcTile<R>) >= 8 * kWave * sizeof(R), "fold buffer");
+    R *buf = reinterpret_cast<R *>(&L.pc);
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < IPL; u++) {
+        if (u >= ly.nu) break;
+        wave_sync();
+        park(T.acc[u], buf, lane);
+        wave_sync();
+        if (ly.act && ly.sl == 0) {
+            for (int s2 = 1; s2 < ly.S; s2++) {
+                const int lane2 = s2 * ly.W + ly.il;
+#pragma unroll
+                for (int k = 0; k < 4; k++) fold_in(T.acc[u], buf, k, lane2);
+            }
+        }
+    }
+    wave_sync();
 }
 
 enum { kKindNone = 0, kKindPc = 1, kKindFar = 2, kKindNear = 3, kKindOpen = 4 };
@@ -417,19 +518,12 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
         const uint32_t gn = (uint32_t)uniform((int)ginfo.y);
         for (uint32_t chunk = 0; chunk < gn; chunk += CH) {
             const uint32_t active = gn - chunk < (uint32_t)CH ? gn - chunk : (uint32_t)CH;
-            Layout ly;
-            ly.nu = (int)((active + kWave - 1) / kWave);
-            // One slot in use: S lanes share a target and split the j loop
-            // (lane = sl * W + il).
-            ly.S = ly.nu > 1 ? 1 : (active <= 8 ? 8 : (active <= 16 ? 4 : (active <= 32 ? 2 : 1)));
-            const int W = kWave / ly.S;
-            const int il = lane & (W - 1);
-            ly.sl = lane / W;
+            const Layout ly = choose_layout<IPL>(active);
             Targets<R, IPL> T;
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
-                uint32_t off = chunk + u * kWave + il;
-                bool valid = off < gn;
+                uint32_t off = chunk + u * ly.W + ly.il;
+                bool valid = ly.act && u < ly.nu && off < gn;
                 uint32_t k = gstart + (valid ? off : 0u);
                 double4 p = f.t.ps[k];
                 double2 rr = f.t.rr[k];
@@ -450,13 +544,22 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 uint32_t node = stk.pop();
                 int kind = kKindNone;
                 uint4 info = make_uint4(0, 0, 0, 0);
+                double4 cm = make_double4(0, 0, 0, 0);
+                double2 s01 = make_double2(0, 0), s23 = s01, s45 = s01;
                 if (node != kNone) {
-                    double4 lo = f.t.nd_lo[node], hi = f.t.nd_hi[node], cm = f.t.nd_com[node];
+                    double4 lo = f.t.nd_lo[node], hi = f.t.nd_hi[node];
+                    cm = f.t.nd_com[node];
+                    const double2 *Sp = reinterpret_cast<const double2 *>(f.t.nd_S) + (int64_t)node * 3;
+                    s01 = Sp[0];
+                    s23 = Sp[1];
+                    s45 = Sp[2];
                     info = f.t.nd_info[node];
                     double D2, R2;
                     box_terms(L.g, lo, hi, &D2, &R2);
-                    bool near = D2 < R2;
-                    if (!near && mac_accept(L.g, cm, hi.w, f.th2))
+                    // both tests unconditionally: the loads of a cell are issued together
+                    const bool near = D2 < R2;
+                    const bool accept = mac_accept(L.g, cm, hi.w, f.th2) & !near;
+                    if (accept)
                         kind = kKindPc;
                     else if (info.z & kLeafFlag)
                         kind = near ? kKindNear : kKindFar;
@@ -474,11 +577,11 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 cnt = __popcll(m);
                 if (cnt) {
                     if (npc + cnt > kWave) {
-                        flush_pc(L, npc, f, ly, T);
+                        flush_pc(L, npc, ly, T);
                         n_pc += npc;
                         npc = 0;
                     }
-                    if (kind == kKindPc) L.pc_buf[npc + lanes_below(m)] = node;
+                    if (kind == kKindPc) stage_pc(L, npc + lanes_below(m), cm, s01, s23, s45);
                     npc += cnt;
                 }
                 m = __ballot(kind == kKindFar);
@@ -517,7 +620,8 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 break;
             }
             if (npc) {
-                flush_pc(L, npc, f, ly, T);
+                wave_sync();
+                flush_pc(L, npc, ly, T);
                 n_pc += npc;
             }
             if (nfar) n_far += flush_leaves<kTileFar>(L, L.far_start, L.far_pre, nfar, f, ly, T,
@@ -528,7 +632,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
             cnt_pc += n_pc * active;
             cnt_far += n_far * active;
             cnt_near += n_near * active - active;  // minus the self pairs
-            if (ly.S > 1) combine_split(T.acc[0], W);
+            if (ly.S > 1) combine_split(L, T, ly);
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
                 if (T.k[u] == kNone || ly.sl != 0) continue;

@@ -47,7 +47,7 @@ __device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &p
     const int lane = lane_id();
     uint32_t c = lane < nleaf ? L.leaf_cnt[lane] : 0u;
     uint32_t incl = wave_incl_scan(c);
-    uint32_t total = (uint32_t)uniform((int)__shfl(incl, kWave - 1, kWave));
+    uint32_t total = last_lane(incl);
     if (lane < nleaf) L.leaf_pre[lane] = incl - c;
     wave_sync();
     for (uint32_t base = 0; base < total; base += kWave) {
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
         uint2 lf = make_uint2(0u, 0u);
         if (lane < nleaf) lf = rec.leaf[loff + lane];
         const uint32_t incl = wave_incl_scan(lf.y);
-        const uint32_t total = (uint32_t)uniform((int)__shfl(incl, kWave - 1, kWave));
+        const uint32_t total = last_lane(incl);
         wave_sync();
         if (lane < nleaf) {
             L.start[lane] = lf.x;

@@ -44,7 +44,7 @@ __device__ __forceinline__ void box_terms(const GroupGeom &G, const double4 &lo,
 #pragma clang fp contract(off)
     *D2 = sum_sq3(gap_box(G.lo[0], G.hi[0], lo.x, hi.x), gap_box(G.lo[1], G.hi[1], lo.y, hi.y),
                   gap_box(G.lo[2], G.hi[2], lo.z, hi.z));
-    double R = G.rs > lo.w ? G.rs : lo.w;
+    double R = fmax(G.rs, lo.w);
     *R2 = R * R;
 }
 
@@ -111,7 +111,7 @@ struct WaveStack {
     // overflow.
     __device__ bool push(uint32_t first, int nc) {
         int incl = wave_incl_scan(nc);
-        int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        int tot = last_lane(incl);
         if (tot == 0) return true;
         if (sp_l + tot > kStackLds) {
             if (sp_g + sp_l > kSpillCap) return false;
@@ -121,7 +121,9 @@ struct WaveStack {
             wave_sync();
         }
         int p = sp_l + incl - nc;
-        for (int c = 0; c < nc; c++) lds[p + c] = first + (uint32_t)c;
+#pragma unroll
+        for (int c = 0; c < 8; c++)  // an octree cell has at most 8 children
+            if (c < nc) lds[p + c] = first + (uint32_t)c;
         sp_l += tot;
         wave_sync();
         return true;
