@@ -31,6 +31,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+FORCE_SOURCES = ["paper_2006_16560_amd/csrc/force.hip", "paper_2006_16560_amd/csrc/walk.h",
+                 "paper_2006_16560_amd/csrc/common.h", "paper_2006_16560_amd/csrc/launch.h"]
+
+
+def force_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per force launch from the committed counter summary, if it
+    was taken on the current force-kernel sources (else None)."""
+    import re
+    path = os.path.join(ROOT, "profiles", "k_force_pmc_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    b = re.search(r"^hbm_bytes_per_launch: (\d+)", text, re.M)
+    h = re.search(r"^sources_sha256_16: ([0-9a-f]+)", text, re.M)
+    if not b or not h or h.group(1) != force_sources_hash():
+        return None
+    return int(b.group(1))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +213,9 @@ def main() -> int:
                    "search_factor": wl.search_factor, "precision": "mixed fp32 pair / fp64 tree",
                    "parallelism": "1 gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": (profiled_traffic(wl.name) if (ipl, group, leaf, theta) ==
+                                 (1, 64, wl.leaf_size, wl.theta) else None),
                      "kernel": "k_force<float,%d>" % ipl,
                      "kernel_ms": kernel_ms,
                      "flops_per_interaction": FLOPS_PER_INTERACTION,
