@@ -9,6 +9,8 @@ Every function cites the passage of the PeTar paper (Wang et al. 2020) it
 follows; see ``oracle.c`` for the formulas. Parity status per function:
   changeover f/W/K, radii, direct long/short/Newton sums, neighbour lists,
   multipole field: pinned by the tests in ``tests/test_oracle_pins.py``.
+  Kepler pericentre, second-stage neighbour filter and clusters: pinned by
+  closed-form orbits and brute-force components.
   tree force at theta > 0: pinned at theta = 0 (equals the direct sum) and by
   the multipole error law; its absolute truncation error at theta > 0 is
   measured only ("parity unpinned" by the paper, which prints no force-error
@@ -80,6 +82,13 @@ def lib():
                                         ctypes.c_int, ctypes.c_int, d, p_i64, i64, p_d, p_d,
                                         p_i64]
         L.oracle_tree_force.restype = ctypes.c_int
+        L.oracle_pericentre.argtypes = [p_d, p_d, d, p_d, p_d, d, d]
+        L.oracle_pericentre.restype = d
+        L.oracle_nb_filter.argtypes = [p_d, p_d, p_d, p_d, i64, d, d, p_i64, p_i32, p_i64, p_i32,
+                                       i64]
+        L.oracle_nb_filter.restype = i64
+        L.oracle_clusters.argtypes = [i64, p_i64, p_i32, p_i32, p_i64, p_i32]
+        L.oracle_clusters.restype = i64
         _lib = L
     return _lib
 
@@ -232,3 +241,42 @@ def tree_force(pos, mass, r_in, r_out, r_search, theta: float, leaf_size: int,
     if rc != 0:
         raise ValueError("invalid tree arguments")
     return acc, pot, counts
+
+
+# ------------------------------------------------- second stage and clusters
+def pericentre(xi, vi, mi: float, xj, vj, mj: float, G: float = 1.0) -> float:
+    """Pericentre separation of the two-body Kepler orbit of a pair (Sec.
+    "Orbit-dependent neighbour criterion", second stage)."""
+    return lib().oracle_pericentre(_p(_f64(xi)), _p(_f64(vi)), float(mi), _p(_f64(xj)),
+                                   _p(_f64(vj)), float(mj), float(G))
+
+
+def nb_filter(pos, vel, mass, r_nb, c_v: float, offsets, idx, G: float = 1.0):
+    """True neighbours among the candidate CSR: r_p,ij < c_v * r_nb,i."""
+    pos, vel, mass, r_nb = _f64(pos), _f64(vel), _f64(mass), _f64(r_nb)
+    n = mass.size
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    counts = np.empty(n, dtype=np.int64)
+    out = np.empty(max(idx.size, 1), dtype=np.int32)
+    total = lib().oracle_nb_filter(_p(pos), _p(vel), _p(mass), _p(r_nb), n, float(c_v), float(G),
+                                   _p(offsets, _c_i64_p), _p(idx, _c_i32_p),
+                                   _p(counts, _c_i64_p), _p(out, _c_i32_p), out.size)
+    offs = np.zeros(n + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(counts)
+    return offs, out[:total]
+
+
+def clusters(n: int, offsets, idx):
+    """Connected components of the neighbour graph (Sec. "Clustering"):
+    (label int32 [n] = smallest member index, cluster offsets int64
+    [n_clusters + 1], members int32 [n]), clusters by label, members
+    ascending."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    label = np.empty(n, dtype=np.int32)
+    cl = np.empty(n + 1, dtype=np.int64)
+    members = np.empty(n, dtype=np.int32)
+    nc = lib().oracle_clusters(int(n), _p(offsets, _c_i64_p), _p(idx, _c_i32_p),
+                               _p(label, _c_i32_p), _p(cl, _c_i64_p), _p(members, _c_i32_p))
+    return label, cl[:nc + 1].copy(), members

@@ -25,6 +25,8 @@
  *      steps" and the P3T figure caption: cells inside the opening angle are
  *      replaced by centre-of-mass + quadrupole super-particles), group-wise
  *      walk with the search-radius opening rule.
+ *   7. Second-stage neighbour filter (Kepler pericentre, Sec. "Orbit-
+ *      dependent neighbour criterion") and clusters (Sec. "Clustering").
  */
 #include <math.h>
 #include <stdint.h>
@@ -765,4 +767,137 @@ OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const dou
     free(groups);
     free_tree(&b);
     return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * 7. Neighbours, second stage, and clusters (Sec. "Clustering" and
+ *    "Orbit-dependent neighbour criterion").
+ *
+ *  Second stage: a first-stage candidate j of particle i is a true
+ *  neighbour iff the pericentre separation of the two-body Kepler orbit of
+ *  the pair is below C_v * r_nb,i, where r_nb,i is the first-stage search
+ *  radius of i (eq. rnb). With r = x_j - x_i, v = v_j - v_i and
+ *  mu = G (m_i + m_j):
+ *    specific energy  eps = v^2/2 - mu/|r|
+ *    angular momentum h   = |r x v|
+ *    eccentricity     e   = sqrt(1 + 2 eps h^2 / mu^2)
+ *    pericentre       r_p = h^2 / (mu (1 + e))     (any conic; e clamped at 0)
+ *  taken over the whole orbit, whatever the current phase. Coincident
+ *  particles have r_p = 0. Two massless particles move on straight lines:
+ *  r_p = |r x v| / |v| (or |r| when v = 0).
+ *
+ *  Clusters: connected components of the graph whose edges are the true
+ *  neighbour pairs (in either direction), so that every member has all its
+ *  neighbours in its own cluster. A cluster is labelled by its smallest
+ *  particle index; clusters are listed by label, members ascending.
+ * ---------------------------------------------------------------------- */
+
+OR_EXPORT double oracle_pericentre(const double xi[3], const double vi[3], double mi,
+                                   const double xj[3], const double vj[3], double mj, double G)
+{
+    double dx = xj[0] - xi[0];
+    double dy = xj[1] - xi[1];
+    double dz = xj[2] - xi[2];
+    double dvx = vj[0] - vi[0];
+    double dvy = vj[1] - vi[1];
+    double dvz = vj[2] - vi[2];
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+    double hx = dy * dvz - dz * dvy;
+    double hy = dz * dvx - dx * dvz;
+    double hz = dx * dvy - dy * dvx;
+    double h2 = (hx * hx + hy * hy) + hz * hz;
+    double mu = G * (mi + mj);
+    if (d2 == 0.0) return 0.0;
+    if (mu > 0.0) {
+        double d = sqrt(d2);
+        double eps = 0.5 * v2 - mu / d;
+        double e2 = 1.0 + ((2.0 * eps) * h2) / (mu * mu);
+        double e = e2 > 0.0 ? sqrt(e2) : 0.0;
+        return h2 / (mu * (1.0 + e));
+    }
+    return v2 > 0.0 ? sqrt(h2 / v2) : sqrt(d2);
+}
+
+/* Filters the CSR candidate lists (offsets [n+1], idx) into true
+ * neighbours. counts[i] receives the kept count; out (capacity cap, may be
+ * NULL) the kept indices in list order. Returns the total kept. pos, vel
+ * are SoA [3][n]. */
+OR_EXPORT int64_t oracle_nb_filter(const double *pos, const double *vel, const double *mass,
+                                   const double *r_nb, int64_t n, double c_v, double G,
+                                   const int64_t *offsets, const int32_t *idx, int64_t *counts,
+                                   int32_t *out, int64_t cap)
+{
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; i++) {
+        double xi[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+        double vi[3] = {vel[i], vel[n + i], vel[2 * n + i]};
+        double lim = c_v * r_nb[i];
+        int64_t c = 0;
+        for (int64_t e = offsets[i]; e < offsets[i + 1]; e++) {
+            int64_t j = idx[e];
+            double xj[3] = {pos[j], pos[n + j], pos[2 * n + j]};
+            double vj[3] = {vel[j], vel[n + j], vel[2 * n + j]};
+            double rp = oracle_pericentre(xi, vi, mass[i], xj, vj, mass[j], G);
+            if (rp < lim) {
+                if (out && total < cap) out[total] = (int32_t)j;
+                total++;
+                c++;
+            }
+        }
+        counts[i] = c;
+    }
+    return total;
+}
+
+static int64_t uf_find(int64_t *parent, int64_t x)
+{
+    int64_t r = x;
+    while (parent[r] != r) r = parent[r];
+    while (parent[x] != r) { /* path compression (does not change the roots) */
+        int64_t next = parent[x];
+        parent[x] = r;
+        x = next;
+    }
+    return r;
+}
+
+/* Connected components of the neighbour graph (offsets [n+1], idx).
+ * label[i] = smallest index of i's cluster. cl_offsets [n+1] (first
+ * n_clusters + 1 entries used) and members [n] list the clusters by label,
+ * members ascending. Returns the number of clusters. */
+OR_EXPORT int64_t oracle_clusters(int64_t n, const int64_t *offsets, const int32_t *idx,
+                                  int32_t *label, int64_t *cl_offsets, int32_t *members)
+{
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) parent[i] = i;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = offsets[i]; e < offsets[i + 1]; e++) {
+            int64_t a = uf_find(parent, i), b = uf_find(parent, idx[e]);
+            if (a == b) continue;
+            if (a < b)
+                parent[b] = a; /* the smaller index stays the root */
+            else
+                parent[a] = b;
+        }
+    int64_t *count = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) {
+        label[i] = (int32_t)uf_find(parent, i);
+        count[label[i]]++;
+    }
+    /* clusters in label order; members ascending by construction */
+    int64_t nc = 0, off = 0;
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t r = 0; r < n; r++) {
+        if (count[r] == 0) continue;
+        cl_offsets[nc++] = off;
+        start[r] = off;
+        off += count[r];
+    }
+    cl_offsets[nc] = off;
+    for (int64_t i = 0; i < n; i++) members[start[label[i]]++] = (int32_t)i;
+    free(start);
+    free(count);
+    free(parent);
+    return nc;
 }

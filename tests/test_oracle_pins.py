@@ -382,3 +382,131 @@ def test_tree_near_list_holds_neighbours(orc):
     offs, _ = orc.neighbours(c.pos, rs)
     # near particles per target (including itself) cover its neighbours
     assert np.all(cnt[2] >= np.diff(offs) + 1)
+
+
+# ------------------------------------------- second stage and clusters
+def _rotation(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    return q * np.sign(np.diag(r))
+
+
+def _conic_state(p, e, f, mu, rng):
+    """Relative state of a Kepler conic with semi-latus rectum p and
+    eccentricity e at true anomaly f (polar form r = p/(1 + e cos f), radial
+    and transverse speeds sqrt(mu/p) e sin f and sqrt(mu/p)(1 + e cos f)),
+    rotated and translated at random."""
+    r = p / (1.0 + e * math.cos(f))
+    s = math.sqrt(mu / p)
+    vr, vt = s * e * math.sin(f), s * (1.0 + e * math.cos(f))
+    rhat = np.array([math.cos(f), math.sin(f), 0.0])
+    that = np.array([-math.sin(f), math.cos(f), 0.0])
+    Q = _rotation(rng)
+    x = Q @ (r * rhat)
+    v = Q @ (vr * rhat + vt * that)
+    x0, v0 = rng.normal(size=3), rng.normal(size=3)
+    return x0, v0, x0 + x, v0 + v
+
+
+@pytest.mark.parametrize("e", [0.0, 0.3, 0.9, 0.999, 1.0, 1.7, 12.0])
+def test_pericentre_of_conics(orc, e):
+    """r_p = p / (1 + e) for ellipses, the parabola and hyperbolae, at any
+    phase of the orbit (the pericentre of the whole orbit)."""
+    rng = np.random.default_rng(int(e * 1000) + 1)
+    for f in (0.0, 0.7, 2.0, -1.3):
+        if e >= 1.0 and 1.0 + e * math.cos(f) <= 0.05:
+            continue  # outside the branch of an open orbit
+        mu, p = 0.8, 0.37
+        xi, vi, xj, vj = _conic_state(p, e, f, mu, rng)
+        mi = 0.3
+        rp = orc.pericentre(xi, vi, mi, xj, vj, mu - mi, 1.0)
+        # near e = 0 the eccentricity is the root of a rounding-level number
+        tol = 1e-9 if e >= 0.3 else 3e-8
+        assert abs(rp / (p / (1.0 + e)) - 1.0) < tol, (e, f, rp)
+
+
+def test_pericentre_special_cases(orc):
+    x0, v0 = np.array([0.1, -0.2, 0.3]), np.array([0.5, 0.1, -0.2])
+    # radial motion: zero angular momentum
+    assert orc.pericentre(x0, v0, 0.5, x0 + [1.0, 0, 0], v0 + [0.3, 0, 0], 0.5) == 0.0
+    # coincident particles
+    assert orc.pericentre(x0, v0, 0.5, x0, v0 + [1.0, 2.0, 0], 0.5) == 0.0
+    # massless pair: straight lines, closest approach = impact parameter
+    rp = orc.pericentre(x0, v0, 0.0, x0 + [2.0, 0.25, 0], v0 + [-1.0, 0, 0], 0.0)
+    assert abs(rp - 0.25) < 1e-15
+    rp = orc.pericentre(x0, v0, 0.0, x0 + [0.0, 0.4, 0.3], v0, 0.0)
+    assert abs(rp - 0.5) < 1e-15
+    # circular orbit: r_p = r
+    rp = orc.pericentre([0, 0, 0], [0, 0, 0], 0.25, [2.0, 0, 0], [0, math.sqrt(0.5 / 2.0), 0],
+                        0.25)
+    assert abs(rp - 2.0) < 1e-14
+    # symmetric in the pair, bit for bit
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        a, b, c, d = rng.normal(size=(4, 3))
+        assert orc.pericentre(a, b, 0.3, c, d, 0.6) == orc.pericentre(c, d, 0.6, a, b, 0.3)
+
+
+def test_nb_filter_selects_by_pericentre(orc):
+    """Second stage on a real candidate list: j is kept in i's list iff its
+    pericentre is below c_v * r_nb,i; list order is kept."""
+    c = workloads.make_cluster(3000, 31, imf=True, binary_fraction=0.5)
+    rin, rout, rnb = orc.radii(c.mass, 0.005, 0.05, vel=c.vel, cr_dt=3.0 * 0.003)
+    offs, idx = orc.neighbours(c.pos, rnb)
+    f_offs, f_idx = orc.nb_filter(c.pos, c.vel, c.mass, rnb, 1.5, offs, idx)
+    p, v = c.pos.T, c.vel.T
+    kept = dropped = 0
+    for i in range(3000):
+        want = [j for j in idx[offs[i]:offs[i + 1]]
+                if orc.pericentre(p[i], v[i], c.mass[i], p[j], v[j], c.mass[j]) < 1.5 * rnb[i]]
+        got = list(f_idx[f_offs[i]:f_offs[i + 1]])
+        assert got == want
+        kept += len(want)
+        dropped += offs[i + 1] - offs[i] - len(want)
+    assert kept > 0 and dropped > 0
+
+
+def _components_bfs(n, offs, idx):
+    adj = [set() for _ in range(n)]
+    for i in range(n):
+        for j in idx[offs[i]:offs[i + 1]]:
+            adj[i].add(int(j))
+            adj[int(j)].add(i)
+    label = [-1] * n
+    for s in range(n):
+        if label[s] >= 0:
+            continue
+        stack, comp = [s], []
+        label[s] = s
+        while stack:
+            u = stack.pop()
+            comp.append(u)
+            for w in adj[u]:
+                if label[w] < 0:
+                    label[w] = s
+                    stack.append(w)
+    return np.array(label, dtype=np.int32)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_clusters_are_connected_components(orc, seed):
+    """Labels equal breadth-first components (label = smallest member);
+    directed lists are closed under the cluster; the cluster CSR lists each
+    cluster by label with members ascending."""
+    rng = np.random.default_rng(seed)
+    n = 400
+    lists = []
+    for i in range(n):
+        k = int(rng.integers(0, 3)) if rng.random() < 0.6 else 0
+        lists.append(sorted(set(int(j) for j in rng.integers(0, n, size=k) if j != i)))
+    offs = np.zeros(n + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(l) for l in lists])
+    idx = np.array([j for l in lists for j in l], dtype=np.int32)
+    label, cl, members = orc.clusters(n, offs, idx)
+    assert np.array_equal(label, _components_bfs(n, offs, idx))
+    for i in range(n):
+        assert all(label[j] == label[i] for j in idx[offs[i]:offs[i + 1]])
+    roots = np.unique(label)
+    assert cl.size == roots.size + 1 and cl[-1] == n
+    for k, r in enumerate(roots):
+        mem = members[cl[k]:cl[k + 1]]
+        assert mem[0] == r and np.all(np.diff(mem) > 0) and np.all(label[mem] == r)
