@@ -211,6 +211,43 @@ PETAR_API petar_status petar_autotune(petar_ctx *ctx, const double *pos_dev,
                                       const double *r_search_dev, const char *cache_path,
                                       petar_tuned *out);
 
+/* Second stage of the neighbour search (Sec. "Orbit-dependent neighbour
+ * criterion"): keeps a first-stage candidate j of particle i iff the
+ * pericentre separation of the pair's two-body Kepler orbit,
+ * r_p = h^2 / (mu (1 + e)) with mu = G (m_i + m_j), specific energy
+ * v^2/2 - mu/r, angular momentum h = |r x v| and e = sqrt(1 + 2 E h^2/mu^2),
+ * is below c_v * r_nb_dev[i] (FP64; the whole orbit, whatever its phase;
+ * 0 for coincident particles, |r x v|/|v| for two massless ones). G is the
+ * context's params.G.
+ * Inputs (device, input order): pos_dev[3][N], vel_dev[3][N], mass_dev[N],
+ * r_nb_dev[N] (the first-stage search radii, eq. rnb), and the candidate
+ * CSR cand_offsets_dev[N + 1] / cand_idx_dev (e.g. the lists of
+ * petar_force_long); c_v > 0 (the paper uses 1.5). Output: out->offsets_dev
+ * [N + 1] and out->idx_dev (capacity out->capacity) with the kept entries in
+ * list order (sorted lists stay sorted); out->required = total kept. Errors:
+ * PETAR_E_INVALID for bad arguments or a candidate index outside [0, N),
+ * PETAR_E_NB_OVERFLOW (offsets complete, idx not written) when the capacity
+ * is too small. The context's tree is not used or changed. */
+PETAR_API petar_status petar_nb_filter(petar_ctx *ctx, int64_t N, const double *pos_dev,
+                                       const double *vel_dev, const double *mass_dev,
+                                       const double *r_nb_dev, double c_v,
+                                       const int64_t *cand_offsets_dev,
+                                       const int32_t *cand_idx_dev, petar_nblist *out);
+
+/* Clusters (Sec. "Clustering"): connected components of the neighbour
+ * graph given as a CSR (nb_offsets_dev[N + 1], nb_idx_dev, each pair taken
+ * in both directions), so that every member of a cluster has all its
+ * neighbours in the same cluster. Outputs (device, caller-owned):
+ * label_dev[N] = smallest particle index of the particle's cluster;
+ * cl_offsets_dev[N + 1] and members_dev[N] list the clusters by label with
+ * members ascending (entries past n_clusters of cl_offsets_dev equal N);
+ * *n_clusters (host) = number of clusters. Deterministic. Errors:
+ * PETAR_E_INVALID for bad arguments or an index outside [0, N). */
+PETAR_API petar_status petar_clusters(petar_ctx *ctx, int64_t N, const int64_t *nb_offsets_dev,
+                                      const int32_t *nb_idx_dev, int32_t *label_dev,
+                                      int64_t *cl_offsets_dev, int32_t *members_dev,
+                                      int64_t *n_clusters);
+
 /* Message of the last failure on ctx (thread-local message if ctx is NULL). */
 PETAR_API const char *petar_last_error(petar_ctx *ctx);
 PETAR_API const char *petar_status_string(petar_status status);

@@ -24,7 +24,7 @@ _lib = _capi.load()
 __all__ = [
     "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
     "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_batch_build",
-    "petar_force_long", "petar_step_graph",
+    "petar_force_long", "petar_step_graph", "petar_nb_filter", "petar_clusters",
     "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
     "PETAR_NO_DEVICE", "lib_path",
 ]
@@ -224,6 +224,54 @@ def petar_step_graph(ctx: Context, pos: torch.Tensor, mass: torch.Tensor, theta:
                                ctypes.byref(nbs) if nbs is not None else None)
     _check(st, ctx, nbs.required if nbs is not None else None)
     return nbs.required if nbs is not None else None
+
+
+def _nonempty(idx: torch.Tensor, d: str) -> torch.Tensor:
+    # an empty list still needs a valid device pointer
+    return idx if idx.numel() > 0 else torch.zeros(1, dtype=torch.int32, device=d)
+
+
+def petar_nb_filter(ctx: Context, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
+                    r_nb: torch.Tensor, c_v: float, offsets: torch.Tensor, idx: torch.Tensor,
+                    capacity: Optional[int] = None):
+    """Second-stage neighbour filter (Kepler pericentre < c_v * r_nb,i) of
+    the candidate CSR (offsets int64 [N+1], idx int32). Returns the kept CSR
+    (offsets int64 [N+1], idx int32 [kept]); with a capacity below the kept
+    count a PetarError PETAR_E_NB_OVERFLOW with ``.required`` is raised."""
+    n = mass.shape[0]
+    dev = ctx.device
+    d = "cuda:%d" % dev
+    cap = int(idx.numel()) if capacity is None else int(capacity)
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=d)
+    out_idx = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
+    nbs = _capi.petar_nblist(out_off.data_ptr(), out_idx.data_ptr(), cap, 0)
+    st = _lib.petar_nb_filter(ctx.handle, n, _dptr(pos, torch.float64, (3, n), "pos", dev),
+                              _dptr(vel, torch.float64, (3, n), "vel", dev),
+                              _dptr(mass, torch.float64, (n,), "mass", dev),
+                              _dptr(r_nb, torch.float64, (n,), "r_nb", dev), float(c_v),
+                              _dptr(offsets, torch.int64, (n + 1,), "offsets", dev),
+                              _dptr(_nonempty(idx, d), torch.int32, None, "idx", dev),
+                              ctypes.byref(nbs))
+    _check(st, ctx, nbs.required)
+    return out_off, out_idx[: nbs.required]
+
+
+def petar_clusters(ctx: Context, offsets: torch.Tensor, idx: torch.Tensor):
+    """Clusters of the neighbour CSR: (label int32 [N], cluster offsets
+    int64 [n_clusters + 1], members int32 [N]); see petar.h."""
+    n = offsets.shape[0] - 1
+    dev = ctx.device
+    d = "cuda:%d" % dev
+    label = torch.empty(n, dtype=torch.int32, device=d)
+    cl = torch.empty(n + 1, dtype=torch.int64, device=d)
+    members = torch.empty(n, dtype=torch.int32, device=d)
+    nc = ctypes.c_int64(0)
+    st = _lib.petar_clusters(ctx.handle, n, _dptr(offsets, torch.int64, (n + 1,), "offsets", dev),
+                             _dptr(_nonempty(idx, d), torch.int32, None, "idx", dev),
+                             ctypes.c_void_p(label.data_ptr()), ctypes.c_void_p(cl.data_ptr()),
+                             ctypes.c_void_p(members.data_ptr()), ctypes.byref(nc))
+    _check(st, ctx)
+    return label, cl[: nc.value + 1], members
 
 
 def petar_copy_counts(ctx: Context) -> torch.Tensor:

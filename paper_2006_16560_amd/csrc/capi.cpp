@@ -42,6 +42,9 @@ struct petar_ctx {
     DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
+    // second-stage filter and clusters
+    DevBuf cl_keep, cl_counts, cl_parent, cl_root, cl_rootpos, cl_count, cl_cursor, cl_status,
+        cl_long;
     uint32_t nbhead_cap = 0, nbleaf_cap = 0;
 
     Status *host_status = nullptr;  // pinned
@@ -199,6 +202,8 @@ void free_all(petar_ctx *c) {
                       &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
                       &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
                       &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws,   &c->nbhead, &c->nbleaf,
+                      &c->cl_keep,  &c->cl_counts,   &c->cl_parent,  &c->cl_root,    &c->cl_rootpos,
+                      &c->cl_count, &c->cl_cursor,   &c->cl_status,  &c->cl_long,
                       &c->sys_off};
     for (DevBuf *b : bufs) {
         if (b->p) hipFree(b->p);
@@ -308,6 +313,97 @@ petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass, const do
                             r_search, ptr<double>(ctx->radii_ws), ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PETAR_OK;
+}
+
+petar_status petar_nb_filter(petar_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                             const double *mass, const double *r_nb, double c_v,
+                             const int64_t *cand_offsets, const int32_t *cand_idx,
+                             petar_nblist *out) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_filter_args(n, pos, vel, mass, r_nb, c_v, cand_offsets, cand_idx,
+                                          out))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    // number of candidate entries (one host read)
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, cand_offsets + n, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const int64_t n_cand = ctx->host_scalar[0];
+    if (n_cand < 0) return fail(ctx, PETAR_E_INVALID, "candidate offsets[N] is negative");
+    TRY(ensure(ctx, ctx->cl_keep, (size_t)n_cand));
+    TRY(ensure(ctx, ctx->cl_counts, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_status, 8));
+    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
+    int32_t *bad = ptr<int32_t>(ctx->cl_status);
+    fill_i64(ptr<int64_t>(ctx->cl_status), 0, 1, s);
+    FilterArgs a{pos, vel, mass, r_nb, cand_offsets, cand_idx, n, c_v, ctx->params.G};
+    launch_filter(a, ptr<uint8_t>(ctx->cl_keep), ptr<uint32_t>(ctx->cl_counts), bad, s);
+    scan_u32_to_i64(ptr<uint32_t>(ctx->cl_counts), out->offsets_dev, n, ptr<int64_t>(ctx->scan_ws),
+                    s);
+    launch_filter_write(a, ptr<uint8_t>(ctx->cl_keep), out->offsets_dev, out->idx_dev,
+                        out->capacity, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, out->offsets_dev + n, 8, hipMemcpyDeviceToHost,
+                                s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    int32_t b = 0;
+    memcpy(&b, ctx->host_scalar + 1, 4);
+    if (b) return fail(ctx, PETAR_E_INVALID, "candidate index outside [0, N)");
+    out->required = ctx->host_scalar[0];
+    if (out->required > out->capacity)
+        return fail(ctx, PETAR_E_NB_OVERFLOW, "neighbour capacity %lld < required %lld",
+                    (long long)out->capacity, (long long)out->required);
+    return PETAR_OK;
+}
+
+petar_status petar_clusters(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
+                            const int32_t *nb_idx, int32_t *label, int64_t *cl_offsets,
+                            int32_t *members, int64_t *n_clusters) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_cluster_args(n, nb_offsets, nb_idx, label, cl_offsets, members,
+                                           n_clusters))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    TRY(ensure(ctx, ctx->cl_parent, (size_t)n * 4));
+    TRY(ensure(ctx, ctx->cl_root, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_rootpos, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_count, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_cursor, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_long, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_status, sizeof(Status)));
+    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
+    Status *st = ptr<Status>(ctx->cl_status);  // only its flags (all zero) and bad word
+    fill_i64(ptr<int64_t>(ctx->cl_status), 0, (int64_t)(sizeof(Status) / 8), s);
+    int32_t *bad = reinterpret_cast<int32_t *>(&st->pad);
+    uint32_t *root = ptr<uint32_t>(ctx->cl_root), *rootpos = ptr<uint32_t>(ctx->cl_rootpos);
+    launch_union_find(nb_offsets, nb_idx, n, ptr<int32_t>(ctx->cl_parent), label, root, bad, s);
+    scan_u32_to_u32(root, rootpos, n, ptr<int64_t>(ctx->scan_ws), s);
+    uint32_t *count = ptr<uint32_t>(ctx->cl_count);
+    fill_u32(count, 0, n + 1, s);
+    launch_cluster_lists(label, n, rootpos, count, nullptr, nullptr, nullptr, 0, s);
+    scan_u32_to_i64(count, cl_offsets, n, ptr<int64_t>(ctx->scan_ws), s);
+    fill_u32(ptr<uint32_t>(ctx->cl_cursor), 0, n + 1, s);
+    launch_cluster_lists(label, n, rootpos, nullptr, cl_offsets, ptr<uint32_t>(ctx->cl_cursor),
+                         members, 1, s);
+    // members ascending within each cluster (rows beyond n_clusters are empty)
+    fill_u32(ptr<uint32_t>(ctx->cl_long) + n, 0, 1, s);
+    launch_nb_sort(cl_offsets, members, n, n, st, ptr<uint32_t>(ctx->cl_long),
+                   ptr<uint32_t>(ctx->cl_long) + n, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, rootpos + n, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    uint32_t nc = 0;
+    int32_t b = 0;
+    memcpy(&nc, ctx->host_scalar, 4);
+    memcpy(&b, ctx->host_scalar + 1, 4);
+    if (b) return fail(ctx, PETAR_E_INVALID, "neighbour index outside [0, N)");
+    *n_clusters = nc;
     return PETAR_OK;
 }
 

@@ -148,4 +148,26 @@ void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *s
                          const int64_t *offsets, uint32_t *cursor, int32_t *idx, int64_t capacity,
                          hipStream_t s);
 
+// ------------------------------------------------------------ cluster.hip
+// Second-stage neighbour filter over a candidate CSR (input order).
+struct FilterArgs {
+    const double *pos, *vel, *mass, *r_nb;  // [3][n], [3][n], [n], [n]
+    const int64_t *offsets;                 // [n + 1]
+    const int32_t *idx;
+    int64_t n;
+    double c_v, G;
+};
+void launch_filter(const FilterArgs &a, uint8_t *keep, uint32_t *counts, int32_t *bad,
+                   hipStream_t s);
+void launch_filter_write(const FilterArgs &a, const uint8_t *keep, const int64_t *out_offsets,
+                         int32_t *out_idx, int64_t capacity, hipStream_t s);
+// Components of a neighbour CSR: label[i] = smallest index of i's cluster;
+// is_root[i] = (label[i] == i).
+void launch_union_find(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *parent,
+                       int32_t *label, uint32_t *is_root, int32_t *bad, hipStream_t s);
+// phase 0: member counts per cluster; phase 1: members scattered (unsorted).
+void launch_cluster_lists(const int32_t *label, int64_t n, const uint32_t *root_pos,
+                          uint32_t *count, const int64_t *cl_offsets, uint32_t *cursor,
+                          int32_t *members, int phase, hipStream_t s);
+
 }  // namespace petar

@@ -69,4 +69,30 @@ const char *check_radii_args(const double *mass, int64_t n, double r_in_ref, dou
     return nullptr;
 }
 
+const char *check_filter_args(int64_t n, const double *pos, const double *vel, const double *mass,
+                              const double *r_nb, double c_v, const int64_t *cand_offsets,
+                              const int32_t *cand_idx, const petar_nblist *out) {
+    if (n < 1) return "N must be >= 1";
+    if (n > kMaxParticles) return "N must be < 2^31";
+    if (!pos || !vel || !mass || !r_nb) return "pos, vel, mass and r_nb must not be NULL";
+    if (!std::isfinite(c_v) || !(c_v > 0.0)) return "c_v must be finite and > 0";
+    if (!cand_offsets || !cand_idx) return "candidate offsets and idx must not be NULL";
+    if (!out) return "out is NULL";
+    if (!out->offsets_dev) return "out->offsets_dev is NULL";
+    if (out->capacity < 0) return "out->capacity must be >= 0";
+    if (out->capacity > 0 && !out->idx_dev) return "out->idx_dev is NULL";
+    return nullptr;
+}
+
+const char *check_cluster_args(int64_t n, const int64_t *nb_offsets, const int32_t *nb_idx,
+                               const int32_t *label, const int64_t *cl_offsets,
+                               const int32_t *members, const int64_t *n_clusters) {
+    if (n < 1) return "N must be >= 1";
+    if (n > kMaxParticles) return "N must be < 2^31";
+    if (!nb_offsets || !nb_idx) return "neighbour offsets and idx must not be NULL";
+    if (!label || !cl_offsets || !members) return "label, cl_offsets and members must not be NULL";
+    if (!n_clusters) return "n_clusters is NULL";
+    return nullptr;
+}
+
 }  // namespace petar

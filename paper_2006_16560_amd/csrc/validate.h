@@ -23,4 +23,11 @@ const char *check_radii_args(const double *mass, int64_t n, double r_in_ref, dou
                              double search_factor, double cr_dt, const double *r_in,
                              const double *r_out, const double *r_search);
 
+const char *check_filter_args(int64_t n, const double *pos, const double *vel, const double *mass,
+                              const double *r_nb, double c_v, const int64_t *cand_offsets,
+                              const int32_t *cand_idx, const petar_nblist *out);
+const char *check_cluster_args(int64_t n, const int64_t *nb_offsets, const int32_t *nb_idx,
+                               const int32_t *label, const int64_t *cl_offsets,
+                               const int32_t *members, const int64_t *n_clusters);
+
 }  // namespace petar

@@ -249,3 +249,44 @@ def test_step_graph_validation(capi, ctx):
     assert lib.petar_step_graph(ctx, 0, None, *bad, None) == _capi.PETAR_E_INVALID
     offs = (ctypes.c_int64 * 3)(0, 5, 5)
     assert lib.petar_step_graph(ctx, 2, offs, *args, None) == _capi.PETAR_E_INVALID
+
+
+@pytest.mark.parametrize("case", ["ok", "n0", "pos", "vel", "mass", "rnb", "cv0", "cvnan",
+                                  "offs", "idx", "out", "out_off", "out_cap", "out_idx"])
+def test_nb_filter_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(n=100, pos=FAKE, vel=FAKE, mass=FAKE, rnb=FAKE, cv=1.5, offs=FAKE, idx=FAKE)
+    out = _nb(capi)
+    if case == "n0":
+        a["n"] = 0
+    elif case in ("pos", "vel", "mass", "rnb", "offs", "idx"):
+        a[case] = None
+    elif case == "cv0":
+        a["cv"] = 0.0
+    elif case == "cvnan":
+        a["cv"] = float("nan")
+    elif case == "out_off":
+        out = _nb(capi, offsets=None)
+    elif case == "out_cap":
+        out = _nb(capi, cap=-1)
+    elif case == "out_idx":
+        out = _nb(capi, idx=None)
+    outp = None if case == "out" else ctypes.byref(out)
+    st = lib.petar_nb_filter(ctx, a["n"], a["pos"], a["vel"], a["mass"], a["rnb"], a["cv"],
+                             a["offs"], a["idx"], outp)
+    assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)
+
+
+@pytest.mark.parametrize("case", ["ok", "n0", "offs", "idx", "label", "cl", "members", "nc"])
+def test_clusters_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(n=100, offs=FAKE, idx=FAKE, label=FAKE, cl=FAKE, members=FAKE)
+    nc = ctypes.c_int64(0)
+    if case == "n0":
+        a["n"] = 0
+    elif case in a:
+        a[case] = None
+    ncp = None if case == "nc" else ctypes.byref(nc)
+    st = lib.petar_clusters(ctx, a["n"], a["offs"], a["idx"], a["label"], a["cl"], a["members"],
+                            ncp)
+    assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)

@@ -529,3 +529,80 @@ def test_step_graph_replays_match_eager(pt, orc, batched):
         if it > 0:
             assert st["ms_graph"] > 0  # replayed, not re-captured
     pt.petar_destroy(ctx)
+
+
+# ------------------------------------- second-stage filter and clusters
+def _rnb_radii(orc, c, r_out_ref):
+    """Changeover radii (eq. rcut) and velocity-dependent search radii
+    (eq. rnb, C_r = 3) with the long step from eq. routdts:
+    dt = r_out,ref / (10 sigma_1D)."""
+    v2 = (c.vel ** 2).sum(axis=0)
+    sigma = np.sqrt((c.mass * v2).sum() / (3.0 * c.mass.sum()))
+    dt = r_out_ref / (10.0 * sigma)
+    return orc.radii(c.mass, 0.1 * r_out_ref, r_out_ref, 1.2, vel=c.vel, cr_dt=3.0 * dt)
+
+
+@pytest.mark.parametrize("n,bf,seed", [(4096, 0.5, 41), (65536, 0.5, 42), (20000, 1.0, 43)])
+def test_nb_filter_and_clusters_match_oracle(pt, ctx, orc, n, bf, seed):
+    c = workloads.make_cluster(n, seed, imf=True, binary_fraction=bf)
+    r_out_ref = workloads.r_out_ref_for(n)
+    rin, rout, rnb = _rnb_radii(orc, c, r_out_ref)
+    c.mass[:7] = 0.0  # a few massless particles (straight-line pericentres)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 8)
+    _, _, (offs, idx) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rnb), nb_capacity=400 * n)
+    o_ref, i_ref = orc.neighbours(c.pos, rnb)
+    assert np.array_equal(offs.cpu().numpy(), o_ref) and np.array_equal(idx.cpu().numpy(), i_ref)
+    f_off, f_idx = pt.petar_nb_filter(ctx, T(c.pos), T(c.vel), T(c.mass), T(rnb), 1.5, offs, idx)
+    fo_ref, fi_ref = orc.nb_filter(c.pos, c.vel, c.mass, rnb, 1.5, o_ref, i_ref)
+    assert np.array_equal(f_off.cpu().numpy(), fo_ref)
+    assert np.array_equal(f_idx.cpu().numpy(), fi_ref)
+    assert 0 < fi_ref.size < i_ref.size  # the second stage removes some candidates
+    label, cl, members = pt.petar_clusters(ctx, f_off, f_idx)
+    l_ref, cl_ref, m_ref = orc.clusters(n, fo_ref, fi_ref)
+    assert np.array_equal(label.cpu().numpy(), l_ref)
+    assert np.array_equal(cl.cpu().numpy(), cl_ref)
+    assert np.array_equal(members.cpu().numpy(), m_ref)
+    assert cl_ref.size - 1 < n  # some clusters have several members
+
+
+def test_clusters_edge_cases(pt, ctx, orc):
+    d = "cuda:0"
+    n = 1000
+    # no neighbours: every particle is its own cluster
+    offs = torch.zeros(n + 1, dtype=torch.int64, device=d)
+    idx = torch.zeros(0, dtype=torch.int32, device=d)
+    label, cl, members = pt.petar_clusters(ctx, offs, idx)
+    ar = np.arange(n)
+    assert np.array_equal(label.cpu().numpy(), ar) and np.array_equal(cl.cpu().numpy(),
+                                                                       np.arange(n + 1))
+    assert np.array_equal(members.cpu().numpy(), ar)
+    # a path 0 - 1 - 2 - ... (row r holds r + 1): one cluster, label 0
+    n = 200000
+    i = np.arange(1, n, dtype=np.int32)
+    o = np.concatenate([[0], np.arange(1, n, dtype=np.int64), [n - 1]])
+    label, cl, members = pt.petar_clusters(ctx, T(o), T(i))
+    l_ref, cl_ref, m_ref = orc.clusters(n, o, i)
+    assert np.array_equal(label.cpu().numpy(), l_ref) and np.all(l_ref == 0)
+    assert np.array_equal(cl.cpu().numpy(), cl_ref) and np.array_equal(members.cpu().numpy(), m_ref)
+    # an index outside [0, N) is rejected, not followed
+    bad_off = T(np.array([0, 1, 1], dtype=np.int64))
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_clusters(ctx, bad_off, T(np.array([5], dtype=np.int32)))
+    assert ei.value.status == pt.PETAR_E_INVALID
+
+
+def test_nb_filter_overflow_and_bad_index(pt, ctx, orc):
+    c = workloads.make_cluster(3000, 44, imf=True, binary_fraction=0.5)
+    rin, rout, rnb = _rnb_radii(orc, c, 0.03)
+    o_ref, i_ref = orc.neighbours(c.pos, rnb)
+    fo_ref, fi_ref = orc.nb_filter(c.pos, c.vel, c.mass, rnb, 1.5, o_ref, i_ref)
+    args = (T(c.pos), T(c.vel), T(c.mass), T(rnb), 1.5, T(o_ref), T(i_ref))
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_nb_filter(ctx, *args, capacity=1)
+    assert ei.value.status == pt.PETAR_E_NB_OVERFLOW and ei.value.required == fi_ref.size
+    bad = i_ref.copy()
+    bad[len(bad) // 2] = 3000
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_nb_filter(ctx, *args[:6], T(bad))
+    assert ei.value.status == pt.PETAR_E_INVALID
