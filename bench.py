@@ -72,6 +72,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sample", type=int, default=4096, help="targets in the error / CPU sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-next-rows", dest="next_rows", action="store_false",
+                    help="skip the second-stage filter and clustering measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters of a profiler) and exit")
@@ -194,6 +196,10 @@ def main() -> int:
                     "p99_pot_vs_oracle": float(np.percentile(np.abs(pot_mixed / p_ref - 1), 99))})
         log("oracle sample: %.1f s on %d threads" % (dt, threads))
 
+    nxt = None
+    if args.next_rows:
+        nxt = bench_next_rows(pt, ctx, c, wl, theta, leaf, group, dev)
+
     line = {
         "metric": "tree-force interactions/s and % FP32 peak at N=1M; p99 force rel. err vs FP64",
         "value": value,
@@ -229,8 +235,51 @@ def main() -> int:
         "errors": err,
         "workspace_bytes": st["workspace_bytes"],
     }
+    if nxt is not None:
+        line["next_rows"] = nxt
     print(json.dumps(line), flush=True)
     return 0
+
+
+def bench_next_rows(pt, ctx, c, wl, theta, leaf, group, dev, reps=5):
+    """Second-stage neighbour filter (Kepler pericentre, c_v = 1.5) and
+    clusters on the same particles, with velocity-dependent search radii
+    (eq. rnb, C_r = 3, long step r_out,ref / (10 sigma_1D)). Outside the
+    timed region of the step; times are device-synchronised wall clock."""
+    import torch
+    n = wl.n
+    v2 = (c.vel ** 2).sum(axis=0)
+    sigma = float(np.sqrt((c.mass * v2).sum() / (3.0 * c.mass.sum())))
+    dt = wl.r_out_ref / (10.0 * sigma)
+    mass = torch.from_numpy(c.mass).to(dev)
+    vel = torch.from_numpy(c.vel).to(dev)
+    pos = torch.from_numpy(c.pos).to(dev)
+    ri, ro, rnb = pt.petar_changeover_radii(ctx, mass, wl.r_in_ref, wl.r_out_ref, 1.2, vel=vel,
+                                            cr_dt=3.0 * dt)
+    pt.petar_tree_build(ctx, pos, mass, theta, leaf)
+    _, _, (offs, idx) = pt.force_long_with_retry(ctx, group, ri, ro, rnb, 64 * n)
+    t_f, t_c = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f_off, f_idx = pt.petar_nb_filter(ctx, pos, vel, mass, rnb, 1.5, offs, idx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        label, cl, members = pt.petar_clusters(ctx, f_off, f_idx)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_f.append(t1 - t0)
+        t_c.append(t2 - t1)
+    sizes = torch.diff(cl).cpu().numpy()
+    out = {"nb_filter_ms": 1e3 * float(np.median(t_f)), "clusters_ms": 1e3 * float(np.median(t_c)),
+           "candidates": int(idx.numel()), "kept": int(f_idx.numel()),
+           "n_clusters": int(sizes.size), "largest_cluster": int(sizes.max()),
+           "particles_in_clusters_gt1": int(sizes[sizes > 1].sum()),
+           "search_radius": "eq. rnb, C_r = 3, dt = %.4g" % dt}
+    log("next rows: filter %.3f ms, clusters %.3f ms, %d -> %d pairs, %d clusters (largest %d)"
+        % (out["nb_filter_ms"], out["clusters_ms"], out["candidates"], out["kept"],
+           out["n_clusters"], out["largest_cluster"]))
+    return out
 
 
 def bench_batched(args) -> int:

@@ -225,7 +225,8 @@ PETAR_API petar_status petar_autotune(petar_ctx *ctx, const double *pos_dev,
  * petar_force_long); c_v > 0 (the paper uses 1.5). Output: out->offsets_dev
  * [N + 1] and out->idx_dev (capacity out->capacity) with the kept entries in
  * list order (sorted lists stay sorted); out->required = total kept. Errors:
- * PETAR_E_INVALID for bad arguments or a candidate index outside [0, N),
+ * PETAR_E_INVALID for bad arguments, candidate offsets that do not start at
+ * 0 or decrease, or a candidate index outside [0, N),
  * PETAR_E_NB_OVERFLOW (offsets complete, idx not written) when the capacity
  * is too small. The context's tree is not used or changed. */
 PETAR_API petar_status petar_nb_filter(petar_ctx *ctx, int64_t N, const double *pos_dev,
@@ -242,7 +243,8 @@ PETAR_API petar_status petar_nb_filter(petar_ctx *ctx, int64_t N, const double *
  * cl_offsets_dev[N + 1] and members_dev[N] list the clusters by label with
  * members ascending (entries past n_clusters of cl_offsets_dev equal N);
  * *n_clusters (host) = number of clusters. Deterministic. Errors:
- * PETAR_E_INVALID for bad arguments or an index outside [0, N). */
+ * PETAR_E_INVALID for bad arguments, offsets that do not start at 0 or
+ * decrease, or an index outside [0, N). */
 PETAR_API petar_status petar_clusters(petar_ctx *ctx, int64_t N, const int64_t *nb_offsets_dev,
                                       const int32_t *nb_idx_dev, int32_t *label_dev,
                                       int64_t *cl_offsets_dev, int32_t *members_dev,

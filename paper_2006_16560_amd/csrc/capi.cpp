@@ -43,8 +43,8 @@ struct petar_ctx {
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
     // second-stage filter and clusters
-    DevBuf cl_keep, cl_counts, cl_parent, cl_root, cl_rootpos, cl_count, cl_cursor, cl_status,
-        cl_long;
+    DevBuf cl_keep, cl_row, cl_counts, cl_parent, cl_root, cl_rootpos, cl_status, cl_flags,
+        cl_key0, cl_key1, cl_val0, cl_val1;
     uint32_t nbhead_cap = 0, nbleaf_cap = 0;
 
     Status *host_status = nullptr;  // pinned
@@ -202,8 +202,9 @@ void free_all(petar_ctx *c) {
                       &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
                       &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
                       &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws,   &c->nbhead, &c->nbleaf,
-                      &c->cl_keep,  &c->cl_counts,   &c->cl_parent,  &c->cl_root,    &c->cl_rootpos,
-                      &c->cl_count, &c->cl_cursor,   &c->cl_status,  &c->cl_long,
+                      &c->cl_keep,  &c->cl_row,      &c->cl_counts,   &c->cl_parent,  &c->cl_root,    &c->cl_rootpos,
+                      &c->cl_status,   &c->cl_flags,   &c->cl_key0,    &c->cl_key1,
+                      &c->cl_val0,  &c->cl_val1,
                       &c->sys_off};
     for (DevBuf *b : bufs) {
         if (b->p) hipFree(b->p);
@@ -327,19 +328,25 @@ petar_status petar_nb_filter(petar_ctx *ctx, int64_t n, const double *pos, const
     if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    // number of candidate entries (one host read)
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, cand_offsets + n, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    const int64_t n_cand = ctx->host_scalar[0];
-    if (n_cand < 0) return fail(ctx, PETAR_E_INVALID, "candidate offsets[N] is negative");
-    TRY(ensure(ctx, ctx->cl_keep, (size_t)n_cand));
-    TRY(ensure(ctx, ctx->cl_counts, (size_t)(n + 1) * 4));
+    // candidate count and CSR sanity (one host read)
     TRY(ensure(ctx, ctx->cl_status, 8));
-    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
     int32_t *bad = ptr<int32_t>(ctx->cl_status);
     fill_i64(ptr<int64_t>(ctx->cl_status), 0, 1, s);
+    launch_check_csr(cand_offsets, n, bad, s);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, cand_offsets + n, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const int64_t n_cand = ctx->host_scalar[0];
+    int32_t b0 = 0;
+    memcpy(&b0, ctx->host_scalar + 1, 4);
+    if (b0) return fail(ctx, PETAR_E_INVALID, "candidate offsets must start at 0 and not decrease");
+    TRY(ensure(ctx, ctx->cl_keep, (size_t)n_cand));
+    TRY(ensure(ctx, ctx->cl_row, (size_t)n_cand * 4));
+    TRY(ensure(ctx, ctx->cl_counts, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
     FilterArgs a{pos, vel, mass, r_nb, cand_offsets, cand_idx, n, c_v, ctx->params.G};
-    launch_filter(a, ptr<uint8_t>(ctx->cl_keep), ptr<uint32_t>(ctx->cl_counts), bad, s);
+    launch_filter(a, n_cand, ptr<int32_t>(ctx->cl_row), ptr<uint8_t>(ctx->cl_keep),
+                  ptr<uint32_t>(ctx->cl_counts), bad, s);
     scan_u32_to_i64(ptr<uint32_t>(ctx->cl_counts), out->offsets_dev, n, ptr<int64_t>(ctx->scan_ws),
                     s);
     launch_filter_write(a, ptr<uint8_t>(ctx->cl_keep), out->offsets_dev, out->idx_dev,
@@ -372,37 +379,58 @@ petar_status petar_clusters(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets
     TRY(ensure(ctx, ctx->cl_parent, (size_t)n * 4));
     TRY(ensure(ctx, ctx->cl_root, (size_t)(n + 1) * 4));
     TRY(ensure(ctx, ctx->cl_rootpos, (size_t)(n + 1) * 4));
-    TRY(ensure(ctx, ctx->cl_count, (size_t)(n + 1) * 4));
-    TRY(ensure(ctx, ctx->cl_cursor, (size_t)(n + 1) * 4));
-    TRY(ensure(ctx, ctx->cl_long, (size_t)(n + 1) * 4));
-    TRY(ensure(ctx, ctx->cl_status, sizeof(Status)));
-    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
-    Status *st = ptr<Status>(ctx->cl_status);  // only its flags (all zero) and bad word
-    fill_i64(ptr<int64_t>(ctx->cl_status), 0, (int64_t)(sizeof(Status) / 8), s);
-    int32_t *bad = reinterpret_cast<int32_t *>(&st->pad);
+    TRY(ensure(ctx, ctx->cl_flags, 8));
+    TRY(ensure(ctx, ctx->cl_key0, (size_t)n * 8));
+    TRY(ensure(ctx, ctx->cl_key1, (size_t)n * 8));
+    TRY(ensure(ctx, ctx->cl_val0, (size_t)n * 4));
+    TRY(ensure(ctx, ctx->cl_val1, (size_t)n * 4));
+    TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(n)));
+    const int64_t sort_scan = 256 * ((n + 2047) / 2048);
+    TRY(ensure(ctx, ctx->scan_ws,
+               (size_t)scan_ws_elems(sort_scan > n + 1 ? sort_scan : n + 1) * 8));
+    // flags = {changed, bad index}
+    int32_t *changed = ptr<int32_t>(ctx->cl_flags), *bad = changed + 1;
+    fill_i64(ptr<int64_t>(ctx->cl_flags), 0, 1, s);
+    launch_check_csr(nb_offsets, n, bad, s);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, changed, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    {
+        int32_t fl[2] = {0, 0};
+        memcpy(fl, ctx->host_scalar, 8);
+        if (fl[1])
+            return fail(ctx, PETAR_E_INVALID, "neighbour offsets must start at 0 and not decrease");
+    }
     uint32_t *root = ptr<uint32_t>(ctx->cl_root), *rootpos = ptr<uint32_t>(ctx->cl_rootpos);
-    launch_union_find(nb_offsets, nb_idx, n, ptr<int32_t>(ctx->cl_parent), label, root, bad, s);
+    // components: hooking/shortcut rounds until the grandparents are stable
+    int32_t *f = ptr<int32_t>(ctx->cl_parent), *gf = reinterpret_cast<int32_t *>(rootpos);
+    launch_cc_init(f, gf, n, s);
+    for (int round = 0;; round++) {
+        if (round > 4096) return fail(ctx, PETAR_E_INTERNAL, "clustering did not converge");
+        fill_u32(reinterpret_cast<uint32_t *>(changed), 0, 1, s);
+        launch_cc_round(nb_offsets, nb_idx, n, f, gf, bad, changed, s);
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, changed, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        int32_t ch[2] = {0, 0};
+        memcpy(ch, ctx->host_scalar, 8);
+        if (ch[1]) return fail(ctx, PETAR_E_INVALID, "neighbour index outside [0, N)");
+        if (!ch[0]) break;
+    }
+    launch_cc_label(gf, n, label, root, s);
     scan_u32_to_u32(root, rootpos, n, ptr<int64_t>(ctx->scan_ws), s);
-    uint32_t *count = ptr<uint32_t>(ctx->cl_count);
-    fill_u32(count, 0, n + 1, s);
-    launch_cluster_lists(label, n, rootpos, count, nullptr, nullptr, nullptr, 0, s);
-    scan_u32_to_i64(count, cl_offsets, n, ptr<int64_t>(ctx->scan_ws), s);
-    fill_u32(ptr<uint32_t>(ctx->cl_cursor), 0, n + 1, s);
-    launch_cluster_lists(label, n, rootpos, nullptr, cl_offsets, ptr<uint32_t>(ctx->cl_cursor),
-                         members, 1, s);
-    // members ascending within each cluster (rows beyond n_clusters are empty)
-    fill_u32(ptr<uint32_t>(ctx->cl_long) + n, 0, 1, s);
-    launch_nb_sort(cl_offsets, members, n, n, st, ptr<uint32_t>(ctx->cl_long),
-                   ptr<uint32_t>(ctx->cl_long) + n, s);
+    // members: stable radix sort of the particle indices by cluster index
+    uint64_t *k = ptr<uint64_t>(ctx->cl_key0), *ka = ptr<uint64_t>(ctx->cl_key1);
+    uint32_t *v = ptr<uint32_t>(ctx->cl_val0), *va = ptr<uint32_t>(ctx->cl_val1);
+    launch_cluster_keys(label, n, rootpos, k, v, s);
+    int passes = 1;
+    while (passes < 4 && (n - 1) >> (8 * passes)) passes++;
+    radix_sort(&k, &v, &ka, &va, n, passes, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s);
+    HIP_TRY(ctx, hipMemcpyAsync(members, v, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    launch_cluster_offsets(k, n, cl_offsets, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, rootpos + n, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, bad, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     uint32_t nc = 0;
-    int32_t b = 0;
     memcpy(&nc, ctx->host_scalar, 4);
-    memcpy(&b, ctx->host_scalar + 1, 4);
-    if (b) return fail(ctx, PETAR_E_INVALID, "neighbour index outside [0, N)");
     *n_clusters = nc;
     return PETAR_OK;
 }

@@ -10,10 +10,13 @@
 // ones. FP64 without contraction, in this exact order, so that every
 // decision is reproducible by any implementation of the same formula.
 //
-// Clusters: connected components of the kept pairs. A lock-free union-find
-// hooks the larger root under the smaller one (so every component ends with
-// its smallest index as root, whatever the order of the unions); reads of
-// the parent array are device-coherent atomics, finds halve the paths.
+// Clusters: connected components of the kept pairs by min-label hooking
+// and pointer-jumping rounds (one launch per phase, repeated until the
+// grandparent labels stop changing). Every update is a minimum of particle
+// indices of the same component, so the labels fall monotonically and end
+// at the smallest index of each component, whatever the order of the
+// updates within a round; a stale read inside a round only delays a change
+// to the next round.
 #include "launch.h"
 
 namespace petar {
@@ -57,31 +60,54 @@ __device__ double pericentre(double xi, double yi, double zi, double vxi, double
     return v2 > 0.0 ? sqrt(h2 / v2) : sqrt(d2);
 }
 
-// keep[e] for every candidate entry, kept count per row; bad indices flag.
-__global__ __launch_bounds__(kThreads) void k_filter_mark(FilterArgs a, uint8_t *keep,
-                                                          uint32_t *counts, int32_t *bad) {
-    const int64_t n = a.n;
+// CSR sanity: offsets start at 0 and never decrease (so every row range
+// lies inside [0, offsets[n])); raises *bad otherwise.
+__global__ __launch_bounds__(kThreads) void k_check_csr(const int64_t *offsets, int64_t n,
+                                                        int32_t *bad) {
+    int b = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double xi = a.pos[i], yi = a.pos[n + i], zi = a.pos[2 * n + i];
-        const double vxi = a.vel[i], vyi = a.vel[n + i], vzi = a.vel[2 * n + i];
-        const double mi = a.mass[i];
-        const double lim = a.c_v * a.r_nb[i];
-        uint32_t c = 0;
-        for (int64_t e = a.offsets[i]; e < a.offsets[i + 1]; e++) {
-            const int64_t j = a.idx[e];
-            if (j < 0 || j >= n) {
-                atomicOr(bad, 1);
-                keep[e] = 0;
-                continue;
-            }
-            const double rp = pericentre(xi, yi, zi, vxi, vyi, vzi, mi, a.pos[j], a.pos[n + j],
-                                         a.pos[2 * n + j], a.vel[j], a.vel[n + j], a.vel[2 * n + j],
-                                         a.mass[j], a.G);
-            const bool k = rp < lim;
-            keep[e] = k ? 1 : 0;
-            c += k ? 1u : 0u;
+        if (offsets[i + 1] < offsets[i]) b = 1;
+        if (i == 0 && offsets[0] != 0) b = 1;
+    }
+    if (__ballot(b) && lane_id() == 0) atomicOr(bad, 1);
+}
+
+// Row of every candidate entry (one thread per row; rows are short).
+__global__ __launch_bounds__(kThreads) void k_filter_rows(FilterArgs a, int32_t *row) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = a.offsets[i]; e < a.offsets[i + 1]; e++) row[e] = (int32_t)i;
+}
+
+// keep[e] for every candidate entry (one thread per entry, so the gathers
+// of the partners' data overlap); an index outside [0, n) raises *bad.
+__global__ __launch_bounds__(kThreads) void k_filter_test(FilterArgs a, const int32_t *row,
+                                                          int64_t n_cand, uint8_t *keep,
+                                                          int32_t *bad) {
+    const int64_t n = a.n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_cand;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = row[e], j = a.idx[e];
+        if (j < 0 || j >= n) {
+            atomicOr(bad, 1);
+            keep[e] = 0;
+            continue;
         }
+        const double rp = pericentre(a.pos[i], a.pos[n + i], a.pos[2 * n + i], a.vel[i],
+                                     a.vel[n + i], a.vel[2 * n + i], a.mass[i], a.pos[j],
+                                     a.pos[n + j], a.pos[2 * n + j], a.vel[j], a.vel[n + j],
+                                     a.vel[2 * n + j], a.mass[j], a.G);
+        keep[e] = rp < a.c_v * a.r_nb[i] ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_filter_count(FilterArgs a, const uint8_t *keep,
+                                                           uint32_t *counts) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c = 0;
+        for (int64_t e = a.offsets[i]; e < a.offsets[i + 1]; e++) c += keep[e];
         counts[i] = c;
     }
 }
@@ -99,88 +125,111 @@ __global__ __launch_bounds__(kThreads) void k_filter_write(FilterArgs a, const u
     }
 }
 
-// ------------------------------------------------------------ union-find
-__device__ __forceinline__ int32_t load_parent(int32_t *parent, int32_t x) {
-    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Root of x; every node visited on the way is pointed at its grandparent
-// (an ancestor, so concurrent finds and hooks stay consistent: only roots
-// are ever hooked, and a node that is not a root never becomes one).
-__device__ int32_t uf_find(int32_t *parent, int32_t x) {
-    int32_t cur = x, next = load_parent(parent, cur);
-    while (cur != next) {
-        const int32_t nn = load_parent(parent, next);
-        if (next != nn)
-            __hip_atomic_store(parent + cur, nn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        cur = next;
-        next = nn;
-    }
-    return cur;
-}
-
-__global__ __launch_bounds__(kThreads) void k_uf_init(int32_t *parent, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        parent[i] = (int32_t)i;
-}
-
-__global__ __launch_bounds__(kThreads) void k_uf_union(const int64_t *offsets, const int32_t *idx,
-                                                       int64_t n, int32_t *parent, int32_t *bad) {
+// ------------------------------------------------------------ components
+__global__ __launch_bounds__(kThreads) void k_cc_init(int32_t *f, int32_t *gf, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        for (int64_t e = offsets[i]; e < offsets[i + 1]; e++) {
-            const int32_t j = idx[e];
-            if (j < 0 || j >= n) {
+        f[i] = (int32_t)i;
+        gf[i] = (int32_t)i;
+    }
+}
+
+// For every pair (u, v), both ways: f[f[u]] = min(f[f[u]], gf[v]) (hook
+// the tree of u under v's grandparent) and f[u] = min(f[u], gf[v]). Plain
+// reads may be stale, i.e. larger: that can only cause an unneeded atomic,
+// never skip a needed one.
+__global__ __launch_bounds__(kThreads) void k_cc_hook(const int64_t *offsets, const int32_t *idx,
+                                                      int64_t n, int32_t *f, const int32_t *gf,
+                                                      int32_t *bad) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t e = offsets[u]; e < offsets[u + 1]; e++) {
+            const int32_t v = idx[e];
+            if (v < 0 || v >= n) {
                 atomicOr(bad, 1);
                 continue;
             }
-            while (true) {
-                const int32_t ra = uf_find(parent, (int32_t)i), rb = uf_find(parent, j);
-                if (ra == rb) break;
-                const int32_t hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
-                if (atomicCAS(parent + hi, hi, lo) == hi) break;  // else hi was hooked: retry
+            const int32_t gu = gf[u], gv = gf[v];
+            if (gv < gu) {
+                const int32_t fu = f[u];
+                if (gv < f[fu]) atomicMin(f + fu, gv);
+                if (gv < fu) atomicMin(f + u, gv);
+            } else if (gu < gv) {
+                const int32_t fv = f[v];
+                if (gu < f[fv]) atomicMin(f + fv, gu);
+                if (gu < fv) atomicMin(f + v, gu);
             }
         }
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_uf_label(int32_t *parent, int64_t n, int32_t *label,
-                                                       uint32_t *is_root) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t r = uf_find(parent, (int32_t)i);
-        label[i] = r;
-        is_root[i] = r == (int32_t)i ? 1u : 0u;
+// Shortcut f[u] = min(f[u], gf[u]), then the new grandparents; flags a change.
+__global__ __launch_bounds__(kThreads) void k_cc_short(int32_t *f, int64_t n) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = f[u], g = f[p];
+        if (g < p) f[u] = g;
     }
 }
 
-// Cluster index of every root (exclusive scan of is_root) -> member counts.
-__global__ __launch_bounds__(kThreads) void k_cl_count(const int32_t *label, int64_t n,
-                                                       const uint32_t *root_pos, uint32_t *count) {
+__global__ __launch_bounds__(kThreads) void k_cc_grand(const int32_t *f, int32_t *gf, int64_t n,
+                                                       int32_t *changed) {
+    int32_t ch = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = f[f[u]];
+        if (g != gf[u]) {
+            gf[u] = g;
+            ch = 1;
+        }
+    }
+    if (__ballot(ch) && lane_id() == 0) atomicOr(changed, 1);
+}
+
+__global__ __launch_bounds__(kThreads) void k_cc_label(const int32_t *gf, int64_t n,
+                                                       int32_t *label, uint32_t *is_root) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        label[i] = gf[i];
+        is_root[i] = gf[i] == (int32_t)i ? 1u : 0u;
+    }
+}
+
+// Sort keys for the member lists: cluster index per particle (a stable
+// radix sort by it keeps the members of each cluster ascending).
+__global__ __launch_bounds__(kThreads) void k_cl_keys(const int32_t *label, int64_t n,
+                                                      const uint32_t *root_pos, uint64_t *key,
+                                                      uint32_t *val) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        key[i] = root_pos[label[i]];
+        val[i] = (uint32_t)i;
+    }
+}
+
+// Cluster offsets from the sorted cluster indices: a cluster starts where
+// its index first appears (entries past the last cluster stay n).
+__global__ __launch_bounds__(kThreads) void k_cl_offsets(const uint64_t *key, int64_t n,
+                                                         int64_t *cl_offsets) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(count + root_pos[label[i]], 1u);
-}
-
-__global__ __launch_bounds__(kThreads) void k_cl_scatter(const int32_t *label, int64_t n,
-                                                         const uint32_t *root_pos,
-                                                         const int64_t *cl_offsets,
-                                                         uint32_t *cursor, int32_t *members) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t c = root_pos[label[i]];
-        const uint32_t s = atomicAdd(cursor + c, 1u);
-        members[cl_offsets[c] + s] = (int32_t)i;
-    }
+        if (i == 0 || key[i] != key[i - 1]) cl_offsets[key[i]] = i;
 }
 
 }  // namespace
 
-void launch_filter(const FilterArgs &a, uint8_t *keep, uint32_t *counts, int32_t *bad,
-                   hipStream_t s) {
-    hipLaunchKernelGGL(k_filter_mark, dim3(grid_for(a.n, kThreads, 8192)), dim3(kThreads), 0, s, a,
-                       keep, counts, bad);
+void launch_check_csr(const int64_t *offsets, int64_t n, int32_t *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s,
+                       offsets, n, bad);
+}
+
+void launch_filter(const FilterArgs &a, int64_t n_cand, int32_t *row, uint8_t *keep,
+                   uint32_t *counts, int32_t *bad, hipStream_t s) {
+    const dim3 g(grid_for(a.n, kThreads, 8192)), b(kThreads);
+    hipLaunchKernelGGL(k_filter_rows, g, b, 0, s, a, row);
+    hipLaunchKernelGGL(k_filter_test, dim3(grid_for(n_cand, kThreads, 16384)), b, 0, s, a,
+                       (const int32_t *)row, n_cand, keep, bad);
+    hipLaunchKernelGGL(k_filter_count, g, b, 0, s, a, (const uint8_t *)keep, counts);
 }
 
 void launch_filter_write(const FilterArgs &a, const uint8_t *keep, const int64_t *out_offsets,
@@ -189,23 +238,36 @@ void launch_filter_write(const FilterArgs &a, const uint8_t *keep, const int64_t
                        a, keep, out_offsets, out_idx, capacity);
 }
 
-void launch_union_find(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *parent,
-                       int32_t *label, uint32_t *is_root, int32_t *bad, hipStream_t s) {
-    const dim3 g(grid_for(n, kThreads, 8192)), b(kThreads);
-    hipLaunchKernelGGL(k_uf_init, g, b, 0, s, parent, n);
-    hipLaunchKernelGGL(k_uf_union, g, b, 0, s, offsets, idx, n, parent, bad);
-    hipLaunchKernelGGL(k_uf_label, g, b, 0, s, parent, n, label, is_root);
+void launch_cc_init(int32_t *f, int32_t *gf, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, f, gf,
+                       n);
 }
 
-void launch_cluster_lists(const int32_t *label, int64_t n, const uint32_t *root_pos,
-                          uint32_t *count, const int64_t *cl_offsets, uint32_t *cursor,
-                          int32_t *members, int phase, hipStream_t s) {
+void launch_cc_round(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *f,
+                     int32_t *gf, int32_t *bad, int32_t *changed, hipStream_t s) {
     const dim3 g(grid_for(n, kThreads, 8192)), b(kThreads);
-    if (phase == 0)
-        hipLaunchKernelGGL(k_cl_count, g, b, 0, s, label, n, root_pos, count);
-    else
-        hipLaunchKernelGGL(k_cl_scatter, g, b, 0, s, label, n, root_pos, cl_offsets, cursor,
-                           members);
+    hipLaunchKernelGGL(k_cc_hook, g, b, 0, s, offsets, idx, n, f, (const int32_t *)gf, bad);
+    hipLaunchKernelGGL(k_cc_short, g, b, 0, s, f, n);
+    hipLaunchKernelGGL(k_cc_grand, g, b, 0, s, (const int32_t *)f, gf, n, changed);
+}
+
+void launch_cc_label(const int32_t *gf, int64_t n, int32_t *label, uint32_t *is_root,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_label, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, gf, n,
+                       label, is_root);
+}
+
+void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_offsets,
+                            hipStream_t s) {
+    fill_i64(cl_offsets, n, n + 1, s);
+    hipLaunchKernelGGL(k_cl_offsets, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s,
+                       sorted_key, n, cl_offsets);
+}
+
+void launch_cluster_keys(const int32_t *label, int64_t n, const uint32_t *root_pos, uint64_t *key,
+                         uint32_t *val, hipStream_t s) {
+    hipLaunchKernelGGL(k_cl_keys, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, label,
+                       n, root_pos, key, val);
 }
 
 }  // namespace petar

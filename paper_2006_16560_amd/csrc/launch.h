@@ -157,17 +157,26 @@ struct FilterArgs {
     int64_t n;
     double c_v, G;
 };
-void launch_filter(const FilterArgs &a, uint8_t *keep, uint32_t *counts, int32_t *bad,
-                   hipStream_t s);
+// *bad |= (offsets[0] != 0 or offsets decrease somewhere)
+void launch_check_csr(const int64_t *offsets, int64_t n, int32_t *bad, hipStream_t s);
+void launch_filter(const FilterArgs &a, int64_t n_cand, int32_t *row, uint8_t *keep,
+                   uint32_t *counts, int32_t *bad, hipStream_t s);
 void launch_filter_write(const FilterArgs &a, const uint8_t *keep, const int64_t *out_offsets,
                          int32_t *out_idx, int64_t capacity, hipStream_t s);
-// Components of a neighbour CSR: label[i] = smallest index of i's cluster;
-// is_root[i] = (label[i] == i).
-void launch_union_find(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *parent,
-                       int32_t *label, uint32_t *is_root, int32_t *bad, hipStream_t s);
-// phase 0: member counts per cluster; phase 1: members scattered (unsorted).
-void launch_cluster_lists(const int32_t *label, int64_t n, const uint32_t *root_pos,
-                          uint32_t *count, const int64_t *cl_offsets, uint32_t *cursor,
-                          int32_t *members, int phase, hipStream_t s);
+// Components of a neighbour CSR: init, then rounds (hook, shortcut, new
+// grandparents; *changed set when a grandparent changed) until no change;
+// label[i] = smallest index of i's cluster, is_root[i] = (label[i] == i).
+void launch_cc_init(int32_t *f, int32_t *gf, int64_t n, hipStream_t s);
+void launch_cc_round(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *f,
+                     int32_t *gf, int32_t *bad, int32_t *changed, hipStream_t s);
+void launch_cc_label(const int32_t *gf, int64_t n, int32_t *label, uint32_t *is_root,
+                     hipStream_t s);
+// Keys (cluster index, root_pos = cluster index of each root) and values
+// (particle index) whose stable sort lists the members of every cluster in
+// ascending order; cluster offsets from the sorted keys.
+void launch_cluster_keys(const int32_t *label, int64_t n, const uint32_t *root_pos, uint64_t *key,
+                         uint32_t *val, hipStream_t s);
+void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_offsets,
+                            hipStream_t s);
 
 }  // namespace petar

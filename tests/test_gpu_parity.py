@@ -590,6 +590,11 @@ def test_clusters_edge_cases(pt, ctx, orc):
     with pytest.raises(pt.PetarError) as ei:
         pt.petar_clusters(ctx, bad_off, T(np.array([5], dtype=np.int32)))
     assert ei.value.status == pt.PETAR_E_INVALID
+    # offsets that decrease are rejected before any list is read
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_clusters(ctx, T(np.array([0, 3, 1, 2], dtype=np.int64)),
+                          T(np.array([1, 2, 0], dtype=np.int32)))
+    assert ei.value.status == pt.PETAR_E_INVALID
 
 
 def test_nb_filter_overflow_and_bad_index(pt, ctx, orc):
@@ -606,3 +611,45 @@ def test_nb_filter_overflow_and_bad_index(pt, ctx, orc):
     with pytest.raises(pt.PetarError) as ei:
         pt.petar_nb_filter(ctx, *args[:6], T(bad))
     assert ei.value.status == pt.PETAR_E_INVALID
+    bad_off = o_ref.copy()
+    bad_off[10] = bad_off[11] + 5  # a row that would run backwards
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_nb_filter(ctx, *args[:5], T(bad_off), T(i_ref))
+    assert ei.value.status == pt.PETAR_E_INVALID
+
+
+def test_plummer1m_filter_and_clusters(pt, ctx, orc, cluster1m):
+    """Full size: sampled rows of the second stage against the oracle (its
+    own first-stage candidates for the sampled targets), and the cluster
+    invariants on every particle (labels are component minima, closed
+    under the kept pairs, lists sorted and consistent)."""
+    wl, c = cluster1m
+    n = wl.n
+    rin, rout, rnb = _rnb_radii(orc, c, wl.r_out_ref)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), wl.theta, wl.leaf_size)
+    _, _, (offs, idx) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rnb), nb_capacity=64 * n)
+    f_off, f_idx = pt.petar_nb_filter(ctx, T(c.pos), T(c.vel), T(c.mass), T(rnb), 1.5, offs, idx)
+    label, cl, members = pt.petar_clusters(ctx, f_off, f_idx)
+    fo, fi = f_off.cpu().numpy(), f_idx.cpu().numpy()
+    s = workloads.sample_indices(n, 1024, 3)
+    so, si = orc.neighbours(c.pos, rnb, idx=s)
+    cnt = np.zeros(n, dtype=np.int64)
+    cnt[s] = np.diff(so)
+    o_s = np.zeros(n + 1, dtype=np.int64)
+    o_s[1:] = np.cumsum(cnt)
+    ro, ri = orc.nb_filter(c.pos, c.vel, c.mass, rnb, 1.5, o_s, si)
+    for i in s:
+        assert np.array_equal(fi[fo[i]:fo[i + 1]], ri[ro[i]:ro[i + 1]]), i
+    lab, clo, mem = label.cpu().numpy(), cl.cpu().numpy(), members.cpu().numpy()
+    row = np.repeat(np.arange(n), np.diff(fo))
+    assert np.array_equal(lab[row], lab[fi])  # closed under the kept pairs
+    assert clo[0] == 0 and clo[-1] == n and np.all(np.diff(clo) > 0)
+    assert np.array_equal(np.sort(mem), np.arange(n))
+    first = mem[clo[:-1]]
+    assert np.array_equal(lab[first], first)  # each cluster starts with its label
+    assert np.all(np.diff(first) > 0)  # listed by label
+    same = np.repeat(np.arange(clo.size - 1), np.diff(clo))
+    assert np.array_equal(lab[mem], first[same])
+    inner = np.diff(mem)[np.diff(same) == 0]
+    assert np.all(inner > 0)  # members ascending
