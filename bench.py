@@ -32,7 +32,7 @@ def log(*a):
 
 
 FORCE_SOURCES = ["paper_2006_16560_amd/csrc/force.hip", "paper_2006_16560_amd/csrc/walk.h",
-                 "paper_2006_16560_amd/csrc/common.h", "paper_2006_16560_amd/csrc/launch.h"]
+                 "paper_2006_16560_amd/csrc/common.h"]
 
 
 def force_sources_hash() -> str:
