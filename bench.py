@@ -44,11 +44,11 @@ def force_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str):
+def profiled_traffic(workload: str, ipl: int):
     """HBM bytes per force launch from the committed counter summary, if it
     was taken on the current force-kernel sources (else None)."""
     import re
-    path = os.path.join(ROOT, "profiles", "k_force_pmc_%s.md" % workload)
+    path = os.path.join(ROOT, "profiles", "k_force_pmc_%s_ipl%d.md" % (workload, ipl))
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -70,6 +70,9 @@ def main() -> int:
     ap.add_argument("--group", type=int, default=None)
     ap.add_argument("--ipl", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the step as a hipGraph (the force kernel is then timed on one "
+                         "eager step after the timed region)")
     ap.add_argument("--sample", type=int, default=4096, help="targets in the error / CPU sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-next-rows", dest="next_rows", action="store_false",
@@ -103,7 +106,7 @@ def main() -> int:
     theta = wl.theta if args.theta is None else args.theta
     leaf = wl.leaf_size if args.leaf is None else args.leaf
     group = 64 if args.group is None else args.group
-    ipl = 1 if args.ipl is None else args.ipl
+    ipl = 2 if args.ipl is None else args.ipl
     n = wl.n
 
     t0 = time.time()
@@ -131,11 +134,19 @@ def main() -> int:
             pt.petar_changeover_radii(ctx, mass, wl.r_in_ref, wl.r_out_ref, wl.search_factor,
                                       out=(r_in, r_out, r_s))
 
+    nb_bufs = (torch.empty(n + 1, dtype=torch.int64, device=dev),
+               torch.empty(nb_cap, dtype=torch.int32, device=dev))
+
     def step():
         radii()
-        pt.petar_tree_build(ctx, pos, mass, theta, leaf)
-        return pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot,
-                                   nb_capacity=nb_cap)
+        if not args.graph:
+            pt.petar_tree_build(ctx, pos, mass, theta, leaf)
+            return pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot,
+                                       nb_capacity=nb_cap)
+        # the whole step (tree build, force, neighbour lists) replayed as one
+        # hipGraph
+        return pt.petar_step_graph(ctx, pos, mass, theta, leaf, group, r_in, r_out, r_s, acc,
+                                   pot, nb=nb_bufs)
 
     for k in range(args.warmup):
         step()
@@ -151,6 +162,10 @@ def main() -> int:
         k_ms.append(st["ms_force_kernel"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    if args.graph:  # stage times are not visible inside a replay: one eager step
+        pt.petar_tree_build(ctx, pos, mass, theta, leaf)
+        pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot, nb_capacity=nb_cap)
+        k_ms = [pt.petar_get_stats(ctx)["ms_force_kernel"]]
     st = pt.petar_get_stats(ctx)
     ms_step = 1e3 * elapsed / args.steps
     inter_step = float(np.mean(inter))
@@ -217,12 +232,13 @@ def main() -> int:
                    wl.binary_fraction, "theta": theta, "leaf_size": leaf, "group_size": group,
                    "i_per_lane": ipl, "r_in_ref": wl.r_in_ref, "r_out_ref": wl.r_out_ref,
                    "search_factor": wl.search_factor, "precision": "mixed fp32 pair / fp64 tree",
+                   "launch": "hipGraph replay" if args.graph else "eager",
                    "parallelism": "1 gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": (profiled_traffic(wl.name) if (ipl, group, leaf, theta) ==
-                                 (1, 64, wl.leaf_size, wl.theta) else None),
-                     "kernel": "k_force<float,%d>" % ipl,
+                     "traffic": (profiled_traffic(wl.name, ipl) if (group, leaf, theta) ==
+                                 (64, wl.leaf_size, wl.theta) else None),
+                     "kernel": "k_force<float, %d>" % ipl,
                      "kernel_ms": kernel_ms,
                      "flops_per_interaction": FLOPS_PER_INTERACTION,
                      "interactions_per_launch": inter_step},

@@ -103,6 +103,8 @@ typedef struct {
     int64_t inter_far;         /* particle-particle, Newtonian (far leaves)     */
     int64_t inter_near;        /* particle-particle, changeover (near leaves)   */
     int64_t nb_total;          /* neighbour-list entries                        */
+    /* device times (HIP events) of the last eager calls; a graph replay     */
+    /* sets ms_graph and zeroes the stage times                              */
     double ms_build;           /* device time of the last tree build            */
     double ms_force;           /* device time of the last force call (total)   */
     double ms_force_kernel;    /* device time of the walk + interaction kernel  */

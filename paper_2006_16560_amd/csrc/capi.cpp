@@ -121,6 +121,7 @@ petar_status ensure(petar_ctx *ctx, DevBuf &b, size_t bytes) {
         b.p = nullptr;
         b.cap = 0;
     }
+    ctx->graph_stale = true;  // a captured step graph may hold the old address
     hipError_t e = hipMalloc(&b.p, want);
     if (e != hipSuccess) {
         b.p = nullptr;
@@ -189,7 +190,10 @@ void drop_graph(petar_ctx *c) {
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();  // a missing timing is not an error of the call
+        return 0.f;
+    }
     return ms;
 }
 
@@ -857,12 +861,15 @@ petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offs
         if (!ctx->cap_stream)
             HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         hipStream_t cs = ctx->cap_stream;
+        // (no stage events inside the graph: replays do not update events
+        // recorded by captured nodes, so a replay is timed as a whole)
         HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         enqueue_build_a(ctx, ba, cs);
         enqueue_build_b(ctx, ba, node_cap, cs);
         set_tree_state(ctx, ba, node_cap);
         enqueue_force(ctx, fa, cs, false);
         hipError_t e = hipStreamEndCapture(cs, &ctx->graph);
+        if (e == hipSuccess) e = hipGetLastError();  // launches inside the capture
         if (e == hipSuccess) e = hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             drop_graph(ctx);

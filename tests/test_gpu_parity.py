@@ -653,3 +653,30 @@ def test_plummer1m_filter_and_clusters(pt, ctx, orc, cluster1m):
     assert np.array_equal(lab[mem], first[same])
     inner = np.diff(mem)[np.diff(same) == 0]
     assert np.all(inner > 0)  # members ascending
+
+
+def test_step_graph_after_workspace_growth(pt, orc):
+    """A call that grows the context's scratch buffers between two graph
+    steps makes the next step capture again (the old graph held the old
+    addresses); results stay equal to the eager calls."""
+    c, rin, rout, rs = cluster_with_radii(orc, 6000, 24, bf=0.5)
+    n = c.mass.size
+    ctx = pt.petar_create(0)
+    d = "cuda:0"
+    dpos, dmass, drin, drout, drs = T(c.pos), T(c.mass), T(rin), T(rout), T(rs)
+    acc = torch.empty((3, n), dtype=torch.float64, device=d)
+    pot = torch.empty(n, dtype=torch.float64, device=d)
+    for _ in range(2):
+        pt.petar_step_graph(ctx, dpos, dmass, 0.5, 8, 64, drin, drout, drs, acc, pot)
+    # clusters of a much larger (empty) graph grow the scan and sort scratch
+    big = 3_000_000
+    pt.petar_clusters(ctx, torch.zeros(big + 1, dtype=torch.int64, device=d),
+                      torch.zeros(0, dtype=torch.int32, device=d))
+    for _ in range(2):
+        pt.petar_step_graph(ctx, dpos, dmass, 0.5, 8, 64, drin, drout, drs, acc, pot)
+    ref = pt.petar_create(0)
+    pt.petar_tree_build(ref, dpos, dmass, 0.5, 8)
+    a, p = pt.petar_force_long(ref, 64, drin, drout, drs)
+    assert torch.equal(acc, a) and torch.equal(pot, p)
+    pt.petar_destroy(ref)
+    pt.petar_destroy(ctx)
