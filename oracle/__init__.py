@@ -11,6 +11,9 @@ follows; see ``oracle.c`` for the formulas. Parity status per function:
   multipole field: pinned by the tests in ``tests/test_oracle_pins.py``.
   Kepler pericentre, second-stage neighbour filter and clusters: pinned by
   closed-form orbits and brute-force components.
+  tidal-tensor fit and pseudoparticles: pinned by the closed forms of the
+  paper's Table A, its condition numbers, exact recovery of polynomial
+  fields, Taylor limits of a point-mass field and eq. avebinquad.
   tree force at theta > 0: pinned at theta = 0 (equals the direct sum) and by
   the multipole error law; its absolute truncation error at theta > 0 is
   measured only ("parity unpinned" by the paper, which prints no force-error
@@ -89,6 +92,18 @@ def lib():
         L.oracle_nb_filter.restype = i64
         L.oracle_clusters.argtypes = [i64, p_i64, p_i32, p_i32, p_i64, p_i32]
         L.oracle_clusters.restype = i64
+        L.oracle_tidal_points.argtypes = [ctypes.c_int, p_d, d, p_d]
+        L.oracle_tidal_points.restype = ctypes.c_int
+        L.oracle_tidal_ginv.argtypes = [ctypes.c_int, p_d]
+        L.oracle_tidal_ginv.restype = ctypes.c_int
+        L.oracle_tidal_fit.argtypes = [ctypes.c_int, d, p_d, p_d, p_d]
+        L.oracle_tidal_fit.restype = ctypes.c_int
+        L.oracle_tidal_eval.argtypes = [ctypes.c_int, p_d, p_d, d, p_d, p_d]
+        L.oracle_tidal_eval.restype = None
+        L.oracle_pseudo_particles.argtypes = [d, d, p_d, p_d, p_d, p_d, d, p_d, p_d]
+        L.oracle_binary_elements.argtypes = [d, d, p_d, p_d, p_d, p_d, d, p_d]
+        L.oracle_binary_elements.restype = ctypes.c_int
+        L.oracle_pseudo_particles.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -280,3 +295,168 @@ def clusters(n: int, offsets, idx):
     nc = lib().oracle_clusters(int(n), _p(offsets, _c_i64_p), _p(idx, _c_i32_p),
                                _p(label, _c_i32_p), _p(cl, _c_i64_p), _p(members, _c_i32_p))
     return label, cl[:nc + 1].copy(), members
+
+
+# --------------------------------------------------- artificial particles
+def tidal_points(order: int, cm, d_c: float) -> np.ndarray:
+    """Measure points (P, 3) of the order-2 (tetrahedron) or order-3 tidal
+    tensor around cm (Table A)."""
+    P = 4 if order == 2 else 8
+    out = np.empty(3 * P)
+    if lib().oracle_tidal_points(int(order), _p(_f64(cm)), float(d_c), _p(out)) != P:
+        raise ValueError("order must be 2 or 3")
+    return out.reshape(P, 3)
+
+
+def tidal_ginv(order: int) -> np.ndarray:
+    """Generalized inverse (K, 3P) of the measure-point map for d_c = 1
+    (eq. map)."""
+    K, P = (6, 4) if order == 2 else (16, 8)
+    out = np.empty(K * 3 * P)
+    if lib().oracle_tidal_ginv(int(order), _p(out)) != K:
+        raise ValueError("bad order or rank-deficient map")
+    return out.reshape(K, 3 * P)
+
+
+def tidal_fit(order: int, d_c: float, acc_cm, acc_pts) -> np.ndarray:
+    """[A(r_cm) (3), tensor coefficients (6 or 16)] from the accelerations
+    at the centre and at the measure points (P, 3)."""
+    K = 6 if order == 2 else 16
+    out = np.empty(3 + K)
+    rc = lib().oracle_tidal_fit(int(order), float(d_c), _p(_f64(acc_cm)),
+                                _p(_f64(np.asarray(acc_pts).reshape(-1))), _p(out))
+    if rc != 3 + K:
+        raise ValueError("tidal fit failed")
+    return out
+
+
+def tidal_eval(order: int, t, rp) -> np.ndarray:
+    """Field of the fitted model t = [A(r_cm), T] at offset rp from the
+    centre (the evaluation rows of Table A)."""
+    out = np.empty(3)
+    lib().oracle_tidal_eval(int(order), _p(_f64(t)), _p(_f64(rp)), 0.0, _p(out), None)
+    return out
+
+
+def tidal_potential(order: int, t, rp, phi_cm: float) -> float:
+    """Potential of the fitted model (minus its gradient is tidal_eval)."""
+    out = np.empty(3)
+    pot = ctypes.c_double()
+    lib().oracle_tidal_eval(int(order), _p(_f64(t)), _p(_f64(rp)), float(phi_cm), _p(out),
+                            ctypes.byref(pot))
+    return pot.value
+
+
+def binary_elements(m1, m2, x1, x2, v1, v2, G: float = 1.0):
+    """(a, e) of a bound two-body orbit, or None when unbound."""
+    out = np.empty(2)
+    rc = lib().oracle_binary_elements(float(m1), float(m2), _p(_f64(x1)), _p(_f64(x2)),
+                                      _p(_f64(v1)), _p(_f64(v2)), float(G), _p(out))
+    return None if rc != 0 else (float(out[0]), float(out[1]))
+
+
+def pseudo_particles(m1, m2, x1, x2, v1, v2, G: float = 1.0):
+    """Positions (3, 3) and common mass of the three pseudoparticles of a
+    bound binary (eq. psep, rotated into the orbit's frame), or None for an
+    unbound or degenerate pair."""
+    pos = np.empty(9)
+    m = ctypes.c_double()
+    rc = lib().oracle_pseudo_particles(float(m1), float(m2), _p(_f64(x1)), _p(_f64(x2)),
+                                       _p(_f64(v1)), _p(_f64(v2)), float(G), _p(pos),
+                                       ctypes.byref(m))
+    if rc != 0:
+        return None
+    return pos.reshape(3, 3), m.value
+
+
+def artificial_set(pos, vel, mass, r_in, r_out, r_search, pairs, order: int, c_d: float,
+                   G: float = 1.0) -> dict:
+    """Particle set of the long-range force with artificial particles (Sec.
+    "Artificial particle algorithm for weak perturbation"; the cycle of
+    Sec. "Implementation", where the tree of the long-range step includes
+    the artificial particles).
+
+    pos, vel (3, N); mass, radii (N,); pairs (n_pair, 2) input indices of
+    bound binaries. The members of the pairs are left out; the singles come
+    first in input order, then one block per pair: its centre of mass and
+    the P measure points of Table A (zero mass) and the three
+    pseudoparticles of eq. psep (mass (m1 + m2)/3 each). Every artificial
+    particle takes the larger of the members' radii; d_c = c_d a (1 + e).
+    Returns dict(pos (3, n_out), mass, r_in, r_out, r_search, src (n_out,),
+    -1 for artificial particles), frame (n_pair, 4) = (r_cm, d_c), pair_of
+    (N,), n_single). Raises ValueError for an unbound pair or a particle in
+    two pairs.
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    n = pos.shape[1]
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    P = 4 if order == 2 else 8
+    pair_of = np.full(n, -1, dtype=np.int64)
+    for b, (i, j) in enumerate(pairs):
+        if i == j or pair_of[i] >= 0 or pair_of[j] >= 0:
+            raise ValueError("a particle in two pairs")
+        pair_of[i] = pair_of[j] = b
+    singles = np.nonzero(pair_of < 0)[0]
+    n_s, n_p = len(singles), len(pairs)
+    n_out = n_s + n_p * (P + 4)
+    out = dict(pos=np.zeros((3, n_out)), mass=np.zeros(n_out), r_in=np.zeros(n_out),
+               r_out=np.zeros(n_out), r_search=np.zeros(n_out),
+               src=np.full(n_out, -1, dtype=np.int64), frame=np.zeros((n_p, 4)),
+               pair_of=pair_of, n_single=n_s)
+    out["pos"][:, :n_s] = pos[:, singles]
+    out["mass"][:n_s] = mass[singles]
+    for name, arr in (("r_in", r_in), ("r_out", r_out), ("r_search", r_search)):
+        out[name][:n_s] = np.asarray(arr)[singles]
+    out["src"][:n_s] = singles
+    for b, (i, j) in enumerate(pairs):
+        m1, m2 = float(mass[i]), float(mass[j])
+        el = binary_elements(m1, m2, pos[:, i], pos[:, j], vel[:, i], vel[:, j], G)
+        pp = pseudo_particles(m1, m2, pos[:, i], pos[:, j], vel[:, i], vel[:, j], G)
+        if el is None or pp is None:
+            raise ValueError("pair %d is not bound" % b)
+        a, e = el
+        cm = (m1 * pos[:, i] + m2 * pos[:, j]) / (m1 + m2)
+        d_c = c_d * a * (1.0 + e)
+        out["frame"][b] = (*cm, d_c)
+        base = n_s + b * (P + 4)
+        out["pos"][:, base] = cm
+        out["pos"][:, base + 1:base + 1 + P] = tidal_points(order, cm, d_c).T
+        out["pos"][:, base + 1 + P:base + 4 + P] = pp[0].T
+        out["mass"][base + 1 + P:base + 4 + P] = pp[1]
+        for name, arr in (("r_in", r_in), ("r_out", r_out), ("r_search", r_search)):
+            out[name][base:base + P + 4] = max(float(arr[i]), float(arr[j]))
+    return out
+
+
+def artificial_fit(order: int, art: dict, pos, acc_set, pot_set, pairs):
+    """Post-fit of the long-range step: per pair the record [phi(r_cm),
+    A(r_cm), T] from the accelerations (and potentials) of its centre and
+    measure points; per input particle the long-range acceleration and
+    potential: singles take theirs from the set, members the fitted field
+    at their position.
+    acc_set (3, n_out), pot_set (n_out,). Returns (records (n_pair, 4 + K),
+    acc (3, N), pot (N,))."""
+    P = 4 if order == 2 else 8
+    K = 6 if order == 2 else 16
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[1]
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    n_s = art["n_single"]
+    rec = np.zeros((len(pairs), 4 + K))
+    acc = np.zeros((3, n))
+    pot = np.zeros(n)
+    src = art["src"][:n_s]
+    acc[:, src] = acc_set[:, :n_s]
+    pot[src] = pot_set[:n_s]
+    for b, (i, j) in enumerate(pairs):
+        base = n_s + b * (P + 4)
+        cm, d_c = art["frame"][b, :3], art["frame"][b, 3]
+        t = tidal_fit(order, d_c, acc_set[:, base], acc_set[:, base + 1:base + 1 + P].T)
+        rec[b, 0] = pot_set[base]
+        rec[b, 1:] = t
+        for m in (i, j):
+            rp = pos[:, m] - cm
+            acc[:, m] = tidal_eval(order, t, rp)
+            pot[m] = tidal_potential(order, t, rp, pot_set[base])
+    return rec, acc, pot

@@ -901,3 +901,259 @@ OR_EXPORT int64_t oracle_clusters(int64_t n, const int64_t *offsets, const int32
     free(parent);
     return nc;
 }
+
+/* ------------------------------------------------------------------------
+ * 8. Artificial particles (Sec. "Artificial particle algorithm for weak
+ *    perturbation"): tidal-tensor measure points and fit (eq. tt, eq. map,
+ *    Table A), pseudoparticle multipole of a binary (eq. quad, eq. quadtr,
+ *    eq. dr, eq. r1r2, eq. avebinquad, eq. psep).
+ *
+ *  Measure points: r_cm + d_c u_p with the unit offsets u_p of Table A
+ *  (order 2: 4 tetrahedron corners; order 3: 8 points).
+ *  Field model (the evaluation rows of Table A): with r' = r - r_cm,
+ *    A_i(r) = A_i(r_cm) + sum_j T_ij r'_j              (order 2)
+ *             + sum_jk T_ijk r'_j r'_k                 (order 3)
+ *  T_ij and T_ijk fully symmetric: 6 and 10 unknowns, collected as
+ *    [xx xy xz yy yz zz] and [xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz].
+ *  Fit: least squares over the 3 P equations A'(r_p) = A(r_p) - A(r_cm),
+ *  i.e. the generalized inverse of the linear map (normal equations,
+ *  solved by Gaussian elimination with partial pivoting).
+ * ---------------------------------------------------------------------- */
+
+static const double OR_S2 = 0.70710678118654752440; /* sqrt(2)/2 */
+
+static int tidal_npts(int order) { return order == 2 ? 4 : 8; }
+static int tidal_nunk(int order) { return order == 2 ? 6 : 16; }
+
+static void tidal_unit(int order, int p, double u[3])
+{
+    static const double t2[4][3] = {{1, 0, -OR_S2}, {-1, 0, -OR_S2}, {0, 1, OR_S2}, {0, -1, OR_S2}};
+    static const double t3[8][3] = {{1, 0, -1}, {0, 1, -1}, {-1, 0, -1}, {0, -1, -1},
+                                    {1, 0, 1},  {0, 1, 1},  {-1, 0, 1},  {0, -1, 1}};
+    for (int d = 0; d < 3; d++) u[d] = order == 2 ? t2[p][d] : t3[p][d];
+}
+
+/* Row of the design matrix: coefficient of unknown k in component i of the
+ * model at offset r. */
+static double tidal_coef(int order, int i, int k, const double r[3])
+{
+    static const int pair[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    static const int trip[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
+                                    {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
+    if (k < 6) { /* T_ab contributes to A_a via r_b and (if a != b) to A_b via r_a */
+        int a = pair[k][0], b = pair[k][1];
+        double c = 0.0;
+        if (i == a) c += r[b];
+        if (i == b && a != b) c += r[a];
+        return c;
+    }
+    (void)order;
+    /* T_abc (a <= b <= c) enters A_i = sum_jk T_ijk r_j r_k through every
+     * ordered (j, k) with {i, j, k} = {a, b, c}: take one i out of the
+     * multiset; the remaining pair {p, q} gives r_p^2, or 2 r_p r_q if
+     * p != q. */
+    int t[3] = {trip[k - 6][0], trip[k - 6][1], trip[k - 6][2]};
+    int at = -1;
+    for (int q = 0; q < 3; q++)
+        if (t[q] == i) at = q;
+    if (at < 0) return 0.0;
+    int rest[2], nr = 0;
+    for (int q = 0; q < 3; q++)
+        if (q != at) rest[nr++] = t[q];
+    return rest[0] == rest[1] ? r[rest[0]] * r[rest[0]] : 2.0 * r[rest[0]] * r[rest[1]];
+}
+
+OR_EXPORT int oracle_tidal_points(int order, const double cm[3], double d_c, double *out)
+{
+    if (order != 2 && order != 3) return -1;
+    int P = tidal_npts(order);
+    for (int p = 0; p < P; p++) {
+        double u[3];
+        tidal_unit(order, p, u);
+        for (int d = 0; d < 3; d++) out[3 * p + d] = cm[d] + d_c * u[d];
+    }
+    return P;
+}
+
+/* Generalized inverse of the design matrix for d_c = 1: ginv [K][3P]. */
+OR_EXPORT int oracle_tidal_ginv(int order, double *ginv)
+{
+    if (order != 2 && order != 3) return -1;
+    int P = tidal_npts(order), K = tidal_nunk(order), R = 3 * P;
+    double *M = (double *)malloc(sizeof(double) * (size_t)R * K);
+    for (int p = 0; p < P; p++) {
+        double u[3];
+        tidal_unit(order, p, u);
+        for (int i = 0; i < 3; i++)
+            for (int k = 0; k < K; k++) M[(3 * p + i) * K + k] = tidal_coef(order, i, k, u);
+    }
+    /* normal matrix N = M^T M and its inverse by Gauss-Jordan */
+    double N[16][32];
+    for (int a = 0; a < K; a++) {
+        for (int b = 0; b < K; b++) {
+            double s = 0.0;
+            for (int r = 0; r < R; r++) s += M[r * K + a] * M[r * K + b];
+            N[a][b] = s;
+            N[a][K + b] = a == b ? 1.0 : 0.0;
+        }
+    }
+    for (int c = 0; c < K; c++) {
+        int piv = c;
+        for (int r = c + 1; r < K; r++)
+            if (fabs(N[r][c]) > fabs(N[piv][c])) piv = r;
+        if (fabs(N[piv][c]) < 1e-300) {
+            free(M);
+            return -2; /* rank deficient */
+        }
+        if (piv != c)
+            for (int b = 0; b < 2 * K; b++) {
+                double t = N[c][b];
+                N[c][b] = N[piv][b];
+                N[piv][b] = t;
+            }
+        double d = N[c][c];
+        for (int b = 0; b < 2 * K; b++) N[c][b] /= d;
+        for (int r = 0; r < K; r++) {
+            if (r == c) continue;
+            double f = N[r][c];
+            if (f == 0.0) continue;
+            for (int b = 0; b < 2 * K; b++) N[r][b] -= f * N[c][b];
+        }
+    }
+    for (int a = 0; a < K; a++)
+        for (int r = 0; r < R; r++) {
+            double s = 0.0;
+            for (int b = 0; b < K; b++) s += N[a][K + b] * M[r * K + b];
+            ginv[a * R + r] = s;
+        }
+    free(M);
+    return K;
+}
+
+/* T from measured accelerations: acc_cm[3], acc_pts[3P] (point-major,
+ * x y z); out[3 + K] = A(r_cm), then the K unknowns. */
+OR_EXPORT int oracle_tidal_fit(int order, double d_c, const double acc_cm[3],
+                               const double *acc_pts, double *out)
+{
+    if (order != 2 && order != 3) return -1;
+    int P = tidal_npts(order), K = tidal_nunk(order), R = 3 * P;
+    double ginv[16 * 24];
+    if (oracle_tidal_ginv(order, ginv) != K) return -2;
+    for (int d = 0; d < 3; d++) out[d] = acc_cm[d];
+    for (int k = 0; k < K; k++) {
+        double s = 0.0;
+        for (int r = 0; r < R; r++) s += ginv[k * R + r] * (acc_pts[r] - acc_cm[r % 3]);
+        /* unknowns of order 1 scale with 1/d_c, of order 2 with 1/d_c^2 */
+        out[3 + k] = k < 6 ? s / d_c : s / (d_c * d_c);
+    }
+    return 3 + K;
+}
+
+/* Field of the fitted model at offset r' from the centre, t = [A(r_cm),
+ * T]. With out_pot non-NULL also the potential of the model, whose
+ * gradient is minus the field (A = -grad phi): phi(r) = phi_cm -
+ * sum_i r'_i (A_i(r_cm) + (1/2) sum_j T_ij r'_j + (1/3) sum_jk T_ijk r'_j
+ * r'_k), i.e. the first-order part of A_i weighted 1/2 and the second-
+ * order part 1/3. */
+OR_EXPORT void oracle_tidal_eval(int order, const double *t, const double rp[3], double phi_cm,
+                                 double out[3], double *out_pot)
+{
+    int K = tidal_nunk(order);
+    double pot = phi_cm;
+    for (int i = 0; i < 3; i++) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < K; k++) {
+            double c = t[3 + k] * tidal_coef(order, i, k, rp);
+            if (k < 6)
+                s1 += c;
+            else
+                s2 += c;
+        }
+        out[i] = t[i] + s1 + s2;
+        pot -= rp[i] * (t[i] + 0.5 * s1 + s2 / 3.0);
+    }
+    if (out_pot) *out_pot = pot;
+}
+
+/* Semi-major axis and eccentricity of a two-body orbit (eq. dr): out[0] = a,
+ * out[1] = e. Returns -1 (and leaves out alone) for an unbound pair
+ * (specific energy >= 0) or coincident particles. */
+OR_EXPORT int oracle_binary_elements(double m1, double m2, const double x1[3], const double x2[3],
+                                     const double v1[3], const double v2[3], double G,
+                                     double out[2])
+{
+    double mu = G * (m1 + m2), r[3], v[3];
+    for (int d = 0; d < 3; d++) {
+        r[d] = x2[d] - x1[d];
+        v[d] = v2[d] - v1[d];
+    }
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double E = 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - mu / rr;
+    if (!(rr > 0.0) || !(E < 0.0)) return -1;
+    double h[3] = {r[1] * v[2] - r[2] * v[1], r[2] * v[0] - r[0] * v[2], r[0] * v[1] - r[1] * v[0]};
+    double h2 = h[0] * h[0] + h[1] * h[1] + h[2] * h[2];
+    double a = -mu / (2.0 * E);
+    double e2 = 1.0 - h2 / (mu * a);
+    out[0] = a;
+    out[1] = e2 > 0.0 ? sqrt(e2) : 0.0;
+    return 0;
+}
+
+/* Three pseudoparticles of a bound binary (masses (m1 + m2)/3 each) at the
+ * positions of eq. psep in the orbital frame (x towards the pericentre,
+ * z along the angular momentum; for e = 0 x along the current separation),
+ * placed around the centre of mass. out_pos[3][3] (point-major). A radial
+ * orbit (zero angular momentum) is the limit e = 1 along the separation.
+ * Returns 0, or -1 for an unbound pair or coincident particles. */
+OR_EXPORT int oracle_pseudo_particles(double m1, double m2, const double x1[3], const double x2[3],
+                                      const double v1[3], const double v2[3], double G,
+                                      double *out_pos, double *out_mass)
+{
+    double M = m1 + m2, mu = G * M;
+    double r[3], v[3], cm[3];
+    for (int d = 0; d < 3; d++) {
+        r[d] = x2[d] - x1[d];
+        v[d] = v2[d] - v1[d];
+        cm[d] = (m1 * x1[d] + m2 * x2[d]) / M;
+    }
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double v2s = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double E = 0.5 * v2s - mu / rr;
+    if (!(E < 0.0) || !(rr > 0.0)) return -1;
+    double a = -mu / (2.0 * E);
+    double h[3] = {r[1] * v[2] - r[2] * v[1], r[2] * v[0] - r[0] * v[2], r[0] * v[1] - r[1] * v[0]};
+    double hn = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+    if (!(hn > 0.0)) {
+        /* radial orbit (e = 1): the three points lie on the line of the
+         * separation, the in-plane y offsets vanish */
+        double s = a * sqrt(m1 * m2 / M / M), q = sqrt(3.75);
+        for (int d = 0; d < 3; d++) {
+            out_pos[d] = cm[d];
+            out_pos[3 + d] = cm[d] + s * q * r[d] / rr;
+            out_pos[6 + d] = cm[d] - s * q * r[d] / rr;
+        }
+        *out_mass = M / 3.0;
+        return 0;
+    }
+    /* eccentricity vector e = v x h / mu - r/|r| */
+    double ev[3] = {(v[1] * h[2] - v[2] * h[1]) / mu - r[0] / rr,
+                    (v[2] * h[0] - v[0] * h[2]) / mu - r[1] / rr,
+                    (v[0] * h[1] - v[1] * h[0]) / mu - r[2] / rr};
+    double e = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
+    double z[3] = {h[0] / hn, h[1] / hn, h[2] / hn}, x[3];
+    if (e > 1e-12) {
+        for (int d = 0; d < 3; d++) x[d] = ev[d] / e;
+    } else {
+        for (int d = 0; d < 3; d++) x[d] = r[d] / rr;
+        e = 0.0;
+    }
+    double y[3] = {z[1] * x[2] - z[2] * x[1], z[2] * x[0] - z[0] * x[2], z[0] * x[1] - z[1] * x[0]};
+    double redm = m1 * m2 / M;
+    double s = a * sqrt(redm / M);
+    double px[3] = {0.0, sqrt(3.0 * e * e + 0.75), -sqrt(3.0 * e * e + 0.75)};
+    double py[3] = {sqrt(1.0 - e * e), -sqrt((1.0 - e * e) / 4.0), -sqrt((1.0 - e * e) / 4.0)};
+    for (int k = 0; k < 3; k++)
+        for (int d = 0; d < 3; d++) out_pos[3 * k + d] = cm[d] + s * (px[k] * x[d] + py[k] * y[d]);
+    *out_mass = M / 3.0;
+    return 0;
+}

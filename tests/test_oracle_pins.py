@@ -510,3 +510,264 @@ def test_clusters_are_connected_components(orc, seed):
     for k, r in enumerate(roots):
         mem = members[cl[k]:cl[k + 1]]
         assert mem[0] == r and np.all(np.diff(mem) > 0) and np.all(label[mem] == r)
+
+
+# ------------------------------------------------- artificial particles
+_TT_NAMES = ["xx", "xy", "xz", "yy", "yz", "zz", "xxx", "xxy", "xxz", "xyy", "xyz", "xzz",
+             "yyy", "yyz", "yzz", "zzz"]
+
+
+def test_tidal_generalized_inverse_equals_table_a(orc):
+    """The least-squares inverse of the measure-point map reproduces the
+    printed closed forms of Table A, row by row."""
+    rows = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "tidal_table_a.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        order, name, point, comp, val = line.split()
+        rows.setdefault((int(order), name), {})[(int(point) - 1, "xyz".index(comp))] = float(val)
+    for (order, name), want in rows.items():
+        g = orc.tidal_ginv(order)[_TT_NAMES.index(name)]
+        got = {(r // 3, r % 3): v for r, v in enumerate(g) if abs(v) > 1e-14}
+        assert set(got) == set(want), (order, name)
+        for key, v in want.items():
+            assert abs(got[key] - v) < 1e-15, (order, name, key)
+
+
+def test_tidal_condition_numbers(orc):
+    """Condition numbers of the normal matrices of the maps: 2 and 12.7
+    (the values the paper quotes)."""
+    for order, want, tol in ((2, 2.0, 1e-12), (3, 12.7, 0.05)):
+        M = np.linalg.pinv(orc.tidal_ginv(order))
+        s = np.linalg.svd(M.T @ M, compute_uv=False)
+        assert abs(s.max() / s.min() - want) < tol, (order, s.max() / s.min())
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_tidal_fit_recovers_polynomial_fields(orc, order):
+    """A field that is exactly of the model's form is recovered exactly
+    (up to rounding), at any d_c; the points sit at d_c times Table A's
+    offsets around the centre."""
+    rng = np.random.default_rng(order)
+    K = 6 if order == 2 else 16
+    t = rng.normal(size=3 + K)
+    cm, d_c = rng.normal(size=3), 0.0123
+    pts = orc.tidal_points(order, cm, d_c)
+    u = (pts - cm) / d_c
+    s2 = math.sqrt(2.0) / 2.0
+    ref_u = (np.array([[1, 0, -s2], [-1, 0, -s2], [0, 1, s2], [0, -1, s2]]) if order == 2 else
+             np.array([[1, 0, -1], [0, 1, -1], [-1, 0, -1], [0, -1, -1], [1, 0, 1], [0, 1, 1],
+                       [-1, 0, 1], [0, -1, 1]]))
+    assert np.allclose(u, ref_u, atol=1e-12)
+    acc = np.array([orc.tidal_eval(order, t, p - cm) for p in pts])
+    fit = orc.tidal_fit(order, d_c, t[:3], acc)
+    assert np.allclose(fit, t, rtol=1e-8, atol=1e-9)
+
+
+def test_tidal_fit_of_point_mass_field(orc):
+    """Measure points near r = 0 in the field of a distant unit mass: the
+    fitted gradient is the Newtonian tidal tensor G m (3 n n^T - I)/D^3 up
+    to the truncation of the model (relative d_c / D for order 2,
+    (d_c / D)^2 for order 3)."""
+    D = np.array([3.0, -1.0, 2.0])
+    dn = np.linalg.norm(D)
+    n = D / dn
+
+    def field(p):
+        r = D - p
+        return r / np.linalg.norm(r) ** 3
+
+    tid = (3.0 * np.outer(n, n) - np.eye(3)) / dn ** 3
+    want = np.array([tid[0, 0], tid[0, 1], tid[0, 2], tid[1, 1], tid[1, 2], tid[2, 2]])
+    for order, d_c in ((2, 1e-3), (3, 1e-2)):
+        cm = np.zeros(3)
+        pts = orc.tidal_points(order, cm, d_c)
+        fit = orc.tidal_fit(order, d_c, field(cm), np.array([field(p) for p in pts]))
+        err = np.abs(fit[3:9] - want).max() / np.abs(want).max()
+        bound = 10 * (d_c / dn) ** (order - 1)
+        assert err < bound, (order, err, bound)
+
+
+def _binary_from_elements(a, e, m1, m2, Q, E0, G=1.0):
+    M = m1 + m2
+    n = math.sqrt(G * M / a ** 3)
+    r_orb = np.array([a * (math.cos(E0) - e), a * math.sqrt(1 - e * e) * math.sin(E0), 0.0])
+    fac = n / (1.0 - e * math.cos(E0))
+    v_orb = np.array([-a * math.sin(E0) * fac, a * math.sqrt(1 - e * e) * math.cos(E0) * fac, 0.0])
+    r, v = Q @ r_orb, Q @ v_orb
+    cm, vcm = np.array([0.3, -0.2, 0.1]), np.array([0.05, 0.0, -0.1])
+    return (cm - m2 / M * r, cm + m1 / M * r, vcm - m2 / M * v, vcm + m1 / M * v, cm)
+
+
+@pytest.mark.parametrize("e", [0.0, 0.3, 0.8, 0.97])
+def test_pseudo_particles_carry_orbit_averaged_quadrupole(orc, e):
+    """The three pseudoparticles have the binary's mass and centre of mass,
+    and their second moment about it equals the time average of the
+    binary's second moment over one orbit, computed by quadrature in the
+    eccentric anomaly (dt proportional to 1 - e cos E)."""
+    rng = np.random.default_rng(int(e * 100))
+    m1, m2, a = 0.7, 0.4, 0.013
+    Q = _rotation(rng)
+    x1, x2, v1, v2, cm = _binary_from_elements(a, e, m1, m2, Q, 1.1)
+    pos, mp = orc.pseudo_particles(m1, m2, x1, x2, v1, v2)
+    assert abs(3 * mp - (m1 + m2)) < 1e-15
+    assert np.allclose(pos.mean(axis=0), cm, atol=1e-14)
+    got = mp * sum(np.outer(p - cm, p - cm) for p in pos)
+    Es = np.linspace(0, 2 * math.pi, 4001)[:-1]
+    w = (1 - e * np.cos(Es))
+    acc = np.zeros((3, 3))
+    for E, wi in zip(Es, w):
+        r = Q @ np.array([a * (math.cos(E) - e), a * math.sqrt(1 - e * e) * math.sin(E), 0.0])
+        r1, r2 = -m2 / (m1 + m2) * r, m1 / (m1 + m2) * r
+        acc += wi * (m1 * np.outer(r1, r1) + m2 * np.outer(r2, r2))
+    want = acc / w.sum()
+    assert np.allclose(got, want, rtol=0, atol=1e-10 * np.abs(want).max())
+
+
+def test_pseudo_particles_reject_unbound(orc):
+    x1, x2 = np.zeros(3), np.array([1.0, 0, 0])
+    assert orc.pseudo_particles(0.5, 0.5, x1, x2, np.zeros(3), np.array([0, 2.0, 0])) is None
+    assert orc.pseudo_particles(0.5, 0.5, x1, x2, np.zeros(3), np.array([0, 0.5, 0])) is not None
+
+
+def test_pseudo_particles_traceless_closed_form(orc):
+    """The traceless form of the pseudoparticles' second moment equals the
+    closed form mu a^2 / 4 diag(9e^2 + 1, 1 - 6e^2, -3e^2 - 2) in the frame
+    (x to the pericentre, z along the angular momentum)."""
+    m1, m2, a, e = 0.3, 0.9, 0.02, 0.6
+    Q = np.eye(3)
+    x1, x2, v1, v2, cm = _binary_from_elements(a, e, m1, m2, Q, 2.3)
+    pos, mp = orc.pseudo_particles(m1, m2, x1, x2, v1, v2)
+    A = mp * sum(np.outer(p - cm, p - cm) for p in pos)
+    At = 1.5 * A - 0.5 * np.trace(A) * np.eye(3)
+    mu = m1 * m2 / (m1 + m2)
+    want = mu * a * a / 4 * np.diag([9 * e * e + 1, 1 - 6 * e * e, -3 * e * e - 2])
+    assert np.allclose(At, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+def test_pseudo_particles_radial_orbit(orc):
+    """Zero angular momentum: the e -> 1 limit, all three points on the
+    separation line, second moment mu a^2 (5/2) along it."""
+    m1, m2 = 0.4, 0.6
+    x1, x2 = np.array([0.0, 0.0, 0.0]), np.array([0.3, 0.4, 0.0])
+    v1, v2 = np.zeros(3), np.array([0.6, 0.8, 0.0]) * 0.5
+    pos, mp = orc.pseudo_particles(m1, m2, x1, x2, v1, v2)
+    a, e = orc.binary_elements(m1, m2, x1, x2, v1, v2)
+    assert abs(e - 1.0) < 1e-7
+    cm = (m1 * x1 + m2 * x2) / (m1 + m2)
+    n = (x2 - x1) / np.linalg.norm(x2 - x1)
+    A = mp * sum(np.outer(p - cm, p - cm) for p in pos)
+    mu = m1 * m2 / (m1 + m2)
+    assert np.allclose(A, 2.5 * mu * a * a * np.outer(n, n), atol=1e-14)
+
+
+@pytest.mark.parametrize("e", [0.0, 0.5, 0.95])
+def test_binary_elements_recovered(orc, e):
+    rng = np.random.default_rng(7)
+    for E0 in (0.0, 1.0, 3.0):
+        x1, x2, v1, v2, _ = _binary_from_elements(0.01, e, 0.2, 0.5, _rotation(rng), E0)
+        a, ee = orc.binary_elements(0.2, 0.5, x1, x2, v1, v2)
+        assert abs(a - 0.01) < 1e-14 and abs(ee - e) < 1e-7
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_tidal_potential_gradient_is_field(orc, order):
+    """Minus the gradient of the model potential is the model field (central
+    differences; the potential is a polynomial of degree order)."""
+    rng = np.random.default_rng(11 + order)
+    t = rng.normal(size=3 + (6 if order == 2 else 16))
+    r0, h = rng.normal(size=3) * 0.3, 1e-4
+    g = np.array([(orc.tidal_potential(order, t, r0 + h * ek, 0.7) -
+                   orc.tidal_potential(order, t, r0 - h * ek, 0.7)) / (2 * h) for ek in np.eye(3)])
+    assert np.allclose(-g, orc.tidal_eval(order, t, r0), rtol=1e-7, atol=1e-7)
+    assert orc.tidal_potential(order, t, np.zeros(3), 0.7) == 0.7
+
+
+def test_artificial_set_bookkeeping(orc):
+    """Members leave the set, singles keep their order and values, every
+    pair adds its centre, P measure points and three pseudoparticles; mass
+    and the pair's centre of mass are conserved."""
+    rng = np.random.default_rng(5)
+    n = 12
+    pos, vel = rng.normal(size=(3, n)), rng.normal(size=(3, n)) * 0.01
+    mass = rng.uniform(0.5, 1.0, n)
+    pairs = np.array([[3, 7], [10, 0]])
+    for b, (i, j) in enumerate(pairs):
+        x1, x2, v1, v2, _ = _binary_from_elements(0.01 * (b + 1), 0.4, mass[i], mass[j],
+                                                  _rotation(rng), 0.5 + b)
+        pos[:, i], pos[:, j], vel[:, i], vel[:, j] = x1 + b, x2 + b, v1, v2
+    r_in, r_out = rng.uniform(0.1, 0.2, n), rng.uniform(0.3, 0.4, n)
+    r_s = r_out * 1.2
+    for order, P in ((2, 4), (3, 8)):
+        art = orc.artificial_set(pos, vel, mass, r_in, r_out, r_s, pairs, order, 0.8)
+        singles = [k for k in range(n) if k not in pairs.ravel()]
+        assert art["n_single"] == len(singles) and list(art["src"][:len(singles)]) == singles
+        assert np.array_equal(art["pos"][:, :len(singles)], pos[:, singles])
+        assert art["pos"].shape[1] == len(singles) + 2 * (P + 4)
+        assert abs(art["mass"].sum() - mass.sum()) < 1e-14
+        for b, (i, j) in enumerate(pairs):
+            base = len(singles) + b * (P + 4)
+            blk = slice(base, base + P + 4)
+            cm = (mass[i] * pos[:, i] + mass[j] * pos[:, j]) / (mass[i] + mass[j])
+            m = art["mass"][blk]
+            assert np.all(m[:P + 1] == 0) and np.allclose(m[P + 1:], (mass[i] + mass[j]) / 3)
+            assert np.allclose(art["pos"][:, blk] @ m / m.sum(), cm, atol=1e-14)
+            a, e = orc.binary_elements(mass[i], mass[j], pos[:, i], pos[:, j], vel[:, i],
+                                       vel[:, j])
+            assert abs(art["frame"][b, 3] - 0.8 * a * (1 + e)) < 1e-15
+            d = np.linalg.norm(art["pos"][:, base + 1:base + 1 + P] - cm[:, None], axis=0)
+            want = art["frame"][b, 3] * (math.sqrt(1.5) if order == 2 else math.sqrt(2.0))
+            assert np.allclose(d, want, rtol=1e-13)
+            assert np.all(art["r_in"][blk] == max(r_in[i], r_in[j]))
+            assert art["pair_of"][i] == b and art["pair_of"][j] == b
+    with pytest.raises(ValueError):
+        orc.artificial_set(pos, vel, mass, r_in, r_out, r_s, [[1, 2], [2, 4]], 2, 1.0)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_artificial_pipeline_binary_and_perturber(orc, order):
+    """A bound binary deep inside its inner changeover radius and a distant
+    perturber outside every outer radius: through the long-range direct sum
+    over the artificial set and the post-fit, (1) each member feels the
+    perturber's Newtonian field at its own position up to the truncation of
+    the tidal model, and (2) the perturber feels the binary's monopole plus
+    its orbit-averaged quadrupole (eq. avebinquad) up to the octupole."""
+    m1, m2, mp, a, e = 0.6, 0.3, 1.0, 1e-3, 0.5
+    rng = np.random.default_rng(order)
+    x1, x2, v1, v2, cm = _binary_from_elements(a, e, m1, m2, _rotation(rng), 0.9)
+    D = np.array([0.25, -0.1, 0.15])
+    pos = np.stack([x1, x2, cm + D], axis=1)
+    vel = np.stack([v1, v2, np.zeros(3)], axis=1)
+    mass = np.array([m1, m2, mp])
+    r_in, r_out = np.full(3, 0.02), np.full(3, 0.1)
+    art = orc.artificial_set(pos, vel, mass, r_in, r_out, 1.2 * r_out, [[0, 1]], order, 1.0)
+    acc_set, pot_set = orc.force_long(art["pos"], art["mass"], art["r_in"], art["r_out"])
+    rec, acc, pot = orc.artificial_fit(order, art, pos, acc_set, pot_set, [[0, 1]])
+    dn = np.linalg.norm(D)
+    # the pair's own pseudoparticles lie inside r_in of its members: their
+    # long-range force vanishes there and their potential is a constant
+    P = 4 if order == 2 else 8
+    own = art["n_single"] + 1 + P
+    sub = np.concatenate([art["pos"][:, own:own + 3], cm[:, None]], axis=1)
+    _, pot_own = orc.force_long(sub, np.append(art["mass"][own:own + 3], 0.0), np.full(4, 0.02),
+                                np.full(4, 0.1))
+    for k in (0, 1):
+        r = pos[:, 2] - pos[:, k]
+        want = mp * r / np.linalg.norm(r) ** 3
+        err = np.linalg.norm(acc[:, k] - want) / np.linalg.norm(want)
+        # the model's first dropped term, relative: (|r'| / D)^order; the
+        # fit through points at d_c adds the same order
+        assert err < 2 * (1.5 * a / dn) ** order, (k, err)
+        assert abs(pot[k] + mp / np.linalg.norm(r) - pot_own[3]) < 2 * (1.5 * a / dn) ** order * mp / dn
+    M, com, q = orc.multipole(art["pos"][:, art["n_single"]:], art["mass"][art["n_single"]:])
+    assert np.allclose(com, cm, atol=1e-15)
+    quad_acc, _ = orc.multipole_eval(M, com, q, pos[:, 2:3])
+    s = a * math.sqrt(m1 * m2) / (m1 + m2)
+    err = np.linalg.norm(acc[:, 2] - quad_acc[:, 0]) / np.linalg.norm(quad_acc[:, 0])
+    assert err < (2 * s / dn) ** 3
+    # the orbit-averaged quadrupole: the pseudoparticles' second moment
+    bin_q = (m1 + m2) / 3 * sum(np.outer(p - cm, p - cm)
+                                for p in art["pos"][:, art["n_single"] + 1 + (4 if order == 2 else 8):].T)
+    A = bin_q
+    mu = m1 * m2 / (m1 + m2)
+    assert abs(np.trace(A) - mu * a * a * (1.5 * e * e + 1.0)) < 1e-15
