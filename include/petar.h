@@ -252,6 +252,83 @@ PETAR_API petar_status petar_clusters(petar_ctx *ctx, int64_t N, const int64_t *
                                       int64_t *cl_offsets_dev, int32_t *members_dev,
                                       int64_t *n_clusters);
 
+/* ---- Artificial particles (Sec. "Artificial particle algorithm for weak
+ * perturbation"). A bound pair that the short-range integrator treats as a
+ * group leaves the long-range set; in its place come its centre of mass
+ * and the P measure points of the tidal tensor (zero mass; P = 4 at the
+ * corners of a regular tetrahedron for order 2, 8 for order 3, the offsets
+ * d_c u_p of Table A) and the three pseudoparticles of eq. psep (mass
+ * (m1 + m2)/3 each, carrying the pair's orbit-averaged quadrupole, eq.
+ * avebinquad). The set goes through petar_tree_build / petar_force_long
+ * like any other particles; petar_tidal_fit then turns the field at the
+ * centre and at the measure points into the tensor of eq. tt (the
+ * generalized inverse of eq. map) and evaluates it at the members. */
+
+/* Output set of petar_artificial_make (caller-owned device buffers). */
+typedef struct {
+    double *pos_dev;      /* [3][n_out]                                          */
+    double *mass_dev;     /* [n_out]                                             */
+    double *r_in_dev;     /* [n_out]                                             */
+    double *r_out_dev;    /* [n_out]                                             */
+    double *r_search_dev; /* [n_out]                                             */
+    int32_t *src_dev;     /* [n_out]: input index of a single, -1 if artificial  */
+    int64_t n_out;        /* must equal N + n_pair (P + 2)                       */
+} petar_art_set;
+
+/* Builds the set: the N - 2 n_pair singles first, in input order, then for
+ * pair b (pairs_dev[2][n_pair], int32 input indices i = pairs[b], j =
+ * pairs[n_pair + b]) the block at n_single + b (P + 4): centre of mass,
+ * the P measure points at r_cm + d_c u_p, the three pseudoparticles
+ * (eq. psep rotated into the orbit's frame: x to the pericentre, z along
+ * the angular momentum; x along the separation for a circular orbit; a
+ * radial orbit as e = 1). Every artificial particle takes the larger of
+ * the members' r_in, r_out and r_search. d_c = c_d a (1 + e) from the
+ * pair's Kepler orbit with G = params.G. Inputs: pos_dev, vel_dev [3][N],
+ * mass_dev and radii [N] (input order); order 2 or 3; c_d > 0. Outputs:
+ * *set, frame_dev[4][n_pair] = (r_cm, d_c), and pair_of_dev[N] (may be
+ * NULL) = the pair of a member, -1 for a single. Errors: PETAR_E_INVALID
+ * for bad arguments, an index outside [0, N), i == j, a particle in two
+ * pairs, or a pair that is not bound (specific energy >= 0); the outputs
+ * are then undefined. */
+PETAR_API petar_status petar_artificial_make(petar_ctx *ctx, int64_t N, const double *pos_dev,
+                                             const double *vel_dev, const double *mass_dev,
+                                             const double *r_in_dev, const double *r_out_dev,
+                                             const double *r_search_dev, int64_t n_pair,
+                                             const int32_t *pairs_dev, int order, double c_d,
+                                             petar_art_set *set, double *frame_dev,
+                                             int32_t *pair_of_dev);
+
+/* Post-fit after the long-range force on the set: acc_set_dev[3][n_out]
+ * and pot_set_dev[n_out] (may be NULL) are the outputs of petar_force_long
+ * for the set of petar_artificial_make (its blocks at n_out - n_pair (P + 4)
+ * onwards). Writes per pair the record tensor_dev[4 + K][n_pair] = phi(r_cm),
+ * A(r_cm) (3), then the K = 6 (order 2: xx xy xz yy yz zz) or 16 (order 3:
+ * also xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz) coefficients of Table A, the
+ * least-squares solution of eq. map for the field differences at the
+ * measure points (the third-order coefficients include the 1/2 of eq. tt).
+ * With acc_dev[3][N] (may be NULL) also the long-range field of every input
+ * particle: singles copy theirs from the set (through set->src_dev), the
+ * members of pair b take the fitted field at their position pos_dev[3][N];
+ * pot_dev[N] (needs pot_set_dev) likewise, members from the model potential
+ * phi(r_cm) - r'.(A(r_cm) + a1/2 + a2/3), a1 and a2 the first- and second-
+ * order parts of the fitted field at r' = r - r_cm. */
+PETAR_API petar_status petar_tidal_fit(petar_ctx *ctx, int order, int64_t N, const double *pos_dev,
+                                       int64_t n_pair, const int32_t *pairs_dev,
+                                       const double *frame_dev, int64_t n_out,
+                                       const int32_t *src_dev, const double *acc_set_dev,
+                                       const double *pot_set_dev, double *tensor_dev,
+                                       double *acc_dev, double *pot_dev);
+
+/* Fitted field (and potential, pot_dev may be NULL) at n_pt points
+ * pos_dev[3][n_pt], point k taking the tensor of pair pair_of_dev[k]
+ * (points with pair_of < 0 are left untouched), e.g. the members along
+ * their orbits between two long-range steps. Errors: PETAR_E_INVALID for
+ * bad arguments or a pair_of >= n_pair. */
+PETAR_API petar_status petar_tidal_eval(petar_ctx *ctx, int order, int64_t n_pair,
+                                        const double *tensor_dev, const double *frame_dev,
+                                        int64_t n_pt, const int32_t *pair_of_dev,
+                                        const double *pos_dev, double *acc_dev, double *pot_dev);
+
 /* Message of the last failure on ctx (thread-local message if ctx is NULL). */
 PETAR_API const char *petar_last_error(petar_ctx *ctx);
 PETAR_API const char *petar_status_string(petar_status status);

@@ -1091,11 +1091,13 @@ OR_EXPORT int oracle_binary_elements(double m1, double m2, const double x1[3], c
     double E = 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - mu / rr;
     if (!(rr > 0.0) || !(E < 0.0)) return -1;
     double h[3] = {r[1] * v[2] - r[2] * v[1], r[2] * v[0] - r[0] * v[2], r[0] * v[1] - r[1] * v[0]};
-    double h2 = h[0] * h[0] + h[1] * h[1] + h[2] * h[2];
-    double a = -mu / (2.0 * E);
-    double e2 = 1.0 - h2 / (mu * a);
-    out[0] = a;
-    out[1] = e2 > 0.0 ? sqrt(e2) : 0.0;
+    /* e as the length of the eccentricity vector v x h / mu - r/|r| (well
+     * conditioned also for nearly circular orbits, unlike 1 - h^2/(mu a)) */
+    double ev[3] = {(v[1] * h[2] - v[2] * h[1]) / mu - r[0] / rr,
+                    (v[2] * h[0] - v[0] * h[2]) / mu - r[1] / rr,
+                    (v[0] * h[1] - v[1] * h[0]) / mu - r[2] / rr};
+    out[0] = -mu / (2.0 * E);
+    out[1] = sqrt(ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2]);
     return 0;
 }
 

@@ -25,6 +25,7 @@ __all__ = [
     "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
     "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_batch_build",
     "petar_force_long", "petar_step_graph", "petar_nb_filter", "petar_clusters",
+    "petar_artificial_make", "petar_tidal_fit", "petar_tidal_eval", "art_points",
     "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
     "PETAR_NO_DEVICE", "lib_path",
 ]
@@ -272,6 +273,113 @@ def petar_clusters(ctx: Context, offsets: torch.Tensor, idx: torch.Tensor):
                              ctypes.c_void_p(members.data_ptr()), ctypes.byref(nc))
     _check(st, ctx)
     return label, cl[: nc.value + 1], members
+
+
+
+def art_points(order: int) -> int:
+    """Measure points of the order-2 (4) or order-3 (8) tidal tensor."""
+    if order not in (2, 3):
+        raise ValueError("order must be 2 or 3")
+    return 4 if order == 2 else 8
+
+
+def petar_artificial_make(ctx: Context, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
+                          r_in: torch.Tensor, r_out: torch.Tensor, r_search: torch.Tensor,
+                          pairs: torch.Tensor, order: int = 3, c_d: float = 1.0) -> dict:
+    """Set of the long-range force with artificial particles for the bound
+    pairs pairs[2, n_pair] (int32): dict(pos (3, n_out), mass, r_in, r_out,
+    r_search, src (int32), frame (4, n_pair), pair_of (N,) int32, n_single);
+    see petar.h."""
+    n = mass.shape[0]
+    dev = ctx.device
+    d = "cuda:%d" % dev
+    n_pair = pairs.shape[1] if pairs.dim() == 2 else 0
+    n_out = n + n_pair * (art_points(order) + 2)
+    out = dict(pos=torch.empty((3, n_out), dtype=torch.float64, device=d),
+               mass=torch.empty(n_out, dtype=torch.float64, device=d),
+               r_in=torch.empty(n_out, dtype=torch.float64, device=d),
+               r_out=torch.empty(n_out, dtype=torch.float64, device=d),
+               r_search=torch.empty(n_out, dtype=torch.float64, device=d),
+               src=torch.empty(n_out, dtype=torch.int32, device=d),
+               frame=torch.empty((4, n_pair), dtype=torch.float64, device=d),
+               pair_of=torch.empty(n, dtype=torch.int32, device=d),
+               n_single=n - 2 * n_pair, order=order)
+    st_ = _capi.petar_art_set(out["pos"].data_ptr(), out["mass"].data_ptr(),
+                              out["r_in"].data_ptr(), out["r_out"].data_ptr(),
+                              out["r_search"].data_ptr(), out["src"].data_ptr(), n_out)
+    frame = out["frame"]
+    st = _lib.petar_artificial_make(
+        ctx.handle, n, _dptr(pos, torch.float64, (3, n), "pos", dev),
+        _dptr(vel, torch.float64, (3, n), "vel", dev), _dptr(mass, torch.float64, (n,), "mass", dev),
+        _dptr(r_in, torch.float64, (n,), "r_in", dev), _dptr(r_out, torch.float64, (n,), "r_out", dev),
+        _dptr(r_search, torch.float64, (n,), "r_search", dev), n_pair,
+        _dptr(pairs, torch.int32, (2, n_pair), "pairs", dev) if n_pair else None, int(order),
+        float(c_d), ctypes.byref(st_), ctypes.c_void_p(frame.data_ptr()) if n_pair else None,
+        ctypes.c_void_p(out["pair_of"].data_ptr()))
+    _check(st, ctx)
+    return out
+
+
+def petar_tidal_fit(ctx: Context, art: dict, pairs: torch.Tensor, acc_set: torch.Tensor,
+                    pot_set: Optional[torch.Tensor], pos: Optional[torch.Tensor] = None):
+    """Post-fit of the long-range force on an artificial set: returns
+    (tensor (4 + K, n_pair), acc (3, N) or None, pot (N,) or None); acc and
+    pot are computed when pos (3, N) is given. See petar.h."""
+    order = art["order"]
+    dev = ctx.device
+    d = "cuda:%d" % dev
+    n_out = art["mass"].shape[0]
+    n_pair = art["frame"].shape[1]
+    K = 6 if order == 2 else 16
+    tensor = torch.empty((4 + K, n_pair), dtype=torch.float64, device=d)
+    acc = pot = None
+    n = 0
+    if pos is not None:
+        n = pos.shape[1]
+        acc = torch.empty((3, n), dtype=torch.float64, device=d)
+        if pot_set is not None:
+            pot = torch.empty(n, dtype=torch.float64, device=d)
+    st = _lib.petar_tidal_fit(
+        ctx.handle, int(order), n, _dptr(pos, torch.float64, (3, n), "pos", dev), n_pair,
+        _dptr(pairs, torch.int32, (2, n_pair), "pairs", dev) if n_pair else None,
+        _dptr(art["frame"], torch.float64, (4, n_pair), "frame", dev) if n_pair else None, n_out,
+        _dptr(art["src"], torch.int32, (n_out,), "src", dev),
+        _dptr(acc_set, torch.float64, (3, n_out), "acc_set", dev),
+        _dptr(pot_set, torch.float64, (n_out,), "pot_set", dev),
+        ctypes.c_void_p(tensor.data_ptr()) if n_pair else None,
+        ctypes.c_void_p(acc.data_ptr()) if acc is not None else None,
+        ctypes.c_void_p(pot.data_ptr()) if pot is not None else None)
+    _check(st, ctx)
+    return tensor, acc, pot
+
+
+def petar_tidal_eval(ctx: Context, order: int, tensor: torch.Tensor, frame: torch.Tensor,
+                     pair_of: torch.Tensor, pos: torch.Tensor, acc: Optional[torch.Tensor] = None,
+                     pot: Optional[torch.Tensor] = None):
+    """Fitted field (3, n_pt) and potential (n_pt,) at pos (3, n_pt); points
+    with pair_of < 0 keep the values already in acc / pot (zeros when those
+    are not given)."""
+    dev = ctx.device
+    d = "cuda:%d" % dev
+    n_pt = pos.shape[1]
+    n_pair = frame.shape[1]
+    K = 6 if order == 2 else 16
+    if acc is None:
+        acc = torch.zeros((3, n_pt), dtype=torch.float64, device=d)
+    if pot is None:
+        pot = torch.zeros(n_pt, dtype=torch.float64, device=d)
+    if n_pt == 0:
+        return acc, pot
+    st = _lib.petar_tidal_eval(
+        ctx.handle, int(order), n_pair,
+        _dptr(tensor, torch.float64, (4 + K, n_pair), "tensor", dev) if n_pair else None,
+        _dptr(frame, torch.float64, (4, n_pair), "frame", dev) if n_pair else None, n_pt,
+        _dptr(pair_of, torch.int32, (n_pt,), "pair_of", dev),
+        _dptr(pos, torch.float64, (3, n_pt), "pos", dev),
+        _dptr(acc, torch.float64, (3, n_pt), "acc", dev),
+        _dptr(pot, torch.float64, (n_pt,), "pot", dev))
+    _check(st, ctx)
+    return acc, pot
 
 
 def petar_copy_counts(ctx: Context) -> torch.Tensor:

@@ -57,6 +57,13 @@ class petar_tuned(ctypes.Structure):
                 ("i_per_lane", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
+class petar_art_set(ctypes.Structure):
+    _fields_ = [("pos_dev", ctypes.c_void_p), ("mass_dev", ctypes.c_void_p),
+                ("r_in_dev", ctypes.c_void_p), ("r_out_dev", ctypes.c_void_p),
+                ("r_search_dev", ctypes.c_void_p), ("src_dev", ctypes.c_void_p),
+                ("n_out", ctypes.c_int64)]
+
+
 # (name, restype, argtypes) of every exported entry point
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -80,6 +87,10 @@ SIGNATURES = [
     ("petar_nb_filter", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P,
                                ctypes.POINTER(petar_nblist)]),
     ("petar_clusters", _INT, [_P, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
+    ("petar_artificial_make", _INT, [_P, _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _INT, _D,
+                                     ctypes.POINTER(petar_art_set), _P, _P]),
+    ("petar_tidal_fit", _INT, [_P, _INT, _I64, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    ("petar_tidal_eval", _INT, [_P, _INT, _I64, _P, _P, _I64, _P, _P, _P, _P]),
     ("petar_last_error", ctypes.c_char_p, [_P]),
     ("petar_status_string", ctypes.c_char_p, [_INT]),
 ]

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpetar.so")
-SOURCES = ["scan.hip", "tree.hip", "force.hip", "nblist.hip", "cluster.hip", "capi.cpp",
+SOURCES = ["scan.hip", "tree.hip", "force.hip", "nblist.hip", "cluster.hip", "artificial.hip", "capi.cpp",
            "validate.cpp", "autotune.cpp"]
 ARCH = os.environ.get("PETAR_OFFLOAD_ARCH", "gfx950")
 

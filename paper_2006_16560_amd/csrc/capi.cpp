@@ -45,6 +45,9 @@ struct petar_ctx {
     // second-stage filter and clusters
     DevBuf cl_keep, cl_row, cl_counts, cl_parent, cl_root, cl_rootpos, cl_status, cl_flags,
         cl_key0, cl_key1, cl_val0, cl_val1;
+    // artificial particles
+    DevBuf art_single, art_spos, art_status, art_pairof, tt_ginv;
+    bool tt_ginv_ready = false;
     uint32_t nbhead_cap = 0, nbleaf_cap = 0;
 
     Status *host_status = nullptr;  // pinned
@@ -209,6 +212,7 @@ void free_all(petar_ctx *c) {
                       &c->cl_keep,  &c->cl_row,      &c->cl_counts,   &c->cl_parent,  &c->cl_root,    &c->cl_rootpos,
                       &c->cl_status,   &c->cl_flags,   &c->cl_key0,    &c->cl_key1,
                       &c->cl_val0,  &c->cl_val1,
+                      &c->art_single, &c->art_spos, &c->art_status, &c->art_pairof, &c->tt_ginv,
                       &c->sys_off};
     for (DevBuf *b : bufs) {
         if (b->p) hipFree(b->p);
@@ -216,6 +220,7 @@ void free_all(petar_ctx *c) {
         b->cap = 0;
     }
     c->ws_bytes = 0;
+    c->tt_ginv_ready = false;
 }
 
 }  // namespace
@@ -436,6 +441,97 @@ petar_status petar_clusters(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets
     uint32_t nc = 0;
     memcpy(&nc, ctx->host_scalar, 4);
     *n_clusters = nc;
+    return PETAR_OK;
+}
+
+petar_status petar_artificial_make(petar_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                                   const double *mass, const double *r_in, const double *r_out,
+                                   const double *r_search, int64_t n_pair, const int32_t *pairs,
+                                   int order, double c_d, petar_art_set *set, double *frame,
+                                   int32_t *pair_of) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_art_make_args(n, pos, vel, mass, r_in, r_out, r_search, n_pair,
+                                            pairs, order, c_d, set, frame))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    TRY(ensure(ctx, ctx->art_single, (size_t)n * 4));
+    TRY(ensure(ctx, ctx->art_spos, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->art_status, 16));
+    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
+    if (!pair_of) {
+        TRY(ensure(ctx, ctx->art_pairof, (size_t)n * 4));
+        pair_of = ptr<int32_t>(ctx->art_pairof);
+    }
+    int32_t *bad = ptr<int32_t>(ctx->art_status);
+    fill_i64(ptr<int64_t>(ctx->art_status), 0, 2, s);
+    ArtArgs a{pos, vel, mass, r_in, r_out, r_search, n, pairs, n_pair, order, c_d,
+              ctx->params.G, n - 2 * n_pair, set->n_out, set->pos_dev, set->mass_dev,
+              set->r_in_dev, set->r_out_dev, set->r_search_dev, set->src_dev, frame, pair_of};
+    launch_art_make(a, ptr<uint32_t>(ctx->art_single), ptr<uint32_t>(ctx->art_spos),
+                    ptr<int64_t>(ctx->scan_ws), bad, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, bad, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    int32_t b[4] = {0, 0, 0, 0};
+    memcpy(b, ctx->host_scalar, 16);
+    if (b[0]) return fail(ctx, PETAR_E_INVALID, "%d pairs with an index outside [0, N) or i == j", b[0]);
+    if (b[1]) return fail(ctx, PETAR_E_INVALID, "a particle appears in more than one pair");
+    if (b[2]) return fail(ctx, PETAR_E_INVALID, "%d pairs are not bound", b[2]);
+    return PETAR_OK;
+}
+
+petar_status petar_tidal_fit(petar_ctx *ctx, int order, int64_t n, const double *pos,
+                             int64_t n_pair, const int32_t *pairs, const double *frame,
+                             int64_t n_out, const int32_t *src, const double *acc_set,
+                             const double *pot_set, double *tensor, double *acc, double *pot) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_tidal_fit_args(order, n, pos, n_pair, pairs, frame, n_out, src,
+                                             acc_set, pot_set, tensor, acc, pot))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int P = order == 2 ? 4 : 8;
+    if (!ctx->tt_ginv_ready) {
+        // both orders, order 2 first (6 x 12), then order 3 (16 x 24)
+        TRY(ensure(ctx, ctx->tt_ginv, (72 + 384) * 8));
+        HIP_TRY(ctx, hipMemcpy(ctx->tt_ginv.p, tidal_ginv_host(2), 72 * 8, hipMemcpyHostToDevice));
+        HIP_TRY(ctx, hipMemcpy(ptr<double>(ctx->tt_ginv) + 72, tidal_ginv_host(3), 384 * 8,
+                               hipMemcpyHostToDevice));
+        ctx->tt_ginv_ready = true;
+    }
+    FitArgs f{order, n_pair, n_out - n_pair * (P + 4), n_out, acc_set, pot_set, frame,
+              ptr<double>(ctx->tt_ginv) + (order == 2 ? 0 : 72), tensor, pos, n, pairs, src,
+              acc, pot};
+    launch_tidal_fit(f, s);
+    HIP_TRY(ctx, hipGetLastError());
+    return PETAR_OK;
+}
+
+petar_status petar_tidal_eval(petar_ctx *ctx, int order, int64_t n_pair, const double *tensor,
+                              const double *frame, int64_t n_pt, const int32_t *pair_of,
+                              const double *pos, double *acc, double *pot) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_tidal_eval_args(order, n_pair, tensor, frame, n_pt, pair_of, pos,
+                                              acc))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    if (n_pt == 0) return PETAR_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    TRY(ensure(ctx, ctx->art_status, 16));
+    int32_t *bad = ptr<int32_t>(ctx->art_status);
+    fill_i64(ptr<int64_t>(ctx->art_status), 0, 1, s);
+    EvalArgs e{order, n_pair, tensor, frame, n_pt, pair_of, pos, acc, pot, bad};
+    launch_tidal_eval(e, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    int32_t b = 0;
+    memcpy(&b, ctx->host_scalar, 4);
+    if (b) return fail(ctx, PETAR_E_INVALID, "%d points with pair_of >= n_pair", b);
     return PETAR_OK;
 }
 

@@ -179,4 +179,57 @@ void launch_cluster_keys(const int32_t *label, int64_t n, const uint32_t *root_p
 void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_offsets,
                             hipStream_t s);
 
+// --------------------------------------------------------- artificial.hip
+// Set of the long-range force with artificial particles: singles first (input
+// order), then one block of P + 4 per pair (centre, P measure points, three
+// pseudoparticles); P = 4 (order 2) or 8 (order 3).
+struct ArtArgs {
+    const double *pos, *vel, *mass, *r_in, *r_out, *r_search;  // [3][n], [3][n], [n] x4
+    int64_t n;
+    const int32_t *pairs;  // [2][n_pair]
+    int64_t n_pair;
+    int order;
+    double c_d, G;
+    int64_t n_single, n_out;  // n - 2 n_pair, n_single + n_pair (P + 4)
+    double *o_pos, *o_mass, *o_rin, *o_rout, *o_rs;  // [3][n_out], [n_out] x4
+    int32_t *src;      // [n_out]: input index of a single, -1 for artificial
+    double *frame;     // [4][n_pair]: centre of mass, d_c
+    int32_t *pair_of;  // [n]: pair of a member, -1 for a single
+};
+// bad[0]: index outside [0, n) or i == j; bad[1]: particle in two pairs;
+// bad[2]: pair not bound. single/spos hold n and n + 1 entries.
+void launch_art_make(const ArtArgs &a, uint32_t *single, uint32_t *spos, int64_t *scan_ws,
+                     int32_t *bad, hipStream_t s);
+
+// Post-fit: per pair the record [phi(r_cm), A(r_cm), T] ([4 + K][n_pair]);
+// with acc set, the members' field and the singles' copies ([3][n]).
+struct FitArgs {
+    int order;
+    int64_t n_pair, n_single, n_out;
+    const double *acc_set, *pot_set;  // [3][n_out], [n_out] (pot_set may be null)
+    const double *frame;              // [4][n_pair]
+    const double *ginv;               // K x 3P, row-major, device
+    double *tensor;                   // [4 + K][n_pair]
+    const double *pos;                // [3][n] (when acc is set)
+    int64_t n;
+    const int32_t *pairs, *src;       // [2][n_pair], [n_out]
+    double *acc, *pot;                // [3][n], [n] (may be null)
+};
+void launch_tidal_fit(const FitArgs &f, hipStream_t s);
+
+struct EvalArgs {
+    int order;
+    int64_t n_pair;
+    const double *tensor, *frame;  // [4 + K][n_pair], [4][n_pair]
+    int64_t n_pt;
+    const int32_t *pair_of;        // [n_pt], < 0: point skipped
+    const double *pos;             // [3][n_pt]
+    double *acc, *pot;             // [3][n_pt], [n_pt] (pot may be null)
+    int32_t *bad;                  // count of pair_of >= n_pair
+};
+void launch_tidal_eval(const EvalArgs &e, hipStream_t s);
+// Generalized inverse of the measure-point map at d_c = 1 (host memory,
+// K x 3P row-major), computed once.
+const double *tidal_ginv_host(int order);
+
 }  // namespace petar

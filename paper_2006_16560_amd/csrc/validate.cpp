@@ -95,4 +95,62 @@ const char *check_cluster_args(int64_t n, const int64_t *nb_offsets, const int32
     return nullptr;
 }
 
+namespace {
+int art_points(int order) { return order == 2 ? 4 : 8; }
+}  // namespace
+
+const char *check_art_make_args(int64_t n, const double *pos, const double *vel,
+                                const double *mass, const double *r_in, const double *r_out,
+                                const double *r_search, int64_t n_pair, const int32_t *pairs,
+                                int order, double c_d, const petar_art_set *set,
+                                const double *frame) {
+    if (n < 1) return "N must be >= 1";
+    if (n > kMaxParticles) return "N must be < 2^31";
+    if (order != 2 && order != 3) return "order must be 2 or 3";
+    if (!std::isfinite(c_d) || !(c_d > 0.0)) return "c_d must be finite and > 0";
+    if (n_pair < 0 || 2 * n_pair > n) return "n_pair must be in [0, N/2]";
+    if (!pos || !vel || !mass) return "pos, vel and mass must not be NULL";
+    if (!r_in || !r_out || !r_search) return "r_in, r_out and r_search must not be NULL";
+    if (n_pair > 0 && (!pairs || !frame)) return "pairs and frame must not be NULL";
+    if (!set) return "set is NULL";
+    const int64_t want = n + n_pair * (art_points(order) + 2);
+    if (set->n_out != want) return "set->n_out must be N + n_pair (P + 2), P = 4 or 8";
+    if (want > kMaxParticles) return "the set must hold < 2^31 particles";
+    if (!set->pos_dev || !set->mass_dev || !set->r_in_dev || !set->r_out_dev ||
+        !set->r_search_dev || !set->src_dev)
+        return "set buffers must not be NULL";
+    return nullptr;
+}
+
+const char *check_tidal_fit_args(int order, int64_t n, const double *pos, int64_t n_pair,
+                                 const int32_t *pairs, const double *frame, int64_t n_out,
+                                 const int32_t *src, const double *acc_set, const double *pot_set,
+                                 const double *tensor, const double *acc, const double *pot) {
+    if (order != 2 && order != 3) return "order must be 2 or 3";
+    if (n_pair < 0) return "n_pair must be >= 0";
+    if (n_out < n_pair * (art_points(order) + 4) || n_out > kMaxParticles)
+        return "n_out must be >= n_pair (P + 4) and < 2^31";
+    if (!acc_set) return "acc_set must not be NULL";
+    if (n_pair > 0 && (!frame || !tensor)) return "frame and tensor must not be NULL";
+    if (pot && !acc) return "pot requires acc";
+    if (acc) {
+        if (n < 1 || n > kMaxParticles) return "N must be in [1, 2^31)";
+        if (!pos || !src) return "pos and src must not be NULL";
+        if (n_pair > 0 && !pairs) return "pairs must not be NULL";
+        if (pot && !pot_set) return "pot requires pot_set";
+    }
+    return nullptr;
+}
+
+const char *check_tidal_eval_args(int order, int64_t n_pair, const double *tensor,
+                                  const double *frame, int64_t n_pt, const int32_t *pair_of,
+                                  const double *pos, const double *acc) {
+    if (order != 2 && order != 3) return "order must be 2 or 3";
+    if (n_pair < 0 || n_pair > kMaxParticles) return "n_pair must be in [0, 2^31)";
+    if (n_pt < 0 || n_pt > kMaxParticles) return "n_pt must be in [0, 2^31)";
+    if (n_pt > 0 && (!pair_of || !pos || !acc)) return "pair_of, pos and acc must not be NULL";
+    if (n_pt > 0 && n_pair > 0 && (!tensor || !frame)) return "tensor and frame must not be NULL";
+    return nullptr;
+}
+
 }  // namespace petar

@@ -30,4 +30,17 @@ const char *check_cluster_args(int64_t n, const int64_t *nb_offsets, const int32
                                const int32_t *label, const int64_t *cl_offsets,
                                const int32_t *members, const int64_t *n_clusters);
 
+const char *check_art_make_args(int64_t n, const double *pos, const double *vel,
+                                const double *mass, const double *r_in, const double *r_out,
+                                const double *r_search, int64_t n_pair, const int32_t *pairs,
+                                int order, double c_d, const petar_art_set *set,
+                                const double *frame);
+const char *check_tidal_fit_args(int order, int64_t n, const double *pos, int64_t n_pair,
+                                 const int32_t *pairs, const double *frame, int64_t n_out,
+                                 const int32_t *src, const double *acc_set, const double *pot_set,
+                                 const double *tensor, const double *acc, const double *pot);
+const char *check_tidal_eval_args(int order, int64_t n_pair, const double *tensor,
+                                  const double *frame, int64_t n_pt, const int32_t *pair_of,
+                                  const double *pos, const double *acc);
+
 }  // namespace petar

@@ -290,3 +290,98 @@ def test_clusters_validation(capi, ctx, case):
     st = lib.petar_clusters(ctx, a["n"], a["offs"], a["idx"], a["label"], a["cl"], a["members"],
                             ncp)
     assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)
+
+
+def _art_set(capi, n_out, null=None):
+    _capi, _ = capi
+    f = {k: FAKE for k in ("pos_dev", "mass_dev", "r_in_dev", "r_out_dev", "r_search_dev",
+                           "src_dev")}
+    if null:
+        f[null] = None
+    return _capi.petar_art_set(n_out=n_out, **f)
+
+
+@pytest.mark.parametrize("case", ["ok", "ok_no_pairs", "n0", "order", "cd0", "cdnan", "npair_big",
+                                  "npair_neg", "pos", "vel", "mass", "rin", "pairs", "frame",
+                                  "set", "nout", "set_src", "set_pos"])
+def test_artificial_make_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(n=100, pos=FAKE, vel=FAKE, mass=FAKE, rin=FAKE, rout=FAKE, rs=FAKE, npair=10,
+             pairs=FAKE, order=3, cd=1.0, frame=FAKE)
+    n_out = lambda: a["n"] + a["npair"] * ((4 if a["order"] == 2 else 8) + 2)
+    null = None
+    if case == "ok_no_pairs":
+        a.update(npair=0, pairs=None, frame=None)
+    elif case == "n0":
+        a["n"] = 0
+    elif case == "order":
+        a["order"] = 4
+    elif case == "cd0":
+        a["cd"] = 0.0
+    elif case == "cdnan":
+        a["cd"] = float("nan")
+    elif case == "npair_big":
+        a["npair"] = 51
+    elif case == "npair_neg":
+        a["npair"] = -1
+    elif case in ("pos", "vel", "mass", "rin", "pairs", "frame"):
+        a[case] = None
+    elif case == "set_src":
+        null = "src_dev"
+    elif case == "set_pos":
+        null = "pos_dev"
+    s = _art_set(capi, n_out() + (1 if case == "nout" else 0), null)
+    st = lib.petar_artificial_make(ctx, a["n"], a["pos"], a["vel"], a["mass"], a["rin"], a["rout"],
+                                   a["rs"], a["npair"], a["pairs"], a["order"], a["cd"],
+                                   None if case == "set" else ctypes.byref(s), a["frame"], None)
+    ok = case in ("ok", "ok_no_pairs")
+    assert st == (_capi.PETAR_E_NODEVICE if ok else _capi.PETAR_E_INVALID), lib.petar_last_error(ctx)
+
+
+@pytest.mark.parametrize("case", ["ok", "ok_tensor_only", "order", "npair", "nout", "acc_set",
+                                  "frame", "tensor", "pot_without_acc", "pot_without_pot_set",
+                                  "pos", "src", "pairs", "n0"])
+def test_tidal_fit_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(order=2, n=100, pos=FAKE, npair=10, pairs=FAKE, frame=FAKE, nout=200, src=FAKE,
+             acc_set=FAKE, pot_set=FAKE, tensor=FAKE, acc=FAKE, pot=FAKE)
+    if case == "ok_tensor_only":
+        a.update(acc=None, pot=None, pos=None, src=None, pairs=None)
+    elif case == "order":
+        a["order"] = 1
+    elif case == "npair":
+        a["npair"] = -2
+    elif case == "nout":
+        a["nout"] = 79  # < 10 * (4 + 4)
+    elif case == "pot_without_acc":
+        a["acc"] = None
+    elif case == "pot_without_pot_set":
+        a["pot_set"] = None
+    elif case == "n0":
+        a["n"] = 0
+    elif case in a:
+        a[case] = None
+    st = lib.petar_tidal_fit(ctx, a["order"], a["n"], a["pos"], a["npair"], a["pairs"], a["frame"],
+                             a["nout"], a["src"], a["acc_set"], a["pot_set"], a["tensor"], a["acc"],
+                             a["pot"])
+    ok = case in ("ok", "ok_tensor_only")
+    assert st == (_capi.PETAR_E_NODEVICE if ok else _capi.PETAR_E_INVALID), lib.petar_last_error(ctx)
+
+
+@pytest.mark.parametrize("case", ["ok", "ok_empty", "order", "npt", "tensor", "frame", "pair_of",
+                                  "pos", "acc"])
+def test_tidal_eval_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(order=3, npair=5, tensor=FAKE, frame=FAKE, npt=40, pair_of=FAKE, pos=FAKE, acc=FAKE)
+    if case == "ok_empty":
+        a.update(npt=0, pair_of=None, pos=None, acc=None)
+    elif case == "order":
+        a["order"] = 0
+    elif case == "npt":
+        a["npt"] = -1
+    elif case in a:
+        a[case] = None
+    st = lib.petar_tidal_eval(ctx, a["order"], a["npair"], a["tensor"], a["frame"], a["npt"],
+                              a["pair_of"], a["pos"], a["acc"], None)
+    ok = case in ("ok", "ok_empty")
+    assert st == (_capi.PETAR_E_NODEVICE if ok else _capi.PETAR_E_INVALID), lib.petar_last_error(ctx)

@@ -680,3 +680,164 @@ def test_step_graph_after_workspace_growth(pt, orc):
     assert torch.equal(acc, a) and torch.equal(pot, p)
     pt.petar_destroy(ref)
     pt.petar_destroy(ctx)
+
+
+# ------------------------------------------------------ artificial particles
+def _pairs_i32(pairs):
+    return T(np.ascontiguousarray(np.asarray(pairs).T.astype(np.int32)))
+
+
+def _gpu_make(pt, ctx, c, rin, rout, rs, pairs, order, c_d):
+    g = pt.petar_artificial_make(ctx, T(c.pos), T(c.vel), T(c.mass), T(rin), T(rout), T(rs),
+                                 _pairs_i32(pairs), order, c_d)
+    torch.cuda.synchronize()
+    return g
+
+
+def _scaled(rec, frame, order):
+    """Record coefficients times d_c^k (k = 1 for T_ij, 2 for T_ijk): the
+    field differences they produce at the measure points."""
+    out = np.array(rec, dtype=np.float64, copy=True)
+    d = frame[:, 3][:, None]
+    out[:, 4:10] *= d
+    if order == 3:
+        out[:, 10:] *= d * d
+    return out
+
+
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("n,bf,seed", [(4096, 0.5, 51), (3001, 1.0, 52)])
+def test_artificial_make_matches_oracle(pt, ctx, orc, order, n, bf, seed):
+    c, rin, rout, rs = cluster_with_radii(orc, n, seed, bf=bf)
+    P = 4 if order == 2 else 8
+    g = _gpu_make(pt, ctx, c, rin, rout, rs, c.pairs, order, 0.7)
+    o = orc.artificial_set(c.pos, c.vel, c.mass, rin, rout, rs, c.pairs, order, 0.7)
+    ns, npair = o["n_single"], len(c.pairs)
+    assert g["n_single"] == ns
+    assert np.array_equal(g["src"].cpu().numpy(), o["src"])
+    assert np.array_equal(g["pair_of"].cpu().numpy(), o["pair_of"])
+    for k in ("r_in", "r_out", "r_search"):
+        assert np.array_equal(g[k].cpu().numpy(), o[k]), k
+    gm, gp = g["mass"].cpu().numpy(), g["pos"].cpu().numpy()
+    assert np.array_equal(gm[:ns], o["mass"][:ns]) and np.array_equal(gp[:, :ns], o["pos"][:, :ns])
+    np.testing.assert_allclose(gm, o["mass"], rtol=1e-15, atol=0)
+    fr = g["frame"].cpu().numpy().T
+    scale = np.abs(c.pos).max()
+    assert np.abs(fr[:, :3] - o["frame"][:, :3]).max() <= 1e-15 * scale
+    np.testing.assert_allclose(fr[:, 3], o["frame"][:, 3], rtol=1e-12)
+    blk = gp[:, ns:].reshape(3, npair, P + 4)
+    oblk = o["pos"][:, ns:].reshape(3, npair, P + 4)
+    err = np.abs(blk - oblk).max(axis=(0, 2))
+    # centre and measure points to rounding; the pseudoparticles also carry
+    # the rounding of the orbit's frame (relative 1e-16 / e)
+    assert np.all(err <= 1e-10 * o["frame"][:, 3] + 1e-15 * scale), err.max()
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_tidal_fit_matches_oracle(pt, ctx, orc, order):
+    """The post-fit on the oracle's own set and accelerations."""
+    c, rin, rout, rs = cluster_with_radii(orc, 2000, 53, bf=0.5)
+    o = orc.artificial_set(c.pos, c.vel, c.mass, rin, rout, rs, c.pairs, order, 1.0)
+    acc_set, pot_set = orc.force_long(o["pos"], o["mass"], o["r_in"], o["r_out"])
+    rec, acc, pot = orc.artificial_fit(order, o, c.pos, acc_set, pot_set, c.pairs)
+    art = dict(order=order, mass=T(o["mass"]), frame=T(o["frame"].T),
+               src=T(o["src"].astype(np.int32)))
+    tg, ag, pg = pt.petar_tidal_fit(ctx, art, _pairs_i32(c.pairs), T(acc_set), T(pot_set),
+                                    pos=T(c.pos))
+    torch.cuda.synchronize()
+    tg, ag, pg = tg.cpu().numpy().T, ag.cpu().numpy(), pg.cpu().numpy()
+    amag = np.linalg.norm(rec[:, 1:4], axis=1)[:, None]
+    d = np.abs(_scaled(tg, o["frame"], order) - _scaled(rec, o["frame"], order))
+    assert np.all(d[:, 1:] <= 1e-13 * amag), (d[:, 1:] / amag).max()
+    assert np.array_equal(tg[:, 0], rec[:, 0])
+    singles = o["src"][:o["n_single"]]
+    assert np.array_equal(ag[:, singles], acc[:, singles])
+    assert np.array_equal(pg[singles], pot[singles])
+    mem = c.pairs.ravel()
+    assert rel_err(ag[:, mem], acc[:, mem]).max() < 1e-13
+    np.testing.assert_allclose(pg[mem], pot[mem], rtol=1e-13)
+    # the generic evaluator gives the members' values again, and the
+    # oracle's model at points anywhere in the cage
+    pair_of = T(o["pair_of"].astype(np.int32))
+    ae, pe = pt.petar_tidal_eval(ctx, order, T(tg.T), art["frame"], pair_of, T(c.pos))
+    ae, pe = ae.cpu().numpy(), pe.cpu().numpy()
+    assert np.array_equal(ae[:, mem], ag[:, mem]) and np.array_equal(pe[mem], pg[mem])
+    assert np.all(ae[:, singles] == 0)
+    rng = np.random.default_rng(3)
+    b = rng.integers(0, len(c.pairs), 500)
+    pts = o["frame"][b, :3].T + rng.uniform(-1, 1, (3, 500)) * o["frame"][b, 3]
+    ae, pe = pt.petar_tidal_eval(ctx, order, T(tg.T), art["frame"], T(b.astype(np.int32)), T(pts))
+    ae, pe = ae.cpu().numpy(), pe.cpu().numpy()
+    for k in range(500):
+        rp = pts[:, k] - o["frame"][b[k], :3]
+        want = orc.tidal_eval(order, rec[b[k], 1:], rp)
+        assert np.linalg.norm(ae[:, k] - want) <= 1e-13 * amag[b[k], 0]
+        assert abs(pe[k] - orc.tidal_potential(order, rec[b[k], 1:], rp, rec[b[k], 0])) <= \
+            1e-13 * abs(rec[b[k], 0])
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_artificial_pipeline_theta0_fp64(pt, ctx, orc, order):
+    """make -> tree build -> long-range force (FP64, every cell opened) ->
+    post-fit against the oracle's set, direct sum and post-fit."""
+    c, rin, rout, rs = cluster_with_radii(orc, 2000, 54, bf=0.5)
+    g = _gpu_make(pt, ctx, c, rin, rout, rs, c.pairs, order, 1.0)
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, g["pos"], g["mass"], 0.0, 8)
+    a_set, p_set = pt.petar_force_long(ctx, 64, g["r_in"], g["r_out"], g["r_search"])
+    tg, ag, pg = pt.petar_tidal_fit(ctx, g, _pairs_i32(c.pairs), a_set, p_set, pos=T(c.pos))
+    torch.cuda.synchronize()
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    o = orc.artificial_set(c.pos, c.vel, c.mass, rin, rout, rs, c.pairs, order, 1.0)
+    acc_set, pot_set = orc.force_long(o["pos"], o["mass"], o["r_in"], o["r_out"])
+    rec, acc, pot = orc.artificial_fit(order, o, c.pos, acc_set, pot_set, c.pairs)
+    assert rel_err(a_set.cpu().numpy(), acc_set).max() < 1e-12
+    tg, ag, pg = tg.cpu().numpy().T, ag.cpu().numpy(), pg.cpu().numpy()
+    amag = np.linalg.norm(rec[:, 1:4], axis=1)[:, None]
+    d = np.abs(_scaled(tg, o["frame"], order) - _scaled(rec, o["frame"], order))
+    assert np.all(d[:, 1:] <= 1e-10 * amag), (d[:, 1:] / amag).max()
+    assert rel_err(ag, acc).max() < 1e-10
+    np.testing.assert_allclose(pg, pot, rtol=1e-11)
+
+
+def test_artificial_edge_cases(pt, ctx, orc):
+    """No pairs (the set is the input), one pair of a two-body system, a
+    circular and a radial orbit, and the errors of invalid pairs."""
+    c, rin, rout, rs = cluster_with_radii(orc, 64, 55, bf=0.5)
+    g = _gpu_make(pt, ctx, c, rin, rout, rs, np.zeros((0, 2), dtype=np.int64), 3, 1.0)
+    assert np.array_equal(g["pos"].cpu().numpy(), c.pos)
+    assert np.array_equal(g["src"].cpu().numpy(), np.arange(64))
+    assert np.all(g["pair_of"].cpu().numpy() == -1)
+    # two particles: circular and radial orbits
+    m = np.array([0.6, 0.4])
+    for vel in (np.array([[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]]),
+                None):
+        pos = np.array([[0.0, 0.01], [0.0, 0.0], [0.0, 0.0]])
+        if vel is None:  # circular: v = sqrt(G M / r) perpendicular
+            v = np.sqrt(1.0 / 0.01)
+            vel = np.array([[0.0, 0.0], [-0.4 * v, 0.6 * v], [0.0, 0.0]])
+        r2 = np.full(2, 0.05)
+        cc = workloads.Cluster(pos=pos, vel=vel, mass=m, n_binaries=1, pairs=np.array([[0, 1]]))
+        for order in (2, 3):
+            g = _gpu_make(pt, ctx, cc, r2, 2 * r2, 3 * r2, cc.pairs, order, 1.0)
+            o = orc.artificial_set(pos, vel, m, r2, 2 * r2, 3 * r2, cc.pairs, order, 1.0)
+            np.testing.assert_allclose(g["pos"].cpu().numpy(), o["pos"], rtol=0, atol=1e-16)
+            np.testing.assert_allclose(g["frame"].cpu().numpy().T, o["frame"], rtol=1e-14)
+    bad_cases = [np.array([[0, 0]]), np.array([[0, 64]]), np.array([[-1, 3]]),
+                 np.array([[1, 2], [2, 3]])]
+    for pairs in bad_cases:
+        with pytest.raises(pt.PetarError):
+            _gpu_make(pt, ctx, c, rin, rout, rs, pairs, 2, 1.0)
+    # an unbound pair
+    vel = c.vel.copy()
+    i, j = c.pairs[0]
+    vel[:, i] += 100.0
+    cu = workloads.Cluster(pos=c.pos, vel=vel, mass=c.mass, n_binaries=1, pairs=c.pairs)
+    with pytest.raises(pt.PetarError):
+        _gpu_make(pt, ctx, cu, rin, rout, rs, c.pairs[:1], 3, 1.0)
+    # eval with a pair index past n_pair
+    fr = torch.zeros((4, 1), dtype=torch.float64, device="cuda:0")
+    ten = torch.zeros((10, 1), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(pt.PetarError):
+        pt.petar_tidal_eval(ctx, 2, ten, fr, T(np.array([0, 1], dtype=np.int32)),
+                            T(np.zeros((3, 2))))

@@ -126,6 +126,7 @@ class Cluster:
     vel: np.ndarray   # (3, N) float64, SoA
     mass: np.ndarray  # (N,) float64, sums to 1
     n_binaries: int
+    pairs: np.ndarray = None  # (n_binaries, 2) int64: indices of the two members
 
 
 def make_cluster(n: int, seed: int, *, imf: bool = True, binary_fraction: float = 0.0,
@@ -170,8 +171,11 @@ def make_cluster(n: int, seed: int, *, imf: bool = True, binary_fraction: float 
         vel[n_single:n_single + n_bin] = c_vel - f1 * dvel
         vel[n_single + n_bin:] = c_vel + f2 * dvel
     perm = rng.permutation(n)
+    where = np.empty(n, dtype=np.int64)
+    where[perm] = np.arange(n)
+    pairs = np.stack([where[n_single:n_single + n_bin], where[n_single + n_bin:]], axis=1)
     return Cluster(pos=np.ascontiguousarray(pos[perm].T), vel=np.ascontiguousarray(vel[perm].T),
-                   mass=np.ascontiguousarray(m[perm]), n_binaries=n_bin)
+                   mass=np.ascontiguousarray(m[perm]), n_binaries=n_bin, pairs=pairs)
 
 
 # --------------------------------------------------------------------------
