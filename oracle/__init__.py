@@ -101,6 +101,8 @@ def lib():
         L.oracle_tidal_eval.argtypes = [ctypes.c_int, p_d, p_d, d, p_d, p_d]
         L.oracle_tidal_eval.restype = None
         L.oracle_pseudo_particles.argtypes = [d, d, p_d, p_d, p_d, p_d, d, p_d, p_d]
+        L.oracle_group_relation.argtypes = [p_d, p_d, i64, d, p_i64, p_i32, i64]
+        L.oracle_group_relation.restype = i64
         L.oracle_binary_elements.argtypes = [d, d, p_d, p_d, p_d, p_d, d, p_d]
         L.oracle_binary_elements.restype = ctypes.c_int
         L.oracle_pseudo_particles.restype = ctypes.c_int
@@ -460,3 +462,45 @@ def artificial_fit(order: int, art: dict, pos, acc_set, pot_set, pairs):
             acc[:, m] = tidal_eval(order, t, rp)
             pot[m] = tidal_potential(order, t, rp, pot_set[base])
     return rec, acc, pot
+
+
+# ------------------------------------------------------------ SDAR groups
+def group_relation(pos, r_in, theta: float):
+    """CSR (offsets int64 [N+1], idx int32) of the pairs r_ij < theta
+    r_in,ij (eq. rbin), all j != i ascending, by brute force."""
+    pos, r_in = _f64(pos), _f64(r_in)
+    n = r_in.size
+    counts = np.empty(n, dtype=np.int64)
+    total = lib().oracle_group_relation(_p(pos), _p(r_in), n, float(theta), _p(counts, _c_i64_p),
+                                        None, 0)
+    out = np.empty(max(total, 1), dtype=np.int32)
+    lib().oracle_group_relation(_p(pos), _p(r_in), n, float(theta), _p(counts, _c_i64_p),
+                                _p(out, _c_i32_p), out.size)
+    offs = np.zeros(n + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(counts)
+    return offs, out[:total]
+
+
+def groups(pos, vel, mass, r_in, theta: float, G: float = 1.0):
+    """SDAR groups (Sec. "SDAR", eq. rbin): (label, offsets, members) as
+    clusters() of the pair relation r_ij < theta r_in,ij, and the bound
+    binaries (n_pairs, 2): the groups of exactly two members with negative
+    Kepler energy, in group order, smaller index first."""
+    offs, idx = group_relation(pos, r_in, theta)
+    label, cl, members = clusters(len(r_in), offs, idx)
+    pos, vel = np.asarray(pos), np.asarray(vel)
+    pairs = []
+    for g in range(len(cl) - 1):
+        if cl[g + 1] - cl[g] != 2:
+            continue
+        i, j = int(members[cl[g]]), int(members[cl[g] + 1])
+        if binary_elements(mass[i], mass[j], pos[:, i], pos[:, j], vel[:, i], vel[:, j],
+                           G) is not None:
+            pairs.append((i, j))
+    return label, cl, members, np.array(pairs, dtype=np.int64).reshape(-1, 2)
+
+
+def kick(vel, acc, dt: float):
+    """Velocity kick of the long-range step, v + a_L dt (eq. lfmap with dt
+    the half step of the KDK cycle)."""
+    return np.asarray(vel, dtype=np.float64) + np.asarray(acc, dtype=np.float64) * dt

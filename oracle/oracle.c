@@ -1159,3 +1159,56 @@ OR_EXPORT int oracle_pseudo_particles(double m1, double m2, const double x1[3], 
     *out_mass = M / 3.0;
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * 9. SDAR groups (Sec. "SDAR", eq. rbin): pairs closer than
+ *    r_g,ij = theta r_in,ij with r_in,ij = max(r_in,i, r_in,j), tested as
+ *    d^2 < (theta r_in,ij)^2 in this order of operations; the groups are the
+ *    connected components of this relation (computed with section 7's
+ *    components from the CSR written here, all j != i, ascending).
+ * ---------------------------------------------------------------------- */
+static int is_group_pair(const double *X, const double *Y, const double *Z, const double *r_in,
+                         double theta, int64_t i, int64_t j)
+{
+    double dx = X[j] - X[i];
+    double dy = Y[j] - Y[i];
+    double dz = Z[j] - Z[i];
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    double d2 = xx + yy;
+    d2 = d2 + zz;
+    double R = r_in[i] > r_in[j] ? r_in[i] : r_in[j];
+    double g = theta * R;
+    double g2 = g * g;
+    return d2 < g2;
+}
+
+OR_EXPORT int64_t oracle_group_relation(const double *pos, const double *r_in, int64_t n,
+                                        double theta, int64_t *counts, int32_t *out,
+                                        int64_t capacity)
+{
+    const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; j++)
+            if (j != i && is_group_pair(X, Y, Z, r_in, theta, i, j)) c++;
+        counts[i] = c;
+    }
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; i++) total += counts[i];
+    if (out && total <= capacity) {
+        int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        start[0] = 0;
+        for (int64_t i = 0; i < n; i++) start[i + 1] = start[i] + counts[i];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; i++) {
+            int64_t w = start[i];
+            for (int64_t j = 0; j < n; j++)
+                if (j != i && is_group_pair(X, Y, Z, r_in, theta, i, j)) out[w++] = (int32_t)j;
+        }
+        free(start);
+    }
+    return total;
+}

@@ -771,3 +771,67 @@ def test_artificial_pipeline_binary_and_perturber(orc, order):
     A = bin_q
     mu = m1 * m2 / (m1 + m2)
     assert abs(np.trace(A) - mu * a * a * (1.5 * e * e + 1.0)) < 1e-15
+
+
+# ------------------------------------------------------------- SDAR groups
+def test_groups_constructed_cases(orc):
+    """eq. rbin with r_in,ij = max(r_in,i, r_in,j): a chain a-b-c with a-c
+    too far is one group of three (the relation is closed transitively), an
+    isolated bound pair is a binary, a close but unbound pair is a group but
+    no binary, and a pair closer than theta r_in of only the larger-radius
+    member still counts."""
+    theta = 0.5
+    pos = np.array([[0.0, 0.009, 0.018, 5.0, 5.004, 9.0, 9.004, 12.0, 12.009],
+                    [0.0] * 9, [0.0] * 9])
+    r_in = np.array([0.02, 0.02, 0.02, 0.01, 0.01, 0.01, 0.01, 0.001, 0.02])
+    vel = np.zeros((3, 9))
+    vel[1, 6] = 1e3  # the pair at x = 9 flies apart
+    mass = np.full(9, 0.1)
+    label, cl, members, pairs = orc.groups(pos, vel, mass, r_in, theta)
+    assert list(label) == [0, 0, 0, 3, 3, 5, 5, 7, 7]
+    assert list(np.diff(cl)) == [3, 2, 2, 2]
+    assert pairs.tolist() == [[3, 4], [7, 8]]
+    # the relation itself against the definition, pair by pair
+    offs, idx = orc.group_relation(pos, r_in, theta)
+    for i in range(9):
+        want = [j for j in range(9) if j != i and
+                np.linalg.norm(pos[:, j] - pos[:, i]) < theta * max(r_in[i], r_in[j])]
+        assert list(idx[offs[i]:offs[i + 1]]) == want
+
+
+def test_groups_match_bfs(orc):
+    """Random clustered points: components by breadth-first search over the
+    brute-force relation written out in numpy."""
+    rng = np.random.default_rng(21)
+    n = 300
+    pos = rng.uniform(0, 1, (3, n))
+    pos[:, 150:] = pos[:, :150] + rng.normal(scale=0.004, size=(3, 150))
+    r_in = rng.uniform(0.004, 0.02, n)
+    theta = 0.7
+    label, cl, members, pairs = orc.groups(pos, np.zeros((3, n)), np.full(n, 1e-3), r_in, theta)
+    d = np.linalg.norm(pos[:, :, None] - pos[:, None, :], axis=0)
+    adj = (d < theta * np.maximum(r_in[:, None], r_in[None, :])) & ~np.eye(n, dtype=bool)
+    want = np.full(n, -1)
+    for s in range(n):
+        if want[s] >= 0:
+            continue
+        comp, todo = [s], [s]
+        want[s] = s
+        while todo:
+            u = todo.pop()
+            for v in np.nonzero(adj[u])[0]:
+                if want[v] < 0:
+                    want[v] = s
+                    todo.append(v)
+    assert np.array_equal(label, want)
+    sizes = np.bincount(want, minlength=n)
+    assert sorted(map(tuple, pairs.tolist())) == sorted(
+        (s, int(np.nonzero(want == s)[0][1])) for s in range(n) if sizes[s] == 2)
+
+
+def test_kick_is_exact_on_dyadic_values(orc):
+    v = np.array([[0.5, -0.75], [1.0, 0.0], [0.125, 3.0]])
+    a = np.array([[0.25, 1.0], [-2.0, 4.0], [0.0, -0.5]])
+    out = orc.kick(v, a, 2.0 ** -8)
+    assert np.array_equal(out, v + a / 256.0)
+    assert np.array_equal(orc.kick(out, a, -(2.0 ** -8)), v)
