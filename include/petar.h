@@ -252,6 +252,32 @@ PETAR_API petar_status petar_clusters(petar_ctx *ctx, int64_t N, const int64_t *
                                       int64_t *cl_offsets_dev, int32_t *members_dev,
                                       int64_t *n_clusters);
 
+/* SDAR groups (Sec. "SDAR", eq. rbin): connected components of the pairs
+ * with r_ij < theta r_in,ij, r_in,ij = max(r_in,i, r_in,j) (FP64, tested
+ * as d^2 < (theta r_in,ij)^2), among the candidate CSR cand_offsets_dev
+ * [N + 1] / cand_idx_dev (the lists of petar_force_long hold every pair
+ * closer than max(r_search) >= r_out > r_in, so none is missed for
+ * theta <= 1). Outputs as petar_clusters: label_dev[N] (smallest member
+ * index), grp_offsets_dev[N + 1], members_dev[N], *n_groups; and the
+ * binaries: the groups of exactly two members with negative Kepler energy
+ * v^2/2 - G (m_i + m_j)/r (G = params.G), smaller index first, in group
+ * order, written to pairs_dev[0 .. n_pairs) and pairs_dev[pair_cap ..
+ * pair_cap + n_pairs) (pair_cap >= N/2), *n_pairs. Inputs pos_dev,
+ * vel_dev [3][N], mass_dev, r_in_dev [N]; theta > 0. Groups of three or
+ * more members get no binary entry. Errors as petar_clusters. */
+PETAR_API petar_status petar_groups(petar_ctx *ctx, int64_t N, const double *pos_dev,
+                                    const double *vel_dev, const double *mass_dev,
+                                    const double *r_in_dev, double theta,
+                                    const int64_t *cand_offsets_dev, const int32_t *cand_idx_dev,
+                                    int32_t *label_dev, int64_t *grp_offsets_dev,
+                                    int32_t *members_dev, int64_t *n_groups, int32_t *pairs_dev,
+                                    int64_t pair_cap, int64_t *n_pairs);
+
+/* Long-range kick of the KDK cycle (eq. lfmap): vel_dev[3][N] += dt *
+ * acc_dev[3][N] (dt the half step), FP64 without contraction. */
+PETAR_API petar_status petar_kick(petar_ctx *ctx, int64_t N, double *vel_dev,
+                                  const double *acc_dev, double dt);
+
 /* ---- Artificial particles (Sec. "Artificial particle algorithm for weak
  * perturbation"). A bound pair that the short-range integrator treats as a
  * group leaves the long-range set; in its place come its centre of mass

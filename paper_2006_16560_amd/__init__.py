@@ -25,7 +25,8 @@ __all__ = [
     "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
     "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_batch_build",
     "petar_force_long", "petar_step_graph", "petar_nb_filter", "petar_clusters",
-    "petar_artificial_make", "petar_tidal_fit", "petar_tidal_eval", "art_points",
+    "petar_groups", "petar_kick", "petar_artificial_make", "petar_tidal_fit", "petar_tidal_eval",
+    "art_points",
     "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
     "PETAR_NO_DEVICE", "lib_path",
 ]
@@ -275,6 +276,43 @@ def petar_clusters(ctx: Context, offsets: torch.Tensor, idx: torch.Tensor):
     return label, cl[: nc.value + 1], members
 
 
+
+def petar_groups(ctx: Context, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor,
+                 r_in: torch.Tensor, theta: float, offsets: torch.Tensor, idx: torch.Tensor):
+    """SDAR groups (r_ij < theta max(r_in,i, r_in,j)) among the candidate
+    CSR: (label int32 [N], group offsets int64 [n_groups + 1], members int32
+    [N], pairs int32 [2, n_pairs]: the bound two-member groups); see
+    petar.h."""
+    n = offsets.shape[0] - 1
+    dev = ctx.device
+    d = "cuda:%d" % dev
+    label = torch.empty(n, dtype=torch.int32, device=d)
+    go = torch.empty(n + 1, dtype=torch.int64, device=d)
+    members = torch.empty(n, dtype=torch.int32, device=d)
+    cap = max(n // 2, 1)
+    pairs = torch.empty((2, cap), dtype=torch.int32, device=d)
+    ng, npair = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = _lib.petar_groups(ctx.handle, n, _dptr(pos, torch.float64, (3, n), "pos", dev),
+                           _dptr(vel, torch.float64, (3, n), "vel", dev),
+                           _dptr(mass, torch.float64, (n,), "mass", dev),
+                           _dptr(r_in, torch.float64, (n,), "r_in", dev), float(theta),
+                           _dptr(offsets, torch.int64, (n + 1,), "offsets", dev),
+                           _dptr(_nonempty(idx, d), torch.int32, None, "idx", dev),
+                           ctypes.c_void_p(label.data_ptr()), ctypes.c_void_p(go.data_ptr()),
+                           ctypes.c_void_p(members.data_ptr()), ctypes.byref(ng),
+                           ctypes.c_void_p(pairs.data_ptr()), cap, ctypes.byref(npair))
+    _check(st, ctx)
+    return label, go[: ng.value + 1], members, pairs[:, : npair.value].contiguous()
+
+
+def petar_kick(ctx: Context, vel: torch.Tensor, acc: torch.Tensor, dt: float) -> torch.Tensor:
+    """vel += dt * acc in place ([3, N] FP64); returns vel."""
+    n = vel.shape[1]
+    dev = ctx.device
+    st = _lib.petar_kick(ctx.handle, n, _dptr(vel, torch.float64, (3, n), "vel", dev),
+                         _dptr(acc, torch.float64, (3, n), "acc", dev), float(dt))
+    _check(st, ctx)
+    return vel
 
 def art_points(order: int) -> int:
     """Measure points of the order-2 (4) or order-3 (8) tidal tensor."""

@@ -87,6 +87,9 @@ SIGNATURES = [
     ("petar_nb_filter", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P,
                                ctypes.POINTER(petar_nblist)]),
     ("petar_clusters", _INT, [_P, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
+    ("petar_groups", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P, _P, _P, _P,
+                            ctypes.POINTER(_I64), _P, _I64, ctypes.POINTER(_I64)]),
+    ("petar_kick", _INT, [_P, _I64, _P, _P, _D]),
     ("petar_artificial_make", _INT, [_P, _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _INT, _D,
                                      ctypes.POINTER(petar_art_set), _P, _P]),
     ("petar_tidal_fit", _INT, [_P, _INT, _I64, _P, _I64, _P, _P, _I64, _P, _P, _P, _P, _P, _P]),

@@ -362,7 +362,20 @@ __global__ __launch_bounds__(kThreads) void k_tidal_eval(EvalArgs e) {
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_kick(double *vel, const double *acc, int64_t n3,
+                                                   double dt) {
+#pragma clang fp contract(off)
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n3;
+         k += (int64_t)gridDim.x * blockDim.x)
+        vel[k] = vel[k] + acc[k] * dt;
+}
+
 }  // namespace
+
+void launch_kick(double *vel, const double *acc, int64_t n, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_kick, dim3(grid_for(3 * n, kThreads, 16384)), dim3(kThreads), 0, s, vel,
+                       acc, 3 * n, dt);
+}
 
 const double *tidal_ginv_host(int order) {
     static double g2[6 * 12], g3[16 * 24];

@@ -46,7 +46,7 @@ struct petar_ctx {
     DevBuf cl_keep, cl_row, cl_counts, cl_parent, cl_root, cl_rootpos, cl_status, cl_flags,
         cl_key0, cl_key1, cl_val0, cl_val1;
     // artificial particles
-    DevBuf art_single, art_spos, art_status, art_pairof, tt_ginv;
+    DevBuf art_single, art_spos, art_status, art_pairof, tt_ginv, grp_off, grp_idx;
     bool tt_ginv_ready = false;
     uint32_t nbhead_cap = 0, nbleaf_cap = 0;
 
@@ -213,6 +213,7 @@ void free_all(petar_ctx *c) {
                       &c->cl_status,   &c->cl_flags,   &c->cl_key0,    &c->cl_key1,
                       &c->cl_val0,  &c->cl_val1,
                       &c->art_single, &c->art_spos, &c->art_status, &c->art_pairof, &c->tt_ginv,
+                      &c->grp_off,  &c->grp_idx,
                       &c->sys_off};
     for (DevBuf *b : bufs) {
         if (b->p) hipFree(b->p);
@@ -326,64 +327,59 @@ petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass, const do
     return PETAR_OK;
 }
 
-petar_status petar_nb_filter(petar_ctx *ctx, int64_t n, const double *pos, const double *vel,
-                             const double *mass, const double *r_nb, double c_v,
-                             const int64_t *cand_offsets, const int32_t *cand_idx,
-                             petar_nblist *out) {
-    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
-    if (const char *m = check_filter_args(n, pos, vel, mass, r_nb, c_v, cand_offsets, cand_idx,
-                                          out))
-        return fail(ctx, PETAR_E_INVALID, "%s", m);
-    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
+}  // extern "C"
+
+namespace {
+
+// Filter of a candidate CSR (mode 0: pericentre, mode 1: group relation) into
+// out_offsets[n + 1] / out_idx[capacity]; *required = kept entries.
+petar_status filter_impl(petar_ctx *ctx, FilterArgs a, int64_t *out_offsets, int32_t *out_idx,
+                         int64_t capacity, int64_t *required) {
+    const int64_t n = a.n;
     hipStream_t s = ctx->stream;
     // candidate count and CSR sanity (one host read)
     TRY(ensure(ctx, ctx->cl_status, 8));
     int32_t *bad = ptr<int32_t>(ctx->cl_status);
     fill_i64(ptr<int64_t>(ctx->cl_status), 0, 1, s);
-    launch_check_csr(cand_offsets, n, bad, s);
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, cand_offsets + n, 8, hipMemcpyDeviceToHost, s));
+    launch_check_csr(a.offsets, n, bad, s);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, a.offsets + n, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, bad, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     const int64_t n_cand = ctx->host_scalar[0];
     int32_t b0 = 0;
     memcpy(&b0, ctx->host_scalar + 1, 4);
     if (b0) return fail(ctx, PETAR_E_INVALID, "candidate offsets must start at 0 and not decrease");
-    TRY(ensure(ctx, ctx->cl_keep, (size_t)n_cand));
-    TRY(ensure(ctx, ctx->cl_row, (size_t)n_cand * 4));
+    if (out_idx == nullptr) {  // internal output sized to the candidates
+        TRY(ensure(ctx, ctx->grp_idx, (size_t)(n_cand > 0 ? n_cand : 1) * 4));
+        out_idx = ptr<int32_t>(ctx->grp_idx);
+        capacity = n_cand;
+    }
+    TRY(ensure(ctx, ctx->cl_keep, (size_t)(n_cand > 0 ? n_cand : 1)));
+    TRY(ensure(ctx, ctx->cl_row, (size_t)(n_cand > 0 ? n_cand : 1) * 4));
     TRY(ensure(ctx, ctx->cl_counts, (size_t)(n + 1) * 4));
     TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
-    FilterArgs a{pos, vel, mass, r_nb, cand_offsets, cand_idx, n, c_v, ctx->params.G};
     launch_filter(a, n_cand, ptr<int32_t>(ctx->cl_row), ptr<uint8_t>(ctx->cl_keep),
                   ptr<uint32_t>(ctx->cl_counts), bad, s);
-    scan_u32_to_i64(ptr<uint32_t>(ctx->cl_counts), out->offsets_dev, n, ptr<int64_t>(ctx->scan_ws),
-                    s);
-    launch_filter_write(a, ptr<uint8_t>(ctx->cl_keep), out->offsets_dev, out->idx_dev,
-                        out->capacity, s);
+    scan_u32_to_i64(ptr<uint32_t>(ctx->cl_counts), out_offsets, n, ptr<int64_t>(ctx->scan_ws), s);
+    launch_filter_write(a, ptr<uint8_t>(ctx->cl_keep), out_offsets, out_idx, capacity, s);
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, out->offsets_dev + n, 8, hipMemcpyDeviceToHost,
-                                s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, out_offsets + n, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, bad, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     int32_t b = 0;
     memcpy(&b, ctx->host_scalar + 1, 4);
     if (b) return fail(ctx, PETAR_E_INVALID, "candidate index outside [0, N)");
-    out->required = ctx->host_scalar[0];
-    if (out->required > out->capacity)
+    *required = ctx->host_scalar[0];
+    if (*required > capacity)
         return fail(ctx, PETAR_E_NB_OVERFLOW, "neighbour capacity %lld < required %lld",
-                    (long long)out->capacity, (long long)out->required);
+                    (long long)capacity, (long long)*required);
     return PETAR_OK;
 }
 
-petar_status petar_clusters(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
-                            const int32_t *nb_idx, int32_t *label, int64_t *cl_offsets,
-                            int32_t *members, int64_t *n_clusters) {
-    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
-    if (const char *m = check_cluster_args(n, nb_offsets, nb_idx, label, cl_offsets, members,
-                                           n_clusters))
-        return fail(ctx, PETAR_E_INVALID, "%s", m);
-    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
-    HIP_TRY(ctx, hipSetDevice(ctx->device));
+// Components of a CSR (label, offsets, members as petar_clusters).
+petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
+                           const int32_t *nb_idx, int32_t *label, int64_t *cl_offsets,
+                           int32_t *members, int64_t *n_clusters) {
     hipStream_t s = ctx->stream;
     TRY(ensure(ctx, ctx->cl_parent, (size_t)n * 4));
     TRY(ensure(ctx, ctx->cl_root, (size_t)(n + 1) * 4));
@@ -441,6 +437,84 @@ petar_status petar_clusters(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets
     uint32_t nc = 0;
     memcpy(&nc, ctx->host_scalar, 4);
     *n_clusters = nc;
+    return PETAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+petar_status petar_clusters(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
+                            const int32_t *nb_idx, int32_t *label, int64_t *cl_offsets,
+                            int32_t *members, int64_t *n_clusters) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_cluster_args(n, nb_offsets, nb_idx, label, cl_offsets, members,
+                                           n_clusters))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return clusters_impl(ctx, n, nb_offsets, nb_idx, label, cl_offsets, members, n_clusters);
+}
+
+petar_status petar_nb_filter(petar_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                             const double *mass, const double *r_nb, double c_v,
+                             const int64_t *cand_offsets, const int32_t *cand_idx,
+                             petar_nblist *out) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_filter_args(n, pos, vel, mass, r_nb, c_v, cand_offsets, cand_idx,
+                                          out))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    FilterArgs a{pos, vel, mass, r_nb, cand_offsets, cand_idx, n, c_v, ctx->params.G, 0};
+    return filter_impl(ctx, a, out->offsets_dev, out->idx_dev, out->capacity, &out->required);
+}
+
+petar_status petar_groups(petar_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                          const double *mass, const double *r_in, double theta,
+                          const int64_t *cand_offsets, const int32_t *cand_idx, int32_t *label,
+                          int64_t *grp_offsets, int32_t *members, int64_t *n_groups,
+                          int32_t *pairs, int64_t pair_cap, int64_t *n_pairs) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_groups_args(n, pos, vel, mass, r_in, theta, cand_offsets, cand_idx,
+                                          label, grp_offsets, members, n_groups, pairs, pair_cap,
+                                          n_pairs))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    TRY(ensure(ctx, ctx->grp_off, (size_t)(n + 1) * 8));
+    FilterArgs a{pos, vel, mass, r_in, cand_offsets, cand_idx, n, theta, ctx->params.G, 1};
+    int64_t kept = 0;
+    TRY(filter_impl(ctx, a, ptr<int64_t>(ctx->grp_off), nullptr, 0, &kept));
+    TRY(clusters_impl(ctx, n, ptr<int64_t>(ctx->grp_off), ptr<int32_t>(ctx->grp_idx), label,
+                      grp_offsets, members, n_groups));
+    const int64_t ng = *n_groups;
+    TRY(ensure(ctx, ctx->art_single, (size_t)(ng + 1) * 4));
+    TRY(ensure(ctx, ctx->art_spos, (size_t)(ng + 1) * 4));
+    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(ng + 1) * 8));
+    uint32_t *flag = ptr<uint32_t>(ctx->art_single), *where = ptr<uint32_t>(ctx->art_spos);
+    launch_group_pairs(grp_offsets, members, ng, pos, vel, mass, n, ctx->params.G, flag, s);
+    scan_u32_to_u32(flag, where, ng, ptr<int64_t>(ctx->scan_ws), s);
+    launch_group_pairs_write(grp_offsets, members, ng, flag, where, pairs, pair_cap, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, where + ng, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    uint32_t np = 0;
+    memcpy(&np, ctx->host_scalar, 4);
+    *n_pairs = np;
+    return PETAR_OK;
+}
+
+petar_status petar_kick(petar_ctx *ctx, int64_t n, double *vel, const double *acc, double dt) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (n < 1 || n > kMaxParticles) return fail(ctx, PETAR_E_INVALID, "N must be in [1, 2^31)");
+    if (!vel || !acc) return fail(ctx, PETAR_E_INVALID, "vel and acc must not be NULL");
+    if (!std::isfinite(dt)) return fail(ctx, PETAR_E_INVALID, "dt must be finite");
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    launch_kick(vel, acc, n, dt, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
     return PETAR_OK;
 }
 

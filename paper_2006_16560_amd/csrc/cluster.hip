@@ -1,5 +1,5 @@
-// Second-stage neighbour filter and clusters (Sec. "Orbit-dependent
-// neighbour criterion" and Sec. "Clustering").
+// Second-stage neighbour filter, clusters and SDAR groups (Sec. "Orbit-
+// dependent neighbour criterion", Sec. "Clustering" and eq. rbin).
 //
 // Filter: a first-stage candidate j of i is kept iff the pericentre
 // separation of the pair's two-body Kepler orbit is below c_v * r_nb,i.
@@ -60,6 +60,21 @@ __device__ double pericentre(double xi, double yi, double zi, double vxi, double
     return v2 > 0.0 ? sqrt(h2 / v2) : sqrt(d2);
 }
 
+// SDAR group relation (eq. rbin): r_ij < theta max(r_in,i, r_in,j), as
+// d^2 < (theta R)^2 in FP64 without contraction, in this order.
+__device__ bool group_pair(double xi, double yi, double zi, double ri, double xj, double yj,
+                           double zj, double rj, double theta) {
+#pragma clang fp contract(off)
+    double dx = xj - xi;
+    double dy = yj - yi;
+    double dz = zj - zi;
+    double d2 = sum_sq3(dx, dy, dz);
+    double R = fmax(ri, rj);
+    double g = theta * R;
+    double g2 = g * g;
+    return d2 < g2;
+}
+
 // CSR sanity: offsets start at 0 and never decrease (so every row range
 // lies inside [0, offsets[n])); raises *bad otherwise.
 __global__ __launch_bounds__(kThreads) void k_check_csr(const int64_t *offsets, int64_t n,
@@ -92,6 +107,13 @@ __global__ __launch_bounds__(kThreads) void k_filter_test(FilterArgs a, const in
         if (j < 0 || j >= n) {
             atomicOr(bad, 1);
             keep[e] = 0;
+            continue;
+        }
+        if (a.mode == 1) {
+            keep[e] = group_pair(a.pos[i], a.pos[n + i], a.pos[2 * n + i], a.r_nb[i], a.pos[j],
+                                 a.pos[n + j], a.pos[2 * n + j], a.r_nb[j], a.c_v)
+                          ? 1
+                          : 0;
             continue;
         }
         const double rp = pericentre(a.pos[i], a.pos[n + i], a.pos[2 * n + i], a.vel[i],
@@ -216,7 +238,60 @@ __global__ __launch_bounds__(kThreads) void k_cl_offsets(const uint64_t *key, in
         if (i == 0 || key[i] != key[i - 1]) cl_offsets[key[i]] = i;
 }
 
+__global__ __launch_bounds__(kThreads) void k_group_pairs(const int64_t *off, const int32_t *mem,
+                                                          int64_t n_groups, const double *pos,
+                                                          const double *vel, const double *mass,
+                                                          int64_t n, double G, uint32_t *is_pair) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_groups;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t f = 0;
+        if (off[g + 1] - off[g] == 2) {
+            const int64_t i = mem[off[g]], j = mem[off[g] + 1];
+            double r2 = 0.0, v2 = 0.0;
+            for (int d = 0; d < 3; d++) {
+                const double dx = pos[d * n + j] - pos[d * n + i];
+                const double dv = vel[d * n + j] - vel[d * n + i];
+                r2 += dx * dx;
+                v2 += dv * dv;
+            }
+            const double r = sqrt(r2);
+            f = (r > 0.0 && 0.5 * v2 - G * (mass[i] + mass[j]) / r < 0.0) ? 1u : 0u;
+        }
+        is_pair[g] = f;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_pairs_write(const int64_t *off,
+                                                                const int32_t *mem,
+                                                                int64_t n_groups,
+                                                                const uint32_t *is_pair,
+                                                                const uint32_t *pos,
+                                                                int32_t *pairs, int64_t cap) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_groups;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        if (!is_pair[g]) continue;
+        const int64_t k = pos[g];
+        pairs[k] = mem[off[g]];
+        pairs[cap + k] = mem[off[g] + 1];
+    }
+}
+
 }  // namespace
+
+void launch_group_pairs(const int64_t *grp_offsets, const int32_t *members, int64_t n_groups,
+                        const double *pos, const double *vel, const double *mass, int64_t n,
+                        double G, uint32_t *is_pair, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_pairs, dim3(grid_for(n_groups, kThreads, 8192)), dim3(kThreads), 0,
+                       s, grp_offsets, members, n_groups, pos, vel, mass, n, G, is_pair);
+}
+
+void launch_group_pairs_write(const int64_t *grp_offsets, const int32_t *members, int64_t n_groups,
+                              const uint32_t *is_pair, const uint32_t *pos, int32_t *pairs,
+                              int64_t pair_cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_pairs_write, dim3(grid_for(n_groups, kThreads, 8192)),
+                       dim3(kThreads), 0, s, grp_offsets, members, n_groups, is_pair, pos, pairs,
+                       pair_cap);
+}
 
 void launch_check_csr(const int64_t *offsets, int64_t n, int32_t *bad, hipStream_t s) {
     hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s,

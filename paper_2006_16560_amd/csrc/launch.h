@@ -150,12 +150,16 @@ void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *s
 
 // ------------------------------------------------------------ cluster.hip
 // Second-stage neighbour filter over a candidate CSR (input order).
+// mode 0: pericentre < c_v r_nb[i] (second neighbour stage);
+// mode 1: separation < c_v max(r_nb[i], r_nb[j]) (SDAR groups, r_nb = r_in,
+// c_v = theta).
 struct FilterArgs {
     const double *pos, *vel, *mass, *r_nb;  // [3][n], [3][n], [n], [n]
     const int64_t *offsets;                 // [n + 1]
     const int32_t *idx;
     int64_t n;
     double c_v, G;
+    int mode;
 };
 // *bad |= (offsets[0] != 0 or offsets decrease somewhere)
 void launch_check_csr(const int64_t *offsets, int64_t n, int32_t *bad, hipStream_t s);
@@ -178,6 +182,15 @@ void launch_cluster_keys(const int32_t *label, int64_t n, const uint32_t *root_p
                          uint32_t *val, hipStream_t s);
 void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_offsets,
                             hipStream_t s);
+// Binaries among the groups: is_pair[g] = 1 for a group of exactly two
+// members with negative Kepler energy (G (m1 + m2) / r > v^2 / 2).
+void launch_group_pairs(const int64_t *grp_offsets, const int32_t *members, int64_t n_groups,
+                        const double *pos, const double *vel, const double *mass, int64_t n,
+                        double G, uint32_t *is_pair, hipStream_t s);
+// pairs[pos[g]] and pairs[pair_cap + pos[g]] for every flagged group.
+void launch_group_pairs_write(const int64_t *grp_offsets, const int32_t *members, int64_t n_groups,
+                              const uint32_t *is_pair, const uint32_t *pos, int32_t *pairs,
+                              int64_t pair_cap, hipStream_t s);
 
 // --------------------------------------------------------- artificial.hip
 // Set of the long-range force with artificial particles: singles first (input
@@ -228,6 +241,8 @@ struct EvalArgs {
     int32_t *bad;                  // count of pair_of >= n_pair
 };
 void launch_tidal_eval(const EvalArgs &e, hipStream_t s);
+// v += a dt over [3][n] (long-range kick).
+void launch_kick(double *vel, const double *acc, int64_t n, double dt, hipStream_t s);
 // Generalized inverse of the measure-point map at d_c = 1 (host memory,
 // K x 3P row-major), computed once.
 const double *tidal_ginv_host(int order);

@@ -95,6 +95,24 @@ const char *check_cluster_args(int64_t n, const int64_t *nb_offsets, const int32
     return nullptr;
 }
 
+const char *check_groups_args(int64_t n, const double *pos, const double *vel, const double *mass,
+                              const double *r_in, double theta, const int64_t *cand_offsets,
+                              const int32_t *cand_idx, const int32_t *label,
+                              const int64_t *grp_offsets, const int32_t *members,
+                              const int64_t *n_groups, const int32_t *pairs, int64_t pair_cap,
+                              const int64_t *n_pairs) {
+    if (n < 1) return "N must be >= 1";
+    if (n > kMaxParticles) return "N must be < 2^31";
+    if (!pos || !vel || !mass || !r_in) return "pos, vel, mass and r_in must not be NULL";
+    if (!std::isfinite(theta) || !(theta > 0.0)) return "theta must be finite and > 0";
+    if (!cand_offsets || !cand_idx) return "candidate offsets and idx must not be NULL";
+    if (!label || !grp_offsets || !members) return "label, grp_offsets and members must not be NULL";
+    if (!n_groups || !n_pairs) return "n_groups and n_pairs must not be NULL";
+    if (pair_cap < n / 2) return "pair_cap must be >= N/2";
+    if (pair_cap > 0 && !pairs) return "pairs must not be NULL";
+    return nullptr;
+}
+
 namespace {
 int art_points(int order) { return order == 2 ? 4 : 8; }
 }  // namespace

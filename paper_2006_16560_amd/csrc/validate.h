@@ -30,6 +30,12 @@ const char *check_cluster_args(int64_t n, const int64_t *nb_offsets, const int32
                                const int32_t *label, const int64_t *cl_offsets,
                                const int32_t *members, const int64_t *n_clusters);
 
+const char *check_groups_args(int64_t n, const double *pos, const double *vel, const double *mass,
+                              const double *r_in, double theta, const int64_t *cand_offsets,
+                              const int32_t *cand_idx, const int32_t *label,
+                              const int64_t *grp_offsets, const int32_t *members,
+                              const int64_t *n_groups, const int32_t *pairs, int64_t pair_cap,
+                              const int64_t *n_pairs);
 const char *check_art_make_args(int64_t n, const double *pos, const double *vel,
                                 const double *mass, const double *r_in, const double *r_out,
                                 const double *r_search, int64_t n_pair, const int32_t *pairs,

@@ -385,3 +385,42 @@ def test_tidal_eval_validation(capi, ctx, case):
                               a["pair_of"], a["pos"], a["acc"], None)
     ok = case in ("ok", "ok_empty")
     assert st == (_capi.PETAR_E_NODEVICE if ok else _capi.PETAR_E_INVALID), lib.petar_last_error(ctx)
+
+
+@pytest.mark.parametrize("case", ["ok", "n0", "pos", "vel", "mass", "rin", "theta0", "thetanan",
+                                  "offs", "idx", "label", "go", "members", "ng", "pairs", "cap",
+                                  "np"])
+def test_groups_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(n=100, pos=FAKE, vel=FAKE, mass=FAKE, rin=FAKE, theta=0.5, offs=FAKE, idx=FAKE,
+             label=FAKE, go=FAKE, members=FAKE, pairs=FAKE, cap=50)
+    ng, npair = ctypes.c_int64(0), ctypes.c_int64(0)
+    if case == "n0":
+        a["n"] = 0
+    elif case == "theta0":
+        a["theta"] = 0.0
+    elif case == "thetanan":
+        a["theta"] = float("nan")
+    elif case == "cap":
+        a["cap"] = 49
+    elif case in a:
+        a[case] = None
+    st = lib.petar_groups(ctx, a["n"], a["pos"], a["vel"], a["mass"], a["rin"], a["theta"],
+                          a["offs"], a["idx"], a["label"], a["go"], a["members"],
+                          None if case == "ng" else ctypes.byref(ng), a["pairs"], a["cap"],
+                          None if case == "np" else ctypes.byref(npair))
+    assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)
+
+
+@pytest.mark.parametrize("case", ["ok", "n0", "vel", "acc", "dtnan"])
+def test_kick_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(n=10, vel=FAKE, acc=FAKE, dt=0.01)
+    if case == "n0":
+        a["n"] = 0
+    elif case == "dtnan":
+        a["dt"] = float("inf")
+    elif case in a:
+        a[case] = None
+    st = lib.petar_kick(ctx, a["n"], a["vel"], a["acc"], a["dt"])
+    assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)

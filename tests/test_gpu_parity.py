@@ -841,3 +841,109 @@ def test_artificial_edge_cases(pt, ctx, orc):
     with pytest.raises(pt.PetarError):
         pt.petar_tidal_eval(ctx, 2, ten, fr, T(np.array([0, 1], dtype=np.int32)),
                             T(np.zeros((3, 2))))
+
+
+# ---------------------------------------------------------- SDAR groups, kick
+@pytest.mark.parametrize("n,bf,seed", [(4096, 0.5, 61), (20000, 1.0, 62)])
+def test_groups_match_oracle(pt, ctx, orc, n, bf, seed):
+    c = workloads.make_cluster(n, seed, imf=True, binary_fraction=bf)
+    r_out_ref = workloads.r_out_ref_for(n)
+    rin, rout, rs = orc.radii(c.mass, 0.1 * r_out_ref, r_out_ref, 1.2)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 8)
+    _, _, (offs, idx) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=400 * n)
+    label, go, members, pairs = pt.petar_groups(ctx, T(c.pos), T(c.vel), T(c.mass), T(rin), 0.5,
+                                                offs, idx)
+    l_ref, g_ref, m_ref, p_ref = orc.groups(c.pos, c.vel, c.mass, rin, 0.5)
+    assert np.array_equal(label.cpu().numpy(), l_ref)
+    assert np.array_equal(go.cpu().numpy(), g_ref)
+    assert np.array_equal(members.cpu().numpy(), m_ref)
+    assert np.array_equal(pairs.cpu().numpy().T, p_ref)
+    assert 0 < len(p_ref) and g_ref.size - 1 < n
+
+
+def test_kick_matches_oracle(pt, ctx, orc):
+    rng = np.random.default_rng(63)
+    for n in (1, 63, 4097):
+        v, a = rng.normal(size=(3, n)), rng.normal(size=(3, n))
+        vg = T(v)
+        pt.petar_kick(ctx, vg, T(a), 0.0078125 / 2)
+        assert np.array_equal(vg.cpu().numpy(), orc.kick(v, a, 0.0078125 / 2))
+
+
+def test_plummer1m_groups_artificial_kick(pt, ctx, orc, cluster1m):
+    """Full size, the configuration of the benchmark: neighbour lists ->
+    SDAR groups -> artificial particles (order 3) -> tree and long-range
+    force on the set -> post-fit -> kick. Group invariants on every particle
+    and the group relation against brute force on sampled rows; the post-fit
+    of sampled binaries in FP64 against the oracle tree on the oracle's own
+    set (same interaction lists); the mixed-precision members' field against
+    the FP64 run (arithmetic error, amplified at most by the condition
+    number 12.7 of the third-order map)."""
+    wl, c = cluster1m
+    n, theta, order = wl.n, wl.theta, 3
+    rin, rout, rs = orc.radii(c.mass, wl.r_in_ref, wl.r_out_ref, wl.search_factor)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), theta, wl.leaf_size)
+    _, _, (offs, idx) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=64 * n)
+    label, go, members, pairs = pt.petar_groups(ctx, T(c.pos), T(c.vel), T(c.mass), T(rin),
+                                                theta, offs, idx)
+    lab, gof, mem = label.cpu().numpy(), go.cpu().numpy(), members.cpu().numpy()
+    pr = pairs.cpu().numpy().T
+    print("groups: %d, binaries %d" % (gof.size - 1, len(pr)), flush=True)
+    assert len(pr) > 0.1 * c.n_binaries
+    assert np.array_equal(np.sort(mem), np.arange(n))
+    first = mem[gof[:-1]]
+    assert np.array_equal(lab[first], first) and np.all(np.diff(first) > 0)
+    s = workloads.sample_indices(n, 512, 5)
+    for i in s:
+        d2 = ((c.pos - c.pos[:, i:i + 1]) ** 2).sum(axis=0)
+        near = np.nonzero(d2 < (theta * np.maximum(rin, rin[i])) ** 2)[0]
+        assert np.all(lab[near] == lab[i]), i
+    size = np.diff(gof)
+    g2 = np.nonzero(size == 2)[0]
+    i2, j2 = mem[gof[g2]], mem[gof[g2] + 1]
+    r = np.linalg.norm(c.pos[:, j2] - c.pos[:, i2], axis=0)
+    eps = 0.5 * ((c.vel[:, j2] - c.vel[:, i2]) ** 2).sum(axis=0) - (c.mass[i2] + c.mass[j2]) / r
+    assert np.array_equal(pr, np.stack([i2, j2], axis=1)[eps < 0])
+
+    def pipeline(prec):
+        g = pt.petar_artificial_make(ctx, T(c.pos), T(c.vel), T(c.mass), T(rin), T(rout), T(rs),
+                                     pairs, order, 1.0)
+        pt.petar_set_params(ctx, precision=prec)
+        pt.petar_tree_build(ctx, g["pos"], g["mass"], theta, wl.leaf_size)
+        a_set, p_set = pt.petar_force_long(ctx, 64, g["r_in"], g["r_out"], g["r_search"])
+        ten, acc, pot = pt.petar_tidal_fit(ctx, g, pairs, a_set, p_set, pos=T(c.pos))
+        torch.cuda.synchronize()
+        return g, a_set.cpu().numpy(), ten.cpu().numpy().T, acc, pot.cpu().numpy()
+
+    g, a_mixed, ten_m, acc_m, _ = pipeline(pt.PETAR_MIXED)
+    vel = T(c.vel)
+    pt.petar_kick(ctx, vel, acc_m, 0.5 * 2.0 ** -9)
+    acc_m = acc_m.cpu().numpy()
+    assert np.array_equal(vel.cpu().numpy(), c.vel + acc_m * (0.5 * 2.0 ** -9))
+    g, a64, ten64, acc64, pot64 = pipeline(pt.PETAR_FP64)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    mem2 = pr.ravel()
+    e = rel_err(acc_m[:, mem2], acc64.cpu().numpy()[:, mem2])
+    print("members' field, mixed vs fp64: p50 %.2e p99 %.2e" % tuple(np.percentile(e, [50, 99])),
+          flush=True)
+    assert np.percentile(e, 99) < 13.7 * 1e-5
+    # sampled binaries against the oracle: its own set (all binaries), the
+    # tree force at the sampled blocks, and the post-fit
+    o = orc.artificial_set(c.pos, c.vel, c.mass, rin, rout, rs, pr, order, 1.0)
+    ns, B = o["n_single"], 12
+    sb = workloads.sample_indices(len(pr), 96, 6)
+    tgt = (ns + sb[:, None] * B + np.arange(9)[None, :]).ravel()
+    a_ref, p_ref, _ = orc.tree_force(o["pos"], o["mass"], o["r_in"], o["r_out"], o["r_search"],
+                                     theta, wl.leaf_size, 64, idx=tgt)
+    ok = rel_err(a64[:, tgt], a_ref).reshape(len(sb), 9).max(axis=1) < 1e-11
+    assert ok.mean() > 0.95, ok.mean()
+    for k, b in enumerate(sb):
+        if not ok[k]:
+            continue
+        blk = a_ref[:, 9 * k:9 * k + 9]
+        t = orc.tidal_fit(order, o["frame"][b, 3], blk[:, 0], blk[:, 1:].T)
+        got = _scaled(ten64[b:b + 1], o["frame"][b:b + 1], order)[0, 1:]
+        want = _scaled(np.concatenate([[0.0], t])[None, :], o["frame"][b:b + 1], order)[0, 1:]
+        assert np.abs(got - want).max() <= 12.7 * 1e-10 * np.linalg.norm(t[:3]), b
