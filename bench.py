@@ -287,16 +287,63 @@ def bench_next_rows(pt, ctx, c, wl, theta, leaf, group, dev, reps=5):
         t_f.append(t1 - t0)
         t_c.append(t2 - t1)
     sizes = torch.diff(cl).cpu().numpy()
+    art = bench_artificial(pt, ctx, c, wl, theta, leaf, group, dev, reps)
     out = {"nb_filter_ms": 1e3 * float(np.median(t_f)), "clusters_ms": 1e3 * float(np.median(t_c)),
            "candidates": int(idx.numel()), "kept": int(f_idx.numel()),
            "n_clusters": int(sizes.size), "largest_cluster": int(sizes.max()),
            "particles_in_clusters_gt1": int(sizes[sizes > 1].sum()),
-           "search_radius": "eq. rnb, C_r = 3, dt = %.4g" % dt}
+           "search_radius": "eq. rnb, C_r = 3, dt = %.4g" % dt,
+           "groups_and_artificial": art}
     log("next rows: filter %.3f ms, clusters %.3f ms, %d -> %d pairs, %d clusters (largest %d)"
         % (out["nb_filter_ms"], out["clusters_ms"], out["candidates"], out["kept"],
            out["n_clusters"], out["largest_cluster"]))
     return out
 
+
+def bench_artificial(pt, ctx, c, wl, theta, leaf, group, dev, reps=5, order=3):
+    """SDAR groups (eq. rbin) from the neighbour lists of the step's radii,
+    the artificial set of the bound binaries (third-order tidal tensor and
+    pseudoparticles), tree build and long-range force on that set, post-fit
+    and kick: each stage's median device-synchronised wall time."""
+    import torch
+    n = wl.n
+    pos = torch.from_numpy(c.pos).to(dev)
+    vel = torch.from_numpy(c.vel).to(dev)
+    mass = torch.from_numpy(c.mass).to(dev)
+    ri, ro, rs = pt.petar_changeover_radii(ctx, mass, wl.r_in_ref, wl.r_out_ref, wl.search_factor)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    pt.petar_tree_build(ctx, pos, mass, theta, leaf)
+    _, _, (offs, idx) = pt.force_long_with_retry(ctx, group, ri, ro, rs, 64 * n)
+    times = {k: [] for k in ("groups", "make", "set_build", "set_force", "fit", "kick")}
+
+    def timed(key, fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        times[key].append(time.perf_counter() - t0)
+        return r
+
+    for _ in range(reps):
+        label, go, members, pairs = timed(
+            "groups", lambda: pt.petar_groups(ctx, pos, vel, mass, ri, theta, offs, idx))
+        g = timed("make", lambda: pt.petar_artificial_make(ctx, pos, vel, mass, ri, ro, rs, pairs,
+                                                           order, 1.0))
+        timed("set_build", lambda: pt.petar_tree_build(ctx, g["pos"], g["mass"], theta, leaf))
+        a_set, p_set = timed("set_force", lambda: pt.petar_force_long(
+            ctx, group, g["r_in"], g["r_out"], g["r_search"]))
+        st = pt.petar_get_stats(ctx)
+        ten, acc, pot = timed("fit", lambda: pt.petar_tidal_fit(ctx, g, pairs, a_set, p_set,
+                                                                pos=pos))
+        v = vel.clone()
+        timed("kick", lambda: pt.petar_kick(ctx, v, acc, 0.5 * wl.r_out_ref))
+    out = {k + "_ms": 1e3 * float(np.median(t)) for k, t in times.items()}
+    out.update({"order": order, "n_groups": int(go.numel() - 1), "binaries": int(pairs.shape[1]),
+                "set_particles": int(g["mass"].numel()),
+                "set_interactions": int(st["inter_pc"] + st["inter_far"] + st["inter_near"]),
+                "set_force_kernel_ms": st["ms_force_kernel"]})
+    log("groups/artificial: %s" % json.dumps(out))
+    return out
 
 def bench_batched(args) -> int:
     """128 independent clusters (N log-uniform in [1024, 131072], 20% binaries).
