@@ -393,34 +393,13 @@ petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
     const int64_t sort_scan = 256 * ((n + 2047) / 2048);
     TRY(ensure(ctx, ctx->scan_ws,
                (size_t)scan_ws_elems(sort_scan > n + 1 ? sort_scan : n + 1) * 8));
-    // flags = {changed, bad index}
-    int32_t *changed = ptr<int32_t>(ctx->cl_flags), *bad = changed + 1;
+    // flags = {bad offsets, bad index}
+    int32_t *csr_bad = ptr<int32_t>(ctx->cl_flags), *bad = csr_bad + 1;
     fill_i64(ptr<int64_t>(ctx->cl_flags), 0, 1, s);
-    launch_check_csr(nb_offsets, n, bad, s);
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, changed, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    {
-        int32_t fl[2] = {0, 0};
-        memcpy(fl, ctx->host_scalar, 8);
-        if (fl[1])
-            return fail(ctx, PETAR_E_INVALID, "neighbour offsets must start at 0 and not decrease");
-    }
+    launch_check_csr(nb_offsets, n, csr_bad, s);
     uint32_t *root = ptr<uint32_t>(ctx->cl_root), *rootpos = ptr<uint32_t>(ctx->cl_rootpos);
-    // components: hooking/shortcut rounds until the grandparents are stable
-    int32_t *f = ptr<int32_t>(ctx->cl_parent), *gf = reinterpret_cast<int32_t *>(rootpos);
-    launch_cc_init(f, gf, n, s);
-    for (int round = 0;; round++) {
-        if (round > 4096) return fail(ctx, PETAR_E_INTERNAL, "clustering did not converge");
-        fill_u32(reinterpret_cast<uint32_t *>(changed), 0, 1, s);
-        launch_cc_round(nb_offsets, nb_idx, n, f, gf, bad, changed, s);
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, changed, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
-        int32_t ch[2] = {0, 0};
-        memcpy(ch, ctx->host_scalar, 8);
-        if (ch[1]) return fail(ctx, PETAR_E_INVALID, "neighbour index outside [0, N)");
-        if (!ch[0]) break;
-    }
-    launch_cc_label(gf, n, label, root, s);
+    launch_components(nb_offsets, nb_idx, n, ptr<int32_t>(ctx->cl_parent), label, root, bad,
+                      csr_bad, s);
     scan_u32_to_u32(root, rootpos, n, ptr<int64_t>(ctx->scan_ws), s);
     // members: stable radix sort of the particle indices by cluster index
     uint64_t *k = ptr<uint64_t>(ctx->cl_key0), *ka = ptr<uint64_t>(ctx->cl_key1);
@@ -433,7 +412,12 @@ petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
     launch_cluster_offsets(k, n, cl_offsets, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, rootpos + n, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, csr_bad, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    int32_t fl[2] = {0, 0};
+    memcpy(fl, ctx->host_scalar + 1, 8);
+    if (fl[0]) return fail(ctx, PETAR_E_INVALID, "neighbour offsets must start at 0 and not decrease");
+    if (fl[1]) return fail(ctx, PETAR_E_INVALID, "neighbour index outside [0, N)");
     uint32_t nc = 0;
     memcpy(&nc, ctx->host_scalar, 4);
     *n_clusters = nc;

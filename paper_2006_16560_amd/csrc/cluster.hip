@@ -10,13 +10,9 @@
 // ones. FP64 without contraction, in this exact order, so that every
 // decision is reproducible by any implementation of the same formula.
 //
-// Clusters: connected components of the kept pairs by min-label hooking
-// and pointer-jumping rounds (one launch per phase, repeated until the
-// grandparent labels stop changing). Every update is a minimum of particle
-// indices of the same component, so the labels fall monotonically and end
-// at the smallest index of each component, whatever the order of the
-// updates within a round; a stale read inside a round only delays a change
-// to the next round.
+// Clusters: connected components of the kept pairs by a one-pass union-find
+// whose roots are the smallest index of each component (so the result does
+// not depend on the order of the unions).
 #include "launch.h"
 
 namespace petar {
@@ -148,72 +144,84 @@ __global__ __launch_bounds__(kThreads) void k_filter_write(FilterArgs a, const u
 }
 
 // ------------------------------------------------------------ components
-__global__ __launch_bounds__(kThreads) void k_cc_init(int32_t *f, int32_t *gf, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        f[i] = (int32_t)i;
-        gf[i] = (int32_t)i;
+// Union-find over the pairs in one pass. Every parent pointer goes to a
+// smaller index (parent[v] <= v), so a root is the smallest index of its
+// tree. rep() follows the pointers and halves the path behind it with plain
+// stores, which only ever replace a non-root's parent by one of its
+// ancestors; a union links the larger of two roots under the smaller with a
+// compare-and-swap, and a failed swap continues from the value it returns
+// (a smaller ancestor), so the loop ends. Plain loads may return older,
+// larger ancestors (caches of other XCDs are not coherent inside a
+// launch): the chain still leads into the same tree, and every link is
+// checked by the swap at the coherence point. After all unions each
+// component is one tree whose root is its smallest index.
+__device__ __forceinline__ int32_t uf_rep(int32_t *parent, int32_t v) {
+    int32_t cur = parent[v];
+    if (cur == v) return v;
+    int32_t prev = v, next;
+    while (cur > (next = parent[cur])) {
+        parent[prev] = next;
+        prev = cur;
+        cur = next;
+    }
+    return cur;
+}
+
+// parent[v] = min(v, smallest in-range neighbour of v). Skipped when the
+// CSR check failed (offsets could then reach outside the index array).
+__global__ __launch_bounds__(kThreads) void k_uf_init(const int64_t *offsets, const int32_t *idx,
+                                                      int64_t n, int32_t *parent,
+                                                      const int32_t *csr_bad) {
+    if (*csr_bad) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t m = (int32_t)v;
+        for (int64_t e = offsets[v]; e < offsets[v + 1]; e++) {
+            const int32_t u = idx[e];
+            if (u >= 0 && u < m) m = u;
+        }
+        parent[v] = m;
     }
 }
 
-// For every pair (u, v), both ways: f[f[u]] = min(f[f[u]], gf[v]) (hook
-// the tree of u under v's grandparent) and f[u] = min(f[u], gf[v]). Plain
-// reads may be stale, i.e. larger: that can only cause an unneeded atomic,
-// never skip a needed one.
-__global__ __launch_bounds__(kThreads) void k_cc_hook(const int64_t *offsets, const int32_t *idx,
-                                                      int64_t n, int32_t *f, const int32_t *gf,
-                                                      int32_t *bad) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        for (int64_t e = offsets[u]; e < offsets[u + 1]; e++) {
-            const int32_t v = idx[e];
-            if (v < 0 || v >= n) {
+__global__ __launch_bounds__(kThreads) void k_uf_union(const int64_t *offsets, const int32_t *idx,
+                                                       int64_t n, int32_t *parent, int32_t *bad,
+                                                       const int32_t *csr_bad) {
+    if (*csr_bad) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t e = offsets[v]; e < offsets[v + 1]; e++) {
+            const int32_t u = idx[e];
+            if (u < 0 || u >= n) {
                 atomicOr(bad, 1);
                 continue;
             }
-            const int32_t gu = gf[u], gv = gf[v];
-            if (gv < gu) {
-                const int32_t fu = f[u];
-                if (gv < f[fu]) atomicMin(f + fu, gv);
-                if (gv < fu) atomicMin(f + u, gv);
-            } else if (gu < gv) {
-                const int32_t fv = f[v];
-                if (gu < f[fv]) atomicMin(f + fv, gu);
-                if (gu < fv) atomicMin(f + v, gu);
+            int32_t vr = uf_rep(parent, (int32_t)v), ur = uf_rep(parent, u);
+            while (vr != ur) {
+                if (vr < ur) {
+                    const int32_t old = atomicCAS(parent + ur, ur, vr);
+                    if (old == ur) break;
+                    ur = old;
+                } else {
+                    const int32_t old = atomicCAS(parent + vr, vr, ur);
+                    if (old == vr) break;
+                    vr = old;
+                }
             }
         }
     }
 }
 
-// Shortcut f[u] = min(f[u], gf[u]), then the new grandparents; flags a change.
-__global__ __launch_bounds__(kThreads) void k_cc_short(int32_t *f, int64_t n) {
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t p = f[u], g = f[p];
-        if (g < p) f[u] = g;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_cc_grand(const int32_t *f, int32_t *gf, int64_t n,
-                                                       int32_t *changed) {
-    int32_t ch = 0;
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t g = f[f[u]];
-        if (g != gf[u]) {
-            gf[u] = g;
-            ch = 1;
-        }
-    }
-    if (__ballot(ch) && lane_id() == 0) atomicOr(changed, 1);
-}
-
-__global__ __launch_bounds__(kThreads) void k_cc_label(const int32_t *gf, int64_t n,
-                                                       int32_t *label, uint32_t *is_root) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        label[i] = gf[i];
-        is_root[i] = gf[i] == (int32_t)i ? 1u : 0u;
+// Labels from the final trees (every particle alone when the CSR check
+// failed, so that the later passes stay in bounds before the error returns).
+__global__ __launch_bounds__(kThreads) void k_uf_label(int32_t *parent, int64_t n, int32_t *label,
+                                                       uint32_t *is_root, const int32_t *csr_bad) {
+    const bool skip = *csr_bad != 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = skip ? (int32_t)v : uf_rep(parent, (int32_t)v);
+        label[v] = r;
+        is_root[v] = r == (int32_t)v ? 1u : 0u;
     }
 }
 
@@ -313,23 +321,19 @@ void launch_filter_write(const FilterArgs &a, const uint8_t *keep, const int64_t
                        a, keep, out_offsets, out_idx, capacity);
 }
 
-void launch_cc_init(int32_t *f, int32_t *gf, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, f, gf,
-                       n);
-}
-
-void launch_cc_round(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *f,
-                     int32_t *gf, int32_t *bad, int32_t *changed, hipStream_t s) {
+void launch_components(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *parent,
+                       int32_t *label, uint32_t *is_root, int32_t *bad, const int32_t *csr_bad,
+                       hipStream_t s) {
     const dim3 g(grid_for(n, kThreads, 8192)), b(kThreads);
-    hipLaunchKernelGGL(k_cc_hook, g, b, 0, s, offsets, idx, n, f, (const int32_t *)gf, bad);
-    hipLaunchKernelGGL(k_cc_short, g, b, 0, s, f, n);
-    hipLaunchKernelGGL(k_cc_grand, g, b, 0, s, (const int32_t *)f, gf, n, changed);
+    hipLaunchKernelGGL(k_uf_init, g, b, 0, s, offsets, idx, n, parent, csr_bad);
+    hipLaunchKernelGGL(k_uf_union, g, b, 0, s, offsets, idx, n, parent, bad, csr_bad);
+    hipLaunchKernelGGL(k_uf_label, g, b, 0, s, parent, n, label, is_root, csr_bad);
 }
 
-void launch_cc_label(const int32_t *gf, int64_t n, int32_t *label, uint32_t *is_root,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_label, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, gf, n,
-                       label, is_root);
+void launch_cluster_keys(const int32_t *label, int64_t n, const uint32_t *root_pos, uint64_t *key,
+                         uint32_t *val, hipStream_t s) {
+    hipLaunchKernelGGL(k_cl_keys, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, label,
+                       n, root_pos, key, val);
 }
 
 void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_offsets,
@@ -337,12 +341,6 @@ void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_o
     fill_i64(cl_offsets, n, n + 1, s);
     hipLaunchKernelGGL(k_cl_offsets, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s,
                        sorted_key, n, cl_offsets);
-}
-
-void launch_cluster_keys(const int32_t *label, int64_t n, const uint32_t *root_pos, uint64_t *key,
-                         uint32_t *val, hipStream_t s) {
-    hipLaunchKernelGGL(k_cl_keys, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, label,
-                       n, root_pos, key, val);
 }
 
 }  // namespace petar

@@ -167,14 +167,12 @@ void launch_filter(const FilterArgs &a, int64_t n_cand, int32_t *row, uint8_t *k
                    uint32_t *counts, int32_t *bad, hipStream_t s);
 void launch_filter_write(const FilterArgs &a, const uint8_t *keep, const int64_t *out_offsets,
                          int32_t *out_idx, int64_t capacity, hipStream_t s);
-// Components of a neighbour CSR: init, then rounds (hook, shortcut, new
-// grandparents; *changed set when a grandparent changed) until no change;
-// label[i] = smallest index of i's cluster, is_root[i] = (label[i] == i).
-void launch_cc_init(int32_t *f, int32_t *gf, int64_t n, hipStream_t s);
-void launch_cc_round(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *f,
-                     int32_t *gf, int32_t *bad, int32_t *changed, hipStream_t s);
-void launch_cc_label(const int32_t *gf, int64_t n, int32_t *label, uint32_t *is_root,
-                     hipStream_t s);
+// Components of a neighbour CSR (pairs taken both ways): label[i] =
+// smallest index of i's component, is_root[i] = (label[i] == i); parent is
+// scratch [n]; *bad |= an index outside [0, n). Nothing runs when *csr_bad.
+void launch_components(const int64_t *offsets, const int32_t *idx, int64_t n, int32_t *parent,
+                       int32_t *label, uint32_t *is_root, int32_t *bad, const int32_t *csr_bad,
+                       hipStream_t s);
 // Keys (cluster index, root_pos = cluster index of each root) and values
 // (particle index) whose stable sort lists the members of every cluster in
 // ascending order; cluster offsets from the sorted keys.
