@@ -184,6 +184,16 @@ __global__ __launch_bounds__(kThreads) void k_uf_init(const int64_t *offsets, co
     }
 }
 
+// Every particle straight to the end of its chain after the init, so that
+// the finds of the union pass start from flat trees.
+__global__ __launch_bounds__(kThreads) void k_uf_flatten(int32_t *parent, int64_t n,
+                                                         const int32_t *csr_bad) {
+    if (*csr_bad) return;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        parent[v] = uf_rep(parent, (int32_t)v);
+}
+
 __global__ __launch_bounds__(kThreads) void k_uf_union(const int64_t *offsets, const int32_t *idx,
                                                        int64_t n, int32_t *parent, int32_t *bad,
                                                        const int32_t *csr_bad) {
@@ -326,6 +336,7 @@ void launch_components(const int64_t *offsets, const int32_t *idx, int64_t n, in
                        hipStream_t s) {
     const dim3 g(grid_for(n, kThreads, 8192)), b(kThreads);
     hipLaunchKernelGGL(k_uf_init, g, b, 0, s, offsets, idx, n, parent, csr_bad);
+    hipLaunchKernelGGL(k_uf_flatten, g, b, 0, s, parent, n, csr_bad);
     hipLaunchKernelGGL(k_uf_union, g, b, 0, s, offsets, idx, n, parent, bad, csr_bad);
     hipLaunchKernelGGL(k_uf_label, g, b, 0, s, parent, n, label, is_root, csr_bad);
 }
