@@ -50,10 +50,13 @@ class Context:
         self.handle = handle
         self.device = device
         self.stream = stream
+        # held by the object: module globals may already be gone when a
+        # context is collected at interpreter exit
+        self._destroy = _lib.petar_destroy
 
     def __del__(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
-            _lib.petar_destroy(self.handle)
+            self._destroy(self.handle)
             self.handle = None
 
 
