@@ -224,55 +224,87 @@ __global__ __launch_bounds__(kThreads) void k_art_singles(ArtArgs a, const uint3
 }
 
 // One block of P + 4 particles per pair: centre, measure points,
-// pseudoparticles. Indices were checked by k_art_mark; they are checked
-// again here so that no access leaves the arrays on invalid input.
-__global__ __launch_bounds__(kThreads) void k_art_pairs(ArtArgs a, int32_t *bad) {
+// pseudoparticles. A workgroup takes 256 consecutive pairs: each thread
+// computes its pair's orbit and offsets into LDS, then the workgroup writes
+// the 256 (P + 4) consecutive entries of every output array with
+// consecutive threads on consecutive addresses. Indices were checked by
+// k_art_mark; they are checked again so that no access leaves the arrays.
+constexpr int kPairsPerBlock = 256;
+
+struct PairLds {
+    double cm[3][kPairsPerBlock];
+    double dc[kPairsPerBlock];
+    double off[3][3][kPairsPerBlock];  // pseudoparticle t, axis d
+    double m3[kPairsPerBlock];
+    double rin[kPairsPerBlock], rout[kPairsPerBlock], rs[kPairsPerBlock];
+    uint8_t ok[kPairsPerBlock];
+};
+
+__global__ __launch_bounds__(kPairsPerBlock) void k_art_pairs(ArtArgs a, int32_t *bad) {
+    __shared__ PairLds L;
     const int P = a.order == 2 ? 4 : 8, B = P + 4;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < a.n_pair;
-         b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b0 = (int64_t)blockIdx.x * kPairsPerBlock;
+    const int t = threadIdx.x;
+    const int cnt = (int)(a.n_pair - b0 < kPairsPerBlock ? a.n_pair - b0 : kPairsPerBlock);
+    if (t < cnt) {
+        const int64_t b = b0 + t;
         const int32_t i = a.pairs[b], j = a.pairs[a.n_pair + b];
-        if (i < 0 || j < 0 || i >= a.n || j >= a.n || i == j) continue;
-        const double m1 = a.mass[i], m2 = a.mass[j], M = m1 + m2;
-        double x1[3], x2[3], r[3], v[3], cm[3];
-        for (int d = 0; d < 3; d++) {
-            x1[d] = a.pos[d * a.n + i];
-            x2[d] = a.pos[d * a.n + j];
-            r[d] = x2[d] - x1[d];
-            v[d] = a.vel[d * a.n + j] - a.vel[d * a.n + i];
-            cm[d] = (m1 * x1[d] + m2 * x2[d]) / M;
-        }
-        const Kepler k = kepler(m1, m2, r, v, a.G);
-        if (!k.ok || !(M > 0.0)) {
-            atomicAdd(&bad[2], 1);
-            continue;
-        }
-        const double d_c = a.c_d * k.a * (1.0 + k.e);
-        const double rin = fmax(a.r_in[i], a.r_in[j]), rout = fmax(a.r_out[i], a.r_out[j]);
-        const double rs = fmax(a.r_search[i], a.r_search[j]);
-        const int64_t base = a.n_single + b * B;
-        for (int q = 0; q < B; q++) {
-            double p[3], m = 0.0;
-            if (q == 0) {
-                for (int d = 0; d < 3; d++) p[d] = cm[d];
-            } else if (q <= P) {
-                double u[3];
-                tt_unit(a.order, q - 1, u);
-                for (int d = 0; d < 3; d++) p[d] = cm[d] + d_c * u[d];
-            } else {
-                const int t = q - 1 - P;
-                for (int d = 0; d < 3; d++)
-                    p[d] = cm[d] + k.s * (k.px[t] * k.ex[d] + k.py[t] * k.ey[d]);
-                m = M / 3.0;
+        uint8_t ok = 0;
+        if (i >= 0 && j >= 0 && i < a.n && j < a.n && i != j) {
+            const double m1 = a.mass[i], m2 = a.mass[j], M = m1 + m2;
+            double x1[3], x2[3], r[3], v[3], cm[3];
+            for (int d = 0; d < 3; d++) {
+                x1[d] = a.pos[d * a.n + i];
+                x2[d] = a.pos[d * a.n + j];
+                r[d] = x2[d] - x1[d];
+                v[d] = a.vel[d * a.n + j] - a.vel[d * a.n + i];
+                cm[d] = (m1 * x1[d] + m2 * x2[d]) / M;
             }
-            for (int d = 0; d < 3; d++) a.o_pos[d * a.n_out + base + q] = p[d];
-            a.o_mass[base + q] = m;
-            a.o_rin[base + q] = rin;
-            a.o_rout[base + q] = rout;
-            a.o_rs[base + q] = rs;
-            a.src[base + q] = -1;
+            const Kepler k = kepler(m1, m2, r, v, a.G);
+            if (!k.ok || !(M > 0.0)) {
+                atomicAdd(&bad[2], 1);
+            } else {
+                ok = 1;
+                const double d_c = a.c_d * k.a * (1.0 + k.e);
+                for (int d = 0; d < 3; d++) {
+                    L.cm[d][t] = cm[d];
+                    for (int q = 0; q < 3; q++)
+                        L.off[q][d][t] = k.s * (k.px[q] * k.ex[d] + k.py[q] * k.ey[d]);
+                    a.frame[d * a.n_pair + b] = cm[d];
+                }
+                L.dc[t] = d_c;
+                L.m3[t] = M / 3.0;
+                L.rin[t] = fmax(a.r_in[i], a.r_in[j]);
+                L.rout[t] = fmax(a.r_out[i], a.r_out[j]);
+                L.rs[t] = fmax(a.r_search[i], a.r_search[j]);
+                a.frame[3 * a.n_pair + b] = d_c;
+            }
         }
-        for (int d = 0; d < 3; d++) a.frame[d * a.n_pair + b] = cm[d];
-        a.frame[3 * a.n_pair + b] = d_c;
+        L.ok[t] = ok;
+    }
+    __syncthreads();
+    const int64_t base0 = a.n_single + b0 * B;
+    for (int e = t; e < cnt * B; e += kPairsPerBlock) {
+        const int pr = e / B, q = e - pr * B;
+        if (!L.ok[pr]) continue;
+        double p[3], m = 0.0;
+        if (q == 0) {
+            for (int d = 0; d < 3; d++) p[d] = L.cm[d][pr];
+        } else if (q <= P) {
+            double u[3];
+            tt_unit(a.order, q - 1, u);
+            for (int d = 0; d < 3; d++) p[d] = L.cm[d][pr] + L.dc[pr] * u[d];
+        } else {
+            for (int d = 0; d < 3; d++) p[d] = L.cm[d][pr] + L.off[q - 1 - P][d][pr];
+            m = L.m3[pr];
+        }
+        const int64_t o = base0 + e;
+        for (int d = 0; d < 3; d++) a.o_pos[d * a.n_out + o] = p[d];
+        a.o_mass[o] = m;
+        a.o_rin[o] = L.rin[pr];
+        a.o_rout[o] = L.rout[pr];
+        a.o_rs[o] = L.rs[pr];
+        a.src[o] = -1;
     }
 }
 
@@ -291,42 +323,56 @@ __device__ inline void tt_eval(int order, const double *rec, double x, double y,
     *pot = ph;
 }
 
+// A workgroup takes 128 consecutive pairs and first copies the
+// accelerations of their centres and measure points (the first P + 1 entries
+// of each block) into LDS, consecutive threads on consecutive addresses;
+// each thread then fits its own pair from LDS.
+constexpr int kFitPairs = 128;
+
 template <int ORDER>
-__global__ __launch_bounds__(kThreads) void k_tidal_fit(FitArgs f) {
+__global__ __launch_bounds__(kFitPairs) void k_tidal_fit(FitArgs f) {
     constexpr int P = ORDER == 2 ? 4 : 8, K = ORDER == 2 ? 6 : 16, R = 4 + K, B = P + 4;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < f.n_pair;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t base = f.n_single + b * B;
-        double A0[3], Ap[3 * P];
-        for (int d = 0; d < 3; d++) A0[d] = f.acc_set[d * f.n_out + base];
+    __shared__ double sa[3][kFitPairs * (P + 1)];
+    const int64_t b0 = (int64_t)blockIdx.x * kFitPairs;
+    const int t = threadIdx.x;
+    const int cnt = (int)(f.n_pair - b0 < kFitPairs ? f.n_pair - b0 : kFitPairs);
+    const int64_t base0 = f.n_single + b0 * B;
+    for (int e = t; e < cnt * (P + 1); e += kFitPairs) {
+        const int pr = e / (P + 1), q = e - pr * (P + 1);
+        for (int d = 0; d < 3; d++) sa[d][e] = f.acc_set[d * f.n_out + base0 + pr * B + q];
+    }
+    __syncthreads();
+    if (t >= cnt) return;
+    const int64_t b = b0 + t;
+    const int64_t base = base0 + (int64_t)t * B;
+    double A0[3], Ap[3 * P];
+    for (int d = 0; d < 3; d++) A0[d] = sa[d][t * (P + 1)];
 #pragma unroll
-        for (int p = 0; p < P; p++)
-            for (int d = 0; d < 3; d++)
-                Ap[3 * p + d] = f.acc_set[d * f.n_out + base + 1 + p] - A0[d];
-        const double d_c = f.frame[3 * f.n_pair + b];
-        double rec[R];
-        rec[0] = f.pot_set ? f.pot_set[base] : 0.0;
-        for (int d = 0; d < 3; d++) rec[1 + d] = A0[d];
+    for (int p = 0; p < P; p++)
+        for (int d = 0; d < 3; d++) Ap[3 * p + d] = sa[d][t * (P + 1) + 1 + p] - A0[d];
+    const double d_c = f.frame[3 * f.n_pair + b];
+    double rec[R];
+    rec[0] = f.pot_set ? f.pot_set[base] : 0.0;
+    for (int d = 0; d < 3; d++) rec[1 + d] = A0[d];
 #pragma unroll
-        for (int k = 0; k < K; k++) {
-            double s = 0.0;
+    for (int k = 0; k < K; k++) {
+        double s = 0.0;
 #pragma unroll
-            for (int r = 0; r < 3 * P; r++) s += f.ginv[k * 3 * P + r] * Ap[r];
-            rec[4 + k] = k < 6 ? s / d_c : s / (d_c * d_c);
-        }
+        for (int r = 0; r < 3 * P; r++) s += f.ginv[k * 3 * P + r] * Ap[r];
+        rec[4 + k] = k < 6 ? s / d_c : s / (d_c * d_c);
+    }
 #pragma unroll
-        for (int k = 0; k < R; k++) f.tensor[k * f.n_pair + b] = rec[k];
-        if (!f.acc) continue;
-        const int32_t mem[2] = {f.pairs[b], f.pairs[f.n_pair + b]};
-        for (int q = 0; q < 2; q++) {
-            const int64_t i = mem[q];
-            if (i < 0 || i >= f.n) continue;
-            double acc[3], pot;
-            tt_eval(ORDER, rec, f.pos[i] - f.frame[b], f.pos[f.n + i] - f.frame[f.n_pair + b],
-                    f.pos[2 * f.n + i] - f.frame[2 * f.n_pair + b], acc, &pot);
-            for (int d = 0; d < 3; d++) f.acc[d * f.n + i] = acc[d];
-            if (f.pot) f.pot[i] = pot;
-        }
+    for (int k = 0; k < R; k++) f.tensor[k * f.n_pair + b] = rec[k];
+    if (!f.acc) return;
+    const int32_t mem[2] = {f.pairs[b], f.pairs[f.n_pair + b]};
+    for (int q = 0; q < 2; q++) {
+        const int64_t i = mem[q];
+        if (i < 0 || i >= f.n) continue;
+        double acc[3], pot;
+        tt_eval(ORDER, rec, f.pos[i] - f.frame[b], f.pos[f.n + i] - f.frame[f.n_pair + b],
+                f.pos[2 * f.n + i] - f.frame[2 * f.n_pair + b], acc, &pot);
+        for (int d = 0; d < 3; d++) f.acc[d * f.n + i] = acc[d];
+        if (f.pot) f.pot[i] = pot;
     }
 }
 
@@ -396,17 +442,20 @@ void launch_art_make(const ArtArgs &a, uint32_t *single, uint32_t *spos, int64_t
     hipLaunchKernelGGL(k_art_flags, gn, b, 0, s, a, single);
     scan_u32_to_u32(single, spos, a.n, scan_ws, s);
     hipLaunchKernelGGL(k_art_singles, gn, b, 0, s, a, (const uint32_t *)spos);
-    if (a.n_pair > 0) hipLaunchKernelGGL(k_art_pairs, gp, b, 0, s, a, bad);
+    if (a.n_pair > 0)
+        hipLaunchKernelGGL(k_art_pairs, dim3((unsigned)((a.n_pair + kPairsPerBlock - 1) /
+                                                        kPairsPerBlock)),
+                           dim3(kPairsPerBlock), 0, s, a, bad);
 }
 
 void launch_tidal_fit(const FitArgs &f, hipStream_t s) {
     const dim3 b(kThreads);
     if (f.n_pair > 0) {
-        const dim3 g(grid_for(f.n_pair, kThreads, 8192));
+        const dim3 g((unsigned)((f.n_pair + kFitPairs - 1) / kFitPairs)), bf(kFitPairs);
         if (f.order == 2)
-            hipLaunchKernelGGL(k_tidal_fit<2>, g, b, 0, s, f);
+            hipLaunchKernelGGL(k_tidal_fit<2>, g, bf, 0, s, f);
         else
-            hipLaunchKernelGGL(k_tidal_fit<3>, g, b, 0, s, f);
+            hipLaunchKernelGGL(k_tidal_fit<3>, g, bf, 0, s, f);
     }
     if (f.acc && f.n_single > 0)
         hipLaunchKernelGGL(k_art_scatter, dim3(grid_for(f.n_single, kThreads, 8192)), b, 0, s, f);
