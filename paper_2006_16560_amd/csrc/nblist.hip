@@ -169,8 +169,8 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
 // the slot order is irrelevant).
 struct NbRecLds {
     uint32_t start[kWave], pre[kWave];
-    double4 jp[kWave];  // x, y, z, r_search
-    uint32_t jk[kWave];
+    double4 jp[2][kWave];  // x, y, z, r_search; two batches (the next is
+    uint32_t jk[2][kWave]; // gathered while the current one is tested)
 };
 
 template <bool kWrite>
@@ -212,22 +212,33 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             const double rsi = t.rsk[ki];
             const uint32_t oi = t.orig[ki];
             uint32_t c = 0;
-            for (uint32_t base = 0; base < total; base += kWave) {
+            // gather of one batch of 64 sources into registers (lane = source)
+            double4 pn = make_double4(0.0, 0.0, 0.0, 0.0);
+            uint32_t kn = 0;
+            auto gather = [&](uint32_t base) {
                 const uint32_t sidx = base + lane;
                 if (sidx < total) {
                     const int l = find_leaf(L.pre, nleaf, sidx);
-                    const uint32_t k = L.start[l] + (sidx - L.pre[l]);
-                    const double4 p = t.ps[k];
-                    L.jp[lane] = make_double4(p.x, p.y, p.z, t.rsk[k]);
-                    L.jk[lane] = k;
+                    kn = L.start[l] + (sidx - L.pre[l]);
+                    const double4 p = t.ps[kn];
+                    pn = make_double4(p.x, p.y, p.z, t.rsk[kn]);
+                }
+            };
+            gather(0);
+            int buf = 0;
+            for (uint32_t base = 0; base < total; base += kWave, buf ^= 1) {
+                if (base + lane < total) {
+                    L.jp[buf][lane] = pn;
+                    L.jk[buf][lane] = kn;
                 }
                 wave_sync();
+                if (base + kWave < total) gather(base + kWave);
                 const int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
                 if (act) {
                     for (int j = sl; j < m; j += S) {
-                        const double4 pj = L.jp[j];
+                        const double4 pj = L.jp[buf][j];
                         if (nb_pair(pi.x, pi.y, pi.z, rsi, pj.x, pj.y, pj.z, pj.w)) {
-                            const uint32_t kj = L.jk[j];
+                            const uint32_t kj = L.jk[buf][j];
                             if (kj == ki) continue;
                             if (kWrite) {
                                 const uint32_t slot = atomicAdd(&cursor[oi], 1u);
@@ -238,8 +249,8 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
                         }
                     }
                 }
-                wave_sync();
             }
+            wave_sync();
             if (!kWrite && c) atomicAdd(&cnt_orig[oi], c);
         }
     }
