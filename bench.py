@@ -182,10 +182,14 @@ def main() -> int:
     acc_mixed = acc.cpu().numpy()[:, sample].copy()
     pot_mixed = pot.cpu().numpy()[sample].copy()
     pt.petar_set_params(ctx, precision=pt.PETAR_FP64)
-    pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot)
+    fp64_ms = []
+    for _ in range(2):  # the same force with FP64 pair arithmetic, timed like the mixed one
+        pt.petar_force_long(ctx, group, r_in, r_out, r_s, acc=acc, pot=pot)
+        fp64_ms.append(pt.petar_get_stats(ctx)["ms_force_kernel"])
     torch.cuda.synchronize()
     acc64 = acc.cpu().numpy()[:, sample]
     pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    log("fp64 force kernel %.3f ms (mixed %.3f ms)" % (fp64_ms[-1], kernel_ms))
     e_arith = np.linalg.norm(acc_mixed - acc64, axis=0) / np.linalg.norm(acc64, axis=0)
     err = {"sample": int(sample.size),
            "p50_arith_vs_fp64gpu": float(np.median(e_arith)),
@@ -249,6 +253,8 @@ def main() -> int:
                       "force_kernel": kernel_ms, "neighbours": st["ms_nb"]},
         "neighbour_entries": st["nb_total"],
         "errors": err,
+        "fp64_gpu": {"force_kernel_ms": fp64_ms[-1],
+                     "mixed_speedup": fp64_ms[-1] / kernel_ms},
         "workspace_bytes": st["workspace_bytes"],
     }
     if nxt is not None:
