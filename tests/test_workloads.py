@@ -79,3 +79,20 @@ def test_determinism_and_sizes():
     assert sizes.size == 128 and sizes.min() >= 1024 and sizes.max() <= 131072
     idx = workloads.sample_indices(1000, 100, 0)
     assert np.unique(idx).size == 100
+
+
+def test_binary_pairs_are_the_generated_binaries():
+    """pairs lists each binary's two members once: distinct particles, bound,
+    with semi-major axes inside the drawn range."""
+    c = workloads.make_cluster(3000, 9, imf=True, binary_fraction=0.5)
+    p = c.pairs
+    assert p.shape == (c.n_binaries, 2)
+    assert len(np.unique(p)) == 2 * c.n_binaries
+    r = np.linalg.norm(c.pos[:, p[:, 1]] - c.pos[:, p[:, 0]], axis=0)
+    v2 = ((c.vel[:, p[:, 1]] - c.vel[:, p[:, 0]]) ** 2).sum(axis=0)
+    mt = c.mass[p[:, 0]] + c.mass[p[:, 1]]
+    eps = 0.5 * v2 - mt / r
+    assert np.all(eps < 0)
+    a = -mt / (2 * eps)
+    assert np.all(a > 1e-5 * (1 - 1e-9)) and np.all(a < 1e-2 * (1 + 1e-9))
+    assert workloads.make_cluster(100, 1, binary_fraction=0.0).pairs.shape == (0, 2)
