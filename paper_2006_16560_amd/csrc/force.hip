@@ -495,6 +495,11 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
     stk.lds = L.stack;
     stk.spill = f.spill + gwave * kSpillCap;
     unsigned long long cnt_pc = 0, cnt_far = 0, cnt_near = 0;
+    // theta^2 held in a vector register: as a scalar it shares a register
+    // tuple with other kernel arguments, which the compiler spills and then
+    // reloads whole at every walk step
+    double th2 = f.th2;
+    asm volatile("" : "+v"(th2));
     int q = blockIdx.x & 7;  // work queue of this XCD
     int moves = 0;
     const int CH = kWave * IPL;
@@ -541,31 +546,26 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
             stk.init((uint32_t)uniform((int)root_of(f.t.nd_info, f.t.level_off, gstart)));
             bool ok = true;
             while (!stk.empty()) {
-                uint32_t node = stk.pop();
-                int kind = kKindNone;
-                uint4 info = make_uint4(0, 0, 0, 0);
-                double4 cm = make_double4(0, 0, 0, 0);
-                double2 s01 = make_double2(0, 0), s23 = s01, s45 = s01;
-                if (node != kNone) {
-                    double4 lo = f.t.nd_lo[node], hi = f.t.nd_hi[node];
-                    cm = f.t.nd_com[node];
-                    const double2 *Sp = reinterpret_cast<const double2 *>(f.t.nd_S) + (int64_t)node * 3;
-                    s01 = Sp[0];
-                    s23 = Sp[1];
-                    s45 = Sp[2];
-                    info = f.t.nd_info[node];
-                    double D2, R2;
-                    box_terms(L.g, lo, hi, &D2, &R2);
-                    // both tests unconditionally: the loads of a cell are issued together
-                    const bool near = D2 < R2;
-                    const bool accept = mac_accept(L.g, cm, hi.w, f.th2) & !near;
-                    if (accept)
-                        kind = kKindPc;
-                    else if (info.z & kLeafFlag)
-                        kind = near ? kKindNear : kKindFar;
-                    else
-                        kind = kKindOpen;
-                }
+                const uint32_t node = stk.pop();
+                // Lanes without a cell classify cell 0 (always present) and
+                // are then marked idle: the wave issues these instructions
+                // for all lanes anyway, and no default values are needed.
+                const bool live = node != kNone;
+                const uint32_t nd = live ? node : 0u;
+                const double4 lo = f.t.nd_lo[nd], hi = f.t.nd_hi[nd];
+                const double4 cm = f.t.nd_com[nd];
+                const double2 *Sp = reinterpret_cast<const double2 *>(f.t.nd_S) + (int64_t)nd * 3;
+                const double2 s01 = Sp[0], s23 = Sp[1], s45 = Sp[2];
+                const uint4 info = f.t.nd_info[nd];
+                double D2, R2;
+                box_terms(L.g, lo, hi, &D2, &R2);
+                const bool near = D2 < R2;
+                const bool accept = mac_accept(L.g, cm, hi.w, th2) & !near;
+                const int kind = !live ? kKindNone
+                                       : (accept ? kKindPc
+                                                 : ((info.z & kLeafFlag)
+                                                        ? (near ? kKindNear : kKindFar)
+                                                        : kKindOpen));
                 int nc = kind == kKindOpen ? info_nchild(info.z) : 0;
                 if (!stk.push(info.w, nc)) {
                     ok = false;
