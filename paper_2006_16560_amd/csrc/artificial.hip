@@ -13,9 +13,11 @@
 // eq. tt through the generalized inverse of the linear map eq. map, and
 // evaluates the fitted field (and its potential) at the members.
 //
-// Every stage is a one-thread-per-item FP64 kernel: the work is a few
-// hundred flops per pair and bound by HBM latency, far below the cost of
-// the force on the set that sits between make and fit.
+// Every stage is an FP64 kernel with one thread per pair or particle: the
+// work is a few hundred flops per pair and bound by memory, far below the
+// cost of the force on the set that sits between make and fit. The pair
+// blocks are written, and the measure-point accelerations read, through
+// LDS so that consecutive lanes touch consecutive addresses.
 #include <cmath>
 #include <mutex>
 
