@@ -204,9 +204,20 @@ def main() -> int:
         a_ref, p_ref = oracle.force_long(c.pos, c.mass, rin_h, rout_h, idx=sample)
         dt = time.perf_counter() - t1
         pairs = float(sample.size) * (n - 1)
+        model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         cpu = {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
                "sample": "FP64 direct sum (changeover-weighted long-range force + potential) "
-                         "for %d seeded targets x all %d sources, %.1f s" % (sample.size, n, dt)}
+                         "for %d seeded targets x all %d sources, %.1f s" % (sample.size, n, dt),
+               "extrapolated_full_direct_sum_s": float(n) * (n - 1) / (pairs / dt),
+               "cpu_model": model}
         e_tot = np.linalg.norm(acc_mixed - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)
         e64 = np.linalg.norm(acc64 - a_ref, axis=0) / np.linalg.norm(a_ref, axis=0)
         err.update({"p50_vs_oracle": float(np.median(e_tot)),
