@@ -44,15 +44,16 @@ def force_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str, ipl: int):
-    """HBM bytes per force launch from the committed counter summary, if it
-    was taken on the current force-kernel sources (else None)."""
+def profiled_value(workload: str, ipl: int, key: str = "hbm_bytes_per_launch"):
+    """A per-launch figure of the force kernel (HBM bytes, FP32 operations)
+    from the committed counter summary, if it was taken on the current
+    force-kernel sources (else None)."""
     import re
     path = os.path.join(ROOT, "profiles", "k_force_pmc_%s_ipl%d.md" % (workload, ipl))
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    b = re.search(r"^hbm_bytes_per_launch: (\d+)", text, re.M)
+    b = re.search(r"^%s: (\d+)" % key, text, re.M)
     h = re.search(r"^sources_sha256_16: ([0-9a-f]+)", text, re.M)
     if not b or not h or h.group(1) != force_sources_hash():
         return None
@@ -230,6 +231,9 @@ def main() -> int:
     if args.next_rows:
         nxt = bench_next_rows(pt, ctx, c, wl, theta, leaf, group, dev)
 
+    default_shape = (group, leaf, theta) == (64, wl.leaf_size, wl.theta)
+    fp32_ops = (profiled_value(wl.name, ipl, "fp32_flops_per_launch") if default_shape
+                else None)
     line = {
         "metric": "tree-force interactions/s and % FP32 peak at N=1M; p99 force rel. err vs FP64",
         "value": value,
@@ -251,8 +255,9 @@ def main() -> int:
                    "parallelism": "1 gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": (profiled_traffic(wl.name, ipl) if (group, leaf, theta) ==
-                                 (64, wl.leaf_size, wl.theta) else None),
+                     "traffic": (profiled_value(wl.name, ipl) if default_shape else None),
+                     "counter_fp32_tflops": (fp32_ops / (kernel_ms * 1e-3) / 1e12
+                                             if fp32_ops else None),
                      "kernel": "k_force<float, %d>" % ipl,
                      "kernel_ms": kernel_ms,
                      "flops_per_interaction": FLOPS_PER_INTERACTION,
