@@ -164,6 +164,17 @@ PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const do
                               const double *r_out_dev, const double *r_search_dev,
                               double *acc_dev, double *pot_dev, petar_nblist *nb);
 
+/* petar_force_long with the long-range kick of the KDK cycle fused into its
+ * output write (eq. lfmap): additionally vel_dev[3][N] (input order) +=
+ * dt * acc, rounded as v + (a dt) in FP64; dt (the half step) finite.
+ * On PETAR_E_NB_OVERFLOW the kick has been applied with the complete acc:
+ * retry the neighbour lists with petar_force_long, not with this call. */
+PETAR_API petar_status petar_force_long_kick(petar_ctx *ctx, int group_size,
+                                             const double *r_in_dev, const double *r_out_dev,
+                                             const double *r_search_dev, double *acc_dev,
+                                             double *pot_dev, petar_nblist *nb, double *vel_dev,
+                                             double dt);
+
 /* One step -- tree build (petar_tree_build when n_sys == 0, else
  * petar_batch_build with sys_offsets[n_sys + 1] and N = sys_offsets[n_sys])
  * followed by petar_force_long -- executed as a captured hipGraph. The

@@ -25,7 +25,8 @@ __all__ = [
     "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
     "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_batch_build",
     "petar_force_long", "petar_step_graph", "petar_nb_filter", "petar_clusters",
-    "petar_groups", "petar_kick", "petar_artificial_make", "petar_tidal_fit", "petar_tidal_eval",
+    "petar_force_long_kick", "petar_groups", "petar_kick", "petar_artificial_make",
+    "petar_tidal_fit", "petar_tidal_eval",
     "art_points",
     "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
     "PETAR_NO_DEVICE", "lib_path",
@@ -162,13 +163,16 @@ def petar_batch_build(ctx: Context, sys_offsets, pos: torch.Tensor, mass: torch.
 
 def petar_force_long(ctx: Context, group_size: int, r_in: torch.Tensor, r_out: torch.Tensor,
                      r_search: torch.Tensor, acc: Optional[torch.Tensor] = None,
-                     pot: Optional[torch.Tensor] = None, nb_capacity: Optional[int] = None):
+                     pot: Optional[torch.Tensor] = None, nb_capacity: Optional[int] = None,
+                     kick: Optional[tuple] = None):
     """Long-range acceleration (3, N) and potential (N,) in input order.
 
     With nb_capacity (int), also returns the neighbour lists as
     (offsets int64 [N+1], idx int32 [total]). If the capacity is too small a
     PetarError with status PETAR_E_NB_OVERFLOW and `.required` is raised;
-    acc and pot are complete in that case.
+    acc and pot are complete in that case. With kick = (vel, dt), vel
+    (3, N) is kicked in place by dt * acc in the same launch
+    (petar_force_long_kick).
     """
     n = r_in.shape[0]
     dev = ctx.device
@@ -183,13 +187,18 @@ def petar_force_long(ctx: Context, group_size: int, r_in: torch.Tensor, r_out: t
         offsets = torch.empty(n + 1, dtype=torch.int64, device=d)
         idx = torch.empty(max(int(nb_capacity), 1), dtype=torch.int32, device=d)
         nb = _capi.petar_nblist(offsets.data_ptr(), idx.data_ptr(), int(nb_capacity), 0)
-    st = _lib.petar_force_long(ctx.handle, int(group_size),
-                               _dptr(r_in, torch.float64, (n,), "r_in", dev),
-                               _dptr(r_out, torch.float64, (n,), "r_out", dev),
-                               _dptr(r_search, torch.float64, (n,), "r_search", dev),
-                               _dptr(acc, torch.float64, (3, n), "acc", dev),
-                               _dptr(pot, torch.float64, (n,), "pot", dev),
-                               ctypes.byref(nb) if nb is not None else None)
+    args = (ctx.handle, int(group_size), _dptr(r_in, torch.float64, (n,), "r_in", dev),
+            _dptr(r_out, torch.float64, (n,), "r_out", dev),
+            _dptr(r_search, torch.float64, (n,), "r_search", dev),
+            _dptr(acc, torch.float64, (3, n), "acc", dev),
+            _dptr(pot, torch.float64, (n,), "pot", dev),
+            ctypes.byref(nb) if nb is not None else None)
+    if kick is None:
+        st = _lib.petar_force_long(*args)
+    else:
+        vel, dt = kick
+        st = _lib.petar_force_long_kick(*args, _dptr(vel, torch.float64, (3, n), "vel", dev),
+                                        float(dt))
     _check(st, ctx, nb.required if nb is not None else None)
     if nb is None:
         return acc, pot

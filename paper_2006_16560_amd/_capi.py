@@ -78,6 +78,8 @@ SIGNATURES = [
     ("petar_tree_build", _INT, [_P, _P, _P, _I64, _D, _INT]),
     ("petar_batch_build", _INT, [_P, _INT, ctypes.POINTER(_I64), _P, _P, _D, _INT]),
     ("petar_force_long", _INT, [_P, _INT, _P, _P, _P, _P, _P, ctypes.POINTER(petar_nblist)]),
+    ("petar_force_long_kick", _INT, [_P, _INT, _P, _P, _P, _P, _P, ctypes.POINTER(petar_nblist),
+                                     _P, _D]),
     ("petar_step_graph", _INT, [_P, _INT, ctypes.POINTER(_I64), _P, _P, _I64, _D, _INT, _INT,
                                 _P, _P, _P, _P, _P, ctypes.POINTER(petar_nblist)]),
     ("petar_copy_counts", _INT, [_P, _P]),

@@ -770,6 +770,8 @@ struct ForceArgs {
     const double *r_in, *r_out, *r_search;
     double *acc, *pot;
     petar_nblist *nb;
+    double *kick_vel = nullptr;  // fused kick (petar_force_long_kick)
+    double kick_dt = 0.0;
 };
 
 petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
@@ -841,6 +843,8 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     f.nb.count = queue + 16;  // [16] headers, [17] leaf entries (zeroed with the queue)
     f.nb.head_cap = a.nb ? ctx->nbhead_cap : 0;
     f.nb.leaf_cap = a.nb ? ctx->nbleaf_cap : 0;
+    f.kick_vel = a.kick_vel;
+    f.kick_dt = a.kick_dt;
     f.precision = prec;
     f.ipl = ipl;
     if (timed) (void)hipEventRecord(ctx->ev[4], s);
@@ -953,6 +957,23 @@ petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in
     if (!ctx->have_tree) return fail(ctx, PETAR_E_STATE, "petar_tree_build has not succeeded");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ForceArgs a{group_size, r_in, r_out, r_search, acc, pot, nb};
+    TRY(alloc_force(ctx, a));
+    enqueue_force(ctx, a, ctx->stream, true);
+    return finish_force(ctx, a, ctx->stream, true);
+}
+
+petar_status petar_force_long_kick(petar_ctx *ctx, int group_size, const double *r_in,
+                                   const double *r_out, const double *r_search, double *acc,
+                                   double *pot, petar_nblist *nb, double *vel, double dt) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_force_args(group_size, r_in, r_out, r_search, acc, pot, nb))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (!vel) return fail(ctx, PETAR_E_INVALID, "vel must not be NULL");
+    if (!std::isfinite(dt)) return fail(ctx, PETAR_E_INVALID, "dt must be finite");
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    if (!ctx->have_tree) return fail(ctx, PETAR_E_STATE, "petar_tree_build has not succeeded");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ForceArgs a{group_size, r_in, r_out, r_search, acc, pot, nb, vel, dt};
     TRY(alloc_force(ctx, a));
     enqueue_force(ctx, a, ctx->stream, true);
     return finish_force(ctx, a, ctx->stream, true);

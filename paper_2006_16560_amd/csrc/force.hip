@@ -481,6 +481,16 @@ __device__ void combine_split(WaveLds<R> &L, Targets<R, IPL> &T, const Layout &l
 
 enum { kKindNone = 0, kKindPc = 1, kKindFar = 2, kKindNear = 3, kKindOpen = 4 };
 
+// Long-range kick fused into the output write (eq. lfmap: v += a_L dt with
+// dt the half step), v + a dt rounded twice as written.
+__device__ __forceinline__ void kick_write(double *vel, int64_t n, uint32_t o, double ax,
+                                           double ay, double az, double dt) {
+#pragma clang fp contract(off)
+    vel[o] = vel[o] + ax * dt;
+    vel[n + o] = vel[n + o] + ay * dt;
+    vel[2 * n + o] = vel[2 * n + o] + az * dt;
+}
+
 template <typename R, int IPL>
 __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
     __shared__ WaveLds<R> lds_all[kWavesPerBlock];
@@ -637,10 +647,13 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
             for (int u = 0; u < IPL; u++) {
                 if (T.k[u] == kNone || ly.sl != 0) continue;
                 uint32_t o = f.t.orig[T.k[u]];
-                f.acc[o] = f.G * T.acc[u].get(0);
-                f.acc[n + o] = f.G * T.acc[u].get(1);
-                f.acc[2 * n + o] = f.G * T.acc[u].get(2);
+                const double ax = f.G * T.acc[u].get(0), ay = f.G * T.acc[u].get(1),
+                             az = f.G * T.acc[u].get(2);
+                f.acc[o] = ax;
+                f.acc[n + o] = ay;
+                f.acc[2 * n + o] = az;
                 f.pot[o] = f.G * T.acc[u].get(3);
+                if (f.kick_vel) kick_write(f.kick_vel, n, o, ax, ay, az, f.kick_dt);
                 if (f.counts) {
                     f.counts[o] = (int32_t)n_pc;
                     f.counts[n + o] = (int32_t)n_far;

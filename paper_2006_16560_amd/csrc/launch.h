@@ -121,6 +121,8 @@ struct ForceLaunch {
     uint32_t *queue;           // 8 work-queue heads
     int32_t *counts;           // optional per-particle counts [4][n]
     NbRecords nb;              // near-leaf lists for the neighbour passes (head null: none)
+    double *kick_vel;          // optional [3][n]: vel += kick_dt * acc with the output write
+    double kick_dt;
     int precision;             // 0 mixed, 1 fp64
     int ipl;                   // 1, 2, 4
 };

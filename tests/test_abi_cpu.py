@@ -424,3 +424,20 @@ def test_kick_validation(capi, ctx, case):
         a[case] = None
     st = lib.petar_kick(ctx, a["n"], a["vel"], a["acc"], a["dt"])
     assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)
+
+
+@pytest.mark.parametrize("case", ["ok", "vel", "dtinf", "group0", "acc"])
+def test_force_long_kick_validation(capi, ctx, case):
+    _capi, lib = capi
+    a = dict(group=64, vel=FAKE, dt=1e-3, acc=FAKE)
+    if case == "vel":
+        a["vel"] = None
+    elif case == "dtinf":
+        a["dt"] = float("inf")
+    elif case == "group0":
+        a["group"] = 0
+    elif case == "acc":
+        a["acc"] = None
+    st = lib.petar_force_long_kick(ctx, a["group"], FAKE, FAKE, FAKE, a["acc"], FAKE, None,
+                                   a["vel"], a["dt"])
+    assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)

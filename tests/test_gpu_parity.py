@@ -947,3 +947,26 @@ def test_plummer1m_groups_artificial_kick(pt, ctx, orc, cluster1m):
         got = _scaled(ten64[b:b + 1], o["frame"][b:b + 1], order)[0, 1:]
         want = _scaled(np.concatenate([[0.0], t])[None, :], o["frame"][b:b + 1], order)[0, 1:]
         assert np.abs(got - want).max() <= 12.7 * 1e-10 * np.linalg.norm(t[:3]), b
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_force_long_kick_fused(pt, ctx, orc, prec):
+    """The kick fused into the force launch leaves acc, pot and the
+    neighbour lists bitwise as petar_force_long gives them and kicks the
+    velocities by exactly v + a dt."""
+    c, rin, rout, rs = cluster_with_radii(orc, 20000, 71, bf=0.5)
+    p = pt.PETAR_MIXED if prec == "mixed" else pt.PETAR_FP64
+    pt.petar_set_params(ctx, precision=p, i_per_lane=2, record_counts=0)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 8)
+    a0, p0, (o0, i0) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=64 * 20000)
+    vel = T(c.vel)
+    dt = 0.5 * 2.0 ** -10
+    a1, p1, (o1, i1) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs),
+                                           nb_capacity=64 * 20000, kick=(vel, dt))
+    torch.cuda.synchronize()
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    a0, a1 = a0.cpu().numpy(), a1.cpu().numpy()
+    assert np.array_equal(a0, a1) and np.array_equal(p0.cpu().numpy(), p1.cpu().numpy())
+    assert np.array_equal(o0.cpu().numpy(), o1.cpu().numpy())
+    assert np.array_equal(i0.cpu().numpy(), i1.cpu().numpy())
+    assert np.array_equal(vel.cpu().numpy(), c.vel + a1 * dt)
