@@ -970,3 +970,32 @@ def test_force_long_kick_fused(pt, ctx, orc, prec):
     assert np.array_equal(o0.cpu().numpy(), o1.cpu().numpy())
     assert np.array_equal(i0.cpu().numpy(), i1.cpu().numpy())
     assert np.array_equal(vel.cpu().numpy(), c.vel + a1 * dt)
+
+
+def test_groups_edge_cases(pt, ctx, orc):
+    """No candidates (every particle alone, no binaries); a close pair that
+    is unbound is a group but no binary; a chain of three is one group and
+    no binary; an index outside [0, N) is an error."""
+    d = "cuda:0"
+    n = 6
+    pos = np.array([[0.0, 0.001, 1.0, 1.0009, 1.0018, 5.0], [0.0] * 6, [0.0] * 6])
+    vel = np.zeros((3, n))
+    vel[1, 1] = 1e3  # the pair at x = 0 flies apart
+    mass = np.full(n, 0.1)
+    rin = np.full(n, 0.004)
+    empty_o = torch.zeros(n + 1, dtype=torch.int64, device=d)
+    empty_i = torch.zeros(0, dtype=torch.int32, device=d)
+    label, go, members, pairs = pt.petar_groups(ctx, T(pos), T(vel), T(mass), T(rin), 0.5,
+                                                empty_o, empty_i)
+    assert np.array_equal(label.cpu().numpy(), np.arange(n)) and pairs.shape[1] == 0
+    assert go.numel() == n + 1
+    o_ref, i_ref = orc.neighbours(pos, np.full(n, 0.01))
+    label, go, members, pairs = pt.petar_groups(ctx, T(pos), T(vel), T(mass), T(rin), 0.5,
+                                                T(o_ref), T(i_ref))
+    l_ref, g_ref, m_ref, p_ref = orc.groups(pos, vel, mass, rin, 0.5)
+    assert np.array_equal(label.cpu().numpy(), l_ref) and list(l_ref) == [0, 0, 2, 2, 2, 5]
+    assert pairs.shape[1] == 0 and len(p_ref) == 0
+    bad_i = T(np.array([7], dtype=np.int32))
+    bad_o = T(np.array([0, 1, 1, 1, 1, 1, 1], dtype=np.int64))
+    with pytest.raises(pt.PetarError):
+        pt.petar_groups(ctx, T(pos), T(vel), T(mass), T(rin), 0.5, bad_o, bad_i)
