@@ -343,7 +343,9 @@ def petar_artificial_make(ctx: Context, pos: torch.Tensor, vel: torch.Tensor, ma
     n = mass.shape[0]
     dev = ctx.device
     d = "cuda:%d" % dev
-    n_pair = pairs.shape[1] if pairs.dim() == 2 else 0
+    if pairs.dim() != 2 or pairs.shape[0] != 2:
+        raise ValueError("pairs must have shape (2, n_pair)")
+    n_pair = pairs.shape[1]
     n_out = n + n_pair * (art_points(order) + 2)
     out = dict(pos=torch.empty((3, n_out), dtype=torch.float64, device=d),
                mass=torch.empty(n_out, dtype=torch.float64, device=d),
