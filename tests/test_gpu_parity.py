@@ -10,6 +10,8 @@ Bars (see the module docstrings of oracle/ and the design notes):
   * neighbour lists: bit-exact CSR against brute force.
 """
 
+import math
+
 import numpy as np
 import pytest
 
@@ -1003,3 +1005,37 @@ def test_groups_edge_cases(pt, ctx, orc):
     bad_o = T(np.array([0, 1, 1, 1, 1, 1, 1], dtype=np.int64))
     with pytest.raises(pt.PetarError):
         pt.petar_groups(ctx, T(pos), T(vel), T(mass), T(rin), 0.5, bad_o, bad_i)
+
+
+def test_neighbours_at_the_search_radius(pt, ctx, orc):
+    """Pairs placed within a few ulp of max(r_s,i, r_s,j), along axes, along
+    diagonals and in random directions, with equal and unequal search radii:
+    the GPU lists equal the oracle's brute force bit for bit (both take the
+    decision in FP64 without contraction, in the same order)."""
+    rng = np.random.default_rng(81)
+    pos, rs = [], []
+    dirs = [np.array([1.0, 0, 0]), np.array([0, 1.0, 0]), np.array([0, 0, 1.0]),
+            np.array([1.0, 1.0, 0]) / math.sqrt(2), np.array([1.0, 1.0, 1.0]) / math.sqrt(3)]
+    dirs += [v / np.linalg.norm(v) for v in rng.normal(size=(5, 3))]
+    k = 0
+    for R in (0.0625, 0.1, 0.0137):
+        for u in dirs:
+            for m in (-3, -1, 0, 1, 3):
+                for other in (R, 0.5 * R):  # the partner's own radius: equal or smaller
+                    base = np.array([k % 20, (k // 20) % 20, k // 400], dtype=np.float64) * 4 * R
+                    base += rng.uniform(0, 0.5, 3)
+                    d = R * (1.0 + m * 2.0 ** -52)
+                    pos += [base, base + d * u]
+                    rs += [R, other]
+                    k += 1
+    pos = np.ascontiguousarray(np.array(pos).T)
+    rs = np.array(rs)
+    n = rs.size
+    mass = np.full(n, 1.0 / n)
+    rin, rout = 0.1 * rs, 0.5 * rs
+    for theta, leaf in ((0.5, 8), (0.0, 1)):
+        _, _, (offs, idx) = run(pt, ctx, pos, mass, rin, rout, rs, theta, leaf, 64, pt.PETAR_MIXED,
+                                nb_cap=64 * n)
+        o_ref, i_ref = orc.neighbours(pos, rs)
+        assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref), theta
+    assert 0 < i_ref.size < 2 * n  # some borderline pairs are in, some are out
