@@ -1039,3 +1039,42 @@ def test_neighbours_at_the_search_radius(pt, ctx, orc):
         o_ref, i_ref = orc.neighbours(pos, rs)
         assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref), theta
     assert 0 < i_ref.size < 2 * n  # some borderline pairs are in, some are out
+
+
+def test_error_falls_with_theta(pt, ctx, orc):
+    """FP64 mode against the direct sum: the median force error falls
+    monotonically as the opening angle closes (0.7 -> 0.1), and theta = 0
+    is the direct sum."""
+    c, rin, rout, rs = cluster_with_radii(orc, 4096, 91, bf=0.3)
+    a_dir, _ = orc.force_long(c.pos, c.mass, rin, rout)
+    med = []
+    for theta in (0.7, 0.5, 0.3, 0.1, 0.0):
+        a, _ = run(pt, ctx, c.pos, c.mass, rin, rout, rs, theta, 8, 64, pt.PETAR_FP64)
+        med.append(float(np.median(rel_err(a, a_dir))))
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    assert all(x > y for x, y in zip(med, med[1:])), med
+    assert med[-1] < 1e-13
+
+
+def test_multipole_error_law(pt, ctx, orc):
+    """One clump of size l seen from a zero-mass target at distance d through
+    a single multipole cell: the FP64 GPU force against the direct Newtonian
+    sum (all pairs far outside r_out) falls as (l/d)^3, the first order the
+    quadrupole leaves out."""
+    rng = np.random.default_rng(92)
+    clump = rng.uniform(-0.5, 0.5, (3, 8)) * 0.01
+    errs = []
+    for d in (0.1, 0.2, 0.4):
+        tgt = np.array([[d], [0.3 * d], [0.2 * d]])
+        pos = np.concatenate([clump, tgt], axis=1)
+        mass = np.concatenate([rng.uniform(0.5, 1.5, 8), [0.0]])
+        r = np.full(9, 1e-6)
+        # leaf 8: the clump is one leaf cell; theta 1 accepts it from the target
+        a, _, cnt = run(pt, ctx, pos, mass, 0.5 * r, r, r, 1.0, 8, 1, pt.PETAR_FP64,
+                        counts=True)
+        assert cnt[0, 8] == 1 and cnt[1, 8] == 0 and cnt[2, 8] == 1  # one PC, itself near
+        a_ref, _ = orc.force_newton(pos, mass, idx=[8])
+        errs.append(np.linalg.norm(a[:, 8] - a_ref[:, 0]) / np.linalg.norm(a_ref[:, 0]))
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 5.0 < e1 / e2 < 12.0, errs
