@@ -1078,3 +1078,28 @@ def test_multipole_error_law(pt, ctx, orc):
     pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
     for e1, e2 in zip(errs, errs[1:]):
         assert 5.0 < e1 / e2 < 12.0, errs
+
+
+def test_every_particle_in_one_group(pt, ctx, orc):
+    """Structure: every particle is written (outputs prefilled with NaN),
+    belongs to exactly one i-group (the per-particle group sizes add up to
+    the number of groups) and sees every other particle once (the three
+    interaction counts of a target at theta = 0 sum to N)."""
+    d = "cuda:0"
+    c, rin, rout, rs = cluster_with_radii(orc, 20000, 93, bf=0.5)
+    n = c.mass.size
+    for theta in (0.5, 0.0):
+        pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=2, record_counts=1)
+        pt.petar_tree_build(ctx, T(c.pos), T(c.mass), theta, 8)
+        acc = torch.full((3, n), float("nan"), dtype=torch.float64, device=d)
+        pot = torch.full((n,), float("nan"), dtype=torch.float64, device=d)
+        pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), acc=acc, pot=pot)
+        cnt = pt.petar_copy_counts(ctx).cpu().numpy().astype(np.int64)
+        st = pt.petar_get_stats(ctx)
+        assert torch.isfinite(acc).all().item() and torch.isfinite(pot).all().item()
+        g = cnt[3]
+        assert np.all(g >= 1) and np.all(g <= 64)
+        assert abs((1.0 / g).sum() - st["n_groups"]) < 1e-6
+        if theta == 0.0:
+            assert np.all(cnt[0] == 0) and np.all(cnt[1] + cnt[2] == n)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, record_counts=0)
