@@ -28,6 +28,11 @@ thread_local std::string g_last_error;
 
 }  // namespace
 
+// host_scalar: words [0, kHostDeep) for single values, then the kDeepWords
+// 32-bit deepest-level words of the build.
+constexpr int kHostDeep = 8;
+constexpr int kHostScalarWords = kHostDeep + kDeepWords / 2;
+
 struct petar_ctx {
     int device = PETAR_NO_DEVICE;
     hipStream_t stream = nullptr;
@@ -60,6 +65,7 @@ struct petar_ctx {
     int leaf_size = 0;
     int64_t n_nodes = 0;
     int levels = kMaxLevel;
+    int deep = kMaxLevel;  // deepest cell level: the per-level passes start above it
     int n_sys = 1;
 
     int force_waves[2][5] = {{0}};
@@ -266,7 +272,7 @@ petar_status petar_create(petar_ctx **out, int device, void *hip_stream) {
         }
         hipError_t e = hipSetDevice(device);
         if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_status, sizeof(Status));
-        if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_scalar, 4 * sizeof(int64_t));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_scalar, kHostScalarWords * sizeof(int64_t));
         for (int k = 0; k < 8 && e == hipSuccess; k++) e = hipEventCreate(&c->ev[k]);
         if (e != hipSuccess) {
             petar_destroy(c);
@@ -629,7 +635,7 @@ petar_status alloc_build_a(petar_ctx *ctx, const BuildArgs &a) {
     TRY(ensure(ctx, ctx->bbox_part, (size_t)bbox_partial_blocks(a.n) * 6 * 8));
     TRY(ensure(ctx, ctx->rootbox, sizeof(RootBox) * (size_t)n_boxes));
     TRY(ensure(ctx, ctx->status, sizeof(Status)));
-    TRY(ensure(ctx, ctx->emit, N * 4));
+    TRY(ensure(ctx, ctx->emit, (N + kDeepWords) * 4));  // + the deepest-level words
     TRY(ensure(ctx, ctx->base, (N + 1) * 8));
     TRY(ensure(ctx, ctx->ps, N * sizeof(double4)));
     TRY(ensure(ctx, ctx->orig, N * 4));
@@ -682,14 +688,19 @@ void enqueue_build_a(petar_ctx *ctx, const BuildArgs &a, hipStream_t s) {
     radix_sort(&k, &v, &ka, &va, a.n, 8, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s);
     launch_gather_particles(a.pos, a.mass, v, a.n, ptr<double4>(ctx->ps), ptr<uint32_t>(ctx->orig),
                             ptr<uint32_t>(ctx->rank), s);
-    launch_octree_count(k, a.n, a.leaf_size, levels, ptr<uint32_t>(ctx->emit), s);
+    uint32_t *deep_slots = ptr<uint32_t>(ctx->emit) + a.n;
+    fill_u32(deep_slots, 0, kDeepWords, s);
+    launch_octree_count(k, a.n, a.leaf_size, levels, ptr<uint32_t>(ctx->emit), deep_slots, s);
     scan_u32_to_i64(ptr<uint32_t>(ctx->emit), ptr<int64_t>(ctx->base), a.n,
                     ptr<int64_t>(ctx->scan_ws), s);
 }
 
 // Phase B with cell arrays of node_cap entries (the cell count is read on the
-// device; more cells than node_cap raise Status::cell_overflow).
-void enqueue_build_b(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap, hipStream_t s) {
+// device; more cells than node_cap raise Status::cell_overflow). The
+// bottom-up passes launch levels deep-1 .. 0 (no cell deeper than deep has
+// children).
+void enqueue_build_b(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap, int deep,
+                     hipStream_t s) {
     const int levels = a.n_sys > 0 ? kBatchLevels : kMaxLevel;
     TreeDev t = tree_view(ctx);
     t.n_nodes = node_cap;
@@ -705,14 +716,15 @@ void enqueue_build_b(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap, hipSt
                t.n_nodes_dev);
     launch_relayout(lv, pre, ptr<RootBox>(ctx->rootbox), k, levels, t,
                     ptr<uint32_t>(ctx->level_off), s);
-    launch_moments(t, levels, s);
+    launch_moments(t, deep, s);
     launch_tree_summary(t, st, s);
 }
 
-void set_tree_state(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap) {
+void set_tree_state(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap, int deep) {
     ctx->n = a.n;
     ctx->n_nodes = node_cap;
     ctx->levels = a.n_sys > 0 ? kBatchLevels : kMaxLevel;
+    ctx->deep = deep;
     ctx->theta = a.theta;
     ctx->leaf_size = a.leaf_size;
     ctx->n_sys = a.n_sys > 0 ? a.n_sys : 1;
@@ -740,6 +752,8 @@ petar_status build_eager(petar_ctx *ctx, const BuildArgs &a) {
                                 hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, &ptr<RootBox>(ctx->rootbox)->bad, 4,
                                 hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + kHostDeep, ptr<uint32_t>(ctx->emit) + a.n,
+                                kDeepWords * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     int32_t bad = 0;
     memcpy(&bad, ctx->host_scalar + 1, 4);
@@ -747,12 +761,21 @@ petar_status build_eager(petar_ctx *ctx, const BuildArgs &a) {
     const int64_t n_nodes = ctx->host_scalar[0];
     if (n_nodes < 1 || n_nodes >= (int64_t)kNone)
         return fail(ctx, PETAR_E_INTERNAL, "cell count %lld out of range", (long long)n_nodes);
+    const int levels = a.n_sys > 0 ? kBatchLevels : kMaxLevel;
+    uint32_t deep = 0;
+    for (int w = 0; w < kDeepSlots; w++) {
+        uint32_t v;
+        memcpy(&v, (const char *)(ctx->host_scalar + kHostDeep) + 4 * (w * kDeepStride), 4);
+        deep = v > deep ? v : deep;
+    }
+    if (deep > (uint32_t)levels)
+        return fail(ctx, PETAR_E_INTERNAL, "deepest cell level %lld out of range", (long long)deep);
     TRY(alloc_build_b(ctx, n_nodes));
-    enqueue_build_b(ctx, a, n_nodes, s);
+    enqueue_build_b(ctx, a, n_nodes, (int)deep, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
     TRY(read_status(ctx, s));
-    set_tree_state(ctx, a, n_nodes);
+    set_tree_state(ctx, a, n_nodes, (int)deep);
     ctx->have_tree = true;
     ctx->stats = petar_stats{};
     ctx->stats.n = a.n;
@@ -819,7 +842,7 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     zero_force_status(ctx, s);
     fill_u32(queue, 0, 64, s);
     launch_gather_radii(a.r_in, a.r_out, a.r_search, t, st, s);
-    launch_rsmax(t, ctx->levels, s);
+    launch_rsmax(t, ctx->deep, s);
     launch_group_flags(pre, t, a.group_size, ptr<uint32_t>(ctx->gflag), s);
     scan_u32_to_u32(ptr<uint32_t>(ctx->gflag), ptr<uint32_t>(ctx->gpos), n_nodes,
                     ptr<int64_t>(ctx->scan_ws), s);
@@ -1040,8 +1063,10 @@ petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offs
         // recorded by captured nodes, so a replay is timed as a whole)
         HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         enqueue_build_a(ctx, ba, cs);
-        enqueue_build_b(ctx, ba, node_cap, cs);
-        set_tree_state(ctx, ba, node_cap);
+        // a replay's tree may be deeper than this one: every level is launched
+        const int all_levels = ba.n_sys > 0 ? kBatchLevels : kMaxLevel;
+        enqueue_build_b(ctx, ba, node_cap, all_levels, cs);
+        set_tree_state(ctx, ba, node_cap, all_levels);
         enqueue_force(ctx, fa, cs, false);
         hipError_t e = hipStreamEndCapture(cs, &ctx->graph);
         if (e == hipSuccess) e = hipGetLastError();  // launches inside the capture
@@ -1059,7 +1084,7 @@ petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offs
     }
     // replay
     hipStream_t s = ctx->stream;
-    set_tree_state(ctx, ba, ctx->node_cap);
+    set_tree_state(ctx, ba, ctx->node_cap, ba.n_sys > 0 ? kBatchLevels : kMaxLevel);
     ctx->have_tree = false;
     HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
     HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, s));

@@ -66,8 +66,13 @@ void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **v
 void launch_gather_particles(const double *pos, const double *mass, const uint32_t *idx,
                              int64_t n, double4 *ps, uint32_t *orig, uint32_t *rank,
                              hipStream_t s);
+// Also the deepest cell level: the maximum of deep_slots[w * kDeepStride],
+// w < kDeepSlots (kDeepWords words, zeroed by the caller), after the kernel.
+constexpr int kDeepSlots = 32;
+constexpr int kDeepStride = 32;  // 128 B
+constexpr int kDeepWords = kDeepSlots * kDeepStride;
 void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int levels,
-                         uint32_t *emit, hipStream_t s);
+                         uint32_t *emit, uint32_t *deep_slots, hipStream_t s);
 // Pre-order cells; also the level keys (lkey, lval) sorted next.
 // Cells beyond node_cap are not written; st->cell_overflow is raised instead.
 void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int levels,

@@ -160,26 +160,48 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
 
 // Neighbour passes over the near leaves handed over by the force walk. A
 // wave takes one header at a time: the group's targets sit in the lanes
-// (FP64 position and search radius in registers; a group of g < 64 targets
-// puts each target on 64/g lanes that split the source loop), the leaves'
-// particles are staged in LDS 64 at a time with one load per lane, and every
-// lane tests its target against its share of the staged particles (LDS
-// broadcasts). Counting adds a lane's hits once per header; writing takes a
-// slot per hit from a per-target cursor (the lists are sorted afterwards, so
-// the slot order is irrelevant).
+// (FP64 position and squared search radius in registers; a group of g < 64
+// targets puts each target on 64/g lanes that split the source loop), the
+// leaves' particles are staged in LDS 64 at a time with one load per lane
+// (the next batch is loaded into registers while the current one is
+// tested), and every lane tests its target against its share of the staged
+// particles (LDS broadcasts). Counting adds a lane's hits once per header;
+// writing collects a lane's hits in LDS and takes kHitBuf slots at a time
+// from a per-target cursor (the lists are sorted afterwards, so the slot
+// order is irrelevant).
+constexpr int kHitBuf = 8;
+
+template <bool kWrite>
 struct NbRecLds {
     uint32_t start[kWave], pre[kWave];
-    double4 jp[2][kWave];  // x, y, z, r_search; two batches (the next is
-    uint32_t jk[2][kWave]; // gathered while the current one is tested)
+    double4 jp[kWave];  // x, y, z, r_search^2 of the staged batch
+    uint32_t jk[kWave];
+    uint32_t hit[kWrite ? kHitBuf : 1][kWave];  // a lane's hits not yet written
 };
+
+// The pair relation of common.h with the squares of the search radii:
+// for non-negative radii, rounding is monotone, so the rounded square of
+// max(rs_i, rs_j) is the larger of the two rounded squares and
+// d2 < fl(max^2) holds iff d2 < fl(rs_i^2) or d2 < fl(rs_j^2).
+// (Two compares: d2 passes through an empty asm between them, which keeps
+// the compiler from folding them into a max that would need a
+// canonicalisation of pj.w.)
+__device__ __forceinline__ bool nb_pair_sq(const double4 &pi, double rsi2, const double4 &pj) {
+#pragma clang fp contract(off)
+    double rj2 = pj.w;
+    double d2 = sum_sq3(pj.x - pi.x, pj.y - pi.y, pj.z - pi.z);
+    const bool near_i = d2 < rsi2;
+    asm volatile("" : "+v"(d2), "+v"(rj2));
+    return near_i | (d2 < rj2);
+}
 
 template <bool kWrite>
 __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, const Status *st,
                                                      uint32_t *cnt_orig, const int64_t *offsets,
                                                      uint32_t *cursor, int32_t *idx,
                                                      int64_t capacity) {
-    __shared__ NbRecLds lds_all[kWavesPerBlock];
-    NbRecLds &L = lds_all[threadIdx.x / kWave];
+    __shared__ NbRecLds<kWrite> lds_all[kWavesPerBlock];
+    NbRecLds<kWrite> &L = lds_all[uniform((int)(threadIdx.x / kWave))];
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
     if (kWrite && offsets[t.n] > capacity) return;
     const uint32_t nrec = rec.count[0];
@@ -210,9 +232,10 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             const uint32_t ki = gfirst + a0 + (uint32_t)a;
             const double4 pi = t.ps[ki];
             const double rsi = t.rsk[ki];
+            const double rsi2 = rsi * rsi;
             const uint32_t oi = t.orig[ki];
             uint32_t c = 0;
-            // gather of one batch of 64 sources into registers (lane = source)
+            // one batch of 64 sources into registers (lane = source)
             double4 pn = make_double4(0.0, 0.0, 0.0, 0.0);
             uint32_t kn = 0;
             auto gather = [&](uint32_t base) {
@@ -221,37 +244,56 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
                     const int l = find_leaf(L.pre, nleaf, sidx);
                     kn = L.start[l] + (sidx - L.pre[l]);
                     const double4 p = t.ps[kn];
-                    pn = make_double4(p.x, p.y, p.z, t.rsk[kn]);
+                    const double rs = t.rsk[kn];
+                    pn = make_double4(p.x, p.y, p.z, rs * rs);
+                }
+            };
+            // write pass: this lane's buffered hits into its target's list
+            auto flush = [&]() {
+                const int64_t w0 = offsets[oi] + (int64_t)atomicAdd(&cursor[oi], c);
+                for (uint32_t h = 0; h < c; h++) idx[w0 + h] = (int32_t)t.orig[L.hit[h][lane]];
+                c = 0;
+            };
+            // the staged source at byte p of L.jp
+            const char *jbase = (const char *)L.jp;
+            auto test = [&](const char *p) {
+                if (nb_pair_sq(pi, rsi2, *(const double4 *)p)) {
+                    const uint32_t kj = L.jk[(uint32_t)(p - jbase) >> 5];
+                    if (kj != ki) {
+                        if constexpr (kWrite) {
+                            if (c == (uint32_t)kHitBuf) flush();
+                            L.hit[c][lane] = kj;
+                        }
+                        c++;
+                    }
                 }
             };
             gather(0);
-            int buf = 0;
-            for (uint32_t base = 0; base < total; base += kWave, buf ^= 1) {
+            for (uint32_t base = 0; base < total; base += kWave) {
+                wave_sync();  // the previous batch has been read
                 if (base + lane < total) {
-                    L.jp[buf][lane] = pn;
-                    L.jk[buf][lane] = kn;
+                    L.jp[lane] = pn;
+                    L.jk[lane] = kn;
                 }
                 wave_sync();
                 if (base + kWave < total) gather(base + kWave);
                 const int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
                 if (act) {
-                    for (int j = sl; j < m; j += S) {
-                        const double4 pj = L.jp[buf][j];
-                        if (nb_pair(pi.x, pi.y, pi.z, rsi, pj.x, pj.y, pj.z, pj.w)) {
-                            const uint32_t kj = L.jk[buf][j];
-                            if (kj == ki) continue;
-                            if (kWrite) {
-                                const uint32_t slot = atomicAdd(&cursor[oi], 1u);
-                                idx[offsets[oi] + slot] = (int32_t)t.orig[kj];
-                            } else {
-                                c++;
-                            }
-                        }
+                    const int step = S * 32;
+                    const char *p = jbase + sl * 32, *pend = jbase + m * 32;
+                    for (; p + step < pend; p += 2 * step) {
+                        test(p);
+                        test(p + step);
                     }
+                    if (p < pend) test(p);
                 }
             }
+            if constexpr (kWrite) {
+                if (c) flush();
+            } else {
+                if (c) atomicAdd(&cnt_orig[oi], c);
+            }
             wave_sync();
-            if (!kWrite && c) atomicAdd(&cnt_orig[oi], c);
         }
     }
 }

@@ -402,16 +402,34 @@ __device__ __forceinline__ int chain_last(const uint64_t *key, int64_t n, int64_
     return last < levels ? last : levels;
 }
 
+// Also the deepest cell level: each block's maximum goes into one of
+// kDeepSlots words kDeepStride apart (atomicMax; spreading the blocks over
+// words in different cache lines keeps them from queueing on one line); the
+// host takes the maximum of the words with the cell count and launches the
+// per-level passes only down to that level.
 __global__ __launch_bounds__(kThreads) void k_octree_count(const uint64_t *key, int64_t n,
                                                            int leaf_size, int levels,
-                                                           uint32_t *emit) {
+                                                           uint32_t *emit, uint32_t *deep_slots) {
+    __shared__ int wmax[kThreads / kWave];
+    int deepest = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int l0 = first_level(key, k, levels);
         uint32_t cnt = 0;
-        if (l0 <= levels && (l0 == 0 || parent_big(key, n, k, l0 - 1, leaf_size, levels)))
-            cnt = (uint32_t)(chain_last(key, n, k, l0, leaf_size, levels) - l0 + 1);
+        if (l0 <= levels && (l0 == 0 || parent_big(key, n, k, l0 - 1, leaf_size, levels))) {
+            const int last = chain_last(key, n, k, l0, leaf_size, levels);
+            cnt = (uint32_t)(last - l0 + 1);
+            deepest = last > deepest ? last : deepest;
+        }
         emit[k] = cnt;
+    }
+    deepest = (int)wave_max((double)deepest);
+    if (lane_id() == 0) wmax[threadIdx.x / kWave] = deepest;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int w = 0; w < kThreads / kWave; w++) m = wmax[w] > m ? wmax[w] : m;
+        if (m > 0) atomicMax(&deep_slots[(blockIdx.x % kDeepSlots) * kDeepStride], (uint32_t)m);
     }
 }
 
@@ -841,9 +859,9 @@ void launch_gather_particles(const double *pos, const double *mass, const uint32
 }
 
 void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int levels,
-                         uint32_t *emit, hipStream_t s) {
+                         uint32_t *emit, uint32_t *deep_slots, hipStream_t s) {
     hipLaunchKernelGGL(k_octree_count, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
-                       levels, emit);
+                       levels, emit, deep_slots);
 }
 
 void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int levels,
