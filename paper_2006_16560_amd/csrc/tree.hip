@@ -207,9 +207,10 @@ __global__ __launch_bounds__(kThreads) void k_keys_systems(const double *pos, in
 
 // ------------------------------------------------------------- radix sort
 // LSD, 8-bit digits, 8 passes. Per pass: tile histograms, one exclusive scan
-// over (digit, tile), and a stable scatter that ranks equal digits inside a
-// tile with wave ballots and reorders the tile through LDS so that the
-// global writes are contiguous runs per digit.
+// per digit over the tiles (a block per digit, which also gives the digit's
+// total), and a stable scatter that scans the 256 digit totals itself, ranks
+// equal digits inside a tile with wave ballots and reorders the tile through
+// LDS so that the global writes are contiguous runs per digit.
 constexpr int kSortRounds = 8;
 constexpr int kSortTile = kThreads * kSortRounds;  // 2048 keys
 constexpr int kRadix = 256;
@@ -230,34 +231,84 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(const uint64_t *key, int
     hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Block d: exclusive prefix of digit d's tile counts over the tiles, and the
+// digit's total.
+constexpr int kRowPer = 4;  // counts per thread and chunk
+__global__ __launch_bounds__(kThreads) void k_sort_rowscan(const uint32_t *hist, int64_t ntiles,
+                                                           uint32_t *offs, uint32_t *dtot) {
+    __shared__ uint32_t wsum[kThreads / kWave];
+    const int t = threadIdx.x, w = t / kWave;
+    const uint32_t *row = hist + (int64_t)blockIdx.x * ntiles;
+    uint32_t *orow = offs + (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < ntiles; c0 += (int64_t)kThreads * kRowPer) {
+        uint32_t v[kRowPer], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kRowPer; q++) {
+            const int64_t i = c0 + (int64_t)t * kRowPer + q;
+            v[q] = i < ntiles ? row[i] : 0u;
+            sum += v[q];
+        }
+        const uint32_t incl = wave_incl_scan(sum);
+        if (lane_id() == kWave - 1) wsum[w] = incl;
+        __syncthreads();
+        uint32_t off = carry, tot = 0;
+        for (int k = 0; k < kThreads / kWave; k++) {
+            if (k < w) off += wsum[k];
+            tot += wsum[k];
+        }
+        off += incl - sum;
+#pragma unroll
+        for (int q = 0; q < kRowPer; q++) {
+            const int64_t i = c0 + (int64_t)t * kRowPer + q;
+            if (i < ntiles) orow[i] = off;
+            off += v[q];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) dtot[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_in,
                                                            const uint32_t *val_in,
                                                            uint64_t *key_out, uint32_t *val_out,
                                                            int64_t n, int shift,
                                                            const uint32_t *hist,
-                                                           const uint32_t *offs, int64_t ntiles,
+                                                           const uint32_t *offs,
+                                                           const uint32_t *dtot, int64_t ntiles,
                                                            const int64_t *n_dev) {
     if (n_dev) n = *n_dev;
     __shared__ uint64_t sk[kSortTile];
     __shared__ uint32_t sv[kSortTile];
     __shared__ uint32_t tile_start[kRadix];
     __shared__ uint32_t digit_base[kRadix];
+    __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t wave_cnt[kThreads / kWave][kRadix];
-    __shared__ uint32_t wsum[kThreads / kWave];
+    __shared__ uint32_t wsum[kThreads / kWave], wsum_d[kThreads / kWave];
     const int t = threadIdx.x;
     const int w = t / kWave;
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * kSortTile;
-    // exclusive scan of this tile's digit counts
-    uint32_t c = hist[(int64_t)t * ntiles + tile];
-    uint32_t incl = wave_incl_scan(c);
-    if (lane_id() == kWave - 1) wsum[w] = incl;
+    // exclusive scans over the digits of this tile's counts and of the
+    // digit totals; a key at tile position p with digit d goes to
+    // gbase[d] + p (modulo 2^32; the true position is below n)
+    const uint32_t c = hist[(int64_t)t * ntiles + tile], dt = dtot[t];
+    const uint32_t incl = wave_incl_scan(c), incl_d = wave_incl_scan(dt);
+    if (lane_id() == kWave - 1) {
+        wsum[w] = incl;
+        wsum_d[w] = incl_d;
+    }
     digit_base[t] = 0;
     for (int k = 0; k < kThreads / kWave; k++) wave_cnt[k][t] = 0;
     __syncthreads();
-    uint32_t off = 0;
-    for (int k = 0; k < w; k++) off += wsum[k];
+    uint32_t off = 0, off_d = 0;
+    for (int k = 0; k < w; k++) {
+        off += wsum[k];
+        off_d += wsum_d[k];
+    }
     tile_start[t] = off + incl - c;
+    gbase[t] = (off_d + incl_d - dt) + offs[(int64_t)t * ntiles + tile] - (off + incl - c);
     __syncthreads();
     for (int r = 0; r < kSortRounds; r++) {
         int64_t k = base + r * kThreads + t;
@@ -294,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_i
     for (int p = t; p < tile_n; p += kThreads) {
         uint64_t kk = sk[p];
         int d = (int)((kk >> shift) & 255);
-        uint32_t g = offs[(int64_t)d * ntiles + tile] + ((uint32_t)p - tile_start[d]);
+        const uint32_t g = gbase[d] + (uint32_t)p;
         key_out[g] = kk;
         val_out[g] = sv[p];
     }
@@ -823,7 +874,7 @@ void launch_keys(const double *pos, int64_t n, const RootBox *rb, uint64_t *key,
 int64_t sort_ws_bytes(int64_t n) {
     int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     if (ntiles < 1) ntiles = 1;
-    return (int64_t)sizeof(uint32_t) * (2 * kRadix * ntiles + 4);
+    return (int64_t)sizeof(uint32_t) * (2 * kRadix * ntiles + kRadix + 4);
 }
 
 void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **val_alt, int64_t n,
@@ -832,14 +883,18 @@ void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **v
     if (ntiles < 1) ntiles = 1;
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + kRadix * ntiles;
+    uint32_t *dtot = offs + kRadix * ntiles;
+    (void)scan_ws;
     for (int pass = 0; pass < passes; pass++) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
                            (const uint64_t *)*key, n, shift, hist, ntiles, n_dev);
-        scan_u32_to_u32(hist, offs, kRadix * ntiles, scan_ws, s);
+        hipLaunchKernelGGL(k_sort_rowscan, dim3(kRadix), dim3(kThreads), 0, s,
+                           (const uint32_t *)hist, ntiles, offs, dtot);
         hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
                            (const uint64_t *)*key, (const uint32_t *)*val, *key_alt, *val_alt, n,
-                           shift, (const uint32_t *)hist, (const uint32_t *)offs, ntiles, n_dev);
+                           shift, (const uint32_t *)hist, (const uint32_t *)offs,
+                           (const uint32_t *)dtot, ntiles, n_dev);
         uint64_t *tk = *key;
         *key = *key_alt;
         *key_alt = tk;
