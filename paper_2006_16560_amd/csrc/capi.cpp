@@ -43,7 +43,7 @@ struct petar_ctx {
     // tree build
     DevBuf key0, key1, val0, val1, sort_ws, scan_ws, bbox_part, rootbox, status, emit, base;
     DevBuf ps, orig, rank, rr, rsk;
-    DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_info, level_off;
+    DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_info, nd_parent, level_off;
     DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
@@ -168,6 +168,7 @@ TreeDev tree_view(petar_ctx *c) {
     t.nd_com = ptr<double4>(c->nd_com);
     t.nd_S = ptr<double>(c->nd_S);
     t.nd_info = ptr<uint4>(c->nd_info);
+    t.nd_parent = ptr<uint32_t>(c->nd_parent);
     t.level_off = ptr<uint32_t>(c->level_off);
     t.n = c->n;
     t.n_nodes = c->n_nodes;
@@ -210,7 +211,7 @@ void free_all(petar_ctx *c) {
     DevBuf *bufs[] = {&c->key0,     &c->key1,        &c->val0,       &c->val1,       &c->sort_ws,
                       &c->scan_ws,  &c->bbox_part,   &c->rootbox,    &c->status,     &c->emit,
                       &c->base,     &c->ps,          &c->orig,       &c->rank,       &c->rr,         &c->rsk,
-                      &c->nd_lo,    &c->nd_hi,       &c->nd_com,     &c->nd_S,       &c->nd_info,
+                      &c->nd_lo,    &c->nd_hi,       &c->nd_com,     &c->nd_S,       &c->nd_info,    &c->nd_parent,
                       &c->level_off, &c->pre_info,   &c->pre_parent, &c->pre_nchild, &c->new_of_old,
                       &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
                       &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
@@ -653,6 +654,7 @@ petar_status alloc_build_b(petar_ctx *ctx, int64_t node_cap) {
     TRY(ensure(ctx, ctx->nd_com, M * sizeof(double4)));
     TRY(ensure(ctx, ctx->nd_S, M * 6 * 8));
     TRY(ensure(ctx, ctx->nd_info, M * sizeof(uint4)));
+    TRY(ensure(ctx, ctx->nd_parent, M * 4));
     TRY(ensure(ctx, ctx->pre_info, M * sizeof(uint4)));
     TRY(ensure(ctx, ctx->pre_parent, M * 4));
     TRY(ensure(ctx, ctx->pre_nchild, M * 4));
@@ -842,7 +844,7 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     zero_force_status(ctx, s);
     fill_u32(queue, 0, 64, s);
     launch_gather_radii(a.r_in, a.r_out, a.r_search, t, st, s);
-    launch_rsmax(t, ctx->deep, s);
+    launch_rsmax(t, s);
     launch_group_flags(pre, t, a.group_size, ptr<uint32_t>(ctx->gflag), s);
     scan_u32_to_u32(ptr<uint32_t>(ctx->gflag), ptr<uint32_t>(ctx->gpos), n_nodes,
                     ptr<int64_t>(ctx->scan_ws), s);

@@ -29,6 +29,7 @@ struct TreeDev {
     double4 *nd_lo, *nd_hi, *nd_com;
     double *nd_S;
     uint4 *nd_info;
+    uint32_t *nd_parent;        // kNone for a root
     const uint32_t *level_off;  // [23]: cells of level l are [level_off[l], level_off[l+1])
     const int64_t *n_nodes_dev; // number of cells (device); n_nodes below bounds it
     int64_t n;
@@ -88,7 +89,7 @@ void launch_tree_summary(const TreeDev &t, Status *st, hipStream_t s);
 // force_long preparation
 void launch_gather_radii(const double *r_in, const double *r_out, const double *r_search,
                          TreeDev t, Status *st, hipStream_t s);
-void launch_rsmax(const TreeDev &t, int levels, hipStream_t s);
+void launch_rsmax(const TreeDev &t, hipStream_t s);
 // flag[] is written for every slot up to t.n_nodes (the capacity), 0 past the cells.
 void launch_group_flags(const PreOrder &pre, const TreeDev &t, int group_size, uint32_t *flag,
                         hipStream_t s);

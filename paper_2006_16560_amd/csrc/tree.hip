@@ -569,6 +569,8 @@ __global__ __launch_bounds__(kThreads) void k_relayout(const uint32_t *perm, Pre
         uint32_t nc = pre.nchild[old];
         uint32_t first = nc ? pre.new_of_old[old + 1] : 0u;
         t.nd_info[i] = make_uint4(in.x, in.y, in.z | (nc << 8), first);
+        const uint32_t par = pre.parent[old];
+        t.nd_parent[i] = par == kNone ? kNone : pre.new_of_old[par];
         const uint64_t sys = key[in.x] >> (3 * levels);
         t.nd_hi[i].w = ldexp(rb[sys].ext, -info_level(in.z));
     }
@@ -732,32 +734,36 @@ __global__ __launch_bounds__(kThreads) void k_gather_radii(const double *r_in, c
     if (__ballot(bad) && lane_id() == 0) atomicAdd(&st->invalid_radii, 1);
 }
 
-// Largest search radius per cell, bottom-up (leaves, then one launch per
-// level for the other cells).
-__device__ __forceinline__ void cell_rsmax(const TreeDev &t, uint32_t c) {
-    const uint4 info = t.nd_info[c];
-    double r = 0.0;
-    if (info.z & kLeafFlag) {
-        for (uint32_t k = info.x; k < info.x + info.y; k++) r = fmax(r, t.rsk[k]);
-    } else {
-        const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
-        for (uint32_t o = first; o < first + nc; o++) r = fmax(r, t.nd_lo[o].w);
-    }
-    t.nd_lo[c].w = r;
-}
-
+// Largest search radius per cell. Leaves take the maximum over their
+// particles and other cells start at 0; then every leaf raises its ancestors
+// with a 64-bit atomicMax on the bits of the value (the order of
+// non-negative doubles is that of their bits), climbing only while it raised
+// the cell above, since otherwise the value there came from another leaf
+// that climbs on. The result does not depend on the order of the atomics.
 __global__ __launch_bounds__(kThreads) void k_rsmax_leaves(TreeDev t) {
     const int64_t n_nodes = *t.n_nodes_dev;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
-         c += (int64_t)gridDim.x * blockDim.x)
-        if (t.nd_info[c].z & kLeafFlag) cell_rsmax(t, (uint32_t)c);
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 info = t.nd_info[c];
+        double r = 0.0;
+        if (info.z & kLeafFlag)
+            for (uint32_t k = info.x; k < info.x + info.y; k++) r = fmax(r, t.rsk[k]);
+        t.nd_lo[c].w = r;
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_rsmax_level(TreeDev t, int level) {
-    const uint32_t beg = t.level_off[level], end = t.level_off[level + 1];
-    for (int64_t c = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < end;
-         c += (int64_t)gridDim.x * blockDim.x)
-        if (!(t.nd_info[c].z & kLeafFlag)) cell_rsmax(t, (uint32_t)c);
+__global__ __launch_bounds__(kThreads) void k_rsmax_up(TreeDev t) {
+    const int64_t n_nodes = *t.n_nodes_dev;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        if (!(t.nd_info[c].z & kLeafFlag)) continue;
+        const unsigned long long v = (unsigned long long)__double_as_longlong(t.nd_lo[c].w);
+        for (uint32_t p = t.nd_parent[c]; p != kNone; p = t.nd_parent[p]) {
+            const unsigned long long old =
+                atomicMax((unsigned long long *)&t.nd_lo[p].w, v);
+            if (old >= v) break;
+        }
+    }
 }
 
 // i-groups: the first cells on each root-to-leaf path holding <= group_size
@@ -955,12 +961,11 @@ void launch_gather_radii(const double *r_in, const double *r_out, const double *
                        r_in, r_out, r_search, t, st);
 }
 
-void launch_rsmax(const TreeDev &t, int levels, hipStream_t s) {
+void launch_rsmax(const TreeDev &t, hipStream_t s) {
     hipLaunchKernelGGL(k_rsmax_leaves, dim3(grid_for(t.n_nodes, kThreads, 8192)), dim3(kThreads), 0,
                        s, t);
-    for (int l = levels - 1; l >= 0; l--)
-        hipLaunchKernelGGL(k_rsmax_level, dim3(grid_for(t.n_nodes, kThreads, 1024)), dim3(kThreads),
-                           0, s, t, l);
+    hipLaunchKernelGGL(k_rsmax_up, dim3(grid_for(t.n_nodes, kThreads, 8192)), dim3(kThreads), 0, s,
+                       t);
 }
 
 void launch_group_flags(const PreOrder &pre, const TreeDev &t, int group_size, uint32_t *flag,
