@@ -308,16 +308,33 @@ constexpr int kShortMax = 32;
 constexpr int kLongMax = 4096;
 constexpr int kStage = 4096;
 
-__device__ __forceinline__ void insertion_sort(int32_t *a, int64_t len) {
-    for (int64_t p = 1; p < len; p++) {
-        int32_t v = a[p];
-        int64_t q = p - 1;
-        while (q >= 0 && a[q] > v) {
-            a[q + 1] = a[q];
-            q--;
+// A list of at most N entries sorted in registers by a bitonic network of
+// N (a power of two) inputs, the tail padded with INT32_MAX. Every lane of
+// a wave runs the same network, sized by the longest short list in the wave.
+template <int N>
+__device__ __forceinline__ void sort_in_registers(int32_t *a, int len) {
+    int32_t v[N];
+#pragma unroll
+    for (int q = 0; q < N; q++) v[q] = q < len ? a[q] : INT32_MAX;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; i++) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t x = v[i], y = v[l];
+                    const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+                    v[i] = (i & k) == 0 ? lo : hi;
+                    v[l] = (i & k) == 0 ? hi : lo;
+                }
+            }
         }
-        a[q + 1] = v;
     }
+#pragma unroll
+    for (int q = 0; q < N; q++)
+        if (q < len) a[q] = v[q];
 }
 
 __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offsets, int32_t *idx,
@@ -342,12 +359,28 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offse
             for (int64_t p = threadIdx.x; p < r1 - r0; p += kThreads) sh[p] = idx[r0 + p];
             __syncthreads();
         }
-        if (i < n) {
-            if (len > kShortMax)
-                long_list[atomicAdd(long_count, 1u)] = (uint32_t)i;
-            else if (len > 1)
-                insertion_sort(staged ? sh + (b - r0) : idx + b, len);
+        // longer lists go to the block-wide sort (one queue slot claim per wave)
+        const bool is_long = len > kShortMax;
+        const unsigned long long lm = __ballot(is_long);
+        if (lm) {
+            uint32_t first = 0;
+            if (lane_id() == __ffsll((long long)lm) - 1) first = atomicAdd(long_count, (uint32_t)__popcll(lm));
+            first = (uint32_t)__shfl((int)first, __ffsll((long long)lm) - 1, kWave);
+            if (is_long) long_list[first + (uint32_t)lanes_below(lm)] = (uint32_t)i;
         }
+        const int ls = (len > 1 && !is_long) ? (int)len : 0;
+        int32_t *a = staged ? sh + (b - r0) : idx + b;
+        const int m = (int)wave_max((double)ls);
+        if (m > 16)
+            sort_in_registers<32>(a, ls);
+        else if (m > 8)
+            sort_in_registers<16>(a, ls);
+        else if (m > 4)
+            sort_in_registers<8>(a, ls);
+        else if (m > 2)
+            sort_in_registers<4>(a, ls);
+        else if (m > 1)
+            sort_in_registers<2>(a, ls);
         if (staged) {
             __syncthreads();
             for (int64_t p = threadIdx.x; p < r1 - r0; p += kThreads) idx[r0 + p] = sh[p];
