@@ -300,11 +300,13 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
 
 // Sorts each list ascending. A block takes 256 consecutive targets; their
 // lists are contiguous, so the block stages them in LDS with coalesced reads
-// (when they fit), each thread insertion-sorts its own short list there
-// (<= 32 entries, almost all), and the block writes them back. Longer lists
-// are queued for a whole block each: bitonic network in LDS, or heap sort
-// by one thread above kLongMax entries.
+// (when they fit), each thread sorts its own short list (<= 32 entries,
+// almost all) in registers, and the block writes them back. Longer lists are
+// queued: up to kWaveMax entries a wave each (bitonic network over the
+// wave's registers), above that a block each (bitonic network in LDS), and
+// above kLongMax entries a heap sort by one thread.
 constexpr int kShortMax = 32;
+constexpr int kWaveMax = 4 * kWave;
 constexpr int kLongMax = 4096;
 constexpr int kStage = 4096;
 
@@ -421,6 +423,53 @@ __device__ void heap_sort(int32_t *a, int64_t len) {
     }
 }
 
+// A list of at most 64 E entries sorted by one wave: entry g = E lane + e in
+// register e of its lane, a bitonic network whose exchanges within a lane
+// stay in registers and across lanes use a shuffle, the tail padded with
+// INT32_MAX.
+template <int E>
+__device__ __forceinline__ void sort_in_wave(int32_t *a, int len) {
+    const int lane = lane_id();
+    int32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int g = lane * E + e;
+        v[e] = g < len ? a[g] : INT32_MAX;
+    }
+#pragma unroll
+    for (int k = 2; k <= kWave * E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= E) {
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const int g = lane * E + e;
+                    const int32_t y = __shfl_xor(v[e], j / E, kWave);
+                    const bool keep_min = ((g & k) == 0) == ((g & j) == 0);
+                    v[e] = keep_min ? (v[e] < y ? v[e] : y) : (v[e] < y ? y : v[e]);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const int l = e ^ j;
+                    if (l > e) {
+                        const bool up = ((lane * E + e) & k) == 0;
+                        const int32_t x = v[e], y = v[l];
+                        const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+                        v[e] = up ? lo : hi;
+                        v[l] = up ? hi : lo;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int g = lane * E + e;
+        if (g < len) a[g] = v[e];
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_nb_sort_long(const int64_t *offsets, int32_t *idx,
                                                            int64_t n, int64_t capacity,
                                                            const Status *st,
@@ -430,10 +479,27 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_long(const int64_t *offset
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow || offsets[n] > capacity)
         return;
     const uint32_t nl = *long_count;
+    // lists of up to kWaveMax entries: a wave each
+    const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+    for (uint32_t q = wave0; q < nl; q += nwaves) {
+        const uint32_t i = long_list[q];
+        const int64_t b = offsets[i];
+        const int len = (int)uniform((int)(offsets[i + 1] - b > kLongMax ? kLongMax + 1
+                                                                           : offsets[i + 1] - b));
+        if (len <= kWave)
+            sort_in_wave<1>(idx + b, len);
+        else if (len <= 2 * kWave)
+            sort_in_wave<2>(idx + b, len);
+        else if (len <= kWaveMax)
+            sort_in_wave<4>(idx + b, len);
+    }
+    // longer lists: a block each
     for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {
         const uint32_t i = long_list[q];
         const int64_t b = offsets[i];
         const int64_t len = offsets[i + 1] - b;
+        if (len <= kWaveMax) continue;
         int32_t *a = idx + b;
         if (len > kLongMax) {
             if (threadIdx.x == 0) heap_sort(a, len);
