@@ -1103,3 +1103,26 @@ def test_every_particle_in_one_group(pt, ctx, orc):
         if theta == 0.0:
             assert np.all(cnt[0] == 0) and np.all(cnt[1] + cnt[2] == n)
     pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, record_counts=0)
+
+
+def test_neighbour_list_length_classes(pt, ctx, orc):
+    """Lists of every length class of the list sort (in registers per lane up
+    to 32 entries, per wave up to 64, 128 and 256, per block up to 4096, one
+    thread above): clumps of k particles in cubes of side 1e-3, 10 apart, with
+    search radius 0.01, so every list holds exactly the other k - 1 members
+    of its clump."""
+    sizes = [1, 2, 17, 33, 34, 64, 65, 66, 128, 129, 130, 256, 257, 258, 700, 4097, 4200]
+    rng = np.random.default_rng(11)
+    pos = np.concatenate([rng.uniform(0.0, 1e-3, (3, k)) + np.array([[10.0 * c], [0.0], [0.0]])
+                          for c, k in enumerate(sizes)], axis=1)
+    n = pos.shape[1]
+    mass = np.full(n, 1.0 / n)
+    rin, rout, rs = np.full(n, 0.001), np.full(n, 0.005), np.full(n, 0.01)
+    need = sum(k * (k - 1) for k in sizes)
+    acc, pot, (offs, idx) = run(pt, ctx, pos, mass, rin, rout, rs, 0.5, 8, 64, pt.PETAR_MIXED,
+                                nb_cap=need)
+    o_ref, i_ref = orc.neighbours(pos, rs)
+    assert o_ref[-1] == need
+    lens = np.diff(o_ref)
+    assert set(lens.tolist()) == {k - 1 for k in sizes}
+    assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
