@@ -138,7 +138,10 @@ PETAR_API petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass
  * calls; leaf_size >= 1 bounds the particles of a leaf cell (cells at the
  * deepest level, 21, may hold more). 1 <= N < 2^31.
  * The positions are copied into the context (sorted); the caller may change
- * its buffers afterwards. */
+ * its buffers afterwards. The call returns once the cell count has been read
+ * back; the rest of the build (cell data from the sorted copies) is still
+ * queued on the stream, and the counters it sets (n_leaves, max_level,
+ * ms_build) are read with the next force call or petar_get_stats. */
 PETAR_API petar_status petar_tree_build(petar_ctx *ctx, const double *pos_dev, const double *mass_dev,
                               int64_t N, double theta, int leaf_size);
 

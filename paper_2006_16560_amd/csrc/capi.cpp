@@ -66,6 +66,7 @@ struct petar_ctx {
     int64_t n_nodes = 0;
     int levels = kMaxLevel;
     int deep = kMaxLevel;  // deepest cell level: the per-level passes start above it
+    bool build_stats_pending = false;  // eager build not yet read back (see settle_build_stats)
     int n_sys = 1;
 
     int force_waves[2][5] = {{0}};
@@ -190,14 +191,6 @@ petar_status read_status(petar_ctx *c, hipStream_t s) {
     return PETAR_OK;
 }
 
-void drop_graph(petar_ctx *c) {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->gexec = nullptr;
-    c->graph = nullptr;
-    c->graph_stale = true;
-}
-
 float elapsed(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
@@ -205,6 +198,27 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
         return 0.f;
     }
     return ms;
+}
+
+// Fills the counters of the last eager build once its status words have
+// been read (host_status current: `fresh`; else they are read here). The
+// build fields of Status are not touched by the force calls.
+petar_status settle_build_stats(petar_ctx *c, bool fresh) {
+    if (!c->build_stats_pending) return PETAR_OK;
+    if (!fresh) TRY(read_status(c, c->stream));
+    c->stats.n_leaves = c->host_status->n_leaves;
+    c->stats.max_level = c->host_status->max_level;
+    c->stats.ms_build = elapsed(c->ev[0], c->ev[1]);
+    c->build_stats_pending = false;
+    return PETAR_OK;
+}
+
+void drop_graph(petar_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_stale = true;
 }
 
 void free_all(petar_ctx *c) {
@@ -776,16 +790,17 @@ petar_status build_eager(petar_ctx *ctx, const BuildArgs &a) {
     enqueue_build_b(ctx, a, n_nodes, (int)deep, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
-    TRY(read_status(ctx, s));
+    // No wait for the second half: it reads only the context's sorted copies
+    // and cannot fail (the cell arrays hold exactly n_nodes cells), so the
+    // next call's launches queue behind it. Its counters are read with the
+    // next status read (settle_build_stats).
     set_tree_state(ctx, a, n_nodes, (int)deep);
     ctx->have_tree = true;
     ctx->stats = petar_stats{};
     ctx->stats.n = a.n;
     ctx->stats.n_nodes = n_nodes;
-    ctx->stats.n_leaves = ctx->host_status->n_leaves;
-    ctx->stats.max_level = ctx->host_status->max_level;
-    ctx->stats.ms_build = elapsed(ctx->ev[0], ctx->ev[1]);
     ctx->stats.workspace_bytes = ctx->ws_bytes;
+    ctx->build_stats_pending = true;
     return PETAR_OK;
 }
 
@@ -906,6 +921,7 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
     }
     HIP_TRY(ctx, hipGetLastError());
     TRY(read_status(ctx, s));
+    TRY(settle_build_stats(ctx, true));
     const Status &h = *ctx->host_status;
     if (h.invalid_radii)
         return fail(ctx, PETAR_E_INVALID,
@@ -1106,6 +1122,7 @@ petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offs
     ctx->stats.n_leaves = h.n_leaves;
     ctx->stats.max_level = h.max_level;
     ctx->stats.ms_build = 0.0;
+    ctx->build_stats_pending = false;
     ctx->stats.ms_force = 0.0;
     ctx->stats.ms_force_kernel = 0.0;
     ctx->stats.ms_nb = 0.0;
@@ -1129,6 +1146,10 @@ petar_status petar_copy_counts(petar_ctx *ctx, int32_t *counts) {
 petar_status petar_get_stats(petar_ctx *ctx, petar_stats *out) {
     if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
     if (!out) return fail(ctx, PETAR_E_INVALID, "stats is NULL");
+    if (ctx->device != PETAR_NO_DEVICE) {
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        TRY(settle_build_stats(ctx, false));
+    }
     *out = ctx->stats;
     return PETAR_OK;
 }
