@@ -484,51 +484,69 @@ __global__ __launch_bounds__(kThreads) void k_octree_count(const uint64_t *key, 
     }
 }
 
+// Two passes over the emitted cells: a thread per particle writes the
+// (particle, level) of each cell its chain starts, then a thread per cell
+// finds the cell's particle count and parent (galloping searches over the
+// keys), so that no thread walks a whole root-to-leaf chain of searches.
+__global__ __launch_bounds__(kThreads) void k_octree_emit(const uint64_t *key, int64_t n,
+                                                          int levels, const int64_t *base,
+                                                          PreOrder pre, const Status *st) {
+    if (st->cell_overflow) return;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = base[k];
+        const int64_t nemit = base[k + 1] - b;
+        if (nemit == 0) continue;
+        const int l0 = first_level(key, k, levels);
+        for (int u = 0; u < nemit; u++)
+            pre.info[b + u] = make_uint4((uint32_t)k, 0u, (uint32_t)(l0 + u) << 1, 0u);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_octree_write(const uint64_t *key, int64_t n,
                                                            int leaf_size, int levels,
                                                            const int64_t *base, PreOrder pre,
                                                            uint64_t *lkey, uint32_t *lval,
                                                            const Status *st) {
-    if (st->cell_overflow) return;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int64_t b = base[k];
-        int64_t nemit = base[k + 1] - b;
-        if (nemit == 0) continue;
-        int l0 = first_level(key, k, levels);
-        for (int u = 0; u < nemit; u++) {
-            int l = l0 + u;
-            uint32_t idx = (uint32_t)(b + u);
-            // the last cell of the chain holds <= leaf_size particles unless it
-            // sits at the deepest level; the others hold more
-            const bool small = u == nemit - 1 && (k + leaf_size >= n ||
-                               common_digits(key[k], key[k + leaf_size], levels) < l);
-            uint32_t cnt = 1;
-            if (small) {
-                while (cnt < (uint32_t)leaf_size && k + cnt < n &&
-                       common_digits(key[k], key[k + cnt], levels) >= l)
-                    cnt++;
-            } else {
-                cnt = (uint32_t)(run_end(key, n, k, l, levels) - k);
-            }
-            bool leaf = (cnt <= (uint32_t)leaf_size) || l == levels;
-            pre.info[idx] = make_uint4((uint32_t)k, cnt, (leaf ? kLeafFlag : 0u) | ((uint32_t)l << 1),
-                                       0u);
-            uint32_t parent;
-            if (u > 0) {
-                parent = idx - 1;
-            } else if (l == 0) {
-                parent = kNone;  // root of a system
-            } else {
-                int L = l - 1;
-                int64_t s = run_start(key, k, L, levels);
-                parent = (uint32_t)(base[s] + (L - first_level(key, s, levels)));
-            }
-            pre.parent[idx] = parent;
-            if (parent != kNone) atomicAdd(&pre.nchild[parent], 1u);
-            lkey[idx] = (uint64_t)l;
-            lval[idx] = idx;
+    const int64_t n_cells = st->n_nodes;  // 0 after an overflow
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 e = pre.info[c];
+        const int64_t k = e.x;
+        const int l = (int)(e.z >> 1);
+        const int64_t b = base[k];
+        const int64_t nemit = base[k + 1] - b;
+        const int64_t u = c - b;
+        const uint32_t idx = (uint32_t)c;
+        // the last cell of the chain holds <= leaf_size particles unless it
+        // sits at the deepest level; the others hold more
+        const bool small = u == nemit - 1 && (k + leaf_size >= n ||
+                           common_digits(key[k], key[k + leaf_size], levels) < l);
+        uint32_t cnt = 1;
+        if (small) {
+            while (cnt < (uint32_t)leaf_size && k + cnt < n &&
+                   common_digits(key[k], key[k + cnt], levels) >= l)
+                cnt++;
+        } else {
+            cnt = (uint32_t)(run_end(key, n, k, l, levels) - k);
         }
+        const bool leaf = (cnt <= (uint32_t)leaf_size) || l == levels;
+        pre.info[idx] = make_uint4((uint32_t)k, cnt, (leaf ? kLeafFlag : 0u) | ((uint32_t)l << 1),
+                                   0u);
+        uint32_t parent;
+        if (u > 0) {
+            parent = idx - 1;
+        } else if (l == 0) {
+            parent = kNone;  // root of a system
+        } else {
+            const int L = l - 1;
+            const int64_t s = run_start(key, k, L, levels);
+            parent = (uint32_t)(base[s] + (L - first_level(key, s, levels)));
+        }
+        pre.parent[idx] = parent;
+        if (parent != kNone) atomicAdd(&pre.nchild[parent], 1u);
+        lkey[idx] = (uint64_t)l;
+        lval[idx] = idx;
     }
 }
 
@@ -929,8 +947,10 @@ void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int leve
                          const int64_t *base, PreOrder pre, uint64_t *lkey, uint32_t *lval,
                          int64_t node_cap, Status *st, hipStream_t s) {
     hipLaunchKernelGGL(k_cell_count, dim3(1), dim3(64), 0, s, base, n, node_cap, st);
-    hipLaunchKernelGGL(k_octree_write, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
-                       levels, base, pre, lkey, lval, (const Status *)st);
+    hipLaunchKernelGGL(k_octree_emit, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, levels,
+                       base, pre, (const Status *)st);
+    hipLaunchKernelGGL(k_octree_write, dim3(grid_for(node_cap)), dim3(kThreads), 0, s, key, n,
+                       leaf_size, levels, base, pre, lkey, lval, (const Status *)st);
 }
 
 void launch_relayout(const uint32_t *perm, PreOrder pre, const RootBox *rb, const uint64_t *key,
