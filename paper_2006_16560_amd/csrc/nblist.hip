@@ -174,6 +174,7 @@ constexpr int kHitBuf = 8;
 template <bool kWrite>
 struct NbRecLds {
     uint32_t start[kWave], pre[kWave];
+    uint32_t self[kWave];  // counting: target a of the chunk is among the staged sources
     double4 jp[kWave];  // x, y, z, r_search^2 of the staged batch
     uint32_t jk[kWave];
     uint32_t hit[kWrite ? kHitBuf : 1][kWave];  // a lane's hits not yet written
@@ -235,6 +236,10 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             const double rsi2 = rsi * rsi;
             const uint32_t oi = t.orig[ki];
             uint32_t c = 0;
+            if (!kWrite) {
+                L.self[lane] = 0;
+                wave_sync();
+            }
             // one batch of 64 sources into registers (lane = source)
             double4 pn = make_double4(0.0, 0.0, 0.0, 0.0);
             uint32_t kn = 0;
@@ -246,6 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
                     const double4 p = t.ps[kn];
                     const double rs = t.rsk[kn];
                     pn = make_double4(p.x, p.y, p.z, rs * rs);
+                    if (!kWrite && kn - (gfirst + a0) < (uint32_t)g) L.self[kn - (gfirst + a0)] = 1;
                 }
             };
             // write pass: this lane's buffered hits into its target's list
@@ -257,13 +263,14 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             // the staged source at byte p of L.jp
             const char *jbase = (const char *)L.jp;
             auto test = [&](const char *p) {
-                if (nb_pair_sq(pi, rsi2, *(const double4 *)p)) {
+                if constexpr (!kWrite) {
+                    // every pair counts, the target itself too (subtracted below)
+                    c += nb_pair_sq(pi, rsi2, *(const double4 *)p) ? 1u : 0u;
+                } else if (nb_pair_sq(pi, rsi2, *(const double4 *)p)) {
                     const uint32_t kj = L.jk[(uint32_t)(p - jbase) >> 5];
                     if (kj != ki) {
-                        if constexpr (kWrite) {
-                            if (c == (uint32_t)kHitBuf) flush();
-                            L.hit[c][lane] = kj;
-                        }
+                        if (c == (uint32_t)kHitBuf) flush();
+                        L.hit[c][lane] = kj;
                         c++;
                     }
                 }
@@ -291,7 +298,11 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             if constexpr (kWrite) {
                 if (c) flush();
             } else {
-                if (c) atomicAdd(&cnt_orig[oi], c);
+                // the pair of a target with itself (d2 = 0) was counted iff
+                // rs_i^2 > 0 and the target was staged; one of its lanes takes it off
+                wave_sync();
+                if (act && sl == 0 && L.self[a] && rsi2 > 0.0) c--;
+                if (act && c) atomicAdd(&cnt_orig[oi], c);
             }
             wave_sync();
         }
