@@ -411,9 +411,7 @@ petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
     TRY(ensure(ctx, ctx->cl_val0, (size_t)n * 4));
     TRY(ensure(ctx, ctx->cl_val1, (size_t)n * 4));
     TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(n)));
-    const int64_t sort_scan = 256 * ((n + 2047) / 2048);
-    TRY(ensure(ctx, ctx->scan_ws,
-               (size_t)scan_ws_elems(sort_scan > n + 1 ? sort_scan : n + 1) * 8));
+    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
     // flags = {bad offsets, bad index}
     int32_t *csr_bad = ptr<int32_t>(ctx->cl_flags), *bad = csr_bad + 1;
     fill_i64(ptr<int64_t>(ctx->cl_flags), 0, 1, s);
@@ -428,7 +426,7 @@ petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
     launch_cluster_keys(label, n, rootpos, k, v, s);
     int passes = 1;
     while (passes < 4 && (n - 1) >> (8 * passes)) passes++;
-    radix_sort(&k, &v, &ka, &va, n, passes, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s);
+    radix_sort(&k, &v, &ka, &va, n, passes, ctx->sort_ws.p, s);
     HIP_TRY(ctx, hipMemcpyAsync(members, v, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
     launch_cluster_offsets(k, n, cl_offsets, s);
     HIP_TRY(ctx, hipGetLastError());
@@ -639,8 +637,7 @@ struct BuildArgs {
 petar_status alloc_build_a(petar_ctx *ctx, const BuildArgs &a) {
     const size_t N = (size_t)a.n;
     const int n_boxes = a.n_sys > 0 ? a.n_sys : 1;
-    int64_t sort_scan = 256 * ((a.n + 2047) / 2048);
-    int64_t scan_need = scan_ws_elems(sort_scan > a.n + 1 ? sort_scan : a.n + 1);
+    const int64_t scan_need = scan_ws_elems(a.n + 1);  // the cell-count scan
     TRY(ensure(ctx, ctx->key0, N * 8));
     TRY(ensure(ctx, ctx->key1, N * 8));
     TRY(ensure(ctx, ctx->val0, N * 4));
@@ -678,9 +675,6 @@ petar_status alloc_build_b(petar_ctx *ctx, int64_t node_cap) {
     TRY(ensure(ctx, ctx->lval0, M * 4));
     TRY(ensure(ctx, ctx->lval1, M * 4));
     TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(node_cap > n ? node_cap : n)));
-    int64_t lsort_scan = 256 * ((node_cap + 2047) / 2048);
-    TRY(ensure(ctx, ctx->scan_ws,
-               (size_t)scan_ws_elems(lsort_scan > n + 1 ? lsort_scan : n + 1) * 8));
     return PETAR_OK;
 }
 
@@ -701,7 +695,7 @@ void enqueue_build_a(petar_ctx *ctx, const BuildArgs &a, hipStream_t s) {
         launch_bbox(a.pos, a.mass, a.n, ptr<double>(ctx->bbox_part), rb, s);
         launch_keys(a.pos, a.n, rb, k, v, s);
     }
-    radix_sort(&k, &v, &ka, &va, a.n, 8, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s);
+    radix_sort(&k, &v, &ka, &va, a.n, 8, ctx->sort_ws.p, s);
     launch_gather_particles(a.pos, a.mass, v, a.n, ptr<double4>(ctx->ps), ptr<uint32_t>(ctx->orig),
                             ptr<uint32_t>(ctx->rank), s);
     uint32_t *deep_slots = ptr<uint32_t>(ctx->emit) + a.n;
@@ -728,7 +722,7 @@ void enqueue_build_b(petar_ctx *ctx, const BuildArgs &a, int64_t node_cap, int d
     const uint64_t *k = ptr<uint64_t>(ctx->key0);
     launch_octree_write(k, a.n, a.leaf_size, levels, ptr<int64_t>(ctx->base), pre, lk, lv,
                         node_cap, st, s);
-    radix_sort(&lk, &lv, &lka, &lva, node_cap, 1, ctx->sort_ws.p, ptr<int64_t>(ctx->scan_ws), s,
+    radix_sort(&lk, &lv, &lka, &lva, node_cap, 1, ctx->sort_ws.p, s,
                t.n_nodes_dev);
     launch_relayout(lv, pre, ptr<RootBox>(ctx->rootbox), k, levels, t,
                     ptr<uint32_t>(ctx->level_off), s);

@@ -61,7 +61,7 @@ void launch_keys_systems(const double *pos, int64_t n, const int64_t *off, int n
 int64_t sort_ws_bytes(int64_t n);
 // n bounds the element count; with n_dev the actual count is read on the device.
 void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **val_alt, int64_t n,
-                int passes, void *ws, int64_t *scan_ws, hipStream_t s,
+                int passes, void *ws, hipStream_t s,
                 const int64_t *n_dev = nullptr);
 
 void launch_gather_particles(const double *pos, const double *mass, const uint32_t *idx,

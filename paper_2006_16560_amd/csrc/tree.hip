@@ -902,13 +902,12 @@ int64_t sort_ws_bytes(int64_t n) {
 }
 
 void radix_sort(uint64_t **key, uint32_t **val, uint64_t **key_alt, uint32_t **val_alt, int64_t n,
-                int passes, void *ws, int64_t *scan_ws, hipStream_t s, const int64_t *n_dev) {
+                int passes, void *ws, hipStream_t s, const int64_t *n_dev) {
     int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     if (ntiles < 1) ntiles = 1;
     uint32_t *hist = (uint32_t *)ws;
     uint32_t *offs = hist + kRadix * ntiles;
     uint32_t *dtot = offs + kRadix * ntiles;
-    (void)scan_ws;
     for (int pass = 0; pass < passes; pass++) {
         int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
