@@ -126,6 +126,9 @@ petar_status ensure(petar_ctx *ctx, DevBuf &b, size_t bytes) {
                         (long long)ctx->params.workspace_cap, (long long)after);
     }
     if (b.p) {
+        // work queued by an earlier call (the second half of a tree build)
+        // may still use the buffer
+        (void)hipStreamSynchronize(ctx->stream);
         hipFree(b.p);
         ctx->ws_bytes -= (int64_t)b.cap;
         b.p = nullptr;

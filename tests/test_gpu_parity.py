@@ -1126,3 +1126,26 @@ def test_neighbour_list_length_classes(pt, ctx, orc):
     lens = np.diff(o_ref)
     assert set(lens.tolist()) == {k - 1 for k in sizes}
     assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
+
+
+def test_back_to_back_builds_growing(pt, orc):
+    """A build returns with its second half still queued; a following build
+    on more particles reallocates the buffers that half uses. The force on
+    the second tree must match the oracle tree, and the first build's
+    counters must be readable afterwards in a fresh context."""
+    small, rin_s, rout_s, rs_s = cluster_with_radii(orc, 3000, 21)
+    big, rin, rout, rs = cluster_with_radii(orc, 20000, 22, bf=0.3)
+    c = pt.petar_create(0)
+    pt.petar_set_params(c, precision=pt.PETAR_FP64)
+    pt.petar_tree_build(c, T(small.pos), T(small.mass), 0.5, 8)
+    pt.petar_tree_build(c, T(big.pos), T(big.mass), 0.5, 8)
+    acc, pot = pt.petar_force_long(c, 64, T(rin), T(rout), T(rs))[:2]
+    torch.cuda.synchronize()
+    a_ref, p_ref, _ = orc.tree_force(big.pos, big.mass, rin, rout, rs, 0.5, 8, 64)
+    assert np.percentile(rel_err(acc.cpu().numpy(), a_ref), 99) < 1e-12
+    st = pt.petar_get_stats(c)
+    assert st["n"] == 20000 and st["n_leaves"] > 0 and st["max_level"] > 0
+    c2 = pt.petar_create(0)
+    pt.petar_tree_build(c2, T(small.pos), T(small.mass), 0.5, 8)
+    st2 = pt.petar_get_stats(c2)  # counters of a build not followed by a force call
+    assert st2["n"] == 3000 and st2["n_leaves"] > 0 and st2["ms_build"] > 0.0
