@@ -133,10 +133,13 @@ PETAR_API petar_status petar_changeover_radii(petar_ctx *ctx, const double *mass
                                     double search_factor, double cr_dt, double *r_in_dev,
                                     double *r_out_dev, double *r_search_dev);
 
-/* Build the octree of N particles: pos_dev[3][N], mass_dev[N] (m >= 0,
- * finite). theta >= 0 is the opening angle used by the following force
- * calls; leaf_size >= 1 bounds the particles of a leaf cell (cells at the
- * deepest level, 21, may hold more). 1 <= N < 2^31.
+/* Build the Barnes-Hut octree of N particles (Sec. "Particle-tree with
+ * individual time steps": the particle-tree half of P3T; its cells carry
+ * the mass, centre of mass and traceless quadrupole of eq. quad and
+ * eq. quadtr): pos_dev[3][N], mass_dev[N] (m >= 0, finite). theta >= 0 is
+ * the opening angle used by the following force calls; leaf_size >= 1
+ * bounds the particles of a leaf cell (cells at the deepest level, 21, may
+ * hold more). 1 <= N < 2^31.
  * The positions are copied into the context (sorted); the caller may change
  * its buffers afterwards. The call returns once the cell count has been read
  * back; the rest of the build (cell data from the sorted copies) is still
@@ -146,23 +149,30 @@ PETAR_API petar_status petar_tree_build(petar_ctx *ctx, const double *pos_dev, c
                               int64_t N, double theta, int leaf_size);
 
 /* Batched mode: n_sys independent particle systems (star clusters) stored
- * back to back; system s holds particles sys_offsets[s] .. sys_offsets[s+1]-1
- * (sys_offsets is a host array of n_sys + 1 entries, sys_offsets[0] = 0,
- * strictly increasing; 1 <= n_sys <= 512). Builds one octree per system (own
- * root cube, 18 levels) in a single pass; the next petar_force_long computes
- * every system's long-range force and neighbour lists in one launch, with
- * no interaction between systems. Output indices are global (input order). */
+ * back to back, each with the octree of petar_tree_build (Sec. "Particle-
+ * tree with individual time steps"; each system is one star cluster like
+ * the models of Sec. "Benchmark", Table inpar). System s holds particles
+ * sys_offsets[s] .. sys_offsets[s+1]-1 (sys_offsets is a host array of
+ * n_sys + 1 entries, sys_offsets[0] = 0, strictly increasing;
+ * 1 <= n_sys <= 512). Builds one octree per system (own root cube, 18
+ * levels) in a single pass; the next petar_force_long computes every
+ * system's long-range force and neighbour lists in one launch, with no
+ * interaction between systems. Output indices are global (input order). */
 PETAR_API petar_status petar_batch_build(petar_ctx *ctx, int n_sys, const int64_t *sys_offsets,
                                          const double *pos_dev, const double *mass_dev,
                                          double theta, int leaf_size);
 
-/* Long-range acceleration and potential on every particle of the last
- * tree build (input order): acc_dev[3][N], pot_dev[N]. group_size >= 1 is
- * the i-group size of the walk. r_in_dev, r_out_dev, r_search_dev [N] are
- * the changeover and search radii; 0 <= r_in < r_out <= r_search and finite
- * for every particle. nb may be NULL (no neighbour lists). On
- * PETAR_E_NB_OVERFLOW acc and pot are complete and nb->required is set: the
- * caller retries with a larger buffer. */
+/* Long-range acceleration and potential of the P3T split (eq. cf; pair
+ * weights 1 - K and (1 - W)/r of eq. Wij; cells accepted inside the
+ * opening angle act through their monopole and quadrupole, eq. quadtr) on
+ * every particle of the last tree build (input order), and the first-stage
+ * neighbour candidates (Sec. "Orbit-dependent neighbour criterion"):
+ * acc_dev[3][N], pot_dev[N]. group_size >= 1 is the i-group size of the
+ * walk. r_in_dev, r_out_dev, r_search_dev [N] are the changeover and search
+ * radii; 0 <= r_in < r_out <= r_search and finite for every particle. nb
+ * may be NULL (no neighbour lists). On PETAR_E_NB_OVERFLOW acc and pot are
+ * complete and nb->required is set: the caller retries with a larger
+ * buffer. */
 PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in_dev,
                               const double *r_out_dev, const double *r_search_dev,
                               double *acc_dev, double *pot_dev, petar_nblist *nb);
@@ -178,16 +188,18 @@ PETAR_API petar_status petar_force_long_kick(petar_ctx *ctx, int group_size,
                                              double *pot_dev, petar_nblist *nb, double *vel_dev,
                                              double dt);
 
-/* One step -- tree build (petar_tree_build when n_sys == 0, else
- * petar_batch_build with sys_offsets[n_sys + 1] and N = sys_offsets[n_sys])
- * followed by petar_force_long -- executed as a captured hipGraph. The
- * first call (and any call whose pointers, sizes, offsets or parameters
- * differ from the captured ones) runs eagerly and captures the launches on a
- * private stream; later calls replay the graph on the context's stream with
- * one status read at the end. Buffer contents may change between calls. The
- * graph holds cells for twice the tree of the capturing call; a tree that
- * outgrows it is redone eagerly and recaptured on the next call. Results and
- * errors are those of the two eager calls. */
+/* One evaluation of the long-range force of the P3T kick (eq. cf,
+ * eq. Wij; step iv of the integration cycle of Sec. "Hybrid N-body code":
+ * the tree is built anew for every long-range force) -- tree build (petar_tree_build when
+ * n_sys == 0, else petar_batch_build with sys_offsets[n_sys + 1] and
+ * N = sys_offsets[n_sys]) followed by petar_force_long -- executed as a
+ * captured hipGraph. The first call (and any call whose pointers, sizes,
+ * offsets or parameters differ from the captured ones) runs eagerly and
+ * captures the launches on a private stream; later calls replay the graph
+ * on the context's stream with one status read at the end. Buffer contents
+ * may change between calls. The graph holds cells for twice the tree of the
+ * capturing call; a tree that outgrows it is redone eagerly and recaptured
+ * on the next call. Results and errors are those of the two eager calls. */
 PETAR_API petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offsets,
                                         const double *pos_dev, const double *mass_dev, int64_t N,
                                         double theta, int leaf_size, int group_size,
@@ -211,21 +223,31 @@ typedef struct {
     double ms;       /* measured build + force time (device ms)  */
 } petar_tuned;
 
-/* Times tree build + long-range force on the given particles (same argument
- * rules as petar_tree_build / petar_force_long) for leaf sizes {4, 8, 16, 32},
- * group sizes {32, 64, 128, 256} and 1, 2 or 4 targets per lane, keeps the
- * fastest, sets params.i_per_lane to it and returns it in *out. With
- * cache_path (host string, may be NULL) results are read from / appended to
- * a JSON-lines file keyed by (floor(log2 N), theta, precision); a cache hit
- * returns without launching anything. The practice follows the paper's
- * wall-clock scans of its integrator parameters (Sec. "Performance on
- * GPU-based Desktop"). Leaves the context holding a tree of some candidate:
- * rebuild with the returned leaf size. */
+/* Times one step -- tree build, long-range force and neighbour lists -- on
+ * the given particles (same argument rules as petar_tree_build /
+ * petar_force_long) for leaf sizes {4, 8, 16}, group sizes {32, 48, 64, 96,
+ * 128, 192, 256} and 1 or 2 targets per lane, keeps the fastest, sets
+ * params.i_per_lane to it and returns it in *out. With cache_path (host
+ * string, may be NULL) results are read from / appended to a JSON-lines
+ * file keyed by (floor(log2 N), theta, precision); a cache hit returns
+ * without launching anything. The practice follows the paper's wall-clock
+ * scans of its integrator parameters (Sec. "Performance on GPU-based
+ * Desktop", the scan of the long step). Allocates its own scratch outputs.
+ * Leaves the context holding a tree of some candidate: rebuild with the
+ * returned leaf size. */
 PETAR_API petar_status petar_autotune(petar_ctx *ctx, const double *pos_dev,
                                       const double *mass_dev, int64_t N, double theta,
                                       const double *r_in_dev, const double *r_out_dev,
                                       const double *r_search_dev, const char *cache_path,
                                       petar_tuned *out);
+
+/* The parameters petar_autotune stored in cache_path (host string) for
+ * (floor(log2 N_hint), theta, params.precision of ctx), without particles
+ * and without launching anything (also on a PETAR_NO_DEVICE context).
+ * Returns PETAR_E_STATE when the cache holds no such entry (or cannot be
+ * read), PETAR_E_INVALID for N_hint < 1, theta < 0 or a NULL pointer. */
+PETAR_API petar_status petar_autotune_lookup(petar_ctx *ctx, int64_t N_hint, double theta,
+                                             const char *cache_path, petar_tuned *out);
 
 /* Second stage of the neighbour search (Sec. "Orbit-dependent neighbour
  * criterion"): keeps a first-stage candidate j of particle i iff the

@@ -10,6 +10,7 @@ when the HIP library has not been built.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional
 
 import torch
@@ -28,7 +29,8 @@ __all__ = [
     "petar_force_long_kick", "petar_groups", "petar_kick", "petar_artificial_make",
     "petar_tidal_fit", "petar_tidal_eval",
     "art_points",
-    "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
+    "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_autotune_lookup",
+    "launch_config", "TUNED_CACHE", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
     "PETAR_NO_DEVICE", "lib_path",
 ]
 
@@ -463,6 +465,38 @@ def petar_autotune(ctx: Context, pos: torch.Tensor, mass: torch.Tensor, theta: f
                              cache_path.encode() if cache_path else None, ctypes.byref(out))
     _check(st, ctx)
     return {name: getattr(out, name) for name, _ in out._fields_}
+
+
+# Parameters petar_autotune chose on an MI355X for the particle sets of the
+# benchmark (JSON lines, written by the autotuner itself).
+TUNED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.jsonl")
+
+
+def petar_autotune_lookup(ctx: Context, n: int, theta: float,
+                          cache_path: Optional[str] = None) -> Optional[dict]:
+    """The stored autotuner choice for (N, theta, the context's precision),
+    or None when the cache holds none; launches nothing. See petar.h."""
+    out = _capi.petar_tuned()
+    path = TUNED_CACHE if cache_path is None else cache_path
+    st = _lib.petar_autotune_lookup(ctx.handle, int(n), float(theta), path.encode(),
+                                    ctypes.byref(out))
+    if st == PETAR_E_STATE:
+        return None
+    _check(st, ctx)
+    return {name: getattr(out, name) for name, _ in out._fields_}
+
+
+def launch_config(ctx: Context, n: int, theta: float, leaf_default: int = 8,
+                  group_default: int = 64, ipl_default: int = 2) -> dict:
+    """Leaf size, group size and targets per lane for a force at (N, theta):
+    the autotuner's stored choice when the package cache holds one (source
+    "autotune"), else the defaults (source "default")."""
+    t = petar_autotune_lookup(ctx, n, theta)
+    if t is None:
+        return {"leaf_size": leaf_default, "group_size": group_default,
+                "i_per_lane": ipl_default, "source": "default"}
+    return {"leaf_size": t["leaf_size"], "group_size": t["group_size"],
+            "i_per_lane": t["i_per_lane"], "source": "autotune", "tuned_ms": t["ms"]}
 
 
 def force_long_with_retry(ctx: Context, group_size: int, r_in, r_out, r_search,

@@ -86,6 +86,7 @@ SIGNATURES = [
     ("petar_get_stats", _INT, [_P, ctypes.POINTER(petar_stats)]),
     ("petar_autotune", _INT, [_P, _P, _P, _I64, _D, _P, _P, _P, ctypes.c_char_p,
                               ctypes.POINTER(petar_tuned)]),
+    ("petar_autotune_lookup", _INT, [_P, _I64, _D, ctypes.c_char_p, ctypes.POINTER(petar_tuned)]),
     ("petar_nb_filter", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P,
                                ctypes.POINTER(petar_nblist)]),
     ("petar_clusters", _INT, [_P, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),

@@ -146,8 +146,8 @@ struct Kepler {
 __device__ Kepler kepler(double m1, double m2, const double r[3], const double v[3], double G) {
     Kepler k;
     const double M = m1 + m2, mu = G * M;
-    const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-    const double E = 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - mu / rr;
+    double rr;
+    const double E = kepler_energy(r, v, mu, &rr);
     k.ok = rr > 0.0 && E < 0.0;
     if (!k.ok) return k;
     k.a = -mu / (2.0 * E);

@@ -1,7 +1,8 @@
 // Autotuner of the tree/walk parameters: leaf size, i-group size and targets
-// per lane. It times tree build + long-range force for each candidate on the
-// caller's particles and keeps the fastest; results are cached as JSON lines
-// keyed by (floor(log2 N), theta, precision).
+// per lane. It times a step (tree build + long-range force + neighbour
+// lists) for each candidate on the caller's particles and keeps the
+// fastest; results are cached as JSON lines keyed by (floor(log2 N), theta,
+// precision), and petar_autotune_lookup reads them back for an N hint.
 //
 // The paper tunes its integrator parameters (dt_L, r_out) by scanning
 // wall-clock time over a range of values (Sec. "Performance on GPU-based
@@ -91,6 +92,22 @@ void write_cache(const char *path, const std::vector<Entry> &entries) {
 
 }  // namespace
 
+extern "C" petar_status petar_autotune_lookup(petar_ctx *ctx, int64_t N_hint, double theta,
+                                              const char *cache_path, petar_tuned *out) {
+    if (!ctx || !out || !cache_path || N_hint < 1 || !(theta >= 0.0)) return PETAR_E_INVALID;
+    petar_params p;
+    petar_status st = petar_get_params(ctx, &p);
+    if (st != PETAR_OK) return st;
+    const int nb = n_bucket(N_hint);
+    for (const Entry &e : read_cache(cache_path)) {
+        if (same_key(e, nb, theta, p.precision)) {
+            *out = e.t;
+            return PETAR_OK;
+        }
+    }
+    return PETAR_E_STATE;
+}
+
 extern "C" petar_status petar_autotune(petar_ctx *ctx, const double *pos, const double *mass,
                                        int64_t N, double theta, const double *r_in,
                                        const double *r_out, const double *r_search,
@@ -112,37 +129,65 @@ extern "C" petar_status petar_autotune(petar_ctx *ctx, const double *pos, const 
         // let the entry points report the exact problem
         return petar_tree_build(ctx, pos, mass, N, theta, 8);
     }
-    // scratch outputs for the timing runs
-    double *acc = nullptr, *pot = nullptr;
     {
         petar_status chk = petar_tree_build(ctx, pos, mass, N, theta, 8);
         if (chk != PETAR_OK) return chk;
     }
-    if (hipMalloc((void **)&acc, (size_t)N * 3 * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&pot, (size_t)N * sizeof(double)) != hipSuccess) {
+    // Scratch outputs of the timing runs, neighbour lists included (a step
+    // of the hot path returns them): the capacity is what the first
+    // candidate needs plus a quarter, grown when a later one needs more.
+    double *acc = nullptr, *pot = nullptr;
+    int64_t *offs = nullptr;
+    int32_t *idx = nullptr;
+    int64_t cap = 0;
+    auto release = [&]() {
         if (acc) (void)hipFree(acc);
+        if (pot) (void)hipFree(pot);
+        if (offs) (void)hipFree(offs);
+        if (idx) (void)hipFree(idx);
+        acc = pot = nullptr;
+        offs = nullptr;
+        idx = nullptr;
+    };
+    if (hipMalloc((void **)&acc, (size_t)N * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&pot, (size_t)N * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&offs, (size_t)(N + 1) * sizeof(int64_t)) != hipSuccess) {
+        release();
         return PETAR_E_NOMEM;
     }
-    const int leaves[] = {4, 8, 16, 32};
-    const int groups[] = {32, 64, 128, 256};
-    const int ipls[] = {1, 2, 4};
+    const int leaves[] = {4, 8, 16};
+    const int groups[] = {32, 48, 64, 96, 128, 192, 256};
+    const int ipls[] = {1, 2};
     petar_tuned best{};
     best.ms = -1.0;
     for (int leaf : leaves) {
         for (int group : groups) {
             for (int ipl : ipls) {
-                if (ipl > 1 && group <= 64) continue;
-                if (ipl * 64 < group / 2) continue;
+                if (ipl > 1 && group < 32) continue;
                 p.i_per_lane = ipl;
-                if ((st = petar_set_params(ctx, &p)) != PETAR_OK) return st;
+                if ((st = petar_set_params(ctx, &p)) != PETAR_OK) {
+                    release();
+                    return st;
+                }
                 double ms[3];
                 for (int rep = 0; rep < 3; rep++) {  // first call warms up
                     st = petar_tree_build(ctx, pos, mass, N, theta, leaf);
+                    petar_nblist nbl{offs, idx, cap, 0};
                     if (st == PETAR_OK)
-                        st = petar_force_long(ctx, group, r_in, r_out, r_search, acc, pot, nullptr);
+                        st = petar_force_long(ctx, group, r_in, r_out, r_search, acc, pot, &nbl);
+                    if (st == PETAR_E_NB_OVERFLOW) {
+                        if (idx) (void)hipFree(idx);
+                        idx = nullptr;
+                        cap = nbl.required + nbl.required / 4 + 1;
+                        if (hipMalloc((void **)&idx, (size_t)cap * sizeof(int32_t)) != hipSuccess) {
+                            release();
+                            return PETAR_E_NOMEM;
+                        }
+                        rep--;  // not timed: repeat with room for the lists
+                        continue;
+                    }
                     if (st != PETAR_OK) {
-                        (void)hipFree(acc);
-                        (void)hipFree(pot);
+                        release();
                         return st;
                     }
                     petar_stats s;
@@ -159,8 +204,7 @@ extern "C" petar_status petar_autotune(petar_ctx *ctx, const double *pos, const 
             }
         }
     }
-    (void)hipFree(acc);
-    (void)hipFree(pot);
+    release();
     p.i_per_lane = best.i_per_lane;
     if ((st = petar_set_params(ctx, &p)) != PETAR_OK) return st;
     *out = best;

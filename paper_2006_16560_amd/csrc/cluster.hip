@@ -265,15 +265,14 @@ __global__ __launch_bounds__(kThreads) void k_group_pairs(const int64_t *off, co
         uint32_t f = 0;
         if (off[g + 1] - off[g] == 2) {
             const int64_t i = mem[off[g]], j = mem[off[g] + 1];
-            double r2 = 0.0, v2 = 0.0;
-            for (int d = 0; d < 3; d++) {
-                const double dx = pos[d * n + j] - pos[d * n + i];
-                const double dv = vel[d * n + j] - vel[d * n + i];
-                r2 += dx * dx;
-                v2 += dv * dv;
-            }
-            const double r = sqrt(r2);
-            f = (r > 0.0 && 0.5 * v2 - G * (mass[i] + mass[j]) / r < 0.0) ? 1u : 0u;
+            const double r[3] = {pos[j] - pos[i], pos[n + j] - pos[n + i],
+                                 pos[2 * n + j] - pos[2 * n + i]};
+            const double v[3] = {vel[j] - vel[i], vel[n + j] - vel[n + i],
+                                 vel[2 * n + j] - vel[2 * n + i]};
+            const double mu = G * (mass[i] + mass[j]);
+            double rr;
+            const double E = kepler_energy(r, v, mu, &rr);
+            f = (rr > 0.0 && E < 0.0) ? 1u : 0u;
         }
         is_pair[g] = f;
     }

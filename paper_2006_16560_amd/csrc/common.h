@@ -182,6 +182,21 @@ __device__ __forceinline__ double sum_sq3(double gx, double gy, double gz) {
     return s + zz;
 }
 
+// Specific Kepler energy v^2/2 - mu/|r| of a pair (eq. dr) from its relative
+// position r and velocity v, with |r| in *rr. Its sign decides integer
+// outputs (which pairs are bound binaries), so every operation is rounded
+// as written: squares summed x, y, then z, no contraction.
+__device__ __forceinline__ double kepler_energy(const double r[3], const double v[3], double mu,
+                                                double *rr) {
+#pragma clang fp contract(off)
+    const double r2 = sum_sq3(r[0], r[1], r[2]);
+    const double v2 = sum_sq3(v[0], v[1], v[2]);
+    *rr = sqrt(r2);
+    const double kin = 0.5 * v2;
+    const double pot = mu / *rr;
+    return kin - pot;
+}
+
 // Neighbour relation of the first search stage: d^2 < max(rs_i, rs_j)^2.
 __device__ __forceinline__ bool nb_pair(double xi, double yi, double zi, double rsi, double xj,
                                         double yj, double zj, double rsj) {

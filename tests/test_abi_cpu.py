@@ -211,6 +211,36 @@ def test_autotune_cache_hit_without_device(capi, ctx, tmp_path):
     assert st == _capi.PETAR_E_INVALID
 
 
+def test_autotune_lookup_by_n_hint(capi, ctx, tmp_path):
+    """petar_autotune_lookup reads a stored choice for (N hint, theta, the
+    context's precision) without particles or a device; a miss is
+    PETAR_E_STATE, bad arguments PETAR_E_INVALID."""
+    _capi, lib = capi
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"n_bucket": 20, "theta": 0.5, "precision": 0, "leaf_size": 16, '
+                     '"group_size": 96, "i_per_lane": 2, "ms": 3.5}\n'
+                     '{"n_bucket": 20, "theta": 0.5, "precision": 1, "leaf_size": 4, '
+                     '"group_size": 32, "i_per_lane": 1, "ms": 9.0}\n')
+    out = _capi.petar_tuned()
+    path = str(cache).encode()
+    assert lib.petar_autotune_lookup(ctx, (1 << 20) + 7, 0.5, path, ctypes.byref(out)) == 0
+    assert (out.leaf_size, out.group_size, out.i_per_lane, out.ms) == (16, 96, 2, 3.5)
+    p = _capi.petar_params()
+    lib.petar_get_params(ctx, ctypes.byref(p))
+    p.precision = _capi.PETAR_FP64
+    lib.petar_set_params(ctx, ctypes.byref(p))
+    assert lib.petar_autotune_lookup(ctx, 1 << 20, 0.5, path, ctypes.byref(out)) == 0
+    assert (out.leaf_size, out.group_size, out.i_per_lane) == (4, 32, 1)
+    for n_hint, theta in ((1 << 21, 0.5), (1 << 20, 0.3)):
+        st = lib.petar_autotune_lookup(ctx, n_hint, theta, path, ctypes.byref(out))
+        assert st == _capi.PETAR_E_STATE
+    missing = str(tmp_path / "none.jsonl").encode()
+    assert lib.petar_autotune_lookup(ctx, 1 << 20, 0.5, missing, ctypes.byref(out)) == \
+        _capi.PETAR_E_STATE
+    for args in ((0, 0.5, path), (1 << 20, -1.0, path), (1 << 20, 0.5, None)):
+        assert lib.petar_autotune_lookup(ctx, *args, ctypes.byref(out)) == _capi.PETAR_E_INVALID
+
+
 @pytest.mark.parametrize("offs,ok", [
     ([0, 10, 25], True),
     ([0, 1], True),

@@ -9,12 +9,15 @@ quadrupole expansion) or brute force on tiny inputs.
 """
 
 import math
+import sys
 import os
 
 import numpy as np
 import pytest
 
 import workloads
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -520,12 +523,22 @@ _TT_NAMES = ["xx", "xy", "xz", "yy", "yz", "zz", "xxx", "xxy", "xxz", "xyy", "xy
 def test_tidal_generalized_inverse_equals_table_a(orc):
     """The least-squares inverse of the measure-point map reproduces the
     printed closed forms of Table A, row by row."""
+    def value(text):
+        # the paper's printed form: +-a/b or +-sqrt2/b
+        sign = -1.0 if text[0] == "-" else 1.0
+        num, den = text.lstrip("+-").split("/")
+        top = math.sqrt(2.0) if num == "sqrt2" else float(num)
+        return sign * top / float(den)
+
     rows = {}
     for line in open(os.path.join(os.path.dirname(__file__), "golden", "tidal_table_a.txt")):
         if line.startswith("#") or not line.strip():
             continue
         order, name, point, comp, val = line.split()
-        rows.setdefault((int(order), name), {})[(int(point) - 1, "xyz".index(comp))] = float(val)
+        rows.setdefault((int(order), name), {})[(int(point) - 1, "xyz".index(comp))] = value(val)
+    # every row of both blocks of the table
+    assert sorted(k for k in rows if k[0] == 2) == sorted((2, nm) for nm in _TT_NAMES[:6])
+    assert sorted(k for k in rows if k[0] == 3) == sorted((3, nm) for nm in _TT_NAMES)
     for (order, name), want in rows.items():
         g = orc.tidal_ginv(order)[_TT_NAMES.index(name)]
         got = {(r // 3, r % 3): v for r, v in enumerate(g) if abs(v) > 1e-14}
@@ -835,3 +848,52 @@ def test_kick_is_exact_on_dyadic_values(orc):
     out = orc.kick(v, a, 2.0 ** -8)
     assert np.array_equal(out, v + a / 256.0)
     assert np.array_equal(orc.kick(out, a, -(2.0 ** -8)), v)
+
+
+def test_kick_drives_a_kepler_orbit(orc):
+    """The kick is pinned by the mechanics it serves: a kick-drift-kick
+    integration whose kicks are oracle.kick with the long-range field of the
+    direct sum (the pair stays beyond r_out, so the field is Newtonian)
+    carries two equal masses around their circular orbit. The separation
+    stays 1 and after one period 2 pi sqrt(a^3 / (G M)) both bodies are back
+    at their start, within the O(dt^2) phase error of the leapfrog. A kick
+    with the wrong sign, without dt or with the full step breaks the orbit."""
+    pos = np.array([[0.5, -0.5], [0.0, 0.0], [0.0, 0.0]])
+    vel = np.array([[0.0, 0.0], [0.5, -0.5], [0.0, 0.0]])
+    mass = np.array([0.5, 0.5])
+    r_in, r_out = np.full(2, 0.01), np.full(2, 0.1)
+    steps = 2000
+    dt = 2.0 * math.pi / steps
+    start = pos.copy()
+    acc, _ = orc.force_long(pos, mass, r_in, r_out)
+    worst = 0.0
+    for _ in range(steps):
+        vel = orc.kick(vel, acc, 0.5 * dt)
+        pos = pos + vel * dt
+        acc, _ = orc.force_long(pos, mass, r_in, r_out)
+        vel = orc.kick(vel, acc, 0.5 * dt)
+        worst = max(worst, abs(np.linalg.norm(pos[:, 0] - pos[:, 1]) - 1.0))
+    assert worst < 2e-5, worst
+    assert np.abs(pos - start).max() < 1e-4, np.abs(pos - start).max()
+
+
+def test_binaries_near_zero_energy(orc):
+    """Pairs within a few ulp of zero Kepler energy: the oracle's bound
+    binaries are the pairs whose energy, rounded as written, is negative;
+    evaluating the squares with fused multiply-adds flips some of them, so
+    the same set pins the GPU's decision to the unfused rounding."""
+    from critical_pairs import fused_signs, near_zero_energy_pairs
+    pos, vel, mass = near_zero_energy_pairs(1500, 3)
+    n = pos.shape[1]
+    _, _, _, pairs = orc.groups(pos, vel, mass, np.full(n, 0.01), 0.5)
+    want = []
+    for b in range(n // 2):
+        r = pos[:, 2 * b + 1] - pos[:, 2 * b]
+        v = vel[:, 2 * b + 1] - vel[:, 2 * b]
+        rr = math.sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2])
+        E = 0.5 * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]) - (mass[2 * b] + mass[2 * b + 1]) / rr
+        if E < 0.0:
+            want.append((2 * b, 2 * b + 1))
+    assert pairs.tolist() == [list(p) for p in want]
+    flipped = fused_signs(pos, vel, mass) != np.isin(np.arange(n // 2), [p[0] // 2 for p in want])
+    assert flipped.sum() >= 10, flipped.sum()
