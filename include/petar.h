@@ -288,6 +288,23 @@ PETAR_API petar_status petar_clusters(petar_ctx *ctx, int64_t N, const int64_t *
                                       int64_t *cl_offsets_dev, int32_t *members_dev,
                                       int64_t *n_clusters);
 
+/* petar_clusters for callers that cannot allocate device memory (code under
+ * stream or graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, with the scratch
+ * taken from a fixed array of 40 MiB that every device the library runs on
+ * holds from its first petar_create on that device until the process ends.
+ * No hipMalloc, hipFree or other allocation is made by the call.
+ * N <= 1048576 (2^20); a larger N returns PETAR_E_INVALID (use
+ * petar_clusters). All calls on one device share its array, which keeps the
+ * last call's contents: calls that overlap on one device (other streams,
+ * other contexts, other host threads) race and must be serialised by the
+ * caller. Returns after the same status read as petar_clusters. */
+PETAR_API petar_status petar_clusters_noalloc(petar_ctx *ctx, int64_t N,
+                                              const int64_t *nb_offsets_dev,
+                                              const int32_t *nb_idx_dev, int32_t *label_dev,
+                                              int64_t *cl_offsets_dev, int32_t *members_dev,
+                                              int64_t *n_clusters);
+
 /* SDAR groups (Sec. "SDAR", eq. rbin): connected components of the pairs
  * with r_ij < theta r_in,ij, r_in,ij = max(r_in,i, r_in,j) (FP64, tested
  * as d^2 < (theta r_in,ij)^2), among the candidate CSR cand_offsets_dev

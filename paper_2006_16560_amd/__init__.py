@@ -25,7 +25,7 @@ _lib = _capi.load()
 __all__ = [
     "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
     "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_batch_build",
-    "petar_force_long", "petar_step_graph", "petar_nb_filter", "petar_clusters",
+    "petar_force_long", "petar_step_graph", "petar_nb_filter", "petar_clusters", "petar_clusters_noalloc",
     "petar_force_long_kick", "petar_groups", "petar_kick", "petar_artificial_make",
     "petar_tidal_fit", "petar_tidal_eval",
     "art_points",
@@ -275,17 +275,31 @@ def petar_nb_filter(ctx: Context, pos: torch.Tensor, vel: torch.Tensor, mass: to
 def petar_clusters(ctx: Context, offsets: torch.Tensor, idx: torch.Tensor):
     """Clusters of the neighbour CSR: (label int32 [N], cluster offsets
     int64 [n_clusters + 1], members int32 [N]); see petar.h."""
+    return _clusters(_lib.petar_clusters, ctx, offsets, idx)
+
+
+def petar_clusters_noalloc(ctx: Context, offsets: torch.Tensor, idx: torch.Tensor, out=None):
+    """petar_clusters with the library's fixed scratch (N <= 2^20, no device
+    allocation inside the call). `out` = (label, cl_offsets, members) of
+    sizes N, N + 1, N may be passed in to allocate nothing here either."""
+    return _clusters(_lib.petar_clusters_noalloc, ctx, offsets, idx, out)
+
+
+def _clusters(fn, ctx: Context, offsets: torch.Tensor, idx: torch.Tensor, out=None):
     n = offsets.shape[0] - 1
     dev = ctx.device
     d = "cuda:%d" % dev
-    label = torch.empty(n, dtype=torch.int32, device=d)
-    cl = torch.empty(n + 1, dtype=torch.int64, device=d)
-    members = torch.empty(n, dtype=torch.int32, device=d)
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=d),
+               torch.empty(n + 1, dtype=torch.int64, device=d),
+               torch.empty(n, dtype=torch.int32, device=d))
+    label, cl, members = out
     nc = ctypes.c_int64(0)
-    st = _lib.petar_clusters(ctx.handle, n, _dptr(offsets, torch.int64, (n + 1,), "offsets", dev),
-                             _dptr(_nonempty(idx, d), torch.int32, None, "idx", dev),
-                             ctypes.c_void_p(label.data_ptr()), ctypes.c_void_p(cl.data_ptr()),
-                             ctypes.c_void_p(members.data_ptr()), ctypes.byref(nc))
+    st = fn(ctx.handle, n, _dptr(offsets, torch.int64, (n + 1,), "offsets", dev),
+            _dptr(_nonempty(idx, d), torch.int32, None, "idx", dev),
+            _dptr(label, torch.int32, (n,), "label", dev),
+            _dptr(cl, torch.int64, (n + 1,), "cl_offsets", dev),
+            _dptr(members, torch.int32, (n,), "members", dev), ctypes.byref(nc))
     _check(st, ctx)
     return label, cl[: nc.value + 1], members
 

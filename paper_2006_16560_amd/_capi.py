@@ -90,6 +90,7 @@ SIGNATURES = [
     ("petar_nb_filter", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P,
                                ctypes.POINTER(petar_nblist)]),
     ("petar_clusters", _INT, [_P, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
+    ("petar_clusters_noalloc", _INT, [_P, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
     ("petar_groups", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P, _P, _P, _P,
                             ctypes.POINTER(_I64), _P, _I64, ctypes.POINTER(_I64)]),
     ("petar_kick", _INT, [_P, _I64, _P, _P, _D]),

@@ -292,6 +292,10 @@ petar_status petar_create(petar_ctx **out, int device, void *hip_stream) {
         if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_status, sizeof(Status));
         if (e == hipSuccess) e = hipHostMalloc((void **)&c->host_scalar, kHostScalarWords * sizeof(int64_t));
         for (int k = 0; k < 8 && e == hipSuccess; k++) e = hipEventCreate(&c->ev[k]);
+        // set-up of this device's fixed scratch (petar_clusters_noalloc)
+        void *scratch_ptr = nullptr;
+        size_t scratch_bytes = 0;
+        if (e == hipSuccess) e = noalloc_scratch(device, &scratch_ptr, &scratch_bytes);
         if (e != hipSuccess) {
             petar_destroy(c);
             return fail(nullptr, PETAR_E_HIP, "context setup failed: %s", hipGetErrorString(e));
@@ -400,40 +404,65 @@ petar_status filter_impl(petar_ctx *ctx, FilterArgs a, int64_t *out_offsets, int
     return PETAR_OK;
 }
 
-// Components of a CSR (label, offsets, members as petar_clusters).
-petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
+// Scratch of the clusters pass for n particles.
+struct ClusterWs {
+    int32_t *parent;             // [n] union-find parents
+    uint32_t *root, *rootpos;    // [n + 1] root flags, their exclusive scan
+    int32_t *flags;              // [2] bad offsets, bad index
+    uint64_t *key0, *key1;       // [n] sort keys (double-buffered)
+    uint32_t *val0, *val1;       // [n] sort values
+    void *sort_ws;               // sort_ws_bytes(n)
+    int64_t *scan_ws;            // scan_ws_elems(n + 1)
+};
+
+// Lays ClusterWs out from `base` in 256-byte aligned pieces and returns the
+// bytes it spans; with base == nullptr only the size is computed.
+size_t cluster_ws_carve(char *base, int64_t n, ClusterWs *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    const size_t un = (size_t)n;
+    ClusterWs c;
+    c.parent = (int32_t *)take(un * 4);
+    c.root = (uint32_t *)take((un + 1) * 4);
+    c.rootpos = (uint32_t *)take((un + 1) * 4);
+    c.flags = (int32_t *)take(8);
+    c.key0 = (uint64_t *)take(un * 8);
+    c.key1 = (uint64_t *)take(un * 8);
+    c.val0 = (uint32_t *)take(un * 4);
+    c.val1 = (uint32_t *)take(un * 4);
+    c.sort_ws = take((size_t)sort_ws_bytes(n));
+    c.scan_ws = (int64_t *)take((size_t)scan_ws_elems(n + 1) * 8);
+    if (w) *w = c;
+    return off;
+}
+
+// Components of a CSR (label, offsets, members as petar_clusters) with the
+// scratch in w.
+petar_status clusters_core(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
                            const int32_t *nb_idx, int32_t *label, int64_t *cl_offsets,
-                           int32_t *members, int64_t *n_clusters) {
+                           int32_t *members, int64_t *n_clusters, const ClusterWs &w) {
     hipStream_t s = ctx->stream;
-    TRY(ensure(ctx, ctx->cl_parent, (size_t)n * 4));
-    TRY(ensure(ctx, ctx->cl_root, (size_t)(n + 1) * 4));
-    TRY(ensure(ctx, ctx->cl_rootpos, (size_t)(n + 1) * 4));
-    TRY(ensure(ctx, ctx->cl_flags, 8));
-    TRY(ensure(ctx, ctx->cl_key0, (size_t)n * 8));
-    TRY(ensure(ctx, ctx->cl_key1, (size_t)n * 8));
-    TRY(ensure(ctx, ctx->cl_val0, (size_t)n * 4));
-    TRY(ensure(ctx, ctx->cl_val1, (size_t)n * 4));
-    TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(n)));
-    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
     // flags = {bad offsets, bad index}
-    int32_t *csr_bad = ptr<int32_t>(ctx->cl_flags), *bad = csr_bad + 1;
-    fill_i64(ptr<int64_t>(ctx->cl_flags), 0, 1, s);
+    int32_t *csr_bad = w.flags, *bad = csr_bad + 1;
+    fill_i64((int64_t *)w.flags, 0, 1, s);
     launch_check_csr(nb_offsets, n, csr_bad, s);
-    uint32_t *root = ptr<uint32_t>(ctx->cl_root), *rootpos = ptr<uint32_t>(ctx->cl_rootpos);
-    launch_components(nb_offsets, nb_idx, n, ptr<int32_t>(ctx->cl_parent), label, root, bad,
-                      csr_bad, s);
-    scan_u32_to_u32(root, rootpos, n, ptr<int64_t>(ctx->scan_ws), s);
+    launch_components(nb_offsets, nb_idx, n, w.parent, label, w.root, bad, csr_bad, s);
+    scan_u32_to_u32(w.root, w.rootpos, n, w.scan_ws, s);
     // members: stable radix sort of the particle indices by cluster index
-    uint64_t *k = ptr<uint64_t>(ctx->cl_key0), *ka = ptr<uint64_t>(ctx->cl_key1);
-    uint32_t *v = ptr<uint32_t>(ctx->cl_val0), *va = ptr<uint32_t>(ctx->cl_val1);
-    launch_cluster_keys(label, n, rootpos, k, v, s);
+    uint64_t *k = w.key0, *ka = w.key1;
+    uint32_t *v = w.val0, *va = w.val1;
+    launch_cluster_keys(label, n, w.rootpos, k, v, s);
     int passes = 1;
     while (passes < 4 && (n - 1) >> (8 * passes)) passes++;
-    radix_sort(&k, &v, &ka, &va, n, passes, ctx->sort_ws.p, s);
+    radix_sort(&k, &v, &ka, &va, n, passes, w.sort_ws, s);
     HIP_TRY(ctx, hipMemcpyAsync(members, v, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
     launch_cluster_offsets(k, n, cl_offsets, s);
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, rootpos + n, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, w.rootpos + n, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, csr_bad, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     int32_t fl[2] = {0, 0};
@@ -444,6 +473,34 @@ petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
     memcpy(&nc, ctx->host_scalar, 4);
     *n_clusters = nc;
     return PETAR_OK;
+}
+
+// petar_clusters with the scratch in the context's workspace.
+petar_status clusters_impl(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
+                           const int32_t *nb_idx, int32_t *label, int64_t *cl_offsets,
+                           int32_t *members, int64_t *n_clusters) {
+    TRY(ensure(ctx, ctx->cl_parent, (size_t)n * 4));
+    TRY(ensure(ctx, ctx->cl_root, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_rootpos, (size_t)(n + 1) * 4));
+    TRY(ensure(ctx, ctx->cl_flags, 8));
+    TRY(ensure(ctx, ctx->cl_key0, (size_t)n * 8));
+    TRY(ensure(ctx, ctx->cl_key1, (size_t)n * 8));
+    TRY(ensure(ctx, ctx->cl_val0, (size_t)n * 4));
+    TRY(ensure(ctx, ctx->cl_val1, (size_t)n * 4));
+    TRY(ensure(ctx, ctx->sort_ws, (size_t)sort_ws_bytes(n)));
+    TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n + 1) * 8));
+    ClusterWs w;
+    w.parent = ptr<int32_t>(ctx->cl_parent);
+    w.root = ptr<uint32_t>(ctx->cl_root);
+    w.rootpos = ptr<uint32_t>(ctx->cl_rootpos);
+    w.flags = ptr<int32_t>(ctx->cl_flags);
+    w.key0 = ptr<uint64_t>(ctx->cl_key0);
+    w.key1 = ptr<uint64_t>(ctx->cl_key1);
+    w.val0 = ptr<uint32_t>(ctx->cl_val0);
+    w.val1 = ptr<uint32_t>(ctx->cl_val1);
+    w.sort_ws = ctx->sort_ws.p;
+    w.scan_ws = ptr<int64_t>(ctx->scan_ws);
+    return clusters_core(ctx, n, nb_offsets, nb_idx, label, cl_offsets, members, n_clusters, w);
 }
 
 }  // namespace
@@ -460,6 +517,30 @@ petar_status petar_clusters(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets
     if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     return clusters_impl(ctx, n, nb_offsets, nb_idx, label, cl_offsets, members, n_clusters);
+}
+
+petar_status petar_clusters_noalloc(petar_ctx *ctx, int64_t n, const int64_t *nb_offsets,
+                                    const int32_t *nb_idx, int32_t *label, int64_t *cl_offsets,
+                                    int32_t *members, int64_t *n_clusters) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (const char *m = check_cluster_args(n, nb_offsets, nb_idx, label, cl_offsets, members,
+                                           n_clusters))
+        return fail(ctx, PETAR_E_INVALID, "%s", m);
+    if (n > kNoAllocMaxN)
+        return fail(ctx, PETAR_E_INVALID,
+                    "N = %lld exceeds the fixed scratch of petar_clusters_noalloc "
+                    "(at most %lld particles); use petar_clusters",
+                    (long long)n, (long long)kNoAllocMaxN);
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    void *base = nullptr;
+    size_t bytes = 0;
+    HIP_TRY(ctx, noalloc_scratch(ctx->device, &base, &bytes));
+    ClusterWs w;
+    if (cluster_ws_carve((char *)base, n, &w) > bytes)
+        return fail(ctx, PETAR_E_INTERNAL, "fixed scratch of %zu bytes too small for N = %lld",
+                    bytes, (long long)n);
+    return clusters_core(ctx, n, nb_offsets, nb_idx, label, cl_offsets, members, n_clusters, w);
 }
 
 petar_status petar_nb_filter(petar_ctx *ctx, int64_t n, const double *pos, const double *vel,
@@ -1147,6 +1228,7 @@ petar_status petar_get_stats(petar_ctx *ctx, petar_stats *out) {
         HIP_TRY(ctx, hipSetDevice(ctx->device));
         TRY(settle_build_stats(ctx, false));
     }
+    ctx->stats.workspace_bytes = ctx->ws_bytes;
     *out = ctx->stats;
     return PETAR_OK;
 }

@@ -13,6 +13,8 @@
 // Clusters: connected components of the kept pairs by a one-pass union-find
 // whose roots are the smallest index of each component (so the result does
 // not depend on the order of the unions).
+#include <mutex>
+
 #include "launch.h"
 
 namespace petar {
@@ -351,6 +353,33 @@ void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_o
     fill_i64(cl_offsets, n, n + 1, s);
     hipLaunchKernelGGL(k_cl_offsets, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s,
                        sorted_key, n, cl_offsets);
+}
+
+namespace {
+
+// The scratch of petar_clusters_noalloc. Its name is a host-side stand-in
+// in host code: kernels get the per-device address kept below.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void **out, size_t *bytes) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    *bytes = sizeof(scratch);
+    return hipSuccess;
 }
 
 }  // namespace petar

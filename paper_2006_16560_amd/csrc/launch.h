@@ -188,6 +188,14 @@ void launch_cluster_keys(const int32_t *label, int64_t n, const uint32_t *root_p
                          uint32_t *val, hipStream_t s);
 void launch_cluster_offsets(const uint64_t *sorted_key, int64_t n, int64_t *cl_offsets,
                             hipStream_t s);
+// Fixed device scratch of petar_clusters_noalloc: one array of
+// kNoAllocScratchBytes per device, in the code object's static data, so the
+// call needs no allocation. noalloc_scratch() must be called with `device`
+// current; the first call on a device looks the array up
+// (hipGetSymbolAddress) and keeps its address, later calls return it.
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 20;
+constexpr size_t kNoAllocScratchBytes = size_t(40) << 20;
+hipError_t noalloc_scratch(int device, void **ptr, size_t *bytes);
 // Binaries among the groups: is_pair[g] = 1 for a group of exactly two
 // members with negative Kepler energy (G (m1 + m2) / r > v^2 / 2).
 void launch_group_pairs(const int64_t *grp_offsets, const int32_t *members, int64_t n_groups,
