@@ -225,6 +225,10 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters of a profiler) and exit")
+    ap.add_argument("--autotune", default=None, metavar="CACHE",
+                    help="only run petar_autotune for every (workload, theta) of this benchmark, "
+                         "writing a fresh cache file CACHE (the package reads "
+                         "paper_2006_16560_amd/tuned.jsonl), and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -245,6 +249,8 @@ def main() -> int:
         torch.cuda.synchronize()
         log("copied %d bytes 5 times" % nbytes)
         return 0
+    if args.autotune:
+        return autotune(pt, workloads, args.autotune)
     if args.workload == "batched128":
         line = run_batched(pt, workloads, args, args.steps, args.warmup)
         print(json.dumps(line), flush=True)
@@ -360,6 +366,44 @@ def main() -> int:
         torch.cuda.empty_cache()
         line["plummer10m_b10"] = run_10m(pt, workloads, args, threads)
     print(json.dumps(line), flush=True)
+    return 0
+
+
+# (workload, theta) pairs whose launch configuration the autotuner picks: the
+# 1M cluster at the paper's opening angles and the 10M cluster at theta 0.5
+TUNED_JOBS = [("plummer1m_b100", 0.5), ("plummer1m_b100", 0.3), ("plummer1m_b100", 0.7),
+              ("plummer10m_b10", 0.5)]
+
+
+def autotune(pt, workloads, cache) -> int:
+    """petar_autotune on each job's particles and radii: it times a full step
+    for every candidate leaf size, group size and number of targets per lane
+    and appends the fastest to `cache` (keyed by floor(log2 N), theta and
+    precision)."""
+    import torch
+    if os.path.exists(cache):
+        os.remove(cache)
+    dev = "cuda:0"
+    made = {}
+    for name, theta in TUNED_JOBS:
+        wl = workloads.WORKLOADS[name]
+        if name not in made:
+            made.clear()
+            torch.cuda.empty_cache()
+            c = workloads.make_cluster(wl.n, 0, imf=wl.imf, binary_fraction=wl.binary_fraction)
+            made[name] = (torch.from_numpy(c.pos).to(dev), torch.from_numpy(c.mass).to(dev))
+        pos, mass = made[name]
+        ctx = pt.petar_create(0)
+        try:
+            pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+            ri, ro, rs = pt.petar_changeover_radii(ctx, mass, wl.r_in_ref, wl.r_out_ref,
+                                                   wl.search_factor)
+            t0 = time.time()
+            best = pt.petar_autotune(ctx, pos, mass, theta, ri, ro, rs, cache_path=cache)
+            log(json.dumps({"workload": name, "theta": theta, "tuned": best,
+                            "seconds": round(time.time() - t0, 1)}))
+        finally:
+            pt.petar_destroy(ctx)
     return 0
 
 
