@@ -593,6 +593,9 @@ def bench_artificial(pt, ctx, c, wl, theta, cfg, dev, reps=5, order=3):
         g = timed("make", lambda: pt.petar_artificial_make(ctx, pos, vel, mass, ri, ro, rs, pairs,
                                                            order, 1.0))
         timed("set_build", lambda: pt.petar_tree_build(ctx, g["pos"], g["mass"], theta, leaf))
+        # pseudoparticles act as sources only: the force is wanted on the
+        # singles, centres and measure points
+        pt.petar_set_targets(ctx, g["target"])
         a_set, p_set = timed("set_force", lambda: pt.petar_force_long(
             ctx, group, g["r_in"], g["r_out"], g["r_search"]))
         st = pt.petar_get_stats(ctx)
@@ -603,6 +606,7 @@ def bench_artificial(pt, ctx, c, wl, theta, cfg, dev, reps=5, order=3):
     out = {k + "_ms": 1e3 * float(np.median(t)) for k, t in times.items()}
     out.update({"order": order, "n_groups": int(go.numel() - 1), "binaries": int(pairs.shape[1]),
                 "set_particles": int(g["mass"].numel()),
+                "set_targets": int(g["target"].sum().item()),
                 "set_interactions": int(st["inter_pc"] + st["inter_far"] + st["inter_near"]),
                 "set_force_kernel_ms": st["ms_force_kernel"]})
     log("groups/artificial: %s" % json.dumps(out))

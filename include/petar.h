@@ -177,6 +177,23 @@ PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const do
                               const double *r_out_dev, const double *r_search_dev,
                               double *acc_dev, double *pot_dev, petar_nblist *nb);
 
+/* Restricts the following petar_force_long / petar_force_long_kick calls on
+ * the current tree to a subset of target particles: target_dev[N] (uint8,
+ * input order, caller-owned and kept alive until those calls return),
+ * nonzero for a particle whose force is wanted. Every particle still acts as
+ * a source. The force, potential (and kick) of the others are not computed:
+ * their acc and pot entries are set to 0 and their velocities are left
+ * alone. This gives the particles of the artificial set their roles (Sec.
+ * "Artificial particle algorithm for weak perturbation"): the measure points
+ * only receive the long-range force, the pseudoparticles (eq. psep) only
+ * exert it (petar_art_set.target_dev). The targets' forces are those of an
+ * unrestricted call up to the rounding order of their sums (a group's
+ * targets may be spread differently over the lanes). NULL restores every
+ * particle as a target; a new tree build does too. Neighbour lists cannot be asked for
+ * while a subset is set (PETAR_E_INVALID). Errors: PETAR_E_STATE without a
+ * tree. */
+PETAR_API petar_status petar_set_targets(petar_ctx *ctx, const uint8_t *target_dev);
+
 /* petar_force_long with the long-range kick of the KDK cycle fused into its
  * output write (eq. lfmap): additionally vel_dev[3][N] (input order) +=
  * dt * acc, rounded as v + (a dt) in FP64; dt (the half step) finite.
@@ -352,6 +369,10 @@ typedef struct {
     double *r_search_dev; /* [n_out]                                             */
     int32_t *src_dev;     /* [n_out]: input index of a single, -1 if artificial  */
     int64_t n_out;        /* must equal N + n_pair (P + 2)                       */
+    uint8_t *target_dev;  /* [n_out] or NULL: 1 for the particles whose long-range */
+                          /* force is used (singles, centres, measure points), 0 */
+                          /* for pseudoparticles (sources only); for             */
+                          /* petar_set_targets                                   */
 } petar_art_set;
 
 /* Builds the set: the N - 2 n_pair singles first, in input order, then for

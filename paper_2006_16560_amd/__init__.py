@@ -25,7 +25,8 @@ _lib = _capi.load()
 __all__ = [
     "PetarError", "Context", "petar_create", "petar_destroy", "petar_set_params",
     "petar_get_params", "petar_changeover_radii", "petar_tree_build", "petar_batch_build",
-    "petar_force_long", "petar_step_graph", "petar_nb_filter", "petar_clusters", "petar_clusters_noalloc",
+    "petar_force_long", "petar_set_targets", "petar_step_graph", "petar_nb_filter",
+    "petar_clusters", "petar_clusters_noalloc",
     "petar_force_long_kick", "petar_groups", "petar_kick", "petar_artificial_make",
     "petar_tidal_fit", "petar_tidal_eval",
     "art_points",
@@ -161,6 +162,17 @@ def petar_batch_build(ctx: Context, sys_offsets, pos: torch.Tensor, mass: torch.
                                   _dptr(pos, torch.float64, (3, n), "pos", ctx.device),
                                   _dptr(mass, torch.float64, (n,), "mass", ctx.device),
                                   float(theta), int(leaf_size)), ctx)
+
+
+def petar_set_targets(ctx: Context, target: Optional[torch.Tensor]) -> None:
+    """Restrict the next force calls on the current tree to the particles
+    with target[i] != 0 (uint8 (N,)); None: every particle. The tensor must
+    stay alive until those calls return. See petar.h."""
+    if target is not None and target.dim() != 1:
+        raise ValueError("target must be one-dimensional (N,)")
+    _check(_lib.petar_set_targets(ctx.handle, _dptr(target, torch.uint8, None, "target",
+                                                    ctx.device)), ctx)
+    ctx._target = target  # kept alive with the context
 
 
 def petar_force_long(ctx: Context, group_size: int, r_in: torch.Tensor, r_out: torch.Tensor,
@@ -354,8 +366,9 @@ def petar_artificial_make(ctx: Context, pos: torch.Tensor, vel: torch.Tensor, ma
                           pairs: torch.Tensor, order: int = 3, c_d: float = 1.0) -> dict:
     """Set of the long-range force with artificial particles for the bound
     pairs pairs[2, n_pair] (int32): dict(pos (3, n_out), mass, r_in, r_out,
-    r_search, src (int32), frame (4, n_pair), pair_of (N,) int32, n_single);
-    see petar.h."""
+    r_search, src (int32), target (uint8: 0 for the pseudoparticles, which
+    are sources only; for petar_set_targets), frame (4, n_pair), pair_of (N,)
+    int32, n_single); see petar.h."""
     n = mass.shape[0]
     dev = ctx.device
     d = "cuda:%d" % dev
@@ -369,12 +382,14 @@ def petar_artificial_make(ctx: Context, pos: torch.Tensor, vel: torch.Tensor, ma
                r_out=torch.empty(n_out, dtype=torch.float64, device=d),
                r_search=torch.empty(n_out, dtype=torch.float64, device=d),
                src=torch.empty(n_out, dtype=torch.int32, device=d),
+               target=torch.empty(n_out, dtype=torch.uint8, device=d),
                frame=torch.empty((4, n_pair), dtype=torch.float64, device=d),
                pair_of=torch.empty(n, dtype=torch.int32, device=d),
                n_single=n - 2 * n_pair, order=order)
     st_ = _capi.petar_art_set(out["pos"].data_ptr(), out["mass"].data_ptr(),
                               out["r_in"].data_ptr(), out["r_out"].data_ptr(),
-                              out["r_search"].data_ptr(), out["src"].data_ptr(), n_out)
+                              out["r_search"].data_ptr(), out["src"].data_ptr(), n_out,
+                              out["target"].data_ptr())
     frame = out["frame"]
     st = _lib.petar_artificial_make(
         ctx.handle, n, _dptr(pos, torch.float64, (3, n), "pos", dev),

@@ -61,7 +61,7 @@ class petar_art_set(ctypes.Structure):
     _fields_ = [("pos_dev", ctypes.c_void_p), ("mass_dev", ctypes.c_void_p),
                 ("r_in_dev", ctypes.c_void_p), ("r_out_dev", ctypes.c_void_p),
                 ("r_search_dev", ctypes.c_void_p), ("src_dev", ctypes.c_void_p),
-                ("n_out", ctypes.c_int64)]
+                ("n_out", ctypes.c_int64), ("target_dev", ctypes.c_void_p)]
 
 
 # (name, restype, argtypes) of every exported entry point
@@ -89,6 +89,7 @@ SIGNATURES = [
     ("petar_autotune_lookup", _INT, [_P, _I64, _D, ctypes.c_char_p, ctypes.POINTER(petar_tuned)]),
     ("petar_nb_filter", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P,
                                ctypes.POINTER(petar_nblist)]),
+    ("petar_set_targets", _INT, [_P, _P]),
     ("petar_clusters", _INT, [_P, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
     ("petar_clusters_noalloc", _INT, [_P, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_I64)]),
     ("petar_groups", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P, _P, _P, _P,

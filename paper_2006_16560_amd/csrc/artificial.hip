@@ -222,6 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_art_singles(ArtArgs a, const uint3
         a.o_rout[k] = a.r_out[i];
         a.o_rs[k] = a.r_search[i];
         a.src[k] = (int32_t)i;
+        if (a.o_target) a.o_target[k] = 1;
     }
 }
 
@@ -307,6 +308,7 @@ __global__ __launch_bounds__(kPairsPerBlock) void k_art_pairs(ArtArgs a, int32_t
         a.o_rout[o] = L.rout[pr];
         a.o_rs[o] = L.rs[pr];
         a.src[o] = -1;
+        if (a.o_target) a.o_target[o] = q <= P ? 1 : 0;  // pseudoparticles are sources only
     }
 }
 

@@ -47,6 +47,7 @@ struct petar_ctx {
     DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
+    DevBuf tflag, tpos, tidx;  // target compaction (petar_set_targets)
     // second-stage filter and clusters
     DevBuf cl_keep, cl_row, cl_counts, cl_parent, cl_root, cl_rootpos, cl_status, cl_flags,
         cl_key0, cl_key1, cl_val0, cl_val1;
@@ -60,6 +61,7 @@ struct petar_ctx {
 
     bool have_tree = false;
     bool have_counts = false;
+    const uint8_t *target = nullptr;  // caller's target flags (input order), none: all
     int64_t n = 0;
     double theta = 0.0;
     int leaf_size = 0;
@@ -237,7 +239,7 @@ void free_all(petar_ctx *c) {
                       &c->cl_status,   &c->cl_flags,   &c->cl_key0,    &c->cl_key1,
                       &c->cl_val0,  &c->cl_val1,
                       &c->art_single, &c->art_spos, &c->art_status, &c->art_pairof, &c->tt_ginv,
-                      &c->grp_off,  &c->grp_idx,
+                      &c->grp_off,  &c->grp_idx,  &c->tflag,      &c->tpos,       &c->tidx,
                       &c->sys_off};
     for (DevBuf *b : bufs) {
         if (b->p) hipFree(b->p);
@@ -629,7 +631,8 @@ petar_status petar_artificial_make(petar_ctx *ctx, int64_t n, const double *pos,
     fill_i64(ptr<int64_t>(ctx->art_status), 0, 2, s);
     ArtArgs a{pos, vel, mass, r_in, r_out, r_search, n, pairs, n_pair, order, c_d,
               ctx->params.G, n - 2 * n_pair, set->n_out, set->pos_dev, set->mass_dev,
-              set->r_in_dev, set->r_out_dev, set->r_search_dev, set->src_dev, frame, pair_of};
+              set->r_in_dev, set->r_out_dev, set->r_search_dev, set->src_dev, frame, pair_of,
+              set->target_dev};
     launch_art_make(a, ptr<uint32_t>(ctx->art_single), ptr<uint32_t>(ctx->art_spos),
                     ptr<int64_t>(ctx->scan_ws), bad, s);
     HIP_TRY(ctx, hipGetLastError());
@@ -836,6 +839,7 @@ petar_status build_eager(petar_ctx *ctx, const BuildArgs &a) {
     hipStream_t s = ctx->stream;
     ctx->have_tree = false;
     ctx->have_counts = false;
+    ctx->target = nullptr;
     ctx->n = a.n;
     TRY(alloc_build_a(ctx, a));
     TRY(copy_offsets(ctx, a, s));
@@ -919,6 +923,11 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
         TRY(ensure(ctx, ctx->nbhead, (size_t)ctx->nbhead_cap * sizeof(uint4)));
         TRY(ensure(ctx, ctx->nbleaf, (size_t)ctx->nbleaf_cap * sizeof(uint2)));
     }
+    if (ctx->target) {
+        TRY(ensure(ctx, ctx->tflag, (size_t)n * 4));
+        TRY(ensure(ctx, ctx->tpos, (size_t)(n + 1) * 4));
+        TRY(ensure(ctx, ctx->tidx, (size_t)n * 4));
+    }
     TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n_nodes + n + 1) * 8));
     return PETAR_OK;
 }
@@ -943,6 +952,16 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
                     ptr<int64_t>(ctx->scan_ws), s);
     launch_group_compact(pre, t, ptr<uint32_t>(ctx->gflag), ptr<uint32_t>(ctx->gpos),
                          ptr<uint32_t>(ctx->groups), st, s);
+    const uint32_t *tpos = nullptr, *tidx = nullptr;
+    if (ctx->target) {  // targets of each group: a compacted list in Morton order
+        launch_target_flags(ctx->target, t, ptr<uint32_t>(ctx->tflag), a.acc, a.pot, s);
+        scan_u32_to_u32(ptr<uint32_t>(ctx->tflag), ptr<uint32_t>(ctx->tpos), n,
+                        ptr<int64_t>(ctx->scan_ws), s);
+        launch_target_compact(ptr<uint32_t>(ctx->tflag), ptr<uint32_t>(ctx->tpos), n,
+                              ptr<uint32_t>(ctx->tidx), s);
+        tpos = ptr<uint32_t>(ctx->tpos);
+        tidx = ptr<uint32_t>(ctx->tidx);
+    }
 
     ForceLaunch f;
     f.t = t;
@@ -963,6 +982,8 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     f.nb.leaf_cap = a.nb ? ctx->nbleaf_cap : 0;
     f.kick_vel = a.kick_vel;
     f.kick_dt = a.kick_dt;
+    f.tpos = tpos;
+    f.tidx = tidx;
     f.precision = prec;
     f.ipl = ipl;
     if (timed) (void)hipEventRecord(ctx->ev[4], s);
@@ -1066,6 +1087,14 @@ petar_status petar_batch_build(petar_ctx *ctx, int n_sys, const int64_t *sys_off
     return build_eager(ctx, a);
 }
 
+petar_status petar_set_targets(petar_ctx *ctx, const uint8_t *target) {
+    if (!ctx) return fail(nullptr, PETAR_E_INVALID, "ctx is NULL");
+    if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
+    if (!ctx->have_tree) return fail(ctx, PETAR_E_STATE, "petar_tree_build has not succeeded");
+    ctx->target = target;
+    return PETAR_OK;
+}
+
 petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in,
                               const double *r_out, const double *r_search, double *acc,
                               double *pot, petar_nblist *nb) {
@@ -1074,6 +1103,9 @@ petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in
         return fail(ctx, PETAR_E_INVALID, "%s", m);
     if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
     if (!ctx->have_tree) return fail(ctx, PETAR_E_STATE, "petar_tree_build has not succeeded");
+    if (nb && ctx->target)
+        return fail(ctx, PETAR_E_INVALID, "neighbour lists need every particle as a target "
+                                          "(petar_set_targets(ctx, NULL) first)");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ForceArgs a{group_size, r_in, r_out, r_search, acc, pot, nb};
     TRY(alloc_force(ctx, a));
@@ -1091,6 +1123,9 @@ petar_status petar_force_long_kick(petar_ctx *ctx, int group_size, const double 
     if (!std::isfinite(dt)) return fail(ctx, PETAR_E_INVALID, "dt must be finite");
     if (ctx->device == PETAR_NO_DEVICE) return fail(ctx, PETAR_E_NODEVICE, "no device");
     if (!ctx->have_tree) return fail(ctx, PETAR_E_STATE, "petar_tree_build has not succeeded");
+    if (nb && ctx->target)
+        return fail(ctx, PETAR_E_INVALID, "neighbour lists need every particle as a target "
+                                          "(petar_set_targets(ctx, NULL) first)");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ForceArgs a{group_size, r_in, r_out, r_search, acc, pot, nb, vel, dt};
     TRY(alloc_force(ctx, a));
@@ -1118,6 +1153,7 @@ petar_status petar_step_graph(petar_ctx *ctx, int n_sys, const int64_t *sys_offs
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     BuildArgs ba{pos, mass, N, theta, leaf_size, n_sys, sys_offsets};
     ForceArgs fa{group_size, r_in, r_out, r_search, acc, pot, nb};
+    ctx->target = nullptr;  // the step builds a new tree: every particle is a target
 
     // everything the captured launches depend on
     std::vector<int64_t> key = {(int64_t)(intptr_t)pos, (int64_t)(intptr_t)mass, N, n_sys,

@@ -526,20 +526,27 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
         }
         const uint32_t gnode = (uint32_t)uniform((int)f.groups[g]);
         const uint4 ginfo = f.t.nd_info[gnode];
+        const uint32_t gstart = (uint32_t)uniform((int)ginfo.x);
+        const uint32_t gn = (uint32_t)uniform((int)ginfo.y);
+        // the group's targets: all its particles, or the listed subset
+        uint32_t t0 = gstart, tn = gn;
+        if (f.tidx) {
+            t0 = (uint32_t)uniform((int)f.tpos[gstart]);
+            tn = (uint32_t)uniform((int)f.tpos[gstart + gn]) - t0;
+            if (tn == 0) continue;  // sources only: no walk
+        }
         wave_sync();
         if (lane == 0) L.g = load_group(f.t.nd_lo, f.t.nd_hi, gnode);
         wave_sync();
-        const uint32_t gstart = (uint32_t)uniform((int)ginfo.x);
-        const uint32_t gn = (uint32_t)uniform((int)ginfo.y);
-        for (uint32_t chunk = 0; chunk < gn; chunk += CH) {
-            const uint32_t active = gn - chunk < (uint32_t)CH ? gn - chunk : (uint32_t)CH;
+        for (uint32_t chunk = 0; chunk < tn; chunk += CH) {
+            const uint32_t active = tn - chunk < (uint32_t)CH ? tn - chunk : (uint32_t)CH;
             const Layout ly = choose_layout<IPL>(active);
             Targets<R, IPL> T;
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
                 uint32_t off = chunk + u * ly.W + ly.il;
-                bool valid = ly.act && u < ly.nu && off < gn;
-                uint32_t k = gstart + (valid ? off : 0u);
+                bool valid = ly.act && u < ly.nu && off < tn;
+                uint32_t k = f.tidx ? f.tidx[t0 + (valid ? off : 0u)] : gstart + (valid ? off : 0u);
                 double4 p = f.t.ps[k];
                 double2 rr = f.t.rr[k];
                 T.x[u] = (R)(p.x - L.g.c[0]);
@@ -670,6 +677,37 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_target_flags(const uint8_t *target,
+                                                            const uint32_t *orig, int64_t n,
+                                                            uint32_t *flag, double *acc,
+                                                            double *pot) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t o = orig[k];
+        const bool t = target[o] != 0;
+        flag[k] = t ? 1u : 0u;
+        if (!t) {
+            acc[o] = 0.0;
+            acc[n + o] = 0.0;
+            acc[2 * n + o] = 0.0;
+            pot[o] = 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_target_compact(const uint32_t *flag,
+                                                              const uint32_t *tpos, int64_t n,
+                                                              uint32_t *tidx) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        if (flag[k]) tidx[tpos[k]] = (uint32_t)k;
+}
+
+inline unsigned blocks_for(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
 template <typename R, int IPL>
 int resident_for(int device) {
     int per_cu = 0;
@@ -689,6 +727,18 @@ void launch_t(const ForceLaunch &f, int resident_waves, hipStream_t s) {
 }  // namespace
 
 int64_t force_spill_elems_per_wave() { return kSpillCap; }
+
+void launch_target_flags(const uint8_t *target, const TreeDev &t, uint32_t *flag, double *acc,
+                         double *pot, hipStream_t s) {
+    hipLaunchKernelGGL(k_target_flags, dim3(blocks_for(t.n)), dim3(kThreads), 0, s, target,
+                       (const uint32_t *)t.orig, t.n, flag, acc, pot);
+}
+
+void launch_target_compact(const uint32_t *flag, const uint32_t *tpos, int64_t n, uint32_t *tidx,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_target_compact, dim3(blocks_for(n)), dim3(kThreads), 0, s, flag, tpos,
+                       n, tidx);
+}
 
 int force_resident_waves(int precision, int ipl, int device) {
     if (precision == 1) {

@@ -131,7 +131,17 @@ struct ForceLaunch {
     double kick_dt;
     int precision;             // 0 mixed, 1 fp64
     int ipl;                   // 1, 2, 4
+    // optional target subset: tpos[k] = targets before Morton position k
+    // ([n + 1]), tidx = their Morton positions; null: every particle
+    const uint32_t *tpos, *tidx;
 };
+// flag[k] = target[orig[k]] != 0 (Morton order); acc and pot of the
+// particles that are not targets are set to 0 (input order).
+void launch_target_flags(const uint8_t *target, const TreeDev &t, uint32_t *flag, double *acc,
+                         double *pot, hipStream_t s);
+// tidx[tpos[k]] = k for every flagged k.
+void launch_target_compact(const uint32_t *flag, const uint32_t *tpos, int64_t n, uint32_t *tidx,
+                           hipStream_t s);
 int force_resident_waves(int precision, int ipl, int device);
 int64_t force_spill_elems_per_wave();
 void launch_force(const ForceLaunch &f, int resident_waves, hipStream_t s);
@@ -222,6 +232,7 @@ struct ArtArgs {
     int32_t *src;      // [n_out]: input index of a single, -1 for artificial
     double *frame;     // [4][n_pair]: centre of mass, d_c
     int32_t *pair_of;  // [n]: pair of a member, -1 for a single
+    uint8_t *o_target; // optional [n_out]: 1 for singles, centres and measure points
 };
 // bad[0]: index outside [0, n) or i == j; bad[1]: particle in two pairs;
 // bad[2]: pair not bound. single/spos hold n and n + 1 entries.

@@ -471,3 +471,19 @@ def test_force_long_kick_validation(capi, ctx, case):
     st = lib.petar_force_long_kick(ctx, a["group"], FAKE, FAKE, FAKE, a["acc"], FAKE, None,
                                    a["vel"], a["dt"])
     assert st == (_capi.PETAR_E_NODEVICE if case == "ok" else _capi.PETAR_E_INVALID)
+
+
+def test_set_targets_and_noalloc_validation(capi, ctx):
+    """petar_set_targets and petar_clusters_noalloc check their arguments on
+    the host: a NULL context, a context without a device, and an N beyond the
+    fixed scratch of the no-allocation call (rejected before the device
+    check)."""
+    _capi, lib = capi
+    assert lib.petar_set_targets(None, FAKE) == _capi.PETAR_E_INVALID
+    assert lib.petar_set_targets(ctx, FAKE) == _capi.PETAR_E_NODEVICE
+    n_cl = ctypes.c_int64(0)
+    args = (FAKE, FAKE, FAKE, FAKE, FAKE, ctypes.byref(n_cl))
+    assert lib.petar_clusters_noalloc(ctx, (1 << 20) + 1, *args) == _capi.PETAR_E_INVALID
+    assert b"fixed scratch" in lib.petar_last_error(ctx)
+    assert lib.petar_clusters_noalloc(ctx, 1 << 20, *args) == _capi.PETAR_E_NODEVICE
+    assert lib.petar_clusters_noalloc(ctx, 0, *args) == _capi.PETAR_E_INVALID

@@ -830,6 +830,89 @@ def test_artificial_pipeline_theta0_fp64(pt, ctx, orc, order):
     np.testing.assert_allclose(pg, pot, rtol=1e-11)
 
 
+@pytest.mark.parametrize("theta", [0.0, 0.5])
+def test_target_subset_matches_oracle_tree(pt, ctx, orc, theta):
+    """petar_set_targets: the force on a random subset of targets (every
+    particle still a source) against the oracle tree evaluated for exactly
+    those targets -- FP64 within 1e-12 with equal interaction counts; the
+    entries of the other particles are 0; mixed precision against the
+    unrestricted call within the arithmetic bound; the restriction ends with
+    petar_set_targets(None) and with the next tree build."""
+    c, rin, rout, rs = cluster_with_radii(orc, 7000, 81, bf=0.5)
+    rng = np.random.default_rng(82)
+    tgt = (rng.random(c.mass.size) < 0.6).astype(np.uint8)
+    tgt[:64] = 0  # a few groups with no target at all
+    idx = np.flatnonzero(tgt)
+    tgt_d = T(tgt)
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64, i_per_lane=1, record_counts=1)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), theta, 8)
+    pt.petar_set_targets(ctx, tgt_d)
+    acc = torch.full((3, c.mass.size), float("nan"), dtype=torch.float64, device="cuda:0")
+    pot = torch.full((c.mass.size,), float("nan"), dtype=torch.float64, device="cuda:0")
+    pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), acc=acc, pot=pot)
+    cnt = pt.petar_copy_counts(ctx).cpu().numpy()
+    acc, pot = acc.cpu().numpy(), pot.cpu().numpy()
+    st = pt.petar_get_stats(ctx)
+    a_ref, p_ref, cnt_ref = orc.tree_force(c.pos, c.mass, rin, rout, rs, theta, 8, 64, idx=idx)
+    assert np.all(acc[:, tgt == 0] == 0) and np.all(pot[tgt == 0] == 0)
+    same = np.all(cnt[:, idx] == cnt_ref, axis=0)
+    assert same.mean() > 0.999
+    assert rel_err(acc[:, idx], a_ref)[same].max() < 1e-12
+    np.testing.assert_allclose(pot[idx][same], p_ref[same], rtol=1e-12)
+    assert st["inter_pc"] == int(cnt_ref[0].sum())
+    assert st["inter_far"] == int(cnt_ref[1].sum())
+    assert st["inter_near"] == int(cnt_ref[2].sum() - idx.size)
+    # neighbour lists need every particle as a target
+    with pytest.raises(pt.PetarError) as ei:
+        pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=64 * c.mass.size)
+    assert ei.value.status == pt.PETAR_E_INVALID
+    # mixed precision on the subset against the unrestricted mixed call
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=2, record_counts=0)
+    am, _ = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs))
+    am = am.cpu().numpy()
+    pt.petar_set_targets(ctx, None)
+    aa, _ = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs))
+    aa = aa.cpu().numpy()
+    assert np.percentile(rel_err(am[:, idx], aa[:, idx]), 99) < 1e-5
+    assert np.all(am[:, tgt == 0] == 0) and np.all(aa[:, tgt == 0] != 0)
+    # a new tree build drops the restriction
+    pt.petar_set_targets(ctx, tgt_d)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), theta, 8)
+    ab, _ = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs))
+    assert np.array_equal(ab.cpu().numpy(), aa)
+
+
+def test_artificial_set_targets(pt, ctx, orc):
+    """The set's target flags mark singles, centres and measure points; the
+    force on the set restricted to them (pseudoparticles as sources only),
+    followed by the post-fit, equals the unrestricted pipeline within the
+    FP64 tolerance, and the oracle's post-fit at theta = 0."""
+    order = 3
+    c, rin, rout, rs = cluster_with_radii(orc, 3000, 83, bf=0.5)
+    g = _gpu_make(pt, ctx, c, rin, rout, rs, c.pairs, order, 1.0)
+    P = pt.art_points(order)
+    n_single = g["n_single"]
+    want = np.ones(g["mass"].numel(), dtype=np.uint8)
+    blk = np.arange(want.size) - n_single
+    want[(blk >= 0) & (blk % (P + 4) > P)] = 0
+    assert np.array_equal(g["target"].cpu().numpy(), want)
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64, i_per_lane=1, record_counts=0)
+    pt.petar_tree_build(ctx, g["pos"], g["mass"], 0.0, 8)
+    pt.petar_set_targets(ctx, g["target"])
+    a_set, p_set = pt.petar_force_long(ctx, 64, g["r_in"], g["r_out"], g["r_search"])
+    tg, ag, pg = pt.petar_tidal_fit(ctx, g, _pairs_i32(c.pairs), a_set, p_set, pos=T(c.pos))
+    torch.cuda.synchronize()
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+    o = orc.artificial_set(c.pos, c.vel, c.mass, rin, rout, rs, c.pairs, order, 1.0)
+    acc_set, pot_set = orc.force_long(o["pos"], o["mass"], o["r_in"], o["r_out"])
+    rec, acc, pot = orc.artificial_fit(order, o, c.pos, acc_set, pot_set, c.pairs)
+    a_set = a_set.cpu().numpy()
+    assert np.all(a_set[:, want == 0] == 0)
+    assert rel_err(a_set[:, want == 1], acc_set[:, want == 1]).max() < 1e-12
+    assert rel_err(ag.cpu().numpy(), acc).max() < 1e-10
+    np.testing.assert_allclose(pg.cpu().numpy(), pot, rtol=1e-11)
+
+
 def test_artificial_edge_cases(pt, ctx, orc):
     """No pairs (the set is the input), one pair of a two-body system, a
     circular and a radial orbit, and the errors of invalid pairs."""
