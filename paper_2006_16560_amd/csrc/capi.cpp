@@ -43,7 +43,7 @@ struct petar_ctx {
     // tree build
     DevBuf key0, key1, val0, val1, sort_ws, scan_ws, bbox_part, rootbox, status, emit, base;
     DevBuf ps, orig, rank, rr, rsk;
-    DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_info, nd_parent, level_off;
+    DevBuf nd_lo, nd_hi, nd_com, nd_S, nd_q, nd_info, nd_parent, level_off;
     DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
@@ -173,6 +173,7 @@ TreeDev tree_view(petar_ctx *c) {
     t.nd_hi = ptr<double4>(c->nd_hi);
     t.nd_com = ptr<double4>(c->nd_com);
     t.nd_S = ptr<double>(c->nd_S);
+    t.nd_q = ptr<float4>(c->nd_q);
     t.nd_info = ptr<uint4>(c->nd_info);
     t.nd_parent = ptr<uint32_t>(c->nd_parent);
     t.level_off = ptr<uint32_t>(c->level_off);
@@ -230,7 +231,7 @@ void free_all(petar_ctx *c) {
     DevBuf *bufs[] = {&c->key0,     &c->key1,        &c->val0,       &c->val1,       &c->sort_ws,
                       &c->scan_ws,  &c->bbox_part,   &c->rootbox,    &c->status,     &c->emit,
                       &c->base,     &c->ps,          &c->orig,       &c->rank,       &c->rr,         &c->rsk,
-                      &c->nd_lo,    &c->nd_hi,       &c->nd_com,     &c->nd_S,       &c->nd_info,    &c->nd_parent,
+                      &c->nd_lo,    &c->nd_hi,       &c->nd_com,     &c->nd_S,       &c->nd_q,       &c->nd_info,    &c->nd_parent,
                       &c->level_off, &c->pre_info,   &c->pre_parent, &c->pre_nchild, &c->new_of_old,
                       &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
                       &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
@@ -751,6 +752,7 @@ petar_status alloc_build_b(petar_ctx *ctx, int64_t node_cap) {
     TRY(ensure(ctx, ctx->nd_hi, M * sizeof(double4)));
     TRY(ensure(ctx, ctx->nd_com, M * sizeof(double4)));
     TRY(ensure(ctx, ctx->nd_S, M * 6 * 8));
+    TRY(ensure(ctx, ctx->nd_q, M * 2 * sizeof(float4)));
     TRY(ensure(ctx, ctx->nd_info, M * sizeof(uint4)));
     TRY(ensure(ctx, ctx->nd_parent, M * 4));
     TRY(ensure(ctx, ctx->pre_info, M * sizeof(uint4)));

@@ -11,6 +11,9 @@
 //                               nd_com[c] = (com.x, com.y, com.z, M)
 //                               nd_S[c*6 + 0..5] = second moment about com
 //                                        (xx, yy, zz, xy, xz, yz)
+//                               nd_q[2c], nd_q[2c+1] = FP32 multipole record:
+//                                        (2A'xx, 2A'yy, 2A'zz, 2A'xy),
+//                                        (2A'xz, 2A'yz, M, 0)
 //                               nd_info[c] = (first particle, count, flags, first child)
 #pragma once
 
@@ -180,6 +183,19 @@ __device__ __forceinline__ double sum_sq3(double gx, double gy, double gz) {
     double zz = gz * gz;
     double s = xx + yy;
     return s + zz;
+}
+
+// Traceless quadrupole A' = 3/2 S - 1/2 tr(S) I (eq. quadtr) of the second
+// moment S about the centre of mass, doubled and rounded to FP32, with the
+// mass: the two records the mixed-precision force kernel stages per
+// accepted cell. Doubling is exact after rounding.
+__device__ __forceinline__ void quad_f32(const double S[6], double M, float4 *q0, float4 *q1) {
+#pragma clang fp contract(off)
+    const double tr = (S[0] + S[1]) + S[2];
+    const double h = 0.5 * tr;
+    *q0 = make_float4(2.0f * (float)(1.5 * S[0] - h), 2.0f * (float)(1.5 * S[1] - h),
+                      2.0f * (float)(1.5 * S[2] - h), 2.0f * (float)(1.5 * S[3]));
+    *q1 = make_float4(2.0f * (float)(1.5 * S[4]), 2.0f * (float)(1.5 * S[5]), (float)M, 0.0f);
 }
 
 // Specific Kepler energy v^2/2 - mu/|r| of a pair (eq. dr) from its relative

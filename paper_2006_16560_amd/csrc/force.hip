@@ -10,9 +10,10 @@
 // Cells are buffered in LDS; a full buffer is staged as records relative to
 // the group centre (FP32 in mixed mode, FP64 otherwise) and broadcast from
 // LDS to all lanes. A lane holds up to IPL targets; small groups spread one
-// target over S lanes that split the j loop. In mixed precision the FP32
-// per-tile partial sums are folded into Neumaier-compensated FP32
-// accumulators and converted to FP64 at the end.
+// target over S lanes that split the j loop. In mixed precision each tile of
+// at most 64 sources is summed in FP32 and the tile partials are accumulated
+// in FP64 (two instructions per component and tile; a Neumaier-compensated
+// FP32 sum takes seven).
 #include "launch.h"
 #include "walk.h"
 
@@ -83,22 +84,18 @@ __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
-// Accumulators: tile partials folded into compensated sums (FP32) or plain
-// FP64 sums.
+// Accumulators: FP64 sums of the tile partials (FP32 partials in mixed
+// precision, FP64 ones otherwise).
 template <typename R>
 struct Acc;
 template <>
 struct Acc<float> {
-    float s[4], c[4];
+    double s[4];  // FP64 sums of the FP32 tile partials
     __device__ void zero() {
-        for (int k = 0; k < 4; k++) s[k] = c[k] = 0.f;
+        for (int k = 0; k < 4; k++) s[k] = 0.0;
     }
-    __device__ void add(int k, float v) {
-        float t = s[k] + v;
-        c[k] += (fabsf(s[k]) >= fabsf(v)) ? ((s[k] - t) + v) : ((v - t) + s[k]);
-        s[k] = t;
-    }
-    __device__ double get(int k) const { return (double)s[k] + (double)c[k]; }
+    __device__ void add(int k, float v) { s[k] += (double)v; }
+    __device__ double get(int k) const { return s[k]; }
 };
 template <>
 struct Acc<double> {
@@ -352,17 +349,44 @@ __device__ void flush_pc(WaveLds<R> &L, int npc, const Layout &ly, Targets<R, IP
 
 // Multipole entry of cell data held in registers (relative to the group
 // centre; traceless quadrupole A' = 3/2 S - 1/2 tr(S) I of the second
-// moment S about the centre of mass).
+// moment S about the centre of mass). FP32: the doubled A' and M come
+// rounded from the build (nd_q); FP64: from the second moments.
 template <typename R>
-__device__ __forceinline__ void stage_pc(WaveLds<R> &L, int p, const double4 &cm,
-                                         const double2 &s01, const double2 &s23,
-                                         const double2 &s45) {
+struct CellQuad;
+template <>
+struct CellQuad<float> {
+    float4 q0, q1;
+    __device__ void load(const TreeDev &t, uint32_t nd) {
+        q0 = t.nd_q[2 * (int64_t)nd];
+        q1 = t.nd_q[2 * (int64_t)nd + 1];
+    }
+};
+template <>
+struct CellQuad<double> {
+    double2 s01, s23, s45;
+    __device__ void load(const TreeDev &t, uint32_t nd) {
+        const double2 *Sp = reinterpret_cast<const double2 *>(t.nd_S) + (int64_t)nd * 3;
+        s01 = Sp[0];
+        s23 = Sp[1];
+        s45 = Sp[2];
+    }
+};
+
+__device__ __forceinline__ void stage_pc(WaveLds<float> &L, int p, const double4 &cm,
+                                         const CellQuad<float> &q) {
+    L.pc.e[p].a = {(float)(cm.x - L.g.c[0]), (float)(cm.y - L.g.c[1]),
+                   (float)(cm.z - L.g.c[2]), q.q1.z};
+    L.pc.e[p].b = q.q0;
+    L.pc.e[p].c = {q.q1.x, q.q1.y};
+}
+__device__ __forceinline__ void stage_pc(WaveLds<double> &L, int p, const double4 &cm,
+                                         const CellQuad<double> &q) {
+    const double2 s01 = q.s01, s23 = q.s23, s45 = q.s45;
     const double tr = s01.x + s01.y + s23.x;
-    L.pc.e[p].a = {(R)(cm.x - L.g.c[0]), (R)(cm.y - L.g.c[1]), (R)(cm.z - L.g.c[2]), (R)cm.w};
-    // 2 A' (the doubling is exact after rounding)
-    L.pc.e[p].b = {(R)2 * (R)(1.5 * s01.x - 0.5 * tr), (R)2 * (R)(1.5 * s01.y - 0.5 * tr),
-                 (R)2 * (R)(1.5 * s23.x - 0.5 * tr), (R)2 * (R)(1.5 * s23.y)};
-    L.pc.e[p].c = {(R)2 * (R)(1.5 * s45.x), (R)2 * (R)(1.5 * s45.y)};
+    L.pc.e[p].a = {cm.x - L.g.c[0], cm.y - L.g.c[1], cm.z - L.g.c[2], cm.w};
+    L.pc.e[p].b = {2.0 * (1.5 * s01.x - 0.5 * tr), 2.0 * (1.5 * s01.y - 0.5 * tr),
+                   2.0 * (1.5 * s23.x - 0.5 * tr), 2.0 * (1.5 * s23.y)};
+    L.pc.e[p].c = {2.0 * (1.5 * s45.x), 2.0 * (1.5 * s45.y)};
 }
 
 // Binary search of the buffered leaf that holds expanded slot s.
@@ -440,27 +464,19 @@ __device__ uint32_t flush_leaves(WaveLds<R> &L, const uint32_t *start, uint32_t 
 // Folds the partial sums of the S lanes that split one target's sources
 // into the lane of split 0, in the fixed order of the splits (staged in the
 // multipole tile, which is free once the walk of the chunk is done).
-__device__ __forceinline__ void fold_in(Acc<float> &a, const float *src, int k, int lane2) {
-    a.add(k, src[k * kWave + lane2]);
-    a.c[k] += src[(4 + k) * kWave + lane2];
+template <typename R>
+__device__ __forceinline__ void fold_in(Acc<R> &a, const double *src, int k, int lane2) {
+    a.s[k] += src[k * kWave + lane2];
 }
-__device__ __forceinline__ void fold_in(Acc<double> &a, const double *src, int k, int lane2) {
-    a.add(k, src[k * kWave + lane2]);
-}
-__device__ __forceinline__ void park(const Acc<float> &a, float *dst, int lane) {
-    for (int k = 0; k < 4; k++) {
-        dst[k * kWave + lane] = a.s[k];
-        dst[(4 + k) * kWave + lane] = a.c[k];
-    }
-}
-__device__ __forceinline__ void park(const Acc<double> &a, double *dst, int lane) {
+template <typename R>
+__device__ __forceinline__ void park(const Acc<R> &a, double *dst, int lane) {
     for (int k = 0; k < 4; k++) dst[k * kWave + lane] = a.s[k];
 }
 
 template <typename R, int IPL>
 __device__ void combine_split(WaveLds<R> &L, Targets<R, IPL> &T, const Layout &ly) {
-    static_assert(sizeof(PcTile<R>) >= 8 * kWave * sizeof(R), "fold buffer");
-    R *buf = reinterpret_cast<R *>(&L.pc);
+    static_assert(sizeof(PcTile<R>) >= 4 * kWave * sizeof(double), "fold buffer");
+    double *buf = reinterpret_cast<double *>(&L.pc);
     const int lane = lane_id();
 #pragma unroll
     for (int u = 0; u < IPL; u++) {
@@ -571,8 +587,8 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 const uint32_t nd = live ? node : 0u;
                 const double4 lo = f.t.nd_lo[nd], hi = f.t.nd_hi[nd];
                 const double4 cm = f.t.nd_com[nd];
-                const double2 *Sp = reinterpret_cast<const double2 *>(f.t.nd_S) + (int64_t)nd * 3;
-                const double2 s01 = Sp[0], s23 = Sp[1], s45 = Sp[2];
+                CellQuad<R> quad;
+                quad.load(f.t, nd);
                 const uint4 info = f.t.nd_info[nd];
                 double D2, R2;
                 box_terms(L.g, lo, hi, &D2, &R2);
@@ -598,7 +614,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                         n_pc += npc;
                         npc = 0;
                     }
-                    if (kind == kKindPc) stage_pc(L, npc + lanes_below(m), cm, s01, s23, s45);
+                    if (kind == kKindPc) stage_pc(L, npc + lanes_below(m), cm, quad);
                     npc += cnt;
                 }
                 m = __ballot(kind == kKindFar);

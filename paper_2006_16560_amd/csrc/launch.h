@@ -28,6 +28,7 @@ struct TreeDev {
     // cells
     double4 *nd_lo, *nd_hi, *nd_com;
     double *nd_S;
+    float4 *nd_q;               // [2 n_nodes]: 2A' and M in FP32 (quad_f32)
     uint4 *nd_info;
     uint32_t *nd_parent;        // kNone for a root
     const uint32_t *level_off;  // [23]: cells of level l are [level_off[l], level_off[l+1])

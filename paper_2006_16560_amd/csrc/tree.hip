@@ -697,6 +697,10 @@ __device__ void cell_moments(const TreeDev &t, uint32_t c) {
     double side = t.nd_hi[c].w;
     t.nd_hi[c] = make_double4(hi[0], hi[1], hi[2], side);
     for (int k = 0; k < 6; k++) t.nd_S[(int64_t)c * 6 + k] = S[k];
+    float4 q0, q1;
+    quad_f32(S, M, &q0, &q1);
+    t.nd_q[2 * (int64_t)c] = q0;
+    t.nd_q[2 * (int64_t)c + 1] = q1;
 }
 
 // Bottom-up cell data: every leaf in one launch (leaves of all levels are
