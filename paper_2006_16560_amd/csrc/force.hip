@@ -71,7 +71,7 @@ struct PartTile {
 
 template <typename R>
 struct WaveLds {
-    uint32_t stack[kStackLds];
+    uint32_t stack[kStackLds + kStackSlack];
     uint32_t far_start[kWave], far_pre[kWave];
     uint32_t near_start[kWave], near_pre[kWave];
     GroupGeom g;

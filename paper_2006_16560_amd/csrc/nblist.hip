@@ -20,7 +20,7 @@ constexpr int kThreads = 256;
 constexpr int kWavesPerBlock = kThreads / kWave;
 
 struct NbLds {
-    uint32_t stack[kStackLds];
+    uint32_t stack[kStackLds + kStackSlack];
     uint32_t leaf_start[kWave], leaf_cnt[kWave], leaf_pre[kWave];
     double4 jp[kWave];
     double jr[kWave];

@@ -14,6 +14,7 @@
 namespace petar {
 
 constexpr int kStackLds = 512;       // >= 64 lanes x 8 children
+constexpr int kStackSlack = 8;       // room for the overhang of the last push (see push)
 constexpr int kSpillCap = 16384;     // per resident wave
 
 struct GroupGeom {
@@ -76,7 +77,7 @@ __device__ __forceinline__ uint32_t root_of(const uint4 *nd_info, const uint32_t
 }
 
 struct WaveStack {
-    uint32_t *lds;     // kStackLds entries
+    uint32_t *lds;     // kStackLds + kStackSlack entries
     uint32_t *spill;   // kSpillCap entries
     int sp_l;          // entries in LDS (wave-uniform)
     int sp_g;          // entries in the spill (wave-uniform)
@@ -121,9 +122,21 @@ struct WaveStack {
             wave_sync();
         }
         int p = sp_l + incl - nc;
+        if (nc > 0) {
+            // Each pushing lane writes 8 slots, the highest first, without a
+            // test per slot (an octree cell has at most 8 children). A slot
+            // past its own nc children lies in the range of a later pushing
+            // lane, which writes that slot at a smaller offset, i.e. in a
+            // later store of this sequence, or past the new top of the stack
+            // (kStackSlack spare entries). The stores of a wave reach LDS in
+            // program order; the empty asm statements keep the compiler from
+            // reordering or merging them.
 #pragma unroll
-        for (int c = 0; c < 8; c++)  // an octree cell has at most 8 children
-            if (c < nc) lds[p + c] = first + (uint32_t)c;
+            for (int c = 7; c >= 0; c--) {
+                lds[p + c] = first + (uint32_t)c;
+                asm volatile("" ::: "memory");
+            }
+        }
         sp_l += tot;
         wave_sync();
         return true;
