@@ -128,7 +128,7 @@ struct Layout {
 // Chooses (nu, S) to keep as many lanes busy as possible: nu = 1 with
 // S = 64 / active lanes per target (at most 8), or, when the kernel holds
 // two targets per lane and it is better, nu = 2 with S = 64 / ceil(active/2)
-// (at most 3); chunks above 64 targets use nu = ceil(active / 64), S = 1.
+// (at most 8); chunks above 64 targets use nu = ceil(active / 64), S = 1.
 template <int IPL>
 __device__ __forceinline__ Layout choose_layout(uint32_t active) {
     Layout ly;
@@ -146,7 +146,7 @@ __device__ __forceinline__ Layout choose_layout(uint32_t active) {
         if (IPL >= 2 && a >= 2) {
             const int W2 = (a + 1) / 2;
             int S2 = kWave / W2;
-            S2 = S2 > 3 ? 3 : S2;
+            S2 = S2 > 8 ? 8 : S2;
             if (S2 > 2 * S1) {  // utilisation a * S / (64 * nu) is higher
                 ly.nu = 2;
                 ly.W = W2;
@@ -311,12 +311,16 @@ __device__ __forceinline__ void run_tile(const TileT &tile, int mpad, const Layo
     }
     if constexpr (IPL >= 2) {
         if (ly.nu == 2) {
-            if (ly.S == 1)
-                loop_kind<KIND, 2, 1>(tile, mpad, ly.sl, T);
-            else if (ly.S == 2)
-                loop_kind<KIND, 2, 2>(tile, mpad, ly.sl, T);
-            else
-                loop_kind<KIND, 2, 3>(tile, mpad, ly.sl, T);
+            switch (ly.S) {
+                case 1: loop_kind<KIND, 2, 1>(tile, mpad, ly.sl, T); break;
+                case 2: loop_kind<KIND, 2, 2>(tile, mpad, ly.sl, T); break;
+                case 3: loop_kind<KIND, 2, 3>(tile, mpad, ly.sl, T); break;
+                case 4: loop_kind<KIND, 2, 4>(tile, mpad, ly.sl, T); break;
+                case 5: loop_kind<KIND, 2, 5>(tile, mpad, ly.sl, T); break;
+                case 6: loop_kind<KIND, 2, 6>(tile, mpad, ly.sl, T); break;
+                case 7: loop_kind<KIND, 2, 7>(tile, mpad, ly.sl, T); break;
+                default: loop_kind<KIND, 2, 8>(tile, mpad, ly.sl, T); break;
+            }
             return;
         }
     }
