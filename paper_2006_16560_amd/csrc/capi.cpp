@@ -28,10 +28,9 @@ thread_local std::string g_last_error;
 
 }  // namespace
 
-// host_scalar: words [0, kHostDeep) for single values, then the kDeepWords
-// 32-bit deepest-level words of the build.
-constexpr int kHostDeep = 8;
-constexpr int kHostScalarWords = kHostDeep + kDeepWords / 2;
+// host_scalar: pinned words for the single values read back by the filter,
+// cluster and artificial-particle calls.
+constexpr int kHostScalarWords = 8;
 
 struct petar_ctx {
     int device = PETAR_NO_DEVICE;
@@ -792,6 +791,7 @@ void enqueue_build_a(petar_ctx *ctx, const BuildArgs &a, hipStream_t s) {
     launch_octree_count(k, a.n, a.leaf_size, levels, ptr<uint32_t>(ctx->emit), deep_slots, s);
     scan_u32_to_i64(ptr<uint32_t>(ctx->emit), ptr<int64_t>(ctx->base), a.n,
                     ptr<int64_t>(ctx->scan_ws), s);
+    launch_build_head(ptr<int64_t>(ctx->base), a.n, rb, deep_slots, ptr<Status>(ctx->status), s);
 }
 
 // Phase B with cell arrays of node_cap entries (the cell count is read on the
@@ -848,26 +848,14 @@ petar_status build_eager(petar_ctx *ctx, const BuildArgs &a) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
     enqueue_build_a(ctx, a, s);
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, ptr<int64_t>(ctx->base) + a.n, 8,
-                                hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 1, &ptr<RootBox>(ctx->rootbox)->bad, 4,
-                                hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + kHostDeep, ptr<uint32_t>(ctx->emit) + a.n,
-                                kDeepWords * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    int32_t bad = 0;
-    memcpy(&bad, ctx->host_scalar + 1, 4);
-    if (bad) return fail(ctx, PETAR_E_INVALID, "non-finite position or mass, or negative mass");
-    const int64_t n_nodes = ctx->host_scalar[0];
+    TRY(read_status(ctx, s));  // cell count, input check, deepest level
+    if (ctx->host_status->bad_input)
+        return fail(ctx, PETAR_E_INVALID, "non-finite position or mass, or negative mass");
+    const int64_t n_nodes = ctx->host_status->cells;
     if (n_nodes < 1 || n_nodes >= (int64_t)kNone)
         return fail(ctx, PETAR_E_INTERNAL, "cell count %lld out of range", (long long)n_nodes);
     const int levels = a.n_sys > 0 ? kBatchLevels : kMaxLevel;
-    uint32_t deep = 0;
-    for (int w = 0; w < kDeepSlots; w++) {
-        uint32_t v;
-        memcpy(&v, (const char *)(ctx->host_scalar + kHostDeep) + 4 * (w * kDeepStride), 4);
-        deep = v > deep ? v : deep;
-    }
+    const uint32_t deep = ctx->host_status->deep;
     if (deep > (uint32_t)levels)
         return fail(ctx, PETAR_E_INTERNAL, "deepest cell level %lld out of range", (long long)deep);
     TRY(alloc_build_b(ctx, n_nodes));
@@ -1006,6 +994,7 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
         launch_nb_write(t, f.groups, st, nb->offsets_dev, nb->idx_dev, nb->capacity, f.spill,
                         queue + 9, f.nb, ctx->nb_waves, s);
         launch_nb_sort(nb->offsets_dev, nb->idx_dev, n, nb->capacity, st, cnt, queue + 10, s);
+        launch_nb_summary(nb->offsets_dev, n, queue + 16, st, s);
         if (timed) (void)hipEventRecord(ctx->ev[7], s);
     }
     if (timed) (void)hipEventRecord(ctx->ev[3], s);
@@ -1013,13 +1002,6 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
 
 // Reads the status words after a force call and fills the statistics.
 petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed) {
-    uint32_t *queue = ptr<uint32_t>(ctx->queue);
-    if (a.nb) {
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar, a.nb->offsets_dev + ctx->n, 8,
-                                    hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->host_scalar + 2, queue + 16, 8, hipMemcpyDeviceToHost,
-                                    s));
-    }
     HIP_TRY(ctx, hipGetLastError());
     TRY(read_status(ctx, s));
     TRY(settle_build_stats(ctx, true));
@@ -1041,8 +1023,7 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
     }
     ctx->stats.workspace_bytes = ctx->ws_bytes;
     if (a.nb) {
-        uint32_t used[2] = {0, 0};  // hand-over headers and leaf entries claimed
-        memcpy(used, ctx->host_scalar + 2, 8);
+        const uint32_t used[2] = {h.rec_used[0], h.rec_used[1]};  // hand-over claimed
         auto grow = [](uint32_t need) {
             uint64_t want = (uint64_t)need + need / 4;
             return (uint32_t)(want > 0xffffffffull ? 0xffffffffull : want);
@@ -1052,7 +1033,7 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
             if (used[1] > ctx->nbleaf_cap) ctx->nbleaf_cap = grow(used[1]);
             ctx->graph_stale = true;
         }
-        a.nb->required = ctx->host_scalar[0];
+        a.nb->required = h.nb_total;
         ctx->stats.nb_total = a.nb->required;
         if (a.nb->required > a.nb->capacity)
             return fail(ctx, PETAR_E_NB_OVERFLOW, "neighbour capacity %lld < required %lld",

@@ -49,15 +49,19 @@ struct Status {
     int32_t stack_overflow;  // walk stack exceeded its capacity
     unsigned long long inter[3];  // pc, far, near interactions
     int64_t n_groups;
-    int64_t nb_total;
+    int64_t nb_total;        // neighbour-list entries
+    uint32_t rec_used[2];    // near-leaf hand-over claimed: headers, leaf entries
     // build
     int32_t cell_overflow;   // more cells than the preallocated capacity (captured graphs)
     int32_t pad;
     int64_t n_nodes;
     int64_t n_leaves;
     int64_t max_level;
+    int64_t cells;           // cells counted by the first half of an eager build
+    int32_t bad_input;       // non-finite or negative input (the root box's count)
+    uint32_t deep;           // deepest cell level
 };
-constexpr int kStatusForceWords = 6;  // int64 words of the force fields
+constexpr int kStatusForceWords = 7;  // int64 words of the force fields
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

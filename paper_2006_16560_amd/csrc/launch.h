@@ -75,6 +75,10 @@ constexpr int kDeepStride = 32;  // 128 B
 constexpr int kDeepWords = kDeepSlots * kDeepStride;
 void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int levels,
                          uint32_t *emit, uint32_t *deep_slots, hipStream_t s);
+// st->cells = base[n], st->bad_input = rb->bad, st->deep = the deepest level
+// among deep_slots (kDeepWords words).
+void launch_build_head(const int64_t *base, int64_t n, const RootBox *rb,
+                       const uint32_t *deep_slots, Status *st, hipStream_t s);
 // Pre-order cells; also the level keys (lkey, lval) sorted next.
 // Cells beyond node_cap are not written; st->cell_overflow is raised instead.
 void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int levels,
@@ -156,6 +160,10 @@ void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint3
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
                      const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
                      uint32_t *queue, const NbRecords &rec, int resident_waves, hipStream_t s);
+// st->nb_total = offsets[n], st->rec_used = rec_count[0..1] (one status
+// copy then tells the host the list size and the hand-over use).
+void launch_nb_summary(const int64_t *offsets, int64_t n, const uint32_t *rec_count, Status *st,
+                       hipStream_t s);
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
                     const Status *st, uint32_t *long_list, uint32_t *long_count, hipStream_t s);
 int nb_resident_waves(int device);

@@ -584,6 +584,20 @@ void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
                        groups, st, (uint32_t *)nullptr, offsets, idx, capacity, spill, queue, rec);
 }
 
+__global__ void k_nb_summary(const int64_t *offsets, int64_t n, const uint32_t *rec_count,
+                             Status *st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->nb_total = offsets[n];
+        st->rec_used[0] = rec_count[0];
+        st->rec_used[1] = rec_count[1];
+    }
+}
+
+void launch_nb_summary(const int64_t *offsets, int64_t n, const uint32_t *rec_count, Status *st,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_nb_summary, dim3(1), dim3(kWave), 0, s, offsets, n, rec_count, st);
+}
+
 void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
                     const Status *st, uint32_t *long_list, uint32_t *long_count, hipStream_t s) {
     int64_t blocks = (n + kThreads - 1) / kThreads;

@@ -553,6 +553,28 @@ __global__ __launch_bounds__(kThreads) void k_octree_write(const uint64_t *key, 
 // Device cell count for the build's second half: the scanned count, or 0
 // (with Status::cell_overflow raised) when it exceeds the arrays' capacity,
 // so that every later kernel does nothing.
+// What the host needs after the first half of an eager build, gathered into
+// the status words so that one copy reads it: the cell count, the input
+// check of the root box and the deepest cell level.
+__global__ void k_build_head(const int64_t *base, int64_t n, const RootBox *rb,
+                             const uint32_t *deep_slots, Status *st) {
+    if (blockIdx.x != 0) return;
+    uint32_t d = 0;
+    for (int w = threadIdx.x; w < kDeepSlots; w += blockDim.x) {
+        const uint32_t v = deep_slots[w * kDeepStride];
+        d = v > d ? v : d;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const uint32_t u = (uint32_t)__shfl_down((int)d, o, kWave);
+        d = u > d ? u : d;
+    }
+    if (threadIdx.x == 0) {
+        st->cells = base[n];
+        st->bad_input = rb->bad;
+        st->deep = d;
+    }
+}
+
 __global__ void k_cell_count(const int64_t *base, int64_t n, int64_t node_cap, Status *st) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t c = base[n];
@@ -944,6 +966,11 @@ void launch_octree_count(const uint64_t *key, int64_t n, int leaf_size, int leve
                          uint32_t *emit, uint32_t *deep_slots, hipStream_t s) {
     hipLaunchKernelGGL(k_octree_count, dim3(grid_for(n)), dim3(kThreads), 0, s, key, n, leaf_size,
                        levels, emit, deep_slots);
+}
+
+void launch_build_head(const int64_t *base, int64_t n, const RootBox *rb,
+                       const uint32_t *deep_slots, Status *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_head, dim3(1), dim3(kWave), 0, s, base, n, rb, deep_slots, st);
 }
 
 void launch_octree_write(const uint64_t *key, int64_t n, int leaf_size, int levels,
