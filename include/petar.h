@@ -243,7 +243,8 @@ typedef struct {
 /* Times one step -- tree build, long-range force and neighbour lists -- on
  * the given particles (same argument rules as petar_tree_build /
  * petar_force_long) for leaf sizes {4, 8, 16}, group sizes {32, 48, 64, 96,
- * 128, 192, 256} and 1 or 2 targets per lane, keeps the fastest, sets
+ * 128, 192, 256} and 1 or 2 targets per lane (a warm-up step, then the
+ * median device time of five), keeps the fastest, sets
  * params.i_per_lane to it and returns it in *out. With cache_path (host
  * string, may be NULL) results are read from / appended to a JSON-lines
  * file keyed by (floor(log2 N), theta, precision); a cache hit returns

@@ -169,8 +169,9 @@ extern "C" petar_status petar_autotune(petar_ctx *ctx, const double *pos, const 
                     release();
                     return st;
                 }
-                double ms[3];
-                for (int rep = 0; rep < 3; rep++) {  // first call warms up
+                constexpr int kReps = 6;  // a warm-up call, then the median of five
+                double ms[kReps];
+                for (int rep = 0; rep < kReps; rep++) {
                     st = petar_tree_build(ctx, pos, mass, N, theta, leaf);
                     petar_nblist nbl{offs, idx, cap, 0};
                     if (st == PETAR_OK)
@@ -194,7 +195,8 @@ extern "C" petar_status petar_autotune(petar_ctx *ctx, const double *pos, const 
                     petar_get_stats(ctx, &s);
                     ms[rep] = s.ms_build + s.ms_force;
                 }
-                double t = std::min(ms[1], ms[2]);
+                std::sort(ms + 1, ms + kReps);
+                const double t = ms[1 + (kReps - 1) / 2];
                 if (best.ms < 0.0 || t < best.ms) {
                     best.leaf_size = leaf;
                     best.group_size = group;
