@@ -126,9 +126,12 @@ struct Layout {
 };
 
 // Chooses (nu, S) to keep as many lanes busy as possible: nu = 1 with
-// S = 64 / active lanes per target (at most 8), or, when the kernel holds
-// two targets per lane and it is better, nu = 2 with S = 64 / ceil(active/2)
-// (at most 8); chunks above 64 targets use nu = ceil(active / 64), S = 1.
+// S = 64 / active lanes per target, or, when the kernel holds two targets
+// per lane and it is better, nu = 2 with S = 64 / ceil(active/2); chunks
+// above 64 targets use nu = ceil(active / 64), S = 1. Splits up to
+// kSplitFixed have loops of their own (fixed stride, unrolled, tiles padded
+// to the step); wider ones (groups of at most 7 targets) share a loop with
+// the stride in a register and no padding.
 template <int IPL>
 __device__ __forceinline__ Layout choose_layout(uint32_t active) {
     Layout ly;
@@ -138,15 +141,13 @@ __device__ __forceinline__ Layout choose_layout(uint32_t active) {
         ly.S = 1;
     } else {
         const int a = (int)active;
-        int S1 = kWave / a;
-        S1 = S1 > 8 ? 8 : S1;
+        const int S1 = kWave / a;
         ly.nu = 1;
         ly.W = a;
         ly.S = S1;
         if (IPL >= 2 && a >= 2) {
             const int W2 = (a + 1) / 2;
-            int S2 = kWave / W2;
-            S2 = S2 > 8 ? 8 : S2;
+            const int S2 = kWave / W2;
             if (S2 > 2 * S1) {  // utilisation a * S / (64 * nu) is higher
                 ly.nu = 2;
                 ly.W = W2;
@@ -167,11 +168,13 @@ __device__ __forceinline__ Layout choose_layout(uint32_t active) {
 // F * S: S lanes share a target and take every S-th source, F sources per
 // lane are unrolled per iteration.
 enum { kTilePc = 0, kTileFar = 1, kTileNear = 2 };
+constexpr int kSplitFixed = 8;  // widest split with a fixed-stride loop
 
 __host__ __device__ constexpr int unroll_of(int kind, int S) {
     return kind == kTileFar ? (S >= 4 ? 1 : 4 / S) : (kind == kTilePc && S <= 4 ? 2 : 1);
 }
 __device__ __forceinline__ int pad_to(int m, int kind, int S) {
+    if (S > kSplitFixed) return m;  // runtime stride: lanes past the end are masked
     const int q = unroll_of(kind, S) * S;
     return (m + q - 1) / q * q;
 }
@@ -299,6 +302,29 @@ __device__ void loop_kind(const TileT &tile, int mpad, int sl, Targets<R, IPL> &
     }
 }
 
+// Splits wider than kSplitFixed: the stride S is a register, each lane
+// takes entries sl, sl + S, ... below m (no padding).
+template <int KIND, int U, typename R, int IPL, typename TileT>
+__device__ void loop_kind_wide(const TileT &tile, int m, int sl, int S, Targets<R, IPL> &T) {
+    Partial<R, U> P;
+    P.zero();
+    for (int j = sl; j < m; j += S) {
+        if constexpr (KIND == kTilePc)
+            pc_one<R, IPL, U>(tile.e[j].a, tile.e[j].b, tile.e[j].c, T, P);
+        else if constexpr (KIND == kTileFar)
+            far_one<R, IPL, U>(tile.e[j].a, T, P);
+        else
+            near_one<R, IPL, U>(tile.e[j].a, tile.e[j].c, tile.e[j].k, T, P);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        T.acc[u].add(0, P.ax[u]);
+        T.acc[u].add(1, P.ay[u]);
+        T.acc[u].add(2, P.az[u]);
+        T.acc[u].add(3, P.ph[u]);
+    }
+}
+
 // Runs the loop of a staged tile for the chunk's layout (nu, S).
 template <int KIND, typename R, int IPL, typename TileT>
 __device__ __forceinline__ void run_tile(const TileT &tile, int mpad, const Layout &ly,
@@ -308,6 +334,16 @@ __device__ __forceinline__ void run_tile(const TileT &tile, int mpad, const Layo
             loop_kind<KIND, IPL, 1>(tile, mpad, ly.sl, T);
             return;
         }
+    }
+    if (ly.S > kSplitFixed) {
+        if constexpr (IPL >= 2) {
+            if (ly.nu == 2) {
+                loop_kind_wide<KIND, 2>(tile, mpad, ly.sl, ly.S, T);
+                return;
+            }
+        }
+        loop_kind_wide<KIND, 1>(tile, mpad, ly.sl, ly.S, T);
+        return;
     }
     if constexpr (IPL >= 2) {
         if (ly.nu == 2) {
