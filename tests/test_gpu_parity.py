@@ -859,6 +859,7 @@ def test_target_subset_matches_oracle_tree(pt, ctx, orc, theta):
     assert same.mean() > 0.999
     assert rel_err(acc[:, idx], a_ref)[same].max() < 1e-12
     np.testing.assert_allclose(pot[idx][same], p_ref[same], rtol=1e-12)
+    _bound_differing(acc[:, idx], c, rin, rout, same, idx, orc)
     assert st["inter_pc"] == int(cnt_ref[0].sum())
     assert st["inter_far"] == int(cnt_ref[1].sum())
     assert st["inter_near"] == int(cnt_ref[2].sum() - idx.size)
