@@ -633,27 +633,20 @@ __global__ void k_level_offsets(TreeDev t, uint32_t *level_off) {
 
 // Cell data of cell c. Leaves sum their particles (two passes: centre of
 // mass, then the second moment about it); other cells combine their children
-// with the parallel-axis shift.
-__device__ void cell_moments(const TreeDev &t, uint32_t c) {
-    uint4 info = t.nd_info[c];
+// with the parallel-axis shift. Items (particles or children) are summed in
+// their order. Up to 8 items are loaded before any is used, so that their
+// loads overlap instead of costing one memory latency each (the slots past
+// the last item repeat it and are not summed; box minima and maxima do not
+// depend on order or repeats); longer leaves (at the deepest level) loop.
+template <bool leaf>
+__device__ void cell_moments(const TreeDev &t, uint32_t c, const uint4 info) {
+    const uint32_t first = leaf ? info.x : info.w;
+    const uint32_t cnt = leaf ? info.y : (uint32_t)info_nchild(info.z);
     double M = 0, sx = 0, sy = 0, sz = 0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double S[6] = {0, 0, 0, 0, 0, 0};
-    double cx, cy, cz;
-    if (info.z & kLeafFlag) {
-        for (uint32_t k = info.x; k < info.x + info.y; k++) {
-            double4 p = t.ps[k];
-            M += p.w;
-            sx += p.w * p.x;
-            sy += p.w * p.y;
-            sz += p.w * p.z;
-            lo[0] = fmin(lo[0], p.x);
-            lo[1] = fmin(lo[1], p.y);
-            lo[2] = fmin(lo[2], p.z);
-            hi[0] = fmax(hi[0], p.x);
-            hi[1] = fmax(hi[1], p.y);
-            hi[2] = fmax(hi[2], p.z);
-        }
+    double cx = 0, cy = 0, cz = 0;
+    auto centre = [&]() {
         if (M > 0.0) {
             cx = sx / M;
             cy = sy / M;
@@ -663,52 +656,86 @@ __device__ void cell_moments(const TreeDev &t, uint32_t c) {
             cy = 0.5 * (lo[1] + hi[1]);
             cz = 0.5 * (lo[2] + hi[2]);
         }
-        for (uint32_t k = info.x; k < info.x + info.y; k++) {
-            double4 p = t.ps[k];
-            double qx = p.x - cx, qy = p.y - cy, qz = p.z - cz;
-            S[0] += p.w * qx * qx;
-            S[1] += p.w * qy * qy;
-            S[2] += p.w * qz * qz;
-            S[3] += p.w * qx * qy;
-            S[4] += p.w * qx * qz;
-            S[5] += p.w * qy * qz;
+    };
+    // (x, y, z, mass) of an item: a particle, or a child's centre and mass
+    auto mass_point = [&](const double4 &p) {
+        M += p.w;
+        sx += p.w * p.x;
+        sy += p.w * p.y;
+        sz += p.w * p.z;
+    };
+    auto grow_box = [&](double x0, double y0, double z0, double x1, double y1, double z1) {
+        lo[0] = fmin(lo[0], x0);
+        lo[1] = fmin(lo[1], y0);
+        lo[2] = fmin(lo[2], z0);
+        hi[0] = fmax(hi[0], x1);
+        hi[1] = fmax(hi[1], y1);
+        hi[2] = fmax(hi[2], z1);
+    };
+    auto second_particle = [&](const double4 &p) {
+        double qx = p.x - cx, qy = p.y - cy, qz = p.z - cz;
+        S[0] += p.w * qx * qx;
+        S[1] += p.w * qy * qy;
+        S[2] += p.w * qz * qz;
+        S[3] += p.w * qx * qy;
+        S[4] += p.w * qx * qz;
+        S[5] += p.w * qy * qz;
+    };
+    auto second_child = [&](const double4 &cm, const double *Sc) {
+        double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
+        S[0] += Sc[0] + cm.w * dx * dx;
+        S[1] += Sc[1] + cm.w * dy * dy;
+        S[2] += Sc[2] + cm.w * dz * dz;
+        S[3] += Sc[3] + cm.w * dx * dy;
+        S[4] += Sc[4] + cm.w * dx * dz;
+        S[5] += Sc[5] + cm.w * dy * dz;
+    };
+    if (cnt >= 1 && cnt <= 8) {
+        double4 p[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t o = first + (k < cnt ? k : cnt - 1);
+            p[k] = leaf ? t.ps[o] : t.nd_com[o];
         }
-    } else {
-        const uint32_t first = info.w, nc = (uint32_t)info_nchild(info.z);
-        for (uint32_t o = first; o < first + nc; o++) {
-            double4 cm = t.nd_com[o];
-            double4 l4 = t.nd_lo[o], h4 = t.nd_hi[o];
-            M += cm.w;
-            sx += cm.w * cm.x;
-            sy += cm.w * cm.y;
-            sz += cm.w * cm.z;
-            lo[0] = fmin(lo[0], l4.x);
-            lo[1] = fmin(lo[1], l4.y);
-            lo[2] = fmin(lo[2], l4.z);
-            hi[0] = fmax(hi[0], h4.x);
-            hi[1] = fmax(hi[1], h4.y);
-            hi[2] = fmax(hi[2], h4.z);
-        }
-        if (M > 0.0) {
-            cx = sx / M;
-            cy = sy / M;
-            cz = sz / M;
+        if constexpr (leaf) {
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) grow_box(p[k].x, p[k].y, p[k].z, p[k].x, p[k].y, p[k].z);
         } else {
-            cx = 0.5 * (lo[0] + hi[0]);
-            cy = 0.5 * (lo[1] + hi[1]);
-            cz = 0.5 * (lo[2] + hi[2]);
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) {
+                const uint32_t o = first + (k < cnt ? k : cnt - 1);
+                const double4 l4 = t.nd_lo[o], h4 = t.nd_hi[o];
+                grow_box(l4.x, l4.y, l4.z, h4.x, h4.y, h4.z);
+            }
         }
-        for (uint32_t o = first; o < first + nc; o++) {
-            double4 cm = t.nd_com[o];
-            const double *Sc = t.nd_S + (int64_t)o * 6;
-            double dx = cm.x - cx, dy = cm.y - cy, dz = cm.z - cz;
-            S[0] += Sc[0] + cm.w * dx * dx;
-            S[1] += Sc[1] + cm.w * dy * dy;
-            S[2] += Sc[2] + cm.w * dz * dz;
-            S[3] += Sc[3] + cm.w * dx * dy;
-            S[4] += Sc[4] + cm.w * dx * dz;
-            S[5] += Sc[5] + cm.w * dy * dz;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++)
+            if (k < cnt) mass_point(p[k]);
+        centre();
+        if constexpr (leaf) {
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++)
+                if (k < cnt) second_particle(p[k]);
+        } else {
+            double Sk[8][6];
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) {
+                const uint32_t o = first + (k < cnt ? k : cnt - 1);
+#pragma unroll
+                for (int j = 0; j < 6; j++) Sk[k][j] = t.nd_S[(int64_t)o * 6 + j];
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++)
+                if (k < cnt) second_child(p[k], Sk[k]);
         }
+    } else if constexpr (leaf) {
+        for (uint32_t k = first; k < first + cnt; k++) {
+            const double4 p = t.ps[k];
+            mass_point(p);
+            grow_box(p.x, p.y, p.z, p.x, p.y, p.z);
+        }
+        centre();
+        for (uint32_t k = first; k < first + cnt; k++) second_particle(t.ps[k]);
     }
     t.nd_com[c] = make_double4(cx, cy, cz, M);
     double4 l4 = t.nd_lo[c];
@@ -731,15 +758,19 @@ __device__ void cell_moments(const TreeDev &t, uint32_t c) {
 __global__ __launch_bounds__(kThreads) void k_moments_leaves(TreeDev t) {
     const int64_t n_nodes = *t.n_nodes_dev;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_nodes;
-         c += (int64_t)gridDim.x * blockDim.x)
-        if (t.nd_info[c].z & kLeafFlag) cell_moments(t, (uint32_t)c);
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 info = t.nd_info[c];
+        if (info.z & kLeafFlag) cell_moments<true>(t, (uint32_t)c, info);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_moments_level(TreeDev t, int level) {
     const uint32_t beg = t.level_off[level], end = t.level_off[level + 1];
     for (int64_t c = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < end;
-         c += (int64_t)gridDim.x * blockDim.x)
-        if (!(t.nd_info[c].z & kLeafFlag)) cell_moments(t, (uint32_t)c);
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 info = t.nd_info[c];
+        if (!(info.z & kLeafFlag)) cell_moments<false>(t, (uint32_t)c, info);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_tree_summary(TreeDev t, Status *st) {
