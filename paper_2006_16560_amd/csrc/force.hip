@@ -646,46 +646,63 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 }
                 unsigned long long m;
                 int cnt;
+                // Each buffer is filled to 64 entries before it is run: a
+                // batch that does not fit completes it, the buffer is run,
+                // and the rest of the batch (still in the lanes' registers)
+                // starts the next one.
                 m = __ballot(kind == kKindPc);
                 cnt = __popcll(m);
                 if (cnt) {
-                    if (npc + cnt > kWave) {
-                        flush_pc(L, npc, ly, T);
-                        n_pc += npc;
-                        npc = 0;
+                    const int p = npc + lanes_below(m);
+                    if (kind == kKindPc && p < kWave) stage_pc(L, p, cm, quad);
+                    if (npc + cnt >= kWave) {
+                        flush_pc(L, kWave, ly, T);
+                        n_pc += kWave;
+                        if (kind == kKindPc && p >= kWave) stage_pc(L, p - kWave, cm, quad);
+                        npc += cnt - kWave;
+                    } else {
+                        npc += cnt;
                     }
-                    if (kind == kKindPc) stage_pc(L, npc + lanes_below(m), cm, quad);
-                    npc += cnt;
                 }
                 m = __ballot(kind == kKindFar);
                 cnt = __popcll(m);
                 if (cnt) {
-                    if (nfar + cnt > kWave) {
-                        n_far += flush_leaves<kTileFar>(L, L.far_start, L.far_pre, nfar, f, ly, T,
-                                                        false, gstart, gn);
-                        nfar = 0;
-                    }
-                    if (kind == kKindFar) {
-                        int p = nfar + lanes_below(m);
+                    const int p = nfar + lanes_below(m);
+                    if (kind == kKindFar && p < kWave) {
                         L.far_start[p] = info.x;
                         L.far_pre[p] = info.y;
                     }
-                    nfar += cnt;
+                    if (nfar + cnt >= kWave) {
+                        n_far += flush_leaves<kTileFar>(L, L.far_start, L.far_pre, kWave, f, ly,
+                                                        T, false, gstart, gn);
+                        if (kind == kKindFar && p >= kWave) {
+                            L.far_start[p - kWave] = info.x;
+                            L.far_pre[p - kWave] = info.y;
+                        }
+                        nfar += cnt - kWave;
+                    } else {
+                        nfar += cnt;
+                    }
                 }
                 m = __ballot(kind == kKindNear);
                 cnt = __popcll(m);
                 if (cnt) {
-                    if (nnear + cnt > kWave) {
-                        n_near += flush_leaves<kTileNear>(L, L.near_start, L.near_pre, nnear, f,
-                                                          ly, T, record, gstart, gn);
-                        nnear = 0;
-                    }
-                    if (kind == kKindNear) {
-                        int p = nnear + lanes_below(m);
+                    const int p = nnear + lanes_below(m);
+                    if (kind == kKindNear && p < kWave) {
                         L.near_start[p] = info.x;
                         L.near_pre[p] = info.y;
                     }
-                    nnear += cnt;
+                    if (nnear + cnt >= kWave) {
+                        n_near += flush_leaves<kTileNear>(L, L.near_start, L.near_pre, kWave, f,
+                                                          ly, T, record, gstart, gn);
+                        if (kind == kKindNear && p >= kWave) {
+                            L.near_start[p - kWave] = info.x;
+                            L.near_pre[p - kWave] = info.y;
+                        }
+                        nnear += cnt - kWave;
+                    } else {
+                        nnear += cnt;
+                    }
                 }
             }
             if (!ok) {
