@@ -282,9 +282,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_i
     __shared__ uint64_t sk[kSortTile];
     __shared__ uint32_t sv[kSortTile];
     __shared__ uint32_t tile_start[kRadix];
-    __shared__ uint32_t digit_base[kRadix];
     __shared__ uint32_t gbase[kRadix];
-    __shared__ uint32_t wave_cnt[kThreads / kWave][kRadix];
+    __shared__ uint32_t wave_cnt[kThreads / kWave][kRadix];  // running, then wave offsets
     __shared__ uint32_t wsum[kThreads / kWave], wsum_d[kThreads / kWave];
     const int t = threadIdx.x;
     const int w = t / kWave;
@@ -299,7 +298,6 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_i
         wsum[w] = incl;
         wsum_d[w] = incl_d;
     }
-    digit_base[t] = 0;
     for (int k = 0; k < kThreads / kWave; k++) wave_cnt[k][t] = 0;
     __syncthreads();
     uint32_t off = 0, off_d = 0;
@@ -309,44 +307,61 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const uint64_t *key_i
     }
     tile_start[t] = off + incl - c;
     gbase[t] = (off_d + incl_d - dt) + offs[(int64_t)t * ntiles + tile] - (off + incl - c);
-    __syncthreads();
+    // Each wave ranks its own quarter of the tile, kSortRounds keys per lane
+    // in order: a key's rank among the wave's earlier keys of its digit is
+    // the wave's running count plus the matching lanes below it (8 ballots).
+    constexpr int kSub = kSortTile / (kThreads / kWave);  // keys of a wave
+    uint64_t kk[kSortRounds];
+    uint32_t vv[kSortRounds], rk[kSortRounds];
+    uint32_t *cnt = wave_cnt[w];
+#pragma unroll
     for (int r = 0; r < kSortRounds; r++) {
-        int64_t k = base + r * kThreads + t;
-        bool valid = k < n;
-        uint64_t kk = valid ? key_in[k] : 0;
-        uint32_t vv = valid ? val_in[k] : 0;
-        int d = valid ? (int)((kk >> shift) & 255) : 0;
+        const int64_t k = base + (int64_t)w * kSub + r * kWave + lane_id();
+        const bool valid = k < n;
+        kk[r] = valid ? key_in[k] : 0;
+        vv[r] = valid ? val_in[k] : 0;
+        const int d = (int)((kk[r] >> shift) & 255);
         unsigned long long m = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            unsigned long long bb = __ballot((d >> b) & 1);
+            const unsigned long long bb = __ballot((d >> b) & 1);
             m &= ((d >> b) & 1) ? bb : ~bb;
         }
-        int wrank = lanes_below(m);
-        if (valid && wrank == 0) wave_cnt[w][d] = (uint32_t)__popcll(m);
-        __syncthreads();
-        if (valid) {
-            uint32_t rank = digit_base[d] + (uint32_t)wrank;
-            for (int q = 0; q < w; q++) rank += wave_cnt[q][d];
-            uint32_t p = tile_start[d] + rank;
-            sk[p] = kk;
-            sv[p] = vv;
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int q = 0; q < kThreads / kWave; q++) {
-            add += wave_cnt[q][t];
-            wave_cnt[q][t] = 0;
-        }
-        digit_base[t] += add;
-        __syncthreads();
+        const int wrank = lanes_below(m);
+        const uint32_t before = valid ? cnt[d] : 0u;
+        wave_sync();  // every lane has read its digit's count
+        rk[r] = before + (uint32_t)wrank;
+        if (valid && wrank == 0) cnt[d] = before + (uint32_t)__popcll(m);
+        wave_sync();
     }
+    __syncthreads();
+    // wave offsets of digit t: the counts of the earlier waves
+    {
+        uint32_t acc = 0;
+        for (int q = 0; q < kThreads / kWave; q++) {
+            const uint32_t v = wave_cnt[q][t];
+            wave_cnt[q][t] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; r++) {
+        const int64_t k = base + (int64_t)w * kSub + r * kWave + lane_id();
+        if (k < n) {
+            const int d = (int)((kk[r] >> shift) & 255);
+            const uint32_t p = tile_start[d] + cnt[d] + rk[r];
+            sk[p] = kk[r];
+            sv[p] = vv[r];
+        }
+    }
+    __syncthreads();
     int64_t tile_n = n - base < kSortTile ? n - base : kSortTile;
     for (int p = t; p < tile_n; p += kThreads) {
-        uint64_t kk = sk[p];
-        int d = (int)((kk >> shift) & 255);
+        const uint64_t k2 = sk[p];
+        const int d = (int)((k2 >> shift) & 255);
         const uint32_t g = gbase[d] + (uint32_t)p;
-        key_out[g] = kk;
+        key_out[g] = k2;
         val_out[g] = sv[p];
     }
 }
