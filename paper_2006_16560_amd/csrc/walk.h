@@ -2,9 +2,9 @@
 //
 // One wavefront walks the tree for its group: each step pops up to 64 cells
 // (one per lane), classifies them in parallel and pushes the children of the
-// opened cells. The stack lives in LDS (kStackLds entries per wave) and
-// spills to a per-wave global area when a push would not fit; pops refill
-// from the spill when the LDS part is empty. Cells are classified with the
+// opened cells. The stack lives in LDS (kStackLds entries per wave); when a
+// push would not fit, its oldest entries move to a per-wave global area, and
+// pops refill from there when the LDS part is empty. Cells are classified with the
 // FP64 geometry of common.h, rounded as written, so the decisions are
 // reproducible bit for bit by any implementation of the same formulas.
 #pragma once
@@ -115,11 +115,23 @@ struct WaveStack {
         int tot = last_lane(incl);
         if (tot == 0) return true;
         if (sp_l + tot > kStackLds) {
-            if (sp_g + sp_l > kSpillCap) return false;
-            for (int t = lane_id(); t < sp_l; t += kWave) spill[sp_g + t] = lds[t];
-            sp_g += sp_l;
-            sp_l = 0;
+            // move the oldest entries, as many as the push needs rounded up
+            // to whole waves, to the spill and shift the rest down (the
+            // order of the whole stack is unchanged)
+            int h = (sp_l + tot - kStackLds + kWave - 1) / kWave * kWave;
+            h = h < sp_l ? h : sp_l;
+            if (sp_g + h > kSpillCap) return false;
+            for (int t = lane_id(); t < h; t += kWave) spill[sp_g + t] = lds[t];
             wave_sync();
+            for (int t0 = 0; t0 < sp_l - h; t0 += kWave) {
+                const int t = t0 + lane_id();
+                const uint32_t v = t < sp_l - h ? lds[h + t] : 0u;
+                wave_sync();
+                if (t < sp_l - h) lds[t] = v;
+                wave_sync();
+            }
+            sp_g += h;
+            sp_l -= h;
         }
         int p = sp_l + incl - nc;
         if (nc > 0) {
