@@ -391,42 +391,75 @@ __global__ __launch_bounds__(kThreads) void k_scatter_particles(const double *po
 }
 
 // ------------------------------------------------------------ octree
+// Run searches over the sorted keys. The keys sharing key[k]'s level-`level`
+// prefix form one contiguous run. A search brackets the run's boundary by
+// galloping (steps growing 16-fold) and then narrows the bracket 8-fold per
+// round with 7 independent probes, so a run of length d costs about
+// 2 log16(d) + 1 rounds of dependent loads rather than 2 log2(d).
+constexpr int kProbes = 7;
+
 // First index after k whose level-`level` prefix differs from key[k]'s.
 __device__ int64_t run_end(const uint64_t *key, int64_t n, int64_t k, int level, int levels) {
-    uint64_t p = key_prefix(key[k], level, levels);
-    int64_t lo = k, hi = k + 1, step = 1;
+    const uint64_t p = key_prefix(key[k], level, levels);
+    int64_t lo = k, hi = k + 1, step = 1;  // key[lo] in the run; hi == n or key[hi] out of it
     while (hi < n && key_prefix(key[hi], level, levels) == p) {
         lo = hi;
-        step <<= 1;
+        step <<= 4;
         hi = k + step;
     }
     if (hi > n) hi = n;
     while (hi - lo > 1) {
-        int64_t mid = lo + (hi - lo) / 2;
-        if (key_prefix(key[mid], level, levels) == p)
-            lo = mid;
-        else
-            hi = mid;
+        const int64_t m = hi - lo;
+        int64_t q[kProbes];
+        bool in[kProbes];
+#pragma unroll
+        for (int j = 0; j < kProbes; j++) {
+            q[j] = lo + m * (j + 1) / (kProbes + 1);
+            in[j] = key_prefix(key[q[j]], level, levels) == p;
+        }
+        int64_t nlo = lo, nhi = hi;
+#pragma unroll
+        for (int j = 0; j < kProbes; j++) {
+            if (in[j])
+                nlo = q[j] > nlo ? q[j] : nlo;
+            else
+                nhi = q[j] < nhi ? q[j] : nhi;
+        }
+        lo = nlo;
+        hi = nhi;
     }
     return hi;
 }
 
 // First index whose level-`level` prefix equals key[k]'s.
 __device__ int64_t run_start(const uint64_t *key, int64_t k, int level, int levels) {
-    uint64_t p = key_prefix(key[k], level, levels);
-    int64_t lo = k, hi = k - 1, step = 1;
+    const uint64_t p = key_prefix(key[k], level, levels);
+    int64_t lo = k, hi = k - 1, step = 1;  // key[lo] in the run; hi == -1 or key[hi] out of it
     while (hi >= 0 && key_prefix(key[hi], level, levels) == p) {
         lo = hi;
-        step <<= 1;
+        step <<= 4;
         hi = k - step;
     }
     if (hi < -1) hi = -1;
     while (lo - hi > 1) {
-        int64_t mid = hi + (lo - hi) / 2;
-        if (key_prefix(key[mid], level, levels) == p)
-            lo = mid;
-        else
-            hi = mid;
+        const int64_t m = lo - hi;
+        int64_t q[kProbes];
+        bool in[kProbes];
+#pragma unroll
+        for (int j = 0; j < kProbes; j++) {
+            q[j] = lo - m * (j + 1) / (kProbes + 1);
+            in[j] = key_prefix(key[q[j]], level, levels) == p;
+        }
+        int64_t nlo = lo, nhi = hi;
+#pragma unroll
+        for (int j = 0; j < kProbes; j++) {
+            if (in[j])
+                nlo = q[j] < nlo ? q[j] : nlo;
+            else
+                nhi = q[j] > nhi ? q[j] : nhi;
+        }
+        lo = nlo;
+        hi = nhi;
     }
     return lo;
 }
