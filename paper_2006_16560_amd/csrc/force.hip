@@ -783,12 +783,15 @@ inline unsigned blocks_for(int64_t n) {
 
 template <typename R, int IPL>
 int resident_for(int device) {
-    int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<R, IPL>, kThreads, 0);
-    hipDeviceProp_t p;
-    (void)hipGetDeviceProperties(&p, device);
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<R, IPL>, kThreads, 0) !=
+        hipSuccess)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus < 1)
+        cus = 256;  // MI355X
     if (per_cu < 1) per_cu = 1;
-    return per_cu * p.multiProcessorCount * kWavesPerBlock;
+    return per_cu * cus * kWavesPerBlock;
 }
 
 template <typename R, int IPL>

@@ -545,14 +545,17 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_long(const int64_t *offset
 }  // namespace
 
 int nb_resident_waves(int device) {
-    int a = 0, b = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_nb<false>, kThreads, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_nb<true>, kThreads, 0);
+    int a = 0, b = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_nb<false>, kThreads, 0) != hipSuccess)
+        a = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_nb<true>, kThreads, 0) != hipSuccess)
+        b = 1;
     int per_cu = a < b ? a : b;
     if (per_cu < 1) per_cu = 1;
-    hipDeviceProp_t p;
-    hipGetDeviceProperties(&p, device);
-    return per_cu * p.multiProcessorCount * kWavesPerBlock;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus < 1)
+        cus = 256;  // MI355X
+    return per_cu * cus * kWavesPerBlock;
 }
 
 void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
