@@ -226,9 +226,9 @@ def main() -> int:
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters of a profiler) and exit")
     ap.add_argument("--autotune", default=None, metavar="CACHE",
-                    help="only run petar_autotune for every (workload, theta) of this benchmark, "
-                         "writing a fresh cache file CACHE (the package reads "
-                         "paper_2006_16560_amd/tuned.jsonl), and exit")
+                    help="only run petar_autotune for every (workload, theta) of this benchmark "
+                         "and petar_autotune_batch for the batched systems, adding what CACHE "
+                         "lacks (the package reads paper_2006_16560_amd/tuned.jsonl), and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -376,13 +376,13 @@ TUNED_JOBS = [("plummer1m_b100", 0.5), ("plummer1m_b100", 0.3), ("plummer1m_b100
 
 
 def autotune(pt, workloads, cache) -> int:
-    """petar_autotune on each job's particles and radii: it times a full step
-    for every candidate leaf size, group size and number of targets per lane
-    and appends the fastest to `cache` (keyed by floor(log2 N), theta and
-    precision)."""
+    """petar_autotune on each job's particles and radii, and
+    petar_autotune_batch on the batched systems: they time a full step for
+    every candidate leaf size, group size and number of targets per lane and
+    append the fastest to `cache` (keyed by floor(log2 N), floor(log2 n_sys),
+    theta and precision). Jobs already in the cache are kept (a cache hit
+    launches nothing): remove the file to tune afresh."""
     import torch
-    if os.path.exists(cache):
-        os.remove(cache)
     dev = "cuda:0"
     made = {}
     for name, theta in TUNED_JOBS:
@@ -404,6 +404,19 @@ def autotune(pt, workloads, cache) -> int:
                             "seconds": round(time.time() - t0, 1)}))
         finally:
             pt.petar_destroy(ctx)
+    made.clear()
+    torch.cuda.empty_cache()
+    ctx = pt.petar_create(0)
+    try:
+        pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+        offs, pos, mass, r_in, r_out, r_s = batched_inputs(pt, workloads, ctx, 0)
+        t0 = time.time()
+        best = pt.petar_autotune_batch(ctx, offs, pos, mass, BATCHED_THETA, r_in, r_out, r_s,
+                                       cache_path=cache)
+        log(json.dumps({"workload": "batched128", "theta": BATCHED_THETA, "tuned": best,
+                        "seconds": round(time.time() - t0, 1)}))
+    finally:
+        pt.petar_destroy(ctx)
     return 0
 
 
@@ -613,6 +626,31 @@ def bench_artificial(pt, ctx, c, wl, theta, cfg, dev, reps=5, order=3):
     return out
 
 
+BATCHED_THETA = 0.5
+
+
+def batched_inputs(pt, workloads, ctx, seed):
+    """The 128 systems of the batched workload on the device: offsets (list),
+    positions, masses and each system's own changeover and search radii
+    (eq. rcut with the system's <m> and r_out,ref ~ N^-1/3)."""
+    import torch
+    t0 = time.time()
+    offs, pos_h, vel_h, mass_h, sizes = workloads.make_batched(seed)
+    n = int(offs[-1])
+    log("batched workload: %d systems, N=%d generated in %.1fs" % (sizes.size, n, time.time() - t0))
+    dev = "cuda:0"
+    pos = torch.from_numpy(pos_h).to(dev)
+    mass = torch.from_numpy(mass_h).to(dev)
+    r_in = torch.empty(n, dtype=torch.float64, device=dev)
+    r_out, r_s = torch.empty_like(r_in), torch.empty_like(r_in)
+    for k in range(sizes.size):
+        a, b = int(offs[k]), int(offs[k + 1])
+        ro = workloads.r_out_ref_for(int(sizes[k]))
+        pt.petar_changeover_radii(ctx, mass[a:b], 0.1 * ro, ro, 1.2,
+                                  out=(r_in[a:b], r_out[a:b], r_s[a:b]))
+    return [int(v) for v in offs], pos, mass, r_in, r_out, r_s
+
+
 def run_batched(pt, workloads, args, steps, warmup) -> dict:
     """128 independent clusters (N log-uniform in [1024, 131072], 20% binaries).
 
@@ -623,29 +661,25 @@ def run_batched(pt, workloads, args, steps, warmup) -> dict:
     """
     import torch
 
-    t0 = time.time()
-    offs, pos_h, vel_h, mass_h, sizes = workloads.make_batched(args.seed)
-    n = int(offs[-1])
-    log("batched workload: %d systems, N=%d generated in %.1fs" % (sizes.size, n, time.time() - t0))
-    dev = "cuda:0"
-    pos = torch.from_numpy(pos_h).to(dev)
-    mass = torch.from_numpy(mass_h).to(dev)
-    r_in = torch.empty(n, dtype=torch.float64, device=dev)
-    r_out, r_s = torch.empty_like(r_in), torch.empty_like(r_in)
-    theta = 0.5 if args.theta is None else args.theta
-    leaf = 8 if args.leaf is None else args.leaf
-    group = 64 if args.group is None else args.group
-    ipl = 1 if args.ipl is None else args.ipl
+    theta = BATCHED_THETA if args.theta is None else args.theta
     ctx = pt.petar_create(0)
     ctx_g = pt.petar_create(0)
     try:
+        pt.petar_set_params(ctx, precision=pt.PETAR_MIXED)
+        offs_l, pos, mass, r_in, r_out, r_s = batched_inputs(pt, workloads, ctx, args.seed)
+        n = offs_l[-1]
+        n_sys = len(offs_l) - 1
+        dev = pos.device
+        cfg = pt.launch_config(ctx, n, theta, leaf_default=8, group_default=64, ipl_default=2,
+                               n_sys=n_sys)
+        over = {"leaf_size": args.leaf, "group_size": args.group, "i_per_lane": args.ipl}
+        for k, v in over.items():
+            if v is not None:
+                cfg[k] = v
+                cfg["source"] = "command line"
+        leaf, group, ipl = cfg["leaf_size"], cfg["group_size"], cfg["i_per_lane"]
         for c in (ctx, ctx_g):
             pt.petar_set_params(c, precision=pt.PETAR_MIXED, i_per_lane=ipl)
-        for k in range(sizes.size):  # per-cluster radii (own <m> and r_out,ref ~ N^-1/3)
-            a, b = int(offs[k]), int(offs[k + 1])
-            ro = workloads.r_out_ref_for(int(sizes[k]))
-            pt.petar_changeover_radii(ctx, mass[a:b], 0.1 * ro, ro, 1.2,
-                                      out=(r_in[a:b], r_out[a:b], r_s[a:b]))
         nb_cap = 64 * n
         acc_b = torch.empty((3, n), dtype=torch.float64, device=dev)
         pot_b = torch.empty(n, dtype=torch.float64, device=dev)
@@ -653,7 +687,6 @@ def run_batched(pt, workloads, args, steps, warmup) -> dict:
         acc_s, pot_s = torch.empty_like(acc_b), torch.empty_like(pot_b)
         nb_g = (torch.empty(n + 1, dtype=torch.int64, device=dev),
                 torch.empty(nb_cap, dtype=torch.int32, device=dev))
-        offs_l = [int(v) for v in offs]
 
         def graph():
             pt.petar_step_graph(ctx_g, pos, mass, theta, leaf, group, r_in, r_out, r_s, acc_g,
@@ -666,7 +699,7 @@ def run_batched(pt, workloads, args, steps, warmup) -> dict:
 
         def sequential():
             tot = 0
-            for k in range(sizes.size):
+            for k in range(n_sys):
                 a, b = offs_l[k], offs_l[k + 1]
                 pt.petar_batch_build(ctx, [0, b - a], pos[:, a:b].contiguous(), mass[a:b], theta,
                                      leaf)
@@ -706,9 +739,9 @@ def run_batched(pt, workloads, args, steps, warmup) -> dict:
             "steps": steps, "warmup": warmup, "ms_per_step": ms_g,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
-            "config": {"workload": "batched128", "n_systems": int(sizes.size), "n": n,
+            "config": {"workload": "batched128", "n_systems": n_sys, "n": n,
                        "theta": theta, "leaf_size": leaf, "group_size": group,
-                       "i_per_lane": ipl, "binary_fraction": 0.2,
+                       "i_per_lane": ipl, "tuning": cfg["source"], "binary_fraction": 0.2,
                        "mode": "hipGraph replay of the batched step"},
             "batched_eager_ms_per_step": ms_b, "sequential_ms_per_step": ms_s,
             "speedup_vs_sequential": ms_s / ms_g,

@@ -259,6 +259,24 @@ PETAR_API petar_status petar_autotune(petar_ctx *ctx, const double *pos_dev,
                                       const double *r_search_dev, const char *cache_path,
                                       petar_tuned *out);
 
+/* petar_autotune for a batch of independent systems, the forest of
+ * petar_batch_build (n_sys >= 1 systems; sys_offsets[n_sys + 1] host array,
+ * same rules; N = sys_offsets[n_sys] particles in pos_dev[3][N],
+ * mass_dev[N] and the radii [N]): times the batched step (petar_batch_build
+ * + petar_force_long with neighbour lists) for the same candidates and
+ * keeps the fastest, as petar_autotune does. Cache entries of batches also
+ * carry floor(log2 n_sys) (a single system is the batch of one, bucket 0),
+ * so batched and single-system choices for one N do not mix. The batching
+ * of uneven systems into one launch is this build's (the paper integrates
+ * one system per run); the practice of scanning wall-clock time over
+ * parameters is the paper's (Sec. "Performance on GPU-based Desktop"). */
+PETAR_API petar_status petar_autotune_batch(petar_ctx *ctx, int n_sys,
+                                            const int64_t *sys_offsets, const double *pos_dev,
+                                            const double *mass_dev, double theta,
+                                            const double *r_in_dev, const double *r_out_dev,
+                                            const double *r_search_dev, const char *cache_path,
+                                            petar_tuned *out);
+
 /* The parameters petar_autotune stored in cache_path (host string) for
  * (floor(log2 N_hint), theta, params.precision of ctx), without particles
  * and without launching anything (also on a PETAR_NO_DEVICE context).
@@ -266,6 +284,14 @@ PETAR_API petar_status petar_autotune(petar_ctx *ctx, const double *pos_dev,
  * read), PETAR_E_INVALID for N_hint < 1, theta < 0 or a NULL pointer. */
 PETAR_API petar_status petar_autotune_lookup(petar_ctx *ctx, int64_t N_hint, double theta,
                                              const char *cache_path, petar_tuned *out);
+
+/* The same for a batch: the parameters petar_autotune_batch stored for
+ * (floor(log2 N_hint), floor(log2 n_sys), theta, params.precision);
+ * n_sys = 1 reads the single-system entries. Errors as for
+ * petar_autotune_lookup, PETAR_E_INVALID also for n_sys < 1. */
+PETAR_API petar_status petar_autotune_lookup_batch(petar_ctx *ctx, int64_t N_hint, int n_sys,
+                                                   double theta, const char *cache_path,
+                                                   petar_tuned *out);
 
 /* Second stage of the neighbour search (Sec. "Orbit-dependent neighbour
  * criterion"): keeps a first-stage candidate j of particle i iff the

@@ -31,7 +31,7 @@ __all__ = [
     "petar_tidal_fit", "petar_tidal_eval",
     "art_points",
     "petar_copy_counts", "petar_get_stats", "petar_autotune", "petar_autotune_lookup",
-    "launch_config", "TUNED_CACHE", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
+    "petar_autotune_batch", "petar_autotune_lookup_batch", "launch_config", "TUNED_CACHE", "petar_last_error", "PETAR_MIXED", "PETAR_FP64",
     "PETAR_NO_DEVICE", "lib_path",
 ]
 
@@ -496,6 +496,29 @@ def petar_autotune(ctx: Context, pos: torch.Tensor, mass: torch.Tensor, theta: f
     return {name: getattr(out, name) for name, _ in out._fields_}
 
 
+def petar_autotune_batch(ctx: Context, sys_offsets, pos: torch.Tensor, mass: torch.Tensor,
+                         theta: float, r_in: torch.Tensor, r_out: torch.Tensor,
+                         r_search: torch.Tensor, cache_path: Optional[str] = None) -> dict:
+    """Fastest (leaf_size, group_size, i_per_lane) for the batched step of
+    these systems (system s owns particles sys_offsets[s]:sys_offsets[s+1]);
+    see petar.h."""
+    offs = [int(v) for v in sys_offsets]
+    n = mass.shape[0] if mass.dim() == 1 else -1
+    dev = ctx.device
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    out = _capi.petar_tuned()
+    st = _lib.petar_autotune_batch(ctx.handle, len(offs) - 1, arr,
+                                   _dptr(pos, torch.float64, (3, n), "pos", dev),
+                                   _dptr(mass, torch.float64, (n,), "mass", dev), float(theta),
+                                   _dptr(r_in, torch.float64, (n,), "r_in", dev),
+                                   _dptr(r_out, torch.float64, (n,), "r_out", dev),
+                                   _dptr(r_search, torch.float64, (n,), "r_search", dev),
+                                   cache_path.encode() if cache_path else None,
+                                   ctypes.byref(out))
+    _check(st, ctx)
+    return {name: getattr(out, name) for name, _ in out._fields_}
+
+
 # Parameters petar_autotune chose on an MI355X for the particle sets of the
 # benchmark (JSON lines, written by the autotuner itself).
 TUNED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.jsonl")
@@ -515,12 +538,28 @@ def petar_autotune_lookup(ctx: Context, n: int, theta: float,
     return {name: getattr(out, name) for name, _ in out._fields_}
 
 
+def petar_autotune_lookup_batch(ctx: Context, n: int, n_sys: int, theta: float,
+                                cache_path: Optional[str] = None) -> Optional[dict]:
+    """The stored autotuner choice for a batch of n_sys systems holding n
+    particles in total, or None; launches nothing. See petar.h."""
+    out = _capi.petar_tuned()
+    path = TUNED_CACHE if cache_path is None else cache_path
+    st = _lib.petar_autotune_lookup_batch(ctx.handle, int(n), int(n_sys), float(theta),
+                                          path.encode(), ctypes.byref(out))
+    if st == PETAR_E_STATE:
+        return None
+    _check(st, ctx)
+    return {name: getattr(out, name) for name, _ in out._fields_}
+
+
 def launch_config(ctx: Context, n: int, theta: float, leaf_default: int = 8,
-                  group_default: int = 64, ipl_default: int = 2) -> dict:
-    """Leaf size, group size and targets per lane for a force at (N, theta):
-    the autotuner's stored choice when the package cache holds one (source
-    "autotune"), else the defaults (source "default")."""
-    t = petar_autotune_lookup(ctx, n, theta)
+                  group_default: int = 64, ipl_default: int = 2, n_sys: int = 1) -> dict:
+    """Leaf size, group size and targets per lane for a force at (N, theta)
+    on one system or a batch of n_sys: the autotuner's stored choice when
+    the package cache holds one (source "autotune"), else the defaults
+    (source "default")."""
+    t = petar_autotune_lookup(ctx, n, theta) if n_sys == 1 else \
+        petar_autotune_lookup_batch(ctx, n, n_sys, theta)
     if t is None:
         return {"leaf_size": leaf_default, "group_size": group_default,
                 "i_per_lane": ipl_default, "source": "default"}

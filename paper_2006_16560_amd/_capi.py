@@ -87,6 +87,10 @@ SIGNATURES = [
     ("petar_autotune", _INT, [_P, _P, _P, _I64, _D, _P, _P, _P, ctypes.c_char_p,
                               ctypes.POINTER(petar_tuned)]),
     ("petar_autotune_lookup", _INT, [_P, _I64, _D, ctypes.c_char_p, ctypes.POINTER(petar_tuned)]),
+    ("petar_autotune_batch", _INT, [_P, _INT, ctypes.POINTER(_I64), _P, _P, _D, _P, _P, _P,
+                                    ctypes.c_char_p, ctypes.POINTER(petar_tuned)]),
+    ("petar_autotune_lookup_batch", _INT, [_P, _I64, _INT, _D, ctypes.c_char_p,
+                                           ctypes.POINTER(petar_tuned)]),
     ("petar_nb_filter", _INT, [_P, _I64, _P, _P, _P, _P, _D, _P, _P,
                                ctypes.POINTER(petar_nblist)]),
     ("petar_set_targets", _INT, [_P, _P]),

@@ -241,6 +241,53 @@ def test_autotune_lookup_by_n_hint(capi, ctx, tmp_path):
         assert lib.petar_autotune_lookup(ctx, *args, ctypes.byref(out)) == _capi.PETAR_E_INVALID
 
 
+def test_autotune_batch_keys(capi, ctx, tmp_path):
+    """Batched choices are keyed by floor(log2 n_sys) besides (floor(log2 N),
+    theta, precision): a batch of one system reads the single-system entries
+    (written without the field), other system counts only their own; a hit
+    of petar_autotune_batch launches nothing, a miss reaches the forest
+    build (no device here)."""
+    _capi, lib = capi
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"n_bucket": 21, "theta": 0.5, "precision": 0, "leaf_size": 4, '
+                     '"group_size": 64, "i_per_lane": 2, "ms": 5.0}\n'
+                     '{"n_bucket": 21, "sys_bucket": 7, "theta": 0.5, "precision": 0, '
+                     '"leaf_size": 8, "group_size": 96, "i_per_lane": 1, "ms": 12.0}\n')
+    path = str(cache).encode()
+    out = _capi.petar_tuned()
+    n = 3354561  # floor(log2) = 21
+    assert lib.petar_autotune_lookup_batch(ctx, n, 128, 0.5, path, ctypes.byref(out)) == 0
+    assert (out.leaf_size, out.group_size, out.i_per_lane, out.ms) == (8, 96, 1, 12.0)
+    for n_sys in (1, None):
+        st = lib.petar_autotune_lookup(ctx, n, 0.5, path, ctypes.byref(out)) if n_sys is None \
+            else lib.petar_autotune_lookup_batch(ctx, n, n_sys, 0.5, path, ctypes.byref(out))
+        assert st == 0 and (out.leaf_size, out.group_size, out.i_per_lane) == (4, 64, 2)
+    assert lib.petar_autotune_lookup_batch(ctx, n, 64, 0.5, path, ctypes.byref(out)) == \
+        _capi.PETAR_E_STATE
+    assert lib.petar_autotune_lookup_batch(ctx, n, 0, 0.5, path, ctypes.byref(out)) == \
+        _capi.PETAR_E_INVALID
+    offs = [0] + [n * (k + 1) // 128 for k in range(128)]
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    st = lib.petar_autotune_batch(ctx, 128, arr, FAKE, FAKE, 0.5, FAKE, FAKE, FAKE, path,
+                                  ctypes.byref(out))
+    assert st == _capi.PETAR_OK and (out.leaf_size, out.group_size, out.i_per_lane) == (8, 96, 1)
+    p = _capi.petar_params()
+    lib.petar_get_params(ctx, ctypes.byref(p))
+    assert p.i_per_lane == 1
+    # 100 systems: bucket 6, a miss, so the forest build runs (and finds no device)
+    offs = [0] + [n * (k + 1) // 100 for k in range(100)]
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    st = lib.petar_autotune_batch(ctx, 100, arr, FAKE, FAKE, 0.5, FAKE, FAKE, FAKE, path,
+                                  ctypes.byref(out))
+    assert st == _capi.PETAR_E_NODEVICE
+    bad = (ctypes.c_int64 * 3)(0, 10, 5)  # decreasing offsets: the build rejects them
+    assert lib.petar_autotune_batch(ctx, 2, bad, FAKE, FAKE, 0.5, FAKE, FAKE, FAKE, None,
+                                    ctypes.byref(out)) == _capi.PETAR_E_INVALID
+    for n_sys, a in ((0, arr), (2, None)):
+        assert lib.petar_autotune_batch(ctx, n_sys, a, FAKE, FAKE, 0.5, FAKE, FAKE, FAKE, path,
+                                        ctypes.byref(out)) == _capi.PETAR_E_INVALID
+
+
 @pytest.mark.parametrize("offs,ok", [
     ([0, 10, 25], True),
     ([0, 1], True),

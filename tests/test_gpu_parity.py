@@ -437,13 +437,16 @@ def test_changeover_radii_kernel(pt, ctx, orc):
             np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=4e-16 * 8, atol=0)
 
 
+TUNED_GROUPS = (32, 48, 64, 96, 128, 192, 256)  # the autotuner's candidate group sizes
+
+
 def test_autotune_small(pt, orc, tmp_path):
     c, rin, rout, rs = cluster_with_radii(orc, 20000, 18, bf=0.5)
     ctx = pt.petar_create(0)
     cache = str(tmp_path / "tune.jsonl")
     best = pt.petar_autotune(ctx, T(c.pos), T(c.mass), 0.5, T(rin), T(rout), T(rs), cache)
-    assert best["leaf_size"] in (4, 8, 16, 32) and best["group_size"] in (32, 64, 128, 256)
-    assert best["ms"] > 0
+    assert best["leaf_size"] in (4, 8, 16) and best["group_size"] in TUNED_GROUPS
+    assert best["i_per_lane"] in (1, 2) and best["ms"] > 0
     again = pt.petar_autotune(ctx, T(c.pos), T(c.mass), 0.5, T(rin), T(rout), T(rs), cache)
     assert again == best
     # the tuned parameters still give the oracle's answer
@@ -453,6 +456,35 @@ def test_autotune_small(pt, orc, tmp_path):
     a_ref, _, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.5, best["leaf_size"],
                                  best["group_size"])
     assert np.percentile(rel_err(acc.cpu().numpy(), a_ref), 99.9) < 1e-12
+    pt.petar_destroy(ctx)
+
+
+def test_autotune_batch_small(pt, orc, tmp_path):
+    """The batched autotuner times the forest step; its choice is cached
+    under the batch's key (a single-system lookup of the same N misses) and
+    still gives every system the oracle tree's answer."""
+    sizes = [3000, 700, 1500]
+    offs, pos, mass, rin, rout, rs = _batch(orc, sizes, 3)
+    ctx = pt.petar_create(0)
+    cache = str(tmp_path / "tune.jsonl")
+    best = pt.petar_autotune_batch(ctx, offs, T(pos), T(mass), 0.5, T(rin), T(rout), T(rs),
+                                   cache)
+    assert best["leaf_size"] in (4, 8, 16) and best["group_size"] in TUNED_GROUPS
+    assert best["i_per_lane"] in (1, 2) and best["ms"] > 0
+    again = pt.petar_autotune_batch(ctx, offs, T(pos), T(mass), 0.5, T(rin), T(rout), T(rs),
+                                    cache)
+    assert again == best
+    assert pt.petar_autotune_lookup_batch(ctx, int(offs[-1]), len(sizes), 0.5, cache) == best
+    assert pt.petar_autotune_lookup(ctx, int(offs[-1]), 0.5, cache) is None
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64)
+    pt.petar_batch_build(ctx, offs, T(pos), T(mass), 0.5, best["leaf_size"])
+    acc, _ = pt.petar_force_long(ctx, best["group_size"], T(rin), T(rout), T(rs))
+    acc = acc.cpu().numpy()
+    for k in range(len(sizes)):
+        sl = slice(offs[k], offs[k + 1])
+        a_ref, _, _ = orc.tree_force(pos[:, sl], mass[sl], rin[sl], rout[sl], rs[sl], 0.5,
+                                     best["leaf_size"], best["group_size"], max_level=18)
+        assert rel_err(acc[:, sl], a_ref).max() < 1e-12, k
     pt.petar_destroy(ctx)
 
 
@@ -473,13 +505,14 @@ def _batch(orc, sizes, seed, bf=0.2):
     return offs, pos, mass, rin, rout, rs
 
 
-def test_batched_matches_oracle_per_system(pt, ctx, orc):
+@pytest.mark.parametrize("ipl", [1, 2])
+def test_batched_matches_oracle_per_system(pt, ctx, orc, ipl):
     """Forest of per-system trees (18 levels) vs the oracle tree of each
     system alone; neighbour lists vs brute force per system (global ids)."""
     sizes = [1500, 700, 3000, 64, 1]
     offs, pos, mass, rin, rout, rs = _batch(orc, sizes, 1)
     for prec, tol in ((pt.PETAR_FP64, 1e-12), (pt.PETAR_MIXED, 1e-5)):
-        pt.petar_set_params(ctx, precision=prec, i_per_lane=1, record_counts=0)
+        pt.petar_set_params(ctx, precision=prec, i_per_lane=ipl, record_counts=0)
         pt.petar_batch_build(ctx, offs, T(pos), T(mass), 0.5, 8)
         acc, pot, (no, ni) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs),
                                                  nb_capacity=10 ** 6)
@@ -499,10 +532,11 @@ def test_batched_matches_oracle_per_system(pt, ctx, orc):
             assert np.array_equal(got_o, o_ref) and np.array_equal(got_i, i_ref)
 
 
-def test_batched_bitwise_equals_per_system(pt, ctx, orc):
+@pytest.mark.parametrize("ipl", [1, 2])
+def test_batched_bitwise_equals_per_system(pt, ctx, orc, ipl):
     sizes = [2000, 5000, 1024, 333]
     offs, pos, mass, rin, rout, rs = _batch(orc, sizes, 2)
-    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=1, record_counts=0)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=ipl, record_counts=0)
     pt.petar_batch_build(ctx, offs, T(pos), T(mass), 0.5, 8)
     acc, pot, (no, ni) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=10 ** 6)
     acc, pot = acc.cpu().numpy(), pot.cpu().numpy()
