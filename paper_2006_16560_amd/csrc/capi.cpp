@@ -46,6 +46,7 @@ struct petar_ctx {
     DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
+    DevBuf nbrowoff, nbrows, nbcnt_in;  // neighbour rows (Morton order), counts in input order
     DevBuf tflag, tpos, tidx;  // target compaction (petar_set_targets)
     // second-stage filter and clusters
     DevBuf cl_keep, cl_row, cl_counts, cl_parent, cl_root, cl_rootpos, cl_status, cl_flags,
@@ -54,6 +55,7 @@ struct petar_ctx {
     DevBuf art_single, art_spos, art_status, art_pairof, tt_ginv, grp_off, grp_idx;
     bool tt_ginv_ready = false;
     uint32_t nbhead_cap = 0, nbleaf_cap = 0;
+    int64_t nbrows_cap = 0;  // entries of nbrows; grown when a call's rows needed more
 
     Status *host_status = nullptr;  // pinned
     int64_t *host_scalar = nullptr; // pinned
@@ -235,6 +237,7 @@ void free_all(petar_ctx *c) {
                       &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
                       &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
                       &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws,   &c->nbhead, &c->nbleaf,
+                      &c->nbrowoff, &c->nbrows,  &c->nbcnt_in,
                       &c->cl_keep,  &c->cl_row,      &c->cl_counts,   &c->cl_parent,  &c->cl_root,    &c->cl_rootpos,
                       &c->cl_status,   &c->cl_flags,   &c->cl_key0,    &c->cl_key1,
                       &c->cl_val0,  &c->cl_val1,
@@ -912,6 +915,12 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
         ctx->nbleaf_cap = cap((uint64_t)n * 2 + 4096, ctx->nbleaf_cap);
         TRY(ensure(ctx, ctx->nbhead, (size_t)ctx->nbhead_cap * sizeof(uint4)));
         TRY(ensure(ctx, ctx->nbleaf, (size_t)ctx->nbleaf_cap * sizeof(uint2)));
+        // rows: a first guess of 32 entries a particle, then what the
+        // previous call needed (finish_force grows it and redoes the passes)
+        if (ctx->nbrows_cap < 32 * n + 4096) ctx->nbrows_cap = 32 * n + 4096;
+        TRY(ensure(ctx, ctx->nbrowoff, (size_t)(n + 1) * 8));
+        TRY(ensure(ctx, ctx->nbcnt_in, (size_t)(n + 1) * 4));
+        TRY(ensure(ctx, ctx->nbrows, (size_t)ctx->nbrows_cap * 4));
     }
     if (ctx->target) {
         TRY(ensure(ctx, ctx->tflag, (size_t)n * 4));
@@ -920,6 +929,44 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
     }
     TRY(ensure(ctx, ctx->scan_ws, (size_t)scan_ws_elems(n_nodes + n + 1) * 8));
     return PETAR_OK;
+}
+
+// The neighbour passes over the near leaves handed over by the force walk
+// (the walk-based pass takes over on the device if the records overflowed).
+// The force kernel has stored each target's list bound in nbcnt (Morton
+// order); their prefix sum gives the rows. `redo`: the passes again after
+// the rows outgrew the scratch, from the kept records and row offsets (the
+// pass queue and the long-list count are cleared again).
+void enqueue_nb(petar_ctx *ctx, petar_nblist *nb, hipStream_t s, bool timed, bool redo) {
+    const int64_t n = ctx->n;
+    TreeDev t = tree_view(ctx);
+    Status *st = ptr<Status>(ctx->status);
+    uint32_t *queue = ptr<uint32_t>(ctx->queue);
+    NbRecords rec;
+    rec.head = ptr<uint4>(ctx->nbhead);
+    rec.leaf = ptr<uint2>(ctx->nbleaf);
+    rec.count = queue + 16;  // [16] headers, [17] leaf entries (zeroed with the queue)
+    rec.head_cap = ctx->nbhead_cap;
+    rec.leaf_cap = ctx->nbleaf_cap;
+    uint32_t *cnt = ptr<uint32_t>(ctx->nbcnt), *cnt_in = ptr<uint32_t>(ctx->nbcnt_in);
+    int64_t *row_off = ptr<int64_t>(ctx->nbrowoff);
+    int32_t *rows = ptr<int32_t>(ctx->nbrows);
+    int64_t *ws = ptr<int64_t>(ctx->scan_ws);
+    if (timed) (void)hipEventRecord(ctx->ev[6], s);
+    if (redo)
+        fill_u32(queue + 8, 0, 8, s);
+    else
+        scan_u32_to_i64(cnt, row_off, n, ws, s);  // bounds -> rows
+    fill_u32(cnt, 0, n + 1, s);                   // the counts of the testing pass
+    launch_nb_write_rec(t, rec, st, row_off, cnt, rows, ctx->nbrows_cap, s);
+    launch_nb_write(t, ptr<uint32_t>(ctx->groups), st, cnt, row_off, rows, ctx->nbrows_cap,
+                    ptr<uint32_t>(ctx->spill), queue + 9, rec, ctx->nb_waves, s);
+    launch_nb_counts_in(t, cnt, cnt_in, s);
+    scan_u32_to_i64(cnt_in, nb->offsets_dev, n, ws, s);
+    launch_nb_sort(t, row_off, rows, nb->offsets_dev, nb->idx_dev, nb->capacity, st, cnt,
+                   queue + 10, s);
+    launch_nb_summary(nb->offsets_dev, row_off, n, queue + 16, st, s);
+    if (timed) (void)hipEventRecord(ctx->ev[7], s);
 }
 
 // Every launch of the force call; no host synchronisation (capturable).
@@ -970,6 +1017,7 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     f.nb.count = queue + 16;  // [16] headers, [17] leaf entries (zeroed with the queue)
     f.nb.head_cap = a.nb ? ctx->nbhead_cap : 0;
     f.nb.leaf_cap = a.nb ? ctx->nbleaf_cap : 0;
+    f.nb_bound = a.nb ? ptr<uint32_t>(ctx->nbcnt) : nullptr;
     f.kick_vel = a.kick_vel;
     f.kick_dt = a.kick_dt;
     f.tpos = tpos;
@@ -979,24 +1027,7 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     if (timed) (void)hipEventRecord(ctx->ev[4], s);
     launch_force(f, fw, s);
     if (timed) (void)hipEventRecord(ctx->ev[5], s);
-    if (a.nb) {
-        // Passes over the near leaves handed over by the force walk; the
-        // walk-based passes take over (on the device) if the records overflowed.
-        petar_nblist *nb = a.nb;
-        if (timed) (void)hipEventRecord(ctx->ev[6], s);
-        uint32_t *cnt = ptr<uint32_t>(ctx->nbcnt);
-        fill_u32(cnt, 0, n + 1, s);
-        launch_nb_count_rec(t, f.nb, st, cnt, s);
-        launch_nb_count(t, f.groups, st, cnt, f.spill, queue + 8, f.nb, ctx->nb_waves, s);
-        scan_u32_to_i64(cnt, nb->offsets_dev, n, ptr<int64_t>(ctx->scan_ws), s);
-        fill_u32(cnt, 0, n + 1, s);
-        launch_nb_write_rec(t, f.nb, st, nb->offsets_dev, cnt, nb->idx_dev, nb->capacity, s);
-        launch_nb_write(t, f.groups, st, nb->offsets_dev, nb->idx_dev, nb->capacity, f.spill,
-                        queue + 9, f.nb, ctx->nb_waves, s);
-        launch_nb_sort(nb->offsets_dev, nb->idx_dev, n, nb->capacity, st, cnt, queue + 10, s);
-        launch_nb_summary(nb->offsets_dev, n, queue + 16, st, s);
-        if (timed) (void)hipEventRecord(ctx->ev[7], s);
-    }
+    if (a.nb) enqueue_nb(ctx, a.nb, s, timed, false);
     if (timed) (void)hipEventRecord(ctx->ev[3], s);
 }
 
@@ -1006,6 +1037,18 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
     TRY(read_status(ctx, s));
     TRY(settle_build_stats(ctx, true));
     const Status &h = *ctx->host_status;
+    if (a.nb && !h.invalid_radii && !h.stack_overflow && !h.cell_overflow &&
+        h.nb_rows > ctx->nbrows_cap) {
+        // the rows outgrew the scratch (nothing was written): enlarge it and
+        // run the neighbour passes again on the kept records; a captured
+        // graph holds the old scratch and is captured again
+        ctx->nbrows_cap = h.nb_rows + h.nb_rows / 4 + 4096;
+        TRY(ensure(ctx, ctx->nbrows, (size_t)ctx->nbrows_cap * 4));
+        ctx->graph_stale = true;
+        enqueue_nb(ctx, a.nb, s, timed, true);
+        HIP_TRY(ctx, hipGetLastError());
+        TRY(read_status(ctx, s));
+    }
     if (h.invalid_radii)
         return fail(ctx, PETAR_E_INVALID,
                     "radii must be finite with 0 <= r_in < r_out <= r_search for every particle");

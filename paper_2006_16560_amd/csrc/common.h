@@ -51,6 +51,7 @@ struct Status {
     int64_t n_groups;
     int64_t nb_total;        // neighbour-list entries
     uint32_t rec_used[2];    // near-leaf hand-over claimed: headers, leaf entries
+    int64_t nb_rows;         // scratch entries the neighbour rows need
     // build
     int32_t cell_overflow;   // more cells than the preallocated capacity (captured graphs)
     int32_t pad;
@@ -61,7 +62,7 @@ struct Status {
     int32_t bad_input;       // non-finite or negative input (the root box's count)
     uint32_t deep;           // deepest cell level
 };
-constexpr int kStatusForceWords = 7;  // int64 words of the force fields
+constexpr int kStatusForceWords = 8;  // int64 words of the force fields
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

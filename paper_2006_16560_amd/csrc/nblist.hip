@@ -6,9 +6,14 @@
 // the group's box than max(rs_group, rs_leaf); the pairs of the group with
 // those leaves are tested with the FP64 relation of common.h. The box test
 // is conservative for the pair test (same rounding, monotone), so every
-// candidate is found. Two passes (count, write) around one prefix sum, then
-// a per-list sort. If the hand-over buffers overflowed, a walk of the near
-// region per group (same opening rule) replaces the hand-over.
+// candidate is found. A target's candidates lie among the particles of its
+// group's near leaves, whose number the force walk stores as the bound of
+// its list: a prefix sum of the bounds gives every target a row of scratch
+// (Morton order), one testing pass writes the hits into the rows and counts
+// them, a prefix sum of the counts in input order gives the CSR offsets, and
+// a per-list sort moves the rows into the CSR. If the hand-over buffers
+// overflowed, a walk of the near region per group (same opening rule)
+// replaces the hand-over.
 #include "launch.h"
 #include "walk.h"
 
@@ -39,8 +44,8 @@ __device__ __forceinline__ int find_leaf(const uint32_t *pre, int nleaf, uint32_
     return lo;
 }
 
-// kWrite == false: count per target; true: write orig indices at wpos.
-template <bool kWrite>
+// Tests the buffered leaves' particles against each lane's target and
+// writes the hits (input-order indices) at out[wpos + count].
 __device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &pi, double rsi,
                          uint32_t ki, bool valid, uint32_t &count, int32_t *out, int64_t wpos) {
     wave_sync();
@@ -66,7 +71,7 @@ __device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &p
             uint32_t kj = L.jk[j];
             bool hit = valid && kj != ki && nb_pair(pi.x, pi.y, pi.z, rsi, pj.x, pj.y, pj.z, L.jr[j]);
             if (hit) {
-                if (kWrite) out[wpos + count] = (int32_t)t.orig[kj];
+                out[wpos + count] = (int32_t)t.orig[kj];
                 count++;
             }
         }
@@ -74,10 +79,9 @@ __device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &p
     }
 }
 
-template <bool kWrite>
 __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *groups, Status *st,
-                                                 uint32_t *cnt_orig, const int64_t *offsets,
-                                                 int32_t *idx, int64_t capacity, uint32_t *spill,
+                                                 uint32_t *cursor, const int64_t *row_off,
+                                                 int32_t *rows, int64_t row_cap, uint32_t *spill,
                                                  uint32_t *queue, NbRecords rec) {
     __shared__ NbLds lds_all[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
     if (rec.count && rec.count[0] <= rec.head_cap && rec.count[1] <= rec.leaf_cap)
         return;  // the record passes run instead
-    if (kWrite && offsets[t.n] > capacity) return;
+    if (row_off[t.n] > row_cap) return;
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + w;
     const int64_t n_groups = st->n_groups;
     WaveStack stk;
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
             double rsi = t.rsk[ki];
             uint32_t count = 0;
             int64_t wpos = 0;
-            if (kWrite && valid) wpos = offsets[t.orig[ki]];
+            if (valid) wpos = row_off[ki];
             int nleaf = 0;
             stk.init((uint32_t)uniform((int)root_of(t.nd_info, t.level_off, ginfo.x)));
             bool ok = true;
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
                 int cnt = __popcll(m);
                 if (cnt) {
                     if (nleaf + cnt > kWave) {
-                        nb_flush<kWrite>(L, nleaf, t, pi, rsi, ki, valid, count, idx, wpos);
+                        nb_flush(L, nleaf, t, pi, rsi, ki, valid, count, rows, wpos);
                         nleaf = 0;
                     }
                     if (leaf_hit) {
@@ -152,32 +156,33 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
                 if (lane == 0) atomicAdd(&st->stack_overflow, 1);
                 break;
             }
-            if (nleaf) nb_flush<kWrite>(L, nleaf, t, pi, rsi, ki, valid, count, idx, wpos);
-            if (!kWrite && valid) cnt_orig[t.orig[ki]] = count;
+            if (nleaf) nb_flush(L, nleaf, t, pi, rsi, ki, valid, count, rows, wpos);
+            if (valid) cursor[ki] = count;
         }
     }
 }
 
 // Neighbour passes over the near leaves handed over by the force walk. A
-// wave takes one header at a time: the group's targets sit in the lanes
-// (FP64 position and squared search radius in registers; a group of g < 64
-// targets puts each target on 64/g lanes that split the source loop), the
-// leaves' particles are staged in LDS 64 at a time with one load per lane
-// (the next batch is loaded into registers while the current one is
-// tested), and every lane tests its target against its share of the staged
-// particles (LDS broadcasts). Counting adds a lane's hits once per header;
-// writing collects a lane's hits in LDS and takes kHitBuf slots at a time
-// from a per-target cursor (the lists are sorted afterwards, so the slot
-// order is irrelevant).
+// header lists one flush of a group's near leaves; a group may have several.
+// Testing pass. A wave takes one header at a time: the group's targets sit
+// in the lanes (FP64 position and squared search radius in registers; a
+// group of g < 64 targets puts each target on 64/g lanes that split the
+// source loop), the leaves' particles are staged in LDS 64 at a time with
+// one load per lane (the next batch is loaded into registers while the
+// current one is tested), and every lane tests its target against its share
+// of the staged particles (LDS broadcasts). A lane collects its hits in LDS
+// and takes kHitBuf slots at a time of its target's row (row_off, Morton
+// order) from a per-target cursor, which ends as the target's count (the
+// lists are sorted afterwards, so the slot order is irrelevant). Nothing is
+// written when the rows exceed the scratch (row_off[n] > row_cap): the
+// caller enlarges it and runs the passes again.
 constexpr int kHitBuf = 8;
 
-template <bool kWrite>
 struct NbRecLds {
     uint32_t start[kWave], pre[kWave];
-    uint32_t self[kWave];  // counting: target a of the chunk is among the staged sources
     double4 jp[kWave];  // x, y, z, r_search^2 of the staged batch
     uint32_t jk[kWave];
-    uint32_t hit[kWrite ? kHitBuf : 1][kWave];  // a lane's hits not yet written
+    uint32_t hit[kHitBuf][kWave];  // a lane's hits not yet written
 };
 
 // The pair relation of common.h with the squares of the search radii:
@@ -196,15 +201,13 @@ __device__ __forceinline__ bool nb_pair_sq(const double4 &pi, double rsi2, const
     return near_i | (d2 < rj2);
 }
 
-template <bool kWrite>
 __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, const Status *st,
-                                                     uint32_t *cnt_orig, const int64_t *offsets,
-                                                     uint32_t *cursor, int32_t *idx,
-                                                     int64_t capacity) {
-    __shared__ NbRecLds<kWrite> lds_all[kWavesPerBlock];
-    NbRecLds<kWrite> &L = lds_all[uniform((int)(threadIdx.x / kWave))];
+                                                     const int64_t *row_off, uint32_t *cursor,
+                                                     int32_t *rows, int64_t row_cap) {
+    __shared__ NbRecLds lds_all[kWavesPerBlock];
+    NbRecLds &L = lds_all[uniform((int)(threadIdx.x / kWave))];
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
-    if (kWrite && offsets[t.n] > capacity) return;
+    if (row_off[t.n] > row_cap) return;
     const uint32_t nrec = rec.count[0];
     if (nrec > rec.head_cap || rec.count[1] > rec.leaf_cap) return;  // walk-based passes run
     const int lane = lane_id();
@@ -234,12 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             const double4 pi = t.ps[ki];
             const double rsi = t.rsk[ki];
             const double rsi2 = rsi * rsi;
-            const uint32_t oi = t.orig[ki];
             uint32_t c = 0;
-            if (!kWrite) {
-                L.self[lane] = 0;
-                wave_sync();
-            }
             // one batch of 64 sources into registers (lane = source)
             double4 pn = make_double4(0.0, 0.0, 0.0, 0.0);
             uint32_t kn = 0;
@@ -251,22 +249,18 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
                     const double4 p = t.ps[kn];
                     const double rs = t.rsk[kn];
                     pn = make_double4(p.x, p.y, p.z, rs * rs);
-                    if (!kWrite && kn - (gfirst + a0) < (uint32_t)g) L.self[kn - (gfirst + a0)] = 1;
                 }
             };
-            // write pass: this lane's buffered hits into its target's list
+            // this lane's buffered hits into its target's row
             auto flush = [&]() {
-                const int64_t w0 = offsets[oi] + (int64_t)atomicAdd(&cursor[oi], c);
-                for (uint32_t h = 0; h < c; h++) idx[w0 + h] = (int32_t)t.orig[L.hit[h][lane]];
+                const int64_t w0 = row_off[ki] + (int64_t)atomicAdd(&cursor[ki], c);
+                for (uint32_t h = 0; h < c; h++) rows[w0 + h] = (int32_t)t.orig[L.hit[h][lane]];
                 c = 0;
             };
             // the staged source at byte p of L.jp
             const char *jbase = (const char *)L.jp;
             auto test = [&](const char *p) {
-                if constexpr (!kWrite) {
-                    // every pair counts, the target itself too (subtracted below)
-                    c += nb_pair_sq(pi, rsi2, *(const double4 *)p) ? 1u : 0u;
-                } else if (nb_pair_sq(pi, rsi2, *(const double4 *)p)) {
+                if (nb_pair_sq(pi, rsi2, *(const double4 *)p)) {
                     const uint32_t kj = L.jk[(uint32_t)(p - jbase) >> 5];
                     if (kj != ki) {
                         if (c == (uint32_t)kHitBuf) flush();
@@ -295,27 +289,21 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
                     if (p < pend) test(p);
                 }
             }
-            if constexpr (kWrite) {
-                if (c) flush();
-            } else {
-                // the pair of a target with itself (d2 = 0) was counted iff
-                // rs_i^2 > 0 and the target was staged; one of its lanes takes it off
-                wave_sync();
-                if (act && sl == 0 && L.self[a] && rsi2 > 0.0) c--;
-                if (act && c) atomicAdd(&cnt_orig[oi], c);
-            }
+            if (c) flush();
             wave_sync();
         }
     }
 }
 
-// Sorts each list ascending. A block takes 256 consecutive targets; their
-// lists are contiguous, so the block stages them in LDS with coalesced reads
-// (when they fit), each thread sorts its own short list (<= 32 entries,
-// almost all) in registers, and the block writes them back. Longer lists are
-// queued: up to kWaveMax entries a wave each (bitonic network over the
-// wave's registers), above that a block each (bitonic network in LDS), and
-// above kLongMax entries a heap sort by one thread.
+// Sorts each list ascending and moves it from its scratch row into the CSR.
+// A block takes 256 consecutive targets (input order); their lists are
+// contiguous in the CSR, so the block gathers them from the rows into LDS
+// (when they fit; else straight into the CSR), each thread sorts its own
+// short list (<= 32 entries, almost all) in registers, and the block writes
+// them out with coalesced stores. Longer lists are queued and sorted in the
+// CSR: up to kWaveMax entries a wave each (bitonic network over the wave's
+// registers), above that a block each (bitonic network in LDS), and above
+// kLongMax entries a heap sort by one thread.
 constexpr int kShortMax = 32;
 constexpr int kWaveMax = 4 * kWave;
 constexpr int kLongMax = 4096;
@@ -350,17 +338,23 @@ __device__ __forceinline__ void sort_in_registers(int32_t *a, int len) {
         if (q < len) a[q] = v[q];
 }
 
-__global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offsets, int32_t *idx,
+__global__ __launch_bounds__(kThreads) void k_nb_sort_short(const uint32_t *rank,
+                                                            const int64_t *row_off,
+                                                            const int32_t *rows,
+                                                            const int64_t *offsets, int32_t *idx,
                                                             int64_t n, int64_t capacity,
                                                             const Status *st, uint32_t *long_list,
                                                             uint32_t *long_count) {
     __shared__ int32_t sh[kStage];
+    __shared__ int64_t row0[kThreads];       // row of each target of the block
+    __shared__ int64_t dst0[kThreads + 1];   // its list's start in the block's CSR range
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow || offsets[n] > capacity)
         return;
     for (int64_t base = (int64_t)blockIdx.x * kThreads; base < n;
          base += (int64_t)gridDim.x * kThreads) {
         const int64_t i = base + threadIdx.x;
         const int64_t iend = base + kThreads < n ? base + kThreads : n;
+        const int nt = (int)(iend - base);
         const int64_t r0 = offsets[base], r1 = offsets[iend];
         const bool staged = r1 - r0 <= kStage;  // same for the whole block
         int64_t b = 0, len = 0;
@@ -368,11 +362,29 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offse
             b = offsets[i];
             len = offsets[i + 1] - b;
         }
-        if (staged) {
-            for (int64_t p = threadIdx.x; p < r1 - r0; p += kThreads) sh[p] = idx[r0 + p];
-            __syncthreads();
+        __syncthreads();  // the previous targets are done with the LDS
+        if ((int)threadIdx.x < nt) {
+            row0[threadIdx.x] = row_off[rank[i]];
+            dst0[threadIdx.x] = b - r0;
         }
-        // longer lists go to the block-wide sort (one queue slot claim per wave)
+        if (threadIdx.x == 0) dst0[nt] = r1 - r0;
+        __syncthreads();
+        // entry e of the block's CSR range belongs to the target j with
+        // dst0[j] <= e < dst0[j + 1]
+        int32_t *dst = staged ? sh : idx + r0;
+        for (int64_t e = threadIdx.x; e < r1 - r0; e += kThreads) {
+            int lo = 0, hi = nt;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (dst0[mid] <= e)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            dst[e] = rows[row0[lo] + (e - dst0[lo])];
+        }
+        __syncthreads();
+        // longer lists go to the wave or block sorts (one queue slot claim per wave)
         const bool is_long = len > kShortMax;
         const unsigned long long lm = __ballot(is_long);
         if (lm) {
@@ -382,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offse
             if (is_long) long_list[first + (uint32_t)lanes_below(lm)] = (uint32_t)i;
         }
         const int ls = (len > 1 && !is_long) ? (int)len : 0;
-        int32_t *a = staged ? sh + (b - r0) : idx + b;
+        int32_t *a = dst + (b - r0);
         const int m = (int)wave_max((double)ls);
         if (m > 16)
             sort_in_registers<32>(a, ls);
@@ -396,8 +408,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *offse
             sort_in_registers<2>(a, ls);
         if (staged) {
             __syncthreads();
-            for (int64_t p = threadIdx.x; p < r1 - r0; p += kThreads) idx[r0 + p] = sh[p];
-            __syncthreads();
+            for (int64_t e = threadIdx.x; e < r1 - r0; e += kThreads) idx[r0 + e] = sh[e];
         }
     }
 }
@@ -545,12 +556,9 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_long(const int64_t *offset
 }  // namespace
 
 int nb_resident_waves(int device) {
-    int a = 0, b = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_nb<false>, kThreads, 0) != hipSuccess)
-        a = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_nb<true>, kThreads, 0) != hipSuccess)
-        b = 1;
-    int per_cu = a < b ? a : b;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_nb, kThreads, 0) != hipSuccess)
+        per_cu = 1;
     if (per_cu < 1) per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         cus < 1)
@@ -558,56 +566,63 @@ int nb_resident_waves(int device) {
     return per_cu * cus * kWavesPerBlock;
 }
 
-void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
-                         uint32_t *cnt_orig, hipStream_t s) {
-    hipLaunchKernelGGL(k_nb_rec<false>, dim3(2048), dim3(kThreads), 0, s, t, rec, st, cnt_orig,
-                       (const int64_t *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr,
-                       (int64_t)0);
-}
-
 void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
-                         const int64_t *offsets, uint32_t *cursor, int32_t *idx, int64_t capacity,
+                         const int64_t *row_off, uint32_t *cursor, int32_t *rows, int64_t row_cap,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_nb_rec<true>, dim3(2048), dim3(kThreads), 0, s, t, rec, st,
-                       (uint32_t *)nullptr, offsets, cursor, idx, capacity);
+    hipLaunchKernelGGL(k_nb_rec, dim3(2048), dim3(kThreads), 0, s, t, rec, st, row_off, cursor,
+                       rows, row_cap);
 }
 
-void launch_nb_count(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cnt_orig,
-                     uint32_t *spill, uint32_t *queue, const NbRecords &rec, int resident_waves,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_nb<false>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
-                       groups, st, cnt_orig, (const int64_t *)nullptr, (int32_t *)nullptr,
-                       (int64_t)0, spill, queue, rec);
+__global__ __launch_bounds__(kThreads) void k_nb_counts_in(const uint32_t *rank,
+                                                           const uint32_t *cursor, int64_t n,
+                                                           uint32_t *cnt_in) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        cnt_in[i] = cursor[rank[i]];
 }
 
-void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st,
-                     const int64_t *offsets, int32_t *idx, int64_t capacity, uint32_t *spill,
+void launch_nb_counts_in(const TreeDev &t, const uint32_t *cursor, uint32_t *cnt_in,
+                         hipStream_t s) {
+    int64_t blocks = (t.n + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_nb_counts_in, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                       (const uint32_t *)t.rank, (const uint32_t *)cursor, t.n, cnt_in);
+}
+
+void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cursor,
+                     const int64_t *row_off, int32_t *rows, int64_t row_cap, uint32_t *spill,
                      uint32_t *queue, const NbRecords &rec, int resident_waves, hipStream_t s) {
-    hipLaunchKernelGGL(k_nb<true>, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
-                       groups, st, (uint32_t *)nullptr, offsets, idx, capacity, spill, queue, rec);
+    hipLaunchKernelGGL(k_nb, dim3(resident_waves / kWavesPerBlock), dim3(kThreads), 0, s, t,
+                       groups, st, cursor, row_off, rows, row_cap, spill, queue, rec);
 }
 
-__global__ void k_nb_summary(const int64_t *offsets, int64_t n, const uint32_t *rec_count,
-                             Status *st) {
+__global__ void k_nb_summary(const int64_t *offsets, const int64_t *row_off, int64_t n,
+                             const uint32_t *rec_count, Status *st) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->nb_total = offsets[n];
+        st->nb_rows = row_off[n];
         st->rec_used[0] = rec_count[0];
         st->rec_used[1] = rec_count[1];
     }
 }
 
-void launch_nb_summary(const int64_t *offsets, int64_t n, const uint32_t *rec_count, Status *st,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_nb_summary, dim3(1), dim3(kWave), 0, s, offsets, n, rec_count, st);
+void launch_nb_summary(const int64_t *offsets, const int64_t *row_off, int64_t n,
+                       const uint32_t *rec_count, Status *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_nb_summary, dim3(1), dim3(kWave), 0, s, offsets, row_off, n, rec_count,
+                       st);
 }
 
-void launch_nb_sort(const int64_t *offsets, int32_t *idx, int64_t n, int64_t capacity,
-                    const Status *st, uint32_t *long_list, uint32_t *long_count, hipStream_t s) {
+void launch_nb_sort(const TreeDev &t, const int64_t *row_off, const int32_t *rows,
+                    const int64_t *offsets, int32_t *idx, int64_t capacity, const Status *st,
+                    uint32_t *long_list, uint32_t *long_count, hipStream_t s) {
+    const int64_t n = t.n;
     int64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_nb_sort_short, dim3((unsigned)blocks), dim3(kThreads), 0, s, offsets, idx,
-                       n, capacity, st, long_list, long_count);
+    hipLaunchKernelGGL(k_nb_sort_short, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                       (const uint32_t *)t.rank, row_off, rows, offsets, idx, n, capacity, st,
+                       long_list, long_count);
     hipLaunchKernelGGL(k_nb_sort_long, dim3(1024), dim3(kThreads), 0, s, offsets, idx, n, capacity,
                        st, (const uint32_t *)long_list, (const uint32_t *)long_count);
 }

@@ -1294,6 +1294,58 @@ def test_neighbour_list_length_classes(pt, ctx, orc):
     assert np.array_equal(offs, o_ref) and np.array_equal(idx, i_ref)
 
 
+def test_nb_rows_grow_and_redo(pt, orc):
+    """A list is bounded by the particles of its group's near leaves; the
+    scratch rows of a context start at 32 entries a particle, and a call
+    whose rows need more enlarges them and runs the neighbour passes again on
+    the records of its force walk. Clumps of 600 particles (each list bounded
+    by its clump) on a fresh context: lists bit-exact on that call and on the
+    next. A captured step graph whose replay outgrows the captured rows (same
+    positions, the search radii raised in the same buffers) is completed the
+    same way, and captured again on the next call."""
+    rng = np.random.default_rng(12)
+    sizes = [600, 600, 50, 1]
+    pos = np.concatenate([rng.uniform(0.0, 1e-3, (3, k)) + np.array([[10.0 * c], [0.0], [0.0]])
+                          for c, k in enumerate(sizes)], axis=1)
+    n = pos.shape[1]
+    mass = np.full(n, 1.0 / n)
+    big = (np.full(n, 0.001), np.full(n, 0.005), np.full(n, 0.01))
+    small = (np.full(n, 1e-6), np.full(n, 5e-6), np.full(n, 1e-5))
+    need = sum(k * (k - 1) for k in sizes)
+    o_ref, i_ref = orc.neighbours(pos, big[2])
+    assert o_ref[-1] == need
+    c = pt.petar_create(0)
+    for _ in range(2):
+        pt.petar_tree_build(c, T(pos), T(mass), 0.5, 8)
+        _, _, (offs, idx) = pt.petar_force_long(c, 64, *(T(r) for r in big), nb_capacity=need)
+        assert np.array_equal(offs.cpu().numpy(), o_ref)
+        assert np.array_equal(idx.cpu().numpy(), i_ref)
+    pt.petar_destroy(c)
+
+    c = pt.petar_create(0)
+    dpos, dmass = T(pos), T(mass)
+    radii = [T(r) for r in small]
+    acc = torch.empty((3, n), dtype=torch.float64, device="cuda:0")
+    pot = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    nbo = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+    nbi = torch.empty(need, dtype=torch.int32, device="cuda:0")
+    ws = []
+    for it, rr in enumerate((small, small, big, big)):
+        for d, h in zip(radii, rr):
+            d.copy_(T(h))
+        tot = pt.petar_step_graph(c, dpos, dmass, 0.5, 8, 64, *radii, acc, pot, nb=(nbo, nbi))
+        torch.cuda.synchronize()
+        o_r, i_r = orc.neighbours(pos, rr[2])
+        assert np.array_equal(nbo.cpu().numpy(), o_r), it
+        assert np.array_equal(nbi.cpu().numpy()[:tot], i_r), it
+        st = pt.petar_get_stats(c)
+        ws.append(st["workspace_bytes"])
+        if it in (1, 2):
+            assert st["ms_graph"] > 0, it  # replayed
+    assert ws[2] > ws[1]  # the replay with the larger lists enlarged the rows
+    pt.petar_destroy(c)
+
+
 def test_back_to_back_builds_growing(pt, orc):
     """A build returns with its second half still queued; a following build
     on more particles reallocates the buffers that half uses. The force on
