@@ -1042,7 +1042,7 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
         // the rows outgrew the scratch (nothing was written): enlarge it and
         // run the neighbour passes again on the kept records; a captured
         // graph holds the old scratch and is captured again
-        ctx->nbrows_cap = h.nb_rows + h.nb_rows / 4 + 4096;
+        ctx->nbrows_cap = h.nb_rows + h.nb_rows / 16 + 4096;
         TRY(ensure(ctx, ctx->nbrows, (size_t)ctx->nbrows_cap * 4));
         ctx->graph_stale = true;
         enqueue_nb(ctx, a.nb, s, timed, true);
