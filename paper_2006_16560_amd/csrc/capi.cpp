@@ -2,6 +2,7 @@
 // launches of the tree build and the long-range force (see include/petar.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -933,11 +934,16 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
 
 // The neighbour passes over the near leaves handed over by the force walk
 // (the walk-based pass takes over on the device if the records overflowed).
-// The force kernel has stored each target's list bound in nbcnt (Morton
-// order); their prefix sum gives the rows. `redo`: the passes again after
-// the rows outgrew the scratch, from the kept records and row offsets (the
-// pass queue and the long-list count are cleared again).
-void enqueue_nb(petar_ctx *ctx, petar_nblist *nb, hipStream_t s, bool timed, bool redo) {
+// Rows: kBounds, the force kernel has stored each target's list bound in
+// nbcnt (Morton order) and their prefix sum places the rows; kRedo, the
+// rows of the previous passes again (they outgrew the scratch, which has
+// been enlarged); kExact, a counting pass first gives exact bounds (when the
+// walk's bounds ask for more rows than the scratch may hold). kRedo and
+// kExact run on the kept records and clear the pass queues and the
+// long-list count again.
+enum NbRows { kBounds, kRedo, kExact };
+
+void enqueue_nb(petar_ctx *ctx, petar_nblist *nb, hipStream_t s, bool timed, NbRows mode) {
     const int64_t n = ctx->n;
     TreeDev t = tree_view(ctx);
     Status *st = ptr<Status>(ctx->status);
@@ -948,19 +954,25 @@ void enqueue_nb(petar_ctx *ctx, petar_nblist *nb, hipStream_t s, bool timed, boo
     rec.count = queue + 16;  // [16] headers, [17] leaf entries (zeroed with the queue)
     rec.head_cap = ctx->nbhead_cap;
     rec.leaf_cap = ctx->nbleaf_cap;
+    const uint32_t *groups = ptr<uint32_t>(ctx->groups);
+    uint32_t *spill = ptr<uint32_t>(ctx->spill);
     uint32_t *cnt = ptr<uint32_t>(ctx->nbcnt), *cnt_in = ptr<uint32_t>(ctx->nbcnt_in);
     int64_t *row_off = ptr<int64_t>(ctx->nbrowoff);
     int32_t *rows = ptr<int32_t>(ctx->nbrows);
     int64_t *ws = ptr<int64_t>(ctx->scan_ws);
     if (timed) (void)hipEventRecord(ctx->ev[6], s);
-    if (redo)
-        fill_u32(queue + 8, 0, 8, s);
-    else
-        scan_u32_to_i64(cnt, row_off, n, ws, s);  // bounds -> rows
-    fill_u32(cnt, 0, n + 1, s);                   // the counts of the testing pass
+    if (mode != kBounds) fill_u32(queue + 8, 0, 8, s);
+    if (mode == kExact) {
+        fill_u32(cnt, 0, n + 1, s);
+        launch_nb_count_rec(t, rec, st, cnt, s);
+        launch_nb_write(t, groups, st, cnt, nullptr, nullptr, 0, spill, queue + 11, rec,
+                        ctx->nb_waves, s);
+    }
+    if (mode != kRedo) scan_u32_to_i64(cnt, row_off, n, ws, s);  // bounds -> rows
+    fill_u32(cnt, 0, n + 1, s);  // the counts of the testing pass
     launch_nb_write_rec(t, rec, st, row_off, cnt, rows, ctx->nbrows_cap, s);
-    launch_nb_write(t, ptr<uint32_t>(ctx->groups), st, cnt, row_off, rows, ctx->nbrows_cap,
-                    ptr<uint32_t>(ctx->spill), queue + 9, rec, ctx->nb_waves, s);
+    launch_nb_write(t, groups, st, cnt, row_off, rows, ctx->nbrows_cap, spill, queue + 9, rec,
+                    ctx->nb_waves, s);
     launch_nb_counts_in(t, cnt, cnt_in, s);
     scan_u32_to_i64(cnt_in, nb->offsets_dev, n, ws, s);
     launch_nb_sort(t, row_off, rows, nb->offsets_dev, nb->idx_dev, nb->capacity, st, cnt,
@@ -1027,7 +1039,7 @@ void enqueue_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, bool timed
     if (timed) (void)hipEventRecord(ctx->ev[4], s);
     launch_force(f, fw, s);
     if (timed) (void)hipEventRecord(ctx->ev[5], s);
-    if (a.nb) enqueue_nb(ctx, a.nb, s, timed, false);
+    if (a.nb) enqueue_nb(ctx, a.nb, s, timed, kBounds);
     if (timed) (void)hipEventRecord(ctx->ev[3], s);
 }
 
@@ -1037,15 +1049,30 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
     TRY(read_status(ctx, s));
     TRY(settle_build_stats(ctx, true));
     const Status &h = *ctx->host_status;
+    bool exact = false;
     if (a.nb && !h.invalid_radii && !h.stack_overflow && !h.cell_overflow &&
         h.nb_rows > ctx->nbrows_cap) {
-        // the rows outgrew the scratch (nothing was written): enlarge it and
-        // run the neighbour passes again on the kept records; a captured
-        // graph holds the old scratch and is captured again
-        ctx->nbrows_cap = h.nb_rows + h.nb_rows / 16 + 4096;
-        TRY(ensure(ctx, ctx->nbrows, (size_t)ctx->nbrows_cap * 4));
-        ctx->graph_stale = true;
-        enqueue_nb(ctx, a.nb, s, timed, true);
+        // The rows outgrew the scratch (nothing was written): enlarge it and
+        // run the neighbour passes again on the kept records (a captured
+        // graph holds the old scratch and is captured again). Rows beyond
+        // 256 entries a particle (degenerate leaves, huge search radii) or
+        // the workspace cap are not taken: exact counts bound the rows
+        // instead, which then need no more than the caller's capacity.
+        const int64_t want = h.nb_rows + h.nb_rows / 16 + 4096;
+        const int64_t limit = std::max<int64_t>(256 * ctx->n, int64_t(1) << 24);
+        const int64_t cap_bytes = ctx->params.workspace_cap;
+        const int64_t after = ctx->ws_bytes - (int64_t)ctx->nbrows.cap + want * 4;
+        exact = want > limit || (cap_bytes > 0 && after > cap_bytes);
+        if (!exact) {
+            ctx->nbrows_cap = want;
+        } else if (a.nb->capacity + 4096 > ctx->nbrows_cap) {
+            ctx->nbrows_cap = a.nb->capacity + 4096;
+        }
+        if ((size_t)ctx->nbrows_cap * 4 > ctx->nbrows.cap) {
+            TRY(ensure(ctx, ctx->nbrows, (size_t)ctx->nbrows_cap * 4));
+            ctx->graph_stale = true;
+        }
+        enqueue_nb(ctx, a.nb, s, timed, exact ? kExact : kRedo);
         HIP_TRY(ctx, hipGetLastError());
         TRY(read_status(ctx, s));
     }
@@ -1076,7 +1103,8 @@ petar_status finish_force(petar_ctx *ctx, const ForceArgs &a, hipStream_t s, boo
             if (used[1] > ctx->nbleaf_cap) ctx->nbleaf_cap = grow(used[1]);
             ctx->graph_stale = true;
         }
-        a.nb->required = h.nb_total;
+        // exact rows that do not fit hold more entries than the capacity
+        a.nb->required = exact && h.nb_rows > ctx->nbrows_cap ? h.nb_rows : h.nb_total;
         ctx->stats.nb_total = a.nb->required;
         if (a.nb->required > a.nb->capacity)
             return fail(ctx, PETAR_E_NB_OVERFLOW, "neighbour capacity %lld < required %lld",

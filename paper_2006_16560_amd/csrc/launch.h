@@ -166,8 +166,14 @@ void launch_force(const ForceLaunch &f, int resident_waves, hipStream_t s);
 void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
                          const int64_t *row_off, uint32_t *cursor, int32_t *rows, int64_t row_cap,
                          hipStream_t s);
+// The same counting only (cnt += hits, Morton order): exact bounds for the
+// fallback when the walk's bounds ask for more rows than the scratch may
+// hold.
+void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
+                         uint32_t *cnt, hipStream_t s);
 // Walk-based testing pass: runs only when the near-leaf records overflowed
-// (or were not written: rec.count == nullptr); stores the counts in cursor.
+// (or were not written: rec.count == nullptr); stores the counts in cursor
+// (rows null: counts only).
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cursor,
                      const int64_t *row_off, int32_t *rows, int64_t row_cap, uint32_t *spill,
                      uint32_t *queue, const NbRecords &rec, int resident_waves, hipStream_t s);

@@ -45,7 +45,8 @@ __device__ __forceinline__ int find_leaf(const uint32_t *pre, int nleaf, uint32_
 }
 
 // Tests the buffered leaves' particles against each lane's target and
-// writes the hits (input-order indices) at out[wpos + count].
+// writes the hits (input-order indices) at out[wpos + count] (out null:
+// counts only).
 __device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &pi, double rsi,
                          uint32_t ki, bool valid, uint32_t &count, int32_t *out, int64_t wpos) {
     wave_sync();
@@ -71,7 +72,7 @@ __device__ void nb_flush(NbLds &L, int nleaf, const TreeDev &t, const double4 &p
             uint32_t kj = L.jk[j];
             bool hit = valid && kj != ki && nb_pair(pi.x, pi.y, pi.z, rsi, pj.x, pj.y, pj.z, L.jr[j]);
             if (hit) {
-                out[wpos + count] = (int32_t)t.orig[kj];
+                if (out) out[wpos + count] = (int32_t)t.orig[kj];
                 count++;
             }
         }
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
     if (rec.count && rec.count[0] <= rec.head_cap && rec.count[1] <= rec.leaf_cap)
         return;  // the record passes run instead
-    if (row_off[t.n] > row_cap) return;
+    if (rows && row_off[t.n] > row_cap) return;
     const int64_t gwave = (int64_t)blockIdx.x * kWavesPerBlock + w;
     const int64_t n_groups = st->n_groups;
     WaveStack stk;
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
             double rsi = t.rsk[ki];
             uint32_t count = 0;
             int64_t wpos = 0;
-            if (valid) wpos = row_off[ki];
+            if (rows && valid) wpos = row_off[ki];
             int nleaf = 0;
             stk.init((uint32_t)uniform((int)root_of(t.nd_info, t.level_off, ginfo.x)));
             bool ok = true;
@@ -201,13 +202,16 @@ __device__ __forceinline__ bool nb_pair_sq(const double4 &pi, double rsi2, const
     return near_i | (d2 < rj2);
 }
 
+// kCount: only count each target's hits into cursor (the exact bounds of
+// the fallback for rows too large for the scratch; row_off, rows unused).
+template <bool kCount>
 __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, const Status *st,
                                                      const int64_t *row_off, uint32_t *cursor,
                                                      int32_t *rows, int64_t row_cap) {
     __shared__ NbRecLds lds_all[kWavesPerBlock];
     NbRecLds &L = lds_all[uniform((int)(threadIdx.x / kWave))];
     if (st->invalid_radii || st->stack_overflow || st->cell_overflow) return;
-    if (row_off[t.n] > row_cap) return;
+    if (!kCount && row_off[t.n] > row_cap) return;
     const uint32_t nrec = rec.count[0];
     if (nrec > rec.head_cap || rec.count[1] > rec.leaf_cap) return;  // walk-based passes run
     const int lane = lane_id();
@@ -263,8 +267,10 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
                 if (nb_pair_sq(pi, rsi2, *(const double4 *)p)) {
                     const uint32_t kj = L.jk[(uint32_t)(p - jbase) >> 5];
                     if (kj != ki) {
-                        if (c == (uint32_t)kHitBuf) flush();
-                        L.hit[c][lane] = kj;
+                        if constexpr (!kCount) {
+                            if (c == (uint32_t)kHitBuf) flush();
+                            L.hit[c][lane] = kj;
+                        }
                         c++;
                     }
                 }
@@ -289,7 +295,12 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
                     if (p < pend) test(p);
                 }
             }
-            if (c) flush();
+            if (c) {
+                if constexpr (kCount)
+                    atomicAdd(&cursor[ki], c);
+                else
+                    flush();
+            }
             wave_sync();
         }
     }
@@ -569,8 +580,14 @@ int nb_resident_waves(int device) {
 void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
                          const int64_t *row_off, uint32_t *cursor, int32_t *rows, int64_t row_cap,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_nb_rec, dim3(2048), dim3(kThreads), 0, s, t, rec, st, row_off, cursor,
-                       rows, row_cap);
+    hipLaunchKernelGGL(k_nb_rec<false>, dim3(2048), dim3(kThreads), 0, s, t, rec, st, row_off,
+                       cursor, rows, row_cap);
+}
+
+void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
+                         uint32_t *cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_nb_rec<true>, dim3(2048), dim3(kThreads), 0, s, t, rec, st,
+                       (const int64_t *)nullptr, cnt, (int32_t *)nullptr, (int64_t)0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_nb_counts_in(const uint32_t *rank,

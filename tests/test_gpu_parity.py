@@ -1346,6 +1346,31 @@ def test_nb_rows_grow_and_redo(pt, orc):
     pt.petar_destroy(c)
 
 
+def test_nb_exact_rows_fallback(pt, orc):
+    """With a leaf size above N the root is one leaf and one group, so the
+    walk bounds every list by all N particles: more scratch than the 256
+    entries a particle the rows may take. The passes then count exactly
+    before writing; the lists stay bit-exact and a capacity one short reports
+    the exact requirement."""
+    c, rin, rout, rs = cluster_with_radii(orc, 6000, 31, bf=0.5)
+    o_ref, i_ref = orc.neighbours(c.pos, rs)
+    need = int(o_ref[-1])
+    ctx = pt.petar_create(0)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=2)
+    pt.petar_tree_build(ctx, T(c.pos), T(c.mass), 0.5, 10000)
+    with pytest.raises(pt.PetarError) as e:
+        pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs), nb_capacity=need - 1)
+    assert e.value.status == pt.PETAR_E_NB_OVERFLOW and e.value.required == need
+    for _ in range(2):
+        acc, _, (offs, idx) = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs),
+                                                  nb_capacity=need)
+        assert np.array_equal(offs.cpu().numpy(), o_ref)
+        assert np.array_equal(idx.cpu().numpy(), i_ref)
+    a_ref, _, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.5, 10000, 64)
+    assert np.percentile(rel_err(acc.cpu().numpy(), a_ref), 99) < 1e-5
+    pt.petar_destroy(ctx)
+
+
 def test_back_to_back_builds_growing(pt, orc):
     """A build returns with its second half still queued; a following build
     on more particles reallocates the buffers that half uses. The force on
