@@ -13,7 +13,8 @@
 // them, a prefix sum of the counts in input order gives the CSR offsets, and
 // a per-list sort moves the rows into the CSR. If the hand-over buffers
 // overflowed, a walk of the near region per group (same opening rule)
-// replaces the hand-over.
+// replaces the hand-over; if the bounds ask for more scratch than the
+// caller allows, a counting pass gives exact bounds first.
 #include "launch.h"
 #include "walk.h"
 
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
 
 // Neighbour passes over the near leaves handed over by the force walk. A
 // header lists one flush of a group's near leaves; a group may have several.
+//
 // Testing pass. A wave takes one header at a time: the group's targets sit
 // in the lanes (FP64 position and squared search radius in registers; a
 // group of g < 64 targets puts each target on 64/g lanes that split the
