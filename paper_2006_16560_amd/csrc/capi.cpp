@@ -47,7 +47,7 @@ struct petar_ctx {
     DevBuf pre_info, pre_parent, pre_nchild, new_of_old, lkey0, lkey1, lval0, lval1;
     // force
     DevBuf gflag, gpos, groups, spill, queue, counts, nbcnt, radii_ws, nbhead, nbleaf, sys_off;
-    DevBuf nbrowoff, nbrows, nbcnt_in;  // neighbour rows (Morton order), counts in input order
+    DevBuf nbrowoff, nbrows;  // neighbour rows: offsets (input order) and scratch
     DevBuf tflag, tpos, tidx;  // target compaction (petar_set_targets)
     // second-stage filter and clusters
     DevBuf cl_keep, cl_row, cl_counts, cl_parent, cl_root, cl_rootpos, cl_status, cl_flags,
@@ -238,7 +238,7 @@ void free_all(petar_ctx *c) {
                       &c->lkey0,    &c->lkey1,       &c->lval0,      &c->lval1,
                       &c->gflag,    &c->gpos,        &c->groups,     &c->spill,
                       &c->queue,    &c->counts,      &c->nbcnt,      &c->radii_ws,   &c->nbhead, &c->nbleaf,
-                      &c->nbrowoff, &c->nbrows,  &c->nbcnt_in,
+                      &c->nbrowoff, &c->nbrows,
                       &c->cl_keep,  &c->cl_row,      &c->cl_counts,   &c->cl_parent,  &c->cl_root,    &c->cl_rootpos,
                       &c->cl_status,   &c->cl_flags,   &c->cl_key0,    &c->cl_key1,
                       &c->cl_val0,  &c->cl_val1,
@@ -920,7 +920,6 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
         // previous call needed (finish_force grows it and redoes the passes)
         if (ctx->nbrows_cap < 32 * n + 4096) ctx->nbrows_cap = 32 * n + 4096;
         TRY(ensure(ctx, ctx->nbrowoff, (size_t)(n + 1) * 8));
-        TRY(ensure(ctx, ctx->nbcnt_in, (size_t)(n + 1) * 4));
         TRY(ensure(ctx, ctx->nbrows, (size_t)ctx->nbrows_cap * 4));
     }
     if (ctx->target) {
@@ -935,7 +934,7 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
 // The neighbour passes over the near leaves handed over by the force walk
 // (the walk-based pass takes over on the device if the records overflowed).
 // Rows: kBounds, the force kernel has stored each target's list bound in
-// nbcnt (Morton order) and their prefix sum places the rows; kRedo, the
+// nbcnt (input order) and their prefix sum places the rows; kRedo, the
 // rows of the previous passes again (they outgrew the scratch, which has
 // been enlarged); kExact, a counting pass first gives exact bounds (when the
 // walk's bounds ask for more rows than the scratch may hold). kRedo and
@@ -956,7 +955,7 @@ void enqueue_nb(petar_ctx *ctx, petar_nblist *nb, hipStream_t s, bool timed, NbR
     rec.leaf_cap = ctx->nbleaf_cap;
     const uint32_t *groups = ptr<uint32_t>(ctx->groups);
     uint32_t *spill = ptr<uint32_t>(ctx->spill);
-    uint32_t *cnt = ptr<uint32_t>(ctx->nbcnt), *cnt_in = ptr<uint32_t>(ctx->nbcnt_in);
+    uint32_t *cnt = ptr<uint32_t>(ctx->nbcnt);
     int64_t *row_off = ptr<int64_t>(ctx->nbrowoff);
     int32_t *rows = ptr<int32_t>(ctx->nbrows);
     int64_t *ws = ptr<int64_t>(ctx->scan_ws);
@@ -973,9 +972,8 @@ void enqueue_nb(petar_ctx *ctx, petar_nblist *nb, hipStream_t s, bool timed, NbR
     launch_nb_write_rec(t, rec, st, row_off, cnt, rows, ctx->nbrows_cap, s);
     launch_nb_write(t, groups, st, cnt, row_off, rows, ctx->nbrows_cap, spill, queue + 9, rec,
                     ctx->nb_waves, s);
-    launch_nb_counts_in(t, cnt, cnt_in, s);
-    scan_u32_to_i64(cnt_in, nb->offsets_dev, n, ws, s);
-    launch_nb_sort(t, row_off, rows, nb->offsets_dev, nb->idx_dev, nb->capacity, st, cnt,
+    scan_u32_to_i64(cnt, nb->offsets_dev, n, ws, s);
+    launch_nb_sort(row_off, rows, nb->offsets_dev, nb->idx_dev, n, nb->capacity, st, cnt,
                    queue + 10, s);
     launch_nb_summary(nb->offsets_dev, row_off, n, queue + 16, st, s);
     if (timed) (void)hipEventRecord(ctx->ev[7], s);

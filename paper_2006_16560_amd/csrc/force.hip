@@ -734,7 +734,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 f.acc[2 * n + o] = az;
                 f.pot[o] = f.G * T.acc[u].get(3);
                 if (f.kick_vel) kick_write(f.kick_vel, n, o, ax, ay, az, f.kick_dt);
-                if (f.nb_bound) f.nb_bound[T.k[u]] = (uint32_t)n_near;
+                if (f.nb_bound) f.nb_bound[o] = (uint32_t)n_near;
                 if (f.counts) {
                     f.counts[o] = (int32_t)n_pc;
                     f.counts[n + o] = (int32_t)n_far;

@@ -132,7 +132,7 @@ struct ForceLaunch {
     uint32_t *queue;           // 8 work-queue heads
     int32_t *counts;           // optional per-particle counts [4][n]
     NbRecords nb;              // near-leaf lists for the neighbour passes (head null: none)
-    uint32_t *nb_bound;        // optional [n], Morton order: particles of the group's near
+    uint32_t *nb_bound;        // optional [n], input order: particles of the group's near
                                // leaves, a bound of each target's neighbour list
     double *kick_vel;          // optional [3][n]: vel += kick_dt * acc with the output write
     double kick_dt;
@@ -154,19 +154,19 @@ int64_t force_spill_elems_per_wave();
 void launch_force(const ForceLaunch &f, int resident_waves, hipStream_t s);
 
 // -------------------------------------------------------------- nblist.hip
-// Neighbour lists around two prefix sums. The force walk bounds each
-// target's list by the particles of its group's near leaves (nb_bound,
-// Morton order); the prefix sum of the bounds gives every target a row of
-// scratch (row_off, Morton order); a testing pass writes each target's hits
-// into its row and counts them (cursor, Morton order); the counts in input
-// order give the CSR offsets; a per-list sort moves the rows into the CSR.
+// Neighbour lists around two prefix sums, all per target in input order. The
+// force walk bounds each target's list by the particles of its group's near
+// leaves (nb_bound); the prefix sum of the bounds gives every target a row
+// of scratch (row_off); a testing pass writes each target's hits into its
+// row and counts them (cursor); the prefix sum of the counts gives the CSR
+// offsets; a per-list sort moves the rows into the CSR.
 // Testing pass over the near-leaf records of the force walk; it does nothing
 // when the records overflowed (*rec_count > rec_cap) or the rows exceed the
 // scratch (row_off[n] > row_cap).
 void launch_nb_write_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
                          const int64_t *row_off, uint32_t *cursor, int32_t *rows, int64_t row_cap,
                          hipStream_t s);
-// The same counting only (cnt += hits, Morton order): exact bounds for the
+// The same counting only (cnt += hits): exact bounds for the
 // fallback when the walk's bounds ask for more rows than the scratch may
 // hold.
 void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *st,
@@ -177,16 +177,13 @@ void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *s
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cursor,
                      const int64_t *row_off, int32_t *rows, int64_t row_cap, uint32_t *spill,
                      uint32_t *queue, const NbRecords &rec, int resident_waves, hipStream_t s);
-// cnt_in[i] = cursor[rank[i]]: the counts in input order.
-void launch_nb_counts_in(const TreeDev &t, const uint32_t *cursor, uint32_t *cnt_in,
-                         hipStream_t s);
 // st->nb_total = offsets[n], st->nb_rows = row_off[n], st->rec_used =
 // rec_count[0..1] (one status copy then tells the host the list size, the
 // scratch the rows need and the hand-over use).
 void launch_nb_summary(const int64_t *offsets, const int64_t *row_off, int64_t n,
                        const uint32_t *rec_count, Status *st, hipStream_t s);
-void launch_nb_sort(const TreeDev &t, const int64_t *row_off, const int32_t *rows,
-                    const int64_t *offsets, int32_t *idx, int64_t capacity, const Status *st,
+void launch_nb_sort(const int64_t *row_off, const int32_t *rows, const int64_t *offsets,
+                    int32_t *idx, int64_t n, int64_t capacity, const Status *st,
                     uint32_t *long_list, uint32_t *long_count, hipStream_t s);
 int nb_resident_waves(int device);
 

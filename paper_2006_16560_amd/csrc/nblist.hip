@@ -9,9 +9,9 @@
 // candidate is found. A target's candidates lie among the particles of its
 // group's near leaves, whose number the force walk stores as the bound of
 // its list: a prefix sum of the bounds gives every target a row of scratch
-// (Morton order), one testing pass writes the hits into the rows and counts
-// them, a prefix sum of the counts in input order gives the CSR offsets, and
-// a per-list sort moves the rows into the CSR. If the hand-over buffers
+// (input order), one testing pass writes the hits into the rows and counts
+// them, a prefix sum of the counts gives the CSR offsets, and a per-list
+// sort moves the rows into the CSR. If the hand-over buffers
 // overflowed, a walk of the near region per group (same opening rule)
 // replaces the hand-over; if the bounds ask for more scratch than the
 // caller allows, a counting pass gives exact bounds first.
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
             double rsi = t.rsk[ki];
             uint32_t count = 0;
             int64_t wpos = 0;
-            if (rows && valid) wpos = row_off[ki];
+            if (rows && valid) wpos = row_off[t.orig[ki]];
             int nleaf = 0;
             stk.init((uint32_t)uniform((int)root_of(t.nd_info, t.level_off, ginfo.x)));
             bool ok = true;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
                 break;
             }
             if (nleaf) nb_flush(L, nleaf, t, pi, rsi, ki, valid, count, rows, wpos);
-            if (valid) cursor[ki] = count;
+            if (valid) cursor[t.orig[ki]] = count;
         }
     }
 }
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_nb(TreeDev t, const uint32_t *grou
 // one load per lane (the next batch is loaded into registers while the
 // current one is tested), and every lane tests its target against its share
 // of the staged particles (LDS broadcasts). A lane collects its hits in LDS
-// and takes kHitBuf slots at a time of its target's row (row_off, Morton
+// and takes kHitBuf slots at a time of its target's row (row_off, input
 // order) from a per-target cursor, which ends as the target's count (the
 // lists are sorted afterwards, so the slot order is irrelevant). Nothing is
 // written when the rows exceed the scratch (row_off[n] > row_cap): the
@@ -243,6 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             const double4 pi = t.ps[ki];
             const double rsi = t.rsk[ki];
             const double rsi2 = rsi * rsi;
+            const uint32_t oi = t.orig[ki];
             uint32_t c = 0;
             // one batch of 64 sources into registers (lane = source)
             double4 pn = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             };
             // this lane's buffered hits into its target's row
             auto flush = [&]() {
-                const int64_t w0 = row_off[ki] + (int64_t)atomicAdd(&cursor[ki], c);
+                const int64_t w0 = row_off[oi] + (int64_t)atomicAdd(&cursor[oi], c);
                 for (uint32_t h = 0; h < c; h++) rows[w0 + h] = (int32_t)t.orig[L.hit[h][lane]];
                 c = 0;
             };
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
             }
             if (c) {
                 if constexpr (kCount)
-                    atomicAdd(&cursor[ki], c);
+                    atomicAdd(&cursor[oi], c);
                 else
                     flush();
             }
@@ -351,8 +352,7 @@ __device__ __forceinline__ void sort_in_registers(int32_t *a, int len) {
         if (q < len) a[q] = v[q];
 }
 
-__global__ __launch_bounds__(kThreads) void k_nb_sort_short(const uint32_t *rank,
-                                                            const int64_t *row_off,
+__global__ __launch_bounds__(kThreads) void k_nb_sort_short(const int64_t *row_off,
                                                             const int32_t *rows,
                                                             const int64_t *offsets, int32_t *idx,
                                                             int64_t n, int64_t capacity,
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_short(const uint32_t *rank
         }
         __syncthreads();  // the previous targets are done with the LDS
         if ((int)threadIdx.x < nt) {
-            row0[threadIdx.x] = row_off[rank[i]];
+            row0[threadIdx.x] = row_off[i];
             dst0[threadIdx.x] = b - r0;
         }
         if (threadIdx.x == 0) dst0[nt] = r1 - r0;
@@ -592,23 +592,6 @@ void launch_nb_count_rec(const TreeDev &t, const NbRecords &rec, const Status *s
                        (const int64_t *)nullptr, cnt, (int32_t *)nullptr, (int64_t)0);
 }
 
-__global__ __launch_bounds__(kThreads) void k_nb_counts_in(const uint32_t *rank,
-                                                           const uint32_t *cursor, int64_t n,
-                                                           uint32_t *cnt_in) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        cnt_in[i] = cursor[rank[i]];
-}
-
-void launch_nb_counts_in(const TreeDev &t, const uint32_t *cursor, uint32_t *cnt_in,
-                         hipStream_t s) {
-    int64_t blocks = (t.n + kThreads - 1) / kThreads;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_nb_counts_in, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                       (const uint32_t *)t.rank, (const uint32_t *)cursor, t.n, cnt_in);
-}
-
 void launch_nb_write(const TreeDev &t, const uint32_t *groups, Status *st, uint32_t *cursor,
                      const int64_t *row_off, int32_t *rows, int64_t row_cap, uint32_t *spill,
                      uint32_t *queue, const NbRecords &rec, int resident_waves, hipStream_t s) {
@@ -632,16 +615,14 @@ void launch_nb_summary(const int64_t *offsets, const int64_t *row_off, int64_t n
                        st);
 }
 
-void launch_nb_sort(const TreeDev &t, const int64_t *row_off, const int32_t *rows,
-                    const int64_t *offsets, int32_t *idx, int64_t capacity, const Status *st,
+void launch_nb_sort(const int64_t *row_off, const int32_t *rows, const int64_t *offsets,
+                    int32_t *idx, int64_t n, int64_t capacity, const Status *st,
                     uint32_t *long_list, uint32_t *long_count, hipStream_t s) {
-    const int64_t n = t.n;
     int64_t blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_nb_sort_short, dim3((unsigned)blocks), dim3(kThreads), 0, s,
-                       (const uint32_t *)t.rank, row_off, rows, offsets, idx, n, capacity, st,
-                       long_list, long_count);
+    hipLaunchKernelGGL(k_nb_sort_short, dim3((unsigned)blocks), dim3(kThreads), 0, s, row_off,
+                       rows, offsets, idx, n, capacity, st, long_list, long_count);
     hipLaunchKernelGGL(k_nb_sort_long, dim3(1024), dim3(kThreads), 0, s, offsets, idx, n, capacity,
                        st, (const uint32_t *)long_list, (const uint32_t *)long_count);
 }
