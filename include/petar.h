@@ -172,7 +172,10 @@ PETAR_API petar_status petar_batch_build(petar_ctx *ctx, int n_sys, const int64_
  * radii; 0 <= r_in < r_out <= r_search and finite for every particle. nb
  * may be NULL (no neighbour lists). On PETAR_E_NB_OVERFLOW acc and pot are
  * complete and nb->required is set: the caller retries with a larger
- * buffer. */
+ * buffer. With lists, the library also holds scratch rows of 4 bytes per
+ * pair its near test examines (bounded by 256 entries a particle and by
+ * params.workspace_cap; beyond that it counts exactly first and needs no
+ * more rows than nb->capacity). */
 PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const double *r_in_dev,
                               const double *r_out_dev, const double *r_search_dev,
                               double *acc_dev, double *pot_dev, petar_nblist *nb);
