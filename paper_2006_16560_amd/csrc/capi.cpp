@@ -916,9 +916,12 @@ petar_status alloc_force(petar_ctx *ctx, const ForceArgs &a) {
         ctx->nbleaf_cap = cap((uint64_t)n * 2 + 4096, ctx->nbleaf_cap);
         TRY(ensure(ctx, ctx->nbhead, (size_t)ctx->nbhead_cap * sizeof(uint4)));
         TRY(ensure(ctx, ctx->nbleaf, (size_t)ctx->nbleaf_cap * sizeof(uint2)));
-        // rows: a first guess of 32 entries a particle, then what the
-        // previous call needed (finish_force grows it and redoes the passes)
-        if (ctx->nbrows_cap < 32 * n + 4096) ctx->nbrows_cap = 32 * n + 4096;
+        // rows: a first guess of 32 entries a particle (no more than the
+        // caller's list capacity, which is all the exact fallback needs), then
+        // what the previous call needed (finish_force grows it and redoes the
+        // passes)
+        const int64_t first = std::min<int64_t>(32 * n, a.nb->capacity) + 4096;
+        if (ctx->nbrows_cap < first) ctx->nbrows_cap = first;
         TRY(ensure(ctx, ctx->nbrowoff, (size_t)(n + 1) * 8));
         TRY(ensure(ctx, ctx->nbrows, (size_t)ctx->nbrows_cap * 4));
     }
