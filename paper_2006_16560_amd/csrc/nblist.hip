@@ -316,10 +316,12 @@ __global__ __launch_bounds__(kThreads) void k_nb_rec(TreeDev t, NbRecords rec, c
 // short list (<= 32 entries, almost all) in registers, and the block writes
 // them out with coalesced stores. Longer lists are queued and sorted in the
 // CSR: up to kWaveMax entries a wave each (bitonic network over the wave's
-// registers), above that a block each (bitonic network in LDS), and above
-// kLongMax entries a heap sort by one thread.
+// registers, 1 to 32 entries a lane: no barriers, so a list of a few hundred
+// entries does not hold a block through hundreds of them), above that a
+// block each (bitonic network in LDS), and above kLongMax entries a heap
+// sort by one thread.
 constexpr int kShortMax = 32;
-constexpr int kWaveMax = 4 * kWave;
+constexpr int kWaveMax = 32 * kWave;
 constexpr int kLongMax = 4096;
 constexpr int kStage = 4096;
 
@@ -526,8 +528,14 @@ __global__ __launch_bounds__(kThreads) void k_nb_sort_long(const int64_t *offset
             sort_in_wave<1>(idx + b, len);
         else if (len <= 2 * kWave)
             sort_in_wave<2>(idx + b, len);
-        else if (len <= kWaveMax)
+        else if (len <= 4 * kWave)
             sort_in_wave<4>(idx + b, len);
+        else if (len <= 8 * kWave)
+            sort_in_wave<8>(idx + b, len);
+        else if (len <= 16 * kWave)
+            sort_in_wave<16>(idx + b, len);
+        else if (len <= kWaveMax)
+            sort_in_wave<32>(idx + b, len);
     }
     // longer lists: a block each
     for (uint32_t q = blockIdx.x; q < nl; q += gridDim.x) {

@@ -1273,11 +1273,12 @@ def test_every_particle_in_one_group(pt, ctx, orc):
 
 def test_neighbour_list_length_classes(pt, ctx, orc):
     """Lists of every length class of the list sort (in registers per lane up
-    to 32 entries, per wave up to 64, 128 and 256, per block up to 4096, one
-    thread above): clumps of k particles in cubes of side 1e-3, 10 apart, with
-    search radius 0.01, so every list holds exactly the other k - 1 members
-    of its clump."""
-    sizes = [1, 2, 17, 33, 34, 64, 65, 66, 128, 129, 130, 256, 257, 258, 700, 4097, 4200]
+    to 32 entries, per wave up to 64, 128, 256, 512, 1024 and 2048, per block
+    up to 4096, one thread above): clumps of k particles in cubes of side
+    1e-3, 10 apart, with search radius 0.01, so every list holds exactly the
+    other k - 1 members of its clump."""
+    sizes = [1, 2, 17, 33, 34, 64, 65, 66, 128, 129, 130, 256, 257, 258, 513, 514, 700, 1025,
+             1026, 1500, 2049, 2050, 4097, 4200]
     rng = np.random.default_rng(11)
     pos = np.concatenate([rng.uniform(0.0, 1e-3, (3, k)) + np.array([[10.0 * c], [0.0], [0.0]])
                           for c, k in enumerate(sizes)], axis=1)
