@@ -189,9 +189,12 @@ PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const do
  * alone. This gives the particles of the artificial set their roles (Sec.
  * "Artificial particle algorithm for weak perturbation"): the measure points
  * only receive the long-range force, the pseudoparticles (eq. psep) only
- * exert it (petar_art_set.target_dev). The targets' forces are those of an
- * unrestricted call up to the rounding order of their sums (a group's
- * targets may be spread differently over the lanes). NULL restores every
+ * exert it (petar_art_set.target_dev). Cells of zero mass (the massless
+ * measure points and centres of the set) are skipped with their subtrees:
+ * they exert no force, so only the interaction counts change. The targets'
+ * forces are those of an unrestricted call up to the rounding order of
+ * their sums (a group's targets may be spread differently over the lanes,
+ * and the skipped zero terms shift the others). NULL restores every
  * particle as a target; a new tree build does too. Neighbour lists cannot be asked for
  * while a subset is set (PETAR_E_INVALID). Errors: PETAR_E_STATE without a
  * tree. */

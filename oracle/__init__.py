@@ -82,8 +82,8 @@ def lib():
                                        p_i64]
         L.oracle_tree_info.restype = ctypes.c_int
         L.oracle_tree_force.argtypes = [p_d, p_d, p_d, p_d, p_d, i64, d, ctypes.c_int,
-                                        ctypes.c_int, ctypes.c_int, d, p_i64, i64, p_d, p_d,
-                                        p_i64]
+                                        ctypes.c_int, ctypes.c_int, d, p_i64, i64, ctypes.c_int,
+                                        p_d, p_d, p_i64]
         L.oracle_tree_force.restype = ctypes.c_int
         L.oracle_pericentre.argtypes = [p_d, p_d, d, p_d, p_d, d, d]
         L.oracle_pericentre.restype = d
@@ -238,9 +238,12 @@ def tree_info(pos, mass, leaf_size: int, group_size: int, max_level: int = 21) -
 
 
 def tree_force(pos, mass, r_in, r_out, r_search, theta: float, leaf_size: int,
-               group_size: int, G: float = 1.0, idx=None, max_level: int = 21):
+               group_size: int, G: float = 1.0, idx=None, max_level: int = 21,
+               skip_massless: bool = False):
     """Barnes-Hut long-range force with the group-wise walk (tree depth
     max_level: 21 for a single system, 18 per system in batched mode).
+    skip_massless: the walk drops cells of zero mass (the rule of a force on
+    a subset of targets), which changes the counts but no value.
 
     Returns (acc (3,k), pot (k,), counts (4,k)) where counts rows are:
     multipole cells, far-leaf particles, near-leaf particles, group size.
@@ -254,7 +257,8 @@ def tree_force(pos, mass, r_in, r_out, r_search, theta: float, leaf_size: int,
     rc = lib().oracle_tree_force(_p(pos), _p(mass), _p(r_in), _p(r_out), _p(r_search), n,
                                  float(theta), int(leaf_size), int(group_size),
                                  int(max_level), G,
-                                 _p(ix, _c_i64_p), k, _p(acc), _p(pot), _p(counts, _c_i64_p))
+                                 _p(ix, _c_i64_p), k, int(bool(skip_massless)), _p(acc), _p(pot),
+                                 _p(counts, _c_i64_p))
     if rc != 0:
         raise ValueError("invalid tree arguments")
     return acc, pot, counts

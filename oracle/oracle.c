@@ -387,6 +387,10 @@ OR_EXPORT void oracle_multipole_eval(double M, const double *com, const double *
  *  Since r_search >= r_out, every pair reached through a multipole or a far
  *  leaf has x >= 1, where K = W = 0: the long-range force there is plain
  *  Newtonian and the expansion is exact in form.
+ *  With skip_massless (a force on a subset of targets), a cell of zero mass
+ *  is dropped with its subtree before the tests: its multipole and every
+ *  pair term with its particles are zero, so no value changes, only the
+ *  interaction counts.
  * ---------------------------------------------------------------------- */
 
 #define OR_MAXLEVEL 21 /* default depth: 21 bits per axis */
@@ -507,9 +511,11 @@ typedef struct {
  * number of cells never overflow. */
 static void lists_push(int64_t **a, int64_t *na, int64_t v) { (*a)[(*na)++] = v; }
 
-static void walk(const ocells *cs, int64_t cid, const ocell *g, double th2, double ext, olists *L)
+static void walk(const ocells *cs, int64_t cid, const ocell *g, double th2, double ext,
+                 int skip_massless, olists *L)
 {
     const ocell *c = &cs->c[cid];
+    if (skip_massless && c->M == 0.0) return;
     double D2 = box_dist2(g->lo, g->hi, c->lo, c->hi);
     double dmin2 = point_box_dist2(g->lo, g->hi, c->com);
     double R = g->rsmax > c->rsmax ? g->rsmax : c->rsmax;
@@ -528,7 +534,7 @@ static void walk(const ocells *cs, int64_t cid, const ocell *g, double th2, doub
             lists_push(&L->far, &L->nfar, cid);
         return;
     }
-    for (int k = 0; k < c->nchild; k++) walk(cs, c->child[k], g, th2, ext, L);
+    for (int k = 0; k < c->nchild; k++) walk(cs, c->child[k], g, th2, ext, skip_massless, L);
 }
 
 static void find_groups(const ocells *cs, int64_t cid, int group_size, int64_t *groups,
@@ -656,12 +662,14 @@ OR_EXPORT int oracle_tree_info(const double *pos, const double *mass, int64_t n,
 /* Tree force for the targets idx[0..n_idx) (all particles if idx == NULL).
  * acc SoA [3][n_idx], pot [n_idx]. counts (optional) SoA [4][n_idx]:
  * number of multipole cells, far-leaf particles and near-leaf particles in
- * the target's group lists, and the size of its group. Returns 0 or -1. */
+ * the target's group lists, and the size of its group. skip_massless: drop
+ * cells of zero mass from the walk (same values, fewer counted
+ * interactions). Returns 0 or -1. */
 OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const double *r_in,
                                 const double *r_out, const double *r_search, int64_t n,
                                 double theta, int leaf_size, int group_size, int max_level,
-                                double G, const int64_t *idx, int64_t n_idx, double *acc,
-                                double *pot, int64_t *counts)
+                                double G, const int64_t *idx, int64_t n_idx, int skip_massless,
+                                double *acc, double *pot, int64_t *counts)
 {
     if (n < 1 || leaf_size < 1 || group_size < 1 || !(theta >= 0.0) || max_level < 1 ||
         max_level > 21)
@@ -698,7 +706,7 @@ OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const dou
         L.far = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.cap);
         L.near = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.cap);
         L.npc = L.nfar = L.nnear = 0;
-        walk(&b.cells, 0, gc, th2, ext, &L);
+        walk(&b.cells, 0, gc, th2, ext, skip_massless, &L);
         int64_t nfarp = 0, nnearp = 0;
         for (int64_t t = 0; t < L.nfar; t++) nfarp += b.cells.c[L.far[t]].count;
         for (int64_t t = 0; t < L.nnear; t++) nnearp += b.cells.c[L.near[t]].count;

@@ -634,11 +634,14 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 box_terms(L.g, lo, hi, &D2, &R2);
                 const bool near = D2 < R2;
                 const bool accept = mac_accept(L.g, cm, hi.w, th2) & !near;
-                const int kind = !live ? kKindNone
-                                       : (accept ? kKindPc
-                                                 : ((info.z & kLeafFlag)
-                                                        ? (near ? kKindNear : kKindFar)
-                                                        : kKindOpen));
+                int kind = !live ? kKindNone
+                                 : (accept ? kKindPc
+                                           : ((info.z & kLeafFlag)
+                                                  ? (near ? kKindNear : kKindFar)
+                                                  : kKindOpen));
+                // on a subset of targets (no neighbour lists), a cell of zero
+                // mass is dropped with its subtree: it exerts no force
+                if (f.tidx && cm.w == 0.0) kind = kKindNone;
                 int nc = kind == kKindOpen ? info_nchild(info.z) : 0;
                 if (!stk.push(info.w, nc)) {
                     ok = false;

@@ -917,6 +917,46 @@ def test_target_subset_matches_oracle_tree(pt, ctx, orc, theta):
     assert np.array_equal(ab.cpu().numpy(), aa)
 
 
+def test_target_subset_skips_massless_cells(pt, ctx, orc):
+    """On a subset of targets the walk drops cells of zero mass (a clump of
+    massless particles and a third of the others without mass): FP64 against
+    the oracle tree with the same rule within 1e-12 and with equal counts;
+    the counts are lower than without the rule; mixed precision against the
+    unrestricted call within the arithmetic bound."""
+    n = 6000
+    c = workloads.make_cluster(n, 84, imf=True, binary_fraction=0.5)
+    rng = np.random.default_rng(84)
+    pos, mass = c.pos.copy(), c.mass.copy()
+    pos[:, :400] = rng.normal(scale=0.02, size=(3, 400)) + np.array([[1.5], [0.0], [0.0]])
+    mass[:400] = 0.0
+    mass[400:][rng.random(n - 400) < 1.0 / 3.0] = 0.0
+    rin, rout, rs = orc.radii(np.maximum(mass, 1e-6), 0.002, 0.02)
+    tgt = (rng.random(n) < 0.7).astype(np.uint8)
+    idx = np.flatnonzero(tgt)
+    pt.petar_set_params(ctx, precision=pt.PETAR_FP64, i_per_lane=1, record_counts=1)
+    pt.petar_tree_build(ctx, T(pos), T(mass), 0.5, 8)
+    pt.petar_set_targets(ctx, T(tgt))
+    acc, pot = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs))
+    cnt = pt.petar_copy_counts(ctx).cpu().numpy()
+    acc, pot = acc.cpu().numpy(), pot.cpu().numpy()
+    a_ref, p_ref, cnt_ref = orc.tree_force(pos, mass, rin, rout, rs, 0.5, 8, 64, idx=idx,
+                                           skip_massless=True)
+    _, _, cnt_all = orc.tree_force(pos, mass, rin, rout, rs, 0.5, 8, 64, idx=idx)
+    assert cnt_ref[:3].sum() < cnt_all[:3].sum()
+    same = np.all(cnt[:, idx] == cnt_ref, axis=0)
+    assert same.mean() > 0.999
+    assert rel_err(acc[:, idx], a_ref)[same].max() < 1e-12
+    np.testing.assert_allclose(pot[idx][same], p_ref[same], rtol=1e-12)
+    _bound_differing(acc[:, idx], workloads.Cluster(pos=pos, vel=c.vel, mass=mass, n_binaries=0,
+                                                    pairs=c.pairs[:0]), rin, rout, same, idx, orc)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=2, record_counts=0)
+    am, _ = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs))
+    pt.petar_set_targets(ctx, None)
+    aa, _ = pt.petar_force_long(ctx, 64, T(rin), T(rout), T(rs))
+    e = rel_err(am.cpu().numpy()[:, idx], aa.cpu().numpy()[:, idx])
+    assert np.percentile(e, 99) < 1e-5
+
+
 def test_artificial_set_targets(pt, ctx, orc):
     """The set's target flags mark singles, centres and measure points; the
     force on the set restricted to them (pseudoparticles as sources only),

@@ -352,6 +352,41 @@ def test_tree_theta0_is_direct_sum(orc):
         assert np.all(cnt[1] + cnt[2] == 3000)
 
 
+def _with_massless(orc, n, seed):
+    """A cluster where some particles have no mass: a clump of 300 massless
+    particles off to one side (whole cells of zero mass) and a third of the
+    others scattered through the cluster."""
+    c = workloads.make_cluster(n, seed, imf=True, binary_fraction=0.5)
+    rng = np.random.default_rng(seed)
+    pos, mass = c.pos.copy(), c.mass.copy()
+    pos[:, :300] = rng.normal(scale=0.02, size=(3, 300)) + np.array([[1.5], [0.0], [0.0]])
+    mass[:300] = 0.0
+    mass[300:][rng.random(n - 300) < 1.0 / 3.0] = 0.0
+    rin, rout, rs = orc.radii(np.maximum(mass, 1e-6), 0.005, 0.05)
+    return pos, mass, rin, rout, rs
+
+
+def test_tree_skip_massless_changes_no_value(orc):
+    """Dropping the cells of zero mass from the walk (the rule of a force on
+    a subset of targets) leaves every acceleration and potential bit for bit
+    as it was, at theta 0 still equal to the direct sum, and only lowers the
+    interaction counts: whole massless cells are no longer visited."""
+    pos, mass, rin, rout, rs = _with_massless(orc, 3000, 25)
+    idx = np.arange(0, 3000, 3)
+    for theta in (0.0, 0.5):
+        a1, p1, c1 = orc.tree_force(pos, mass, rin, rout, rs, theta, 8, 64, idx=idx)
+        a2, p2, c2 = orc.tree_force(pos, mass, rin, rout, rs, theta, 8, 64, idx=idx,
+                                    skip_massless=True)
+        assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+        assert np.all(c2[:3] <= c1[:3]) and c2[:3].sum() < c1[:3].sum()
+        assert np.array_equal(c2[3], c1[3])
+    a0, p0 = orc.force_long(pos, mass, rin, rout, idx=idx)
+    err = np.linalg.norm(a2 - a0, axis=0) / np.linalg.norm(a0, axis=0)
+    a0t, _, _ = orc.tree_force(pos, mass, rin, rout, rs, 0.0, 8, 64, idx=idx, skip_massless=True)
+    err0 = np.linalg.norm(a0t - a0, axis=0) / np.linalg.norm(a0, axis=0)
+    assert err0.max() < 1e-11 and err.max() < 1e-2
+
+
 def test_tree_error_decreases_with_theta(orc):
     c = workloads.make_cluster(4096, 0, imf=False)
     rin, rout, rs = np.full(4096, 0.01), np.full(4096, 0.1), np.full(4096, 0.12)
