@@ -600,17 +600,24 @@ def bench_artificial(pt, ctx, c, wl, theta, cfg, dev, reps=5, order=3):
         times[key].append(time.perf_counter() - t0)
         return r
 
+    cfg_set = None
     for _ in range(reps):
+        pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=cfg["i_per_lane"])
         label, go, members, pairs = timed(
             "groups", lambda: pt.petar_groups(ctx, pos, vel, mass, ri, theta, offs, idx))
         g = timed("make", lambda: pt.petar_artificial_make(ctx, pos, vel, mass, ri, ro, rs, pairs,
                                                            order, 1.0))
-        timed("set_build", lambda: pt.petar_tree_build(ctx, g["pos"], g["mass"], theta, leaf))
+        if cfg_set is None:  # the set's own launch configuration (autotuner's cache)
+            cfg_set = pt.launch_config(ctx, int(g["mass"].numel()), theta, leaf_default=leaf,
+                                       group_default=group, ipl_default=cfg["i_per_lane"])
+        pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=cfg_set["i_per_lane"])
+        timed("set_build", lambda: pt.petar_tree_build(ctx, g["pos"], g["mass"], theta,
+                                                       cfg_set["leaf_size"]))
         # pseudoparticles act as sources only: the force is wanted on the
         # singles, centres and measure points
         pt.petar_set_targets(ctx, g["target"])
         a_set, p_set = timed("set_force", lambda: pt.petar_force_long(
-            ctx, group, g["r_in"], g["r_out"], g["r_search"]))
+            ctx, cfg_set["group_size"], g["r_in"], g["r_out"], g["r_search"]))
         st = pt.petar_get_stats(ctx)
         ten, acc, pot = timed("fit", lambda: pt.petar_tidal_fit(ctx, g, pairs, a_set, p_set,
                                                                 pos=pos))
@@ -621,7 +628,10 @@ def bench_artificial(pt, ctx, c, wl, theta, cfg, dev, reps=5, order=3):
                 "set_particles": int(g["mass"].numel()),
                 "set_targets": int(g["target"].sum().item()),
                 "set_interactions": int(st["inter_pc"] + st["inter_far"] + st["inter_near"]),
-                "set_force_kernel_ms": st["ms_force_kernel"]})
+                "set_force_kernel_ms": st["ms_force_kernel"],
+                "set_launch": {"leaf_size": cfg_set["leaf_size"],
+                               "group_size": cfg_set["group_size"],
+                               "i_per_lane": cfg_set["i_per_lane"], "tuning": cfg_set["source"]}})
     log("groups/artificial: %s" % json.dumps(out))
     return out
 
