@@ -640,8 +640,13 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                                                   ? (near ? kKindNear : kKindFar)
                                                   : kKindOpen));
                 // on a subset of targets (no neighbour lists), a cell of zero
-                // mass is dropped with its subtree: it exerts no force
-                if (f.tidx && cm.w == 0.0) kind = kKindNone;
+                // mass is dropped with its subtree: it exerts no force (a
+                // branch on the uniform flag, which the empty asm keeps from
+                // being turned into selects executed on every step)
+                if (f.tidx) {
+                    asm volatile("" ::: "memory");
+                    if (cm.w == 0.0) kind = kKindNone;
+                }
                 int nc = kind == kKindOpen ? info_nchild(info.z) : 0;
                 if (!stk.push(info.w, nc)) {
                     ok = false;
