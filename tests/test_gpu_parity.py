@@ -1410,6 +1410,24 @@ def test_nb_exact_rows_fallback(pt, orc):
     a_ref, _, _ = orc.tree_force(c.pos, c.mass, rin, rout, rs, 0.5, 10000, 64)
     assert np.percentile(rel_err(acc.cpu().numpy(), a_ref), 99) < 1e-5
     pt.petar_destroy(ctx)
+    # the same through a captured step: the first call runs eagerly, the
+    # replays take the exact-count passes after the graph
+    ctx = pt.petar_create(0)
+    pt.petar_set_params(ctx, precision=pt.PETAR_MIXED, i_per_lane=2)
+    n = c.mass.size
+    acc_g = torch.empty((3, n), dtype=torch.float64, device="cuda:0")
+    pot_g = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    nbo = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+    nbi = torch.empty(need, dtype=torch.int32, device="cuda:0")
+    args = (T(c.pos), T(c.mass), 0.5, 10000, 64, T(rin), T(rout), T(rs), acc_g, pot_g)
+    for it in range(3):
+        tot = pt.petar_step_graph(ctx, *args, nb=(nbo, nbi))
+        torch.cuda.synchronize()
+        assert tot == need, it
+        assert np.array_equal(nbo.cpu().numpy(), o_ref), it
+        assert np.array_equal(nbi.cpu().numpy(), i_ref), it
+        assert np.array_equal(acc_g.cpu().numpy(), acc.cpu().numpy()), it
+    pt.petar_destroy(ctx)
 
 
 def test_back_to_back_builds_growing(pt, orc):
