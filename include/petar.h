@@ -273,7 +273,7 @@ PETAR_API petar_status petar_autotune(petar_ctx *ctx, const double *pos_dev,
  * keeps the fastest, as petar_autotune does. Cache entries of batches also
  * carry floor(log2 n_sys) (a single system is the batch of one, bucket 0),
  * so batched and single-system choices for one N do not mix. The batching
- * of uneven systems into one launch is this build's (the paper integrates
+ * of uneven systems into one launch is this library's (the paper integrates
  * one system per run); the practice of scanning wall-clock time over
  * parameters is the paper's (Sec. "Performance on GPU-based Desktop"). */
 PETAR_API petar_status petar_autotune_batch(petar_ctx *ctx, int n_sys,
