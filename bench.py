@@ -337,7 +337,7 @@ def main() -> int:
                      "traffic": profiled_value(wl.name, cfg),
                      "counter_fp32_tflops": (fp32_ops / (kernel_ms * 1e-3) / 1e12
                                              if fp32_ops else None),
-                     "kernel": "k_force<float, %d>" % cfg["i_per_lane"],
+                     "kernel": "k_force<float, %d, false>" % cfg["i_per_lane"],
                      "kernel_ms": kernel_ms,
                      "flops_per_interaction": FLOPS_PER_INTERACTION,
                      "interactions_per_launch": inter_step},

@@ -190,8 +190,9 @@ PETAR_API petar_status petar_force_long(petar_ctx *ctx, int group_size, const do
  * "Artificial particle algorithm for weak perturbation"): the measure points
  * only receive the long-range force, the pseudoparticles (eq. psep) only
  * exert it (petar_art_set.target_dev). Cells of zero mass (the massless
- * measure points and centres of the set) are skipped with their subtrees:
- * they exert no force, so only the interaction counts change. The targets'
+ * measure points and centres of the set) are skipped with their subtrees,
+ * and particles of zero mass in the leaves reached are no sources: they
+ * exert no force, so only the interaction counts change. The targets'
  * forces are those of an unrestricted call up to the rounding order of
  * their sums (a group's targets may be spread differently over the lanes,
  * and the skipped zero terms shift the others). NULL restores every

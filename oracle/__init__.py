@@ -242,8 +242,9 @@ def tree_force(pos, mass, r_in, r_out, r_search, theta: float, leaf_size: int,
                skip_massless: bool = False):
     """Barnes-Hut long-range force with the group-wise walk (tree depth
     max_level: 21 for a single system, 18 per system in batched mode).
-    skip_massless: the walk drops cells of zero mass (the rule of a force on
-    a subset of targets), which changes the counts but no value.
+    skip_massless: the walk drops cells of zero mass and the leaf lists
+    particles of zero mass (the rule of a force on a subset of targets),
+    which changes the counts but no value.
 
     Returns (acc (3,k), pot (k,), counts (4,k)) where counts rows are:
     multipole cells, far-leaf particles, near-leaf particles, group size.

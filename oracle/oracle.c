@@ -388,9 +388,10 @@ OR_EXPORT void oracle_multipole_eval(double M, const double *com, const double *
  *  leaf has x >= 1, where K = W = 0: the long-range force there is plain
  *  Newtonian and the expansion is exact in form.
  *  With skip_massless (a force on a subset of targets), a cell of zero mass
- *  is dropped with its subtree before the tests: its multipole and every
- *  pair term with its particles are zero, so no value changes, only the
- *  interaction counts.
+ *  is dropped with its subtree before the tests, and a particle of zero mass
+ *  in a far or near leaf is not a source: its multipole and every pair term
+ *  with such a particle are zero, so no value changes, only the interaction
+ *  counts.
  * ---------------------------------------------------------------------- */
 
 #define OR_MAXLEVEL 21 /* default depth: 21 bits per axis */
@@ -659,12 +660,23 @@ OR_EXPORT int oracle_tree_info(const double *pos, const double *mass, int64_t n,
     return 0;
 }
 
+/* Number of particles of leaf c that act as sources: all of them, or with
+ * skip_massless those of non-zero mass. */
+static int64_t source_count(const obuild *b, const ocell *c, const double *mass,
+                            int skip_massless)
+{
+    if (!skip_massless) return c->count;
+    int64_t k = 0;
+    for (int64_t u = 0; u < c->count; u++) k += mass[b->perm[c->begin + u]] != 0.0;
+    return k;
+}
+
 /* Tree force for the targets idx[0..n_idx) (all particles if idx == NULL).
  * acc SoA [3][n_idx], pot [n_idx]. counts (optional) SoA [4][n_idx]:
  * number of multipole cells, far-leaf particles and near-leaf particles in
  * the target's group lists, and the size of its group. skip_massless: drop
- * cells of zero mass from the walk (same values, fewer counted
- * interactions). Returns 0 or -1. */
+ * cells of zero mass from the walk and particles of zero mass from the leaf
+ * lists (same values, fewer counted interactions). Returns 0 or -1. */
 OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const double *r_in,
                                 const double *r_out, const double *r_search, int64_t n,
                                 double theta, int leaf_size, int group_size, int max_level,
@@ -707,9 +719,13 @@ OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const dou
         L.near = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.cap);
         L.npc = L.nfar = L.nnear = 0;
         walk(&b.cells, 0, gc, th2, ext, skip_massless, &L);
+        /* particles of the far and near leaves (with skip_massless, those
+         * with mass) */
         int64_t nfarp = 0, nnearp = 0;
-        for (int64_t t = 0; t < L.nfar; t++) nfarp += b.cells.c[L.far[t]].count;
-        for (int64_t t = 0; t < L.nnear; t++) nnearp += b.cells.c[L.near[t]].count;
+        for (int64_t t = 0; t < L.nfar; t++)
+            nfarp += source_count(&b, &b.cells.c[L.far[t]], mass, skip_massless);
+        for (int64_t t = 0; t < L.nnear; t++)
+            nnearp += source_count(&b, &b.cells.c[L.near[t]], mass, skip_massless);
         for (int64_t m = 0; m < gc->count; m++) {
             int64_t i = b.perm[gc->begin + m];
             int64_t k = slot[i];
@@ -725,6 +741,7 @@ OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const dou
                 const ocell *c = &b.cells.c[L.far[t]];
                 for (int64_t u = 0; u < c->count; u++) {
                     int64_t j = b.perm[c->begin + u];
+                    if (skip_massless && mass[j] == 0.0) continue;
                     double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
                     double r = sqrt(dx * dx + dy * dy + dz * dz);
                     double s = G * mass[j] / (r * r * r);
@@ -739,7 +756,7 @@ OR_EXPORT int oracle_tree_force(const double *pos, const double *mass, const dou
                 const ocell *c = &b.cells.c[L.near[t]];
                 for (int64_t u = 0; u < c->count; u++) {
                     int64_t j = b.perm[c->begin + u];
-                    if (j == i) continue;
+                    if (j == i || (skip_massless && mass[j] == 0.0)) continue;
                     double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
                     double r = sqrt(dx * dx + dy * dy + dz * dz);
                     double rin, rout, fw, pw;

@@ -442,10 +442,25 @@ __device__ __forceinline__ int find_leaf(const uint32_t *pre, int nleaf, uint32_
     return lo;
 }
 
+// Source particle k (position p) into entry e of the particle tile.
+template <int KIND, typename R>
+__device__ __forceinline__ void stage_part(WaveLds<R> &L, int e, const double4 &p, uint32_t k,
+                                           const ForceLaunch &f) {
+    L.part.e[e].a = {(R)(p.x - L.g.c[0]), (R)(p.y - L.g.c[1]), (R)(p.z - L.g.c[2]), (R)p.w};
+    if (KIND == kTileNear) {
+        const double2 rr = f.t.rr[k];
+        L.part.e[e].c = {(R)rr.x, (R)rr.y};
+        L.part.e[e].k = k;
+    }
+}
+
 // ---- leaves (far: Newtonian pairs; near: changeover pairs). On entry
 // pre[] holds each buffered leaf's particle count; it is turned into an
-// exclusive prefix and the particles are expanded in tiles of 64.
-template <int KIND, typename R, int IPL>
+// exclusive prefix and the particles are expanded in tiles of 64. Returns
+// the number of source particles run. kSub: a force on a subset of targets
+// (no neighbour lists), where particles of zero mass are dropped as sources
+// (their terms are zero) and the rest packed to the front of the tile.
+template <int KIND, bool kSub, typename R, int IPL>
 __device__ uint32_t flush_leaves(WaveLds<R> &L, const uint32_t *start, uint32_t *pre, int nleaf,
                                  const ForceLaunch &f, const Layout &ly, Targets<R, IPL> &T,
                                  bool record, uint32_t gstart, uint32_t gn) {
@@ -471,22 +486,43 @@ __device__ uint32_t flush_leaves(WaveLds<R> &L, const uint32_t *start, uint32_t 
     uint32_t total = last_lane(incl);
     if (lane < nleaf) pre[lane] = incl - c;
     wave_sync();
+    uint32_t kept = 0;
     for (uint32_t base = 0; base < total; base += kWave) {
         const uint32_t s = base + lane;
-        const int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
-        const int mpad = pad_to(m, KIND, ly.S);
+        int m = (int)(total - base < (uint32_t)kWave ? total - base : (uint32_t)kWave);
+        bool have = false;
         if (s < total) {
-            int l = find_leaf(pre, nleaf, s);
-            uint32_t k = start[l] + (s - pre[l]);
-            double4 p = f.t.ps[k];
-            L.part.e[lane].a = {(R)(p.x - L.g.c[0]), (R)(p.y - L.g.c[1]), (R)(p.z - L.g.c[2]),
-                              (R)p.w};
-            if (KIND == kTileNear) {
-                double2 rr = f.t.rr[k];
-                L.part.e[lane].c = {(R)rr.x, (R)rr.y};
-                L.part.e[lane].k = k;
+            const int l = find_leaf(pre, nleaf, s);
+            const uint32_t k = start[l] + (s - pre[l]);
+            const double4 p = f.t.ps[k];
+            have = p.w != 0.0;
+            stage_part<KIND>(L, lane, p, k, f);
+        }
+        if constexpr (kSub) {
+            // move the entries with mass to the front of the tile
+            const unsigned long long km = __ballot(have);
+            if (km != (m == kWave ? ~0ull : (1ull << m) - 1ull)) {
+                wave_sync();
+                const typename Vec<R>::v4 a = L.part.e[lane].a;
+                typename Vec<R>::v2 c = {(R)0, (R)0};
+                uint32_t k = 0;
+                if (KIND == kTileNear) {
+                    c = L.part.e[lane].c;
+                    k = L.part.e[lane].k;
+                }
+                wave_sync();
+                if (have) {
+                    const int e = lanes_below(km);
+                    L.part.e[e].a = a;
+                    if (KIND == kTileNear) {
+                        L.part.e[e].c = c;
+                        L.part.e[e].k = k;
+                    }
+                }
+                m = __popcll(km);
             }
         }
+        const int mpad = pad_to(m, KIND, ly.S);
         for (int t = m + lane; t < mpad; t += kWave) {
             L.part.e[t].a = {(R)kFarAway, (R)kFarAway, (R)kFarAway, (R)0};
             if (KIND == kTileNear) {
@@ -497,8 +533,9 @@ __device__ uint32_t flush_leaves(WaveLds<R> &L, const uint32_t *start, uint32_t 
         wave_sync();
         run_tile<KIND>(L.part, mpad, ly, T);
         wave_sync();
+        kept += (uint32_t)m;
     }
-    return total;
+    return kept;
 }
 
 // Folds the partial sums of the S lanes that split one target's sources
@@ -547,7 +584,10 @@ __device__ __forceinline__ void kick_write(double *vel, int64_t n, uint32_t o, d
     vel[2 * n + o] = vel[2 * n + o] + az * dt;
 }
 
-template <typename R, int IPL>
+// kSub: the targets are the listed subset (tpos, tidx) and cells and
+// particles of zero mass are no sources; otherwise every particle is a
+// target.
+template <typename R, int IPL, bool kSub>
 __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
     __shared__ WaveLds<R> lds_all[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
@@ -586,7 +626,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
         const uint32_t gn = (uint32_t)uniform((int)ginfo.y);
         // the group's targets: all its particles, or the listed subset
         uint32_t t0 = gstart, tn = gn;
-        if (f.tidx) {
+        if constexpr (kSub) {
             t0 = (uint32_t)uniform((int)f.tpos[gstart]);
             tn = (uint32_t)uniform((int)f.tpos[gstart + gn]) - t0;
             if (tn == 0) continue;  // sources only: no walk
@@ -602,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
             for (int u = 0; u < IPL; u++) {
                 uint32_t off = chunk + u * ly.W + ly.il;
                 bool valid = ly.act && u < ly.nu && off < tn;
-                uint32_t k = f.tidx ? f.tidx[t0 + (valid ? off : 0u)] : gstart + (valid ? off : 0u);
+                uint32_t k = kSub ? f.tidx[t0 + (valid ? off : 0u)] : gstart + (valid ? off : 0u);
                 double4 p = f.t.ps[k];
                 double2 rr = f.t.rr[k];
                 T.x[u] = (R)(p.x - L.g.c[0]);
@@ -640,11 +680,8 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                                                   ? (near ? kKindNear : kKindFar)
                                                   : kKindOpen));
                 // on a subset of targets (no neighbour lists), a cell of zero
-                // mass is dropped with its subtree: it exerts no force (a
-                // branch on the uniform flag, which the empty asm keeps from
-                // being turned into selects executed on every step)
-                if (f.tidx) {
-                    asm volatile("" ::: "memory");
+                // mass is dropped with its subtree: it exerts no force
+                if constexpr (kSub) {
                     if (cm.w == 0.0) kind = kKindNone;
                 }
                 int nc = kind == kKindOpen ? info_nchild(info.z) : 0;
@@ -681,7 +718,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                         L.far_pre[p] = info.y;
                     }
                     if (nfar + cnt >= kWave) {
-                        n_far += flush_leaves<kTileFar>(L, L.far_start, L.far_pre, kWave, f, ly,
+                        n_far += flush_leaves<kTileFar, kSub>(L, L.far_start, L.far_pre, kWave, f, ly,
                                                         T, false, gstart, gn);
                         if (kind == kKindFar && p >= kWave) {
                             L.far_start[p - kWave] = info.x;
@@ -701,7 +738,7 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                         L.near_pre[p] = info.y;
                     }
                     if (nnear + cnt >= kWave) {
-                        n_near += flush_leaves<kTileNear>(L, L.near_start, L.near_pre, kWave, f,
+                        n_near += flush_leaves<kTileNear, kSub>(L, L.near_start, L.near_pre, kWave, f,
                                                           ly, T, record, gstart, gn);
                         if (kind == kKindNear && p >= kWave) {
                             L.near_start[p - kWave] = info.x;
@@ -722,14 +759,26 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 flush_pc(L, npc, ly, T);
                 n_pc += npc;
             }
-            if (nfar) n_far += flush_leaves<kTileFar>(L, L.far_start, L.far_pre, nfar, f, ly, T,
+            if (nfar) n_far += flush_leaves<kTileFar, kSub>(L, L.far_start, L.far_pre, nfar, f, ly, T,
                                                         false, gstart, gn);
             if (nnear)
-                n_near += flush_leaves<kTileNear>(L, L.near_start, L.near_pre, nnear, f, ly, T,
+                n_near += flush_leaves<kTileNear, kSub>(L, L.near_start, L.near_pre, nnear, f, ly, T,
                                                   record, gstart, gn);
             cnt_pc += n_pc * active;
             cnt_far += n_far * active;
-            cnt_near += n_near * active - active;  // minus the self pairs
+            // minus the self pairs: every target's, or on a subset (massless
+            // sources dropped) those of the targets with mass
+            uint32_t n_self = active;
+            if constexpr (kSub) {
+                n_self = 0;
+#pragma unroll
+                for (int u = 0; u < IPL; u++) {
+                    const bool own = T.k[u] != kNone && ly.sl == 0;
+                    n_self += (uint32_t)__popcll(
+                        __ballot(own && f.t.ps[own ? T.k[u] : 0u].w != 0.0));
+                }
+            }
+            cnt_near += n_near * active - n_self;
             if (ly.S > 1) combine_split(L, T, ly);
 #pragma unroll
             for (int u = 0; u < IPL; u++) {
@@ -793,7 +842,8 @@ inline unsigned blocks_for(int64_t n) {
 template <typename R, int IPL>
 int resident_for(int device) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<R, IPL>, kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<R, IPL, false>, kThreads,
+                                                     0) !=
         hipSuccess)
         per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
@@ -806,7 +856,10 @@ int resident_for(int device) {
 template <typename R, int IPL>
 void launch_t(const ForceLaunch &f, int resident_waves, hipStream_t s) {
     int blocks = resident_waves / kWavesPerBlock;
-    hipLaunchKernelGGL((k_force<R, IPL>), dim3(blocks), dim3(kThreads), 0, s, f);
+    if (f.tidx)
+        hipLaunchKernelGGL((k_force<R, IPL, true>), dim3(blocks), dim3(kThreads), 0, s, f);
+    else
+        hipLaunchKernelGGL((k_force<R, IPL, false>), dim3(blocks), dim3(kThreads), 0, s, f);
 }
 
 }  // namespace

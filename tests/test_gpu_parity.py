@@ -918,8 +918,9 @@ def test_target_subset_matches_oracle_tree(pt, ctx, orc, theta):
 
 
 def test_target_subset_skips_massless_cells(pt, ctx, orc):
-    """On a subset of targets the walk drops cells of zero mass (a clump of
-    massless particles and a third of the others without mass): FP64 against
+    """On a subset of targets the walk drops cells of zero mass and the leaf
+    tiles particles of zero mass (a clump of massless particles and a third
+    of the others without mass): FP64 against
     the oracle tree with the same rule within 1e-12 and with equal counts;
     the counts are lower than without the rule; mixed precision against the
     unrestricted call within the arithmetic bound."""

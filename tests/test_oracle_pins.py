@@ -367,10 +367,12 @@ def _with_massless(orc, n, seed):
 
 
 def test_tree_skip_massless_changes_no_value(orc):
-    """Dropping the cells of zero mass from the walk (the rule of a force on
-    a subset of targets) leaves every acceleration and potential bit for bit
-    as it was, at theta 0 still equal to the direct sum, and only lowers the
-    interaction counts: whole massless cells are no longer visited."""
+    """Dropping the cells of zero mass from the walk and the particles of
+    zero mass from the leaf lists (the rule of a force on a subset of
+    targets) leaves every acceleration and potential bit for bit as it was,
+    at theta 0 still equal to the direct sum, and only lowers the
+    interaction counts: at theta 0 each target's particle lists hold exactly
+    the particles with mass."""
     pos, mass, rin, rout, rs = _with_massless(orc, 3000, 25)
     idx = np.arange(0, 3000, 3)
     for theta in (0.0, 0.5):
@@ -382,7 +384,18 @@ def test_tree_skip_massless_changes_no_value(orc):
         assert np.array_equal(c2[3], c1[3])
     a0, p0 = orc.force_long(pos, mass, rin, rout, idx=idx)
     err = np.linalg.norm(a2 - a0, axis=0) / np.linalg.norm(a0, axis=0)
-    a0t, _, _ = orc.tree_force(pos, mass, rin, rout, rs, 0.0, 8, 64, idx=idx, skip_massless=True)
+    a0t, _, c0t = orc.tree_force(pos, mass, rin, rout, rs, 0.0, 8, 64, idx=idx,
+                                 skip_massless=True)
+    # at theta 0 every leaf is reached: the far and near lists of each target
+    # hold every particle with mass once (and every particle without the rule)
+    _, _, c0 = orc.tree_force(pos, mass, rin, rout, rs, 0.0, 8, 64, idx=idx)
+    assert np.all(c0t[0] == 0) and np.all(c0t[1] + c0t[2] == np.count_nonzero(mass))
+    assert np.all(c0[1] + c0[2] == mass.size)
+    # with every mass nonzero the rule changes nothing, the counts included
+    m1 = np.where(mass == 0.0, 1e-7, mass)
+    r1 = orc.tree_force(pos, m1, rin, rout, rs, 0.5, 8, 64, idx=idx)
+    r2 = orc.tree_force(pos, m1, rin, rout, rs, 0.5, 8, 64, idx=idx, skip_massless=True)
+    assert all(np.array_equal(x, y) for x, y in zip(r1, r2))
     err0 = np.linalg.norm(a0t - a0, axis=0) / np.linalg.norm(a0, axis=0)
     assert err0.max() < 1e-11 and err.max() < 1e-2
 
