@@ -718,8 +718,8 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                         L.far_pre[p] = info.y;
                     }
                     if (nfar + cnt >= kWave) {
-                        n_far += flush_leaves<kTileFar, kSub>(L, L.far_start, L.far_pre, kWave, f, ly,
-                                                        T, false, gstart, gn);
+                        n_far += flush_leaves<kTileFar, kSub>(L, L.far_start, L.far_pre, kWave,
+                                                              f, ly, T, false, gstart, gn);
                         if (kind == kKindFar && p >= kWave) {
                             L.far_start[p - kWave] = info.x;
                             L.far_pre[p - kWave] = info.y;
@@ -738,8 +738,9 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                         L.near_pre[p] = info.y;
                     }
                     if (nnear + cnt >= kWave) {
-                        n_near += flush_leaves<kTileNear, kSub>(L, L.near_start, L.near_pre, kWave, f,
-                                                          ly, T, record, gstart, gn);
+                        n_near += flush_leaves<kTileNear, kSub>(L, L.near_start, L.near_pre,
+                                                                kWave, f, ly, T, record, gstart,
+                                                                gn);
                         if (kind == kKindNear && p >= kWave) {
                             L.near_start[p - kWave] = info.x;
                             L.near_pre[p - kWave] = info.y;
@@ -759,11 +760,12 @@ __global__ __launch_bounds__(kThreads) void k_force(ForceLaunch f) {
                 flush_pc(L, npc, ly, T);
                 n_pc += npc;
             }
-            if (nfar) n_far += flush_leaves<kTileFar, kSub>(L, L.far_start, L.far_pre, nfar, f, ly, T,
-                                                        false, gstart, gn);
+            if (nfar)
+                n_far += flush_leaves<kTileFar, kSub>(L, L.far_start, L.far_pre, nfar, f, ly, T,
+                                                      false, gstart, gn);
             if (nnear)
-                n_near += flush_leaves<kTileNear, kSub>(L, L.near_start, L.near_pre, nnear, f, ly, T,
-                                                  record, gstart, gn);
+                n_near += flush_leaves<kTileNear, kSub>(L, L.near_start, L.near_pre, nnear, f, ly,
+                                                        T, record, gstart, gn);
             cnt_pc += n_pc * active;
             cnt_far += n_far * active;
             // minus the self pairs: every target's, or on a subset (massless
